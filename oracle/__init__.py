@@ -1,0 +1,177 @@
+"""Plain CPU FP64 reference for the randomized LUPP interpolative decomposition.
+
+TEST INFRASTRUCTURE ONLY.  This package is imported by the tests, by the smoke
+check and by the CPU-baseline leg of the benchmark, never by the library.  It
+shares no code with the GPU path: the arithmetic lives in ``rid_oracle.c``
+(plain C, double precision, ascending-order sums, no fused multiply-add) and
+this module only marshals NumPy arrays into it.
+
+Method: Pearce, Chen, Dong, Martinsson, arXiv 2310.09417.
+  * sketch                 -- Sec. 2.4 (randomized column/row sketch)
+  * LU with partial pivots -- Sec. 2.3.2 (pivot rule and Schur update)
+  * E_Schur estimate       -- Sec. 3.2, eq. (errSch)
+  * interpolation matrix   -- Sec. 3.2, eq. (inty); Alg. 1, final step
+  * adaptive blocked loop  -- Sec. 4.2 and Alg. 1 (randLUPPadap)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rid_oracle.c")
+_LIB = os.path.join(_HERE, "librid_oracle.so")
+
+OK, NOT_CONVERGED, RANK_DEFICIENT, ERR_ARG, ERR_NONFINITE = 0, 1, 2, -1, -2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+            "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("err_est", ctypes.c_double),
+                ("status", ctypes.c_int32), ("nsteps", ctypes.c_int32),
+                ("min_gap", ctypes.c_double), ("min_gap_step", ctypes.c_int64),
+                ("fro_a", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, u64, dbl, cint = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
+        lib.orc_philox4x32_10.argtypes = [P, P, P]
+        lib.orc_philox4x32_10.restype = None
+        lib.orc_omega.argtypes = [u64, i64, i64, i64, P]
+        lib.orc_omega.restype = None
+        lib.orc_sketch.argtypes = [P, i64, i64, i64, u64, i64, i64, P, i64]
+        lib.orc_sketch.restype = None
+        lib.orc_rid_lupp.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
+                                     P, P, i64, P, i64, ctypes.POINTER(_Result)]
+        lib.orc_rid_lupp.restype = cint
+        lib.orc_lupp_factors.argtypes = [P, i64, i64, i64, i64, i64, u64, P, P, P]
+        lib.orc_lupp_factors.restype = cint
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: 4 counter words, 2 key words -> 4 words."""
+    lib = _load()
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def omega(seed: int, c0: int, w: int, m: int) -> np.ndarray:
+    """Gaussian embedding block: out[c, i] = omega(c0 + c, i)."""
+    lib = _load()
+    out = np.empty((w, m), dtype=np.float64)
+    lib.orc_omega(seed, c0, w, m, _ptr(out))
+    return out
+
+
+def sketch(A: np.ndarray, seed: int, c0: int, w: int) -> np.ndarray:
+    """Y = Omega(c0:c0+w, :) @ A, summed in ascending row order."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    Y = np.empty((w, n), dtype=np.float64)
+    lib.orc_sketch(_ptr(A), m, n, n, seed, c0, w, _ptr(Y), n)
+    return Y
+
+
+@dataclass
+class IDResult:
+    J: np.ndarray           # skeleton columns, pivot order
+    T: np.ndarray           # k x (n-k), column q <-> q-th non-skeleton in ascending order
+    k: int
+    err_est: float          # E_Schur / sqrt(w); -1 when no estimate was taken
+    status: int
+    E_hist: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    min_gap: float = float("inf")
+    min_gap_step: int = -1
+    fro_a: float = 0.0
+
+    def X(self, n: int) -> np.ndarray:
+        """Column interpolation matrix (k x n) with X[:, J] = I."""
+        k = self.k
+        X = np.zeros((k, n))
+        rest = np.setdiff1d(np.arange(n), self.J)
+        X[:, self.J] = np.eye(k)
+        X[:, rest] = self.T
+        return X
+
+
+def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096) -> IDResult:
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    cap = max(1, min(m, n))
+    J = np.zeros(cap, dtype=np.int64)
+    T = np.zeros((cap, n), dtype=np.float64)
+    hist = np.zeros(hist_cap, dtype=np.float64)
+    res = _Result()
+    lib.orc_rid_lupp(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
+                     _ptr(J), _ptr(T), n, _ptr(hist), hist_cap, ctypes.byref(res))
+    k = int(res.k)
+    return IDResult(J=J[:k].copy(), T=T[:k, : n - k].copy(), k=k, err_est=float(res.err_est),
+                    status=int(res.status), E_hist=hist[: res.nsteps].copy(),
+                    min_gap=float(res.min_gap), min_gap_step=int(res.min_gap_step),
+                    fro_a=float(res.fro_a))
+
+
+def rid_fixed_rank(A, k: int, p: int, seed: int) -> IDResult:
+    """randLUPP at fixed rank k with p extra sketch vectors for E_Schur."""
+    return _run(A, 0, k, p, 0.0, False, k, seed)
+
+
+def rid_adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True) -> IDResult:
+    """randLUPPadap (Alg. 1): blocks of b sketch vectors until E <= tol."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed)
+
+
+def lupp_factors(A, l: int, k: int, seed: int):
+    """k LUPP steps on Y^T for Y = Omega(0:l) A; returns (L n x k, U k x l, perm)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    L = np.zeros((n, k))
+    U = np.zeros((k, l))
+    perm = np.zeros(n, dtype=np.int64)
+    st = lib.orc_lupp_factors(_ptr(A), m, n, n, l, k, seed, _ptr(L), _ptr(U), _ptr(perm))
+    return st, L, U, perm
+
+
+def true_residual(A: np.ndarray, J: np.ndarray, T: np.ndarray) -> float:
+    """||A(:, J^c) - A(:, J) T||_F (the skeleton columns are reproduced exactly)."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[1]
+    rest = np.setdiff1d(np.arange(n), J)
+    if len(rest) == 0:
+        return 0.0
+    return float(np.linalg.norm(A[:, rest] - A[:, J] @ T))
+

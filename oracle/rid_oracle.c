@@ -1,0 +1,443 @@
+/*
+ * rid_oracle.c -- plain, slow CPU reference for the randomized LUPP
+ * interpolative decomposition (Pearce, Chen, Dong, Martinsson, "Adaptive
+ * parallelizable algorithms for interpolative decompositions via partially
+ * pivoted LU", arXiv 2310.09417).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library links or calls this file;
+ * only the tests, the smoke check and the CPU-baseline leg of the benchmark do.
+ * It shares no code, header or constant table with the GPU path.
+ *
+ * Arithmetic: IEEE double, every sum taken in ascending index order, built
+ * with -ffp-contract=off so that no multiply-add is fused.  OpenMP is used only
+ * across independent outputs (columns of a sketch, candidates of the final
+ * solve), so every result is independent of the thread count.
+ *
+ * Column form throughout: A is m x n (row-major, leading dimension lda), the
+ * sketch is Y = Omega * A (l x n), LU with partial pivoting runs on Y^T
+ * (n x l) and selects columns of A.  The paper writes the row form
+ * (Y = A * Omega, LUPP on Y); the column form is the same algorithm applied to
+ * A^T (paper, Sec. 4, last sentence before Sec. 4.1).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Status codes (same numbering as the library's public header: an interface
+ * both sides must agree on, restated here rather than shared). */
+enum {
+  ORC_OK = 0,
+  ORC_NOT_CONVERGED = 1,
+  ORC_RANK_DEFICIENT = 2,
+  ORC_ERR_ARG = -1,
+  ORC_ERR_NONFINITE = -2
+};
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,       */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11, Sec. 4.2).          */
+/* One round maps (c0,c1,c2,c3) with key (k0,k1) to                          */
+/*   (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0));       */
+/* the key is advanced by the Weyl constants (W0,W1) between rounds.         */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian embedding entries (paper Sec. 3.2 and Alg. 1: independent        */
+/* Gaussian blocks Omega^(t)).  Entry omega(c, i) of sketch vector c at row  */
+/* i is a pure function of (seed, c, i):                                     */
+/*   counter = (floor(i/4), c, 0, 0), key = (seed low 32, seed high 32),     */
+/*   u_a = (x_a + 1/2) * 2^-32 in (0,1) for the four output words x_a,       */
+/*   Box-Muller on (u0,u1) gives rows 4q, 4q+1 and on (u2,u3) rows 4q+2,     */
+/*   4q+3:  sqrt(-2 ln u) * (cos 2 pi v, sin 2 pi v).                        */
+/* Sketch vectors are numbered globally: block t of width b holds vectors    */
+/* t*b .. t*b+b-1, so every block is independent of every other.            */
+/* ------------------------------------------------------------------------ */
+static void omega_quad(uint64_t seed, uint32_t q, uint32_t c, double w[4]) {
+  uint32_t ctr[4] = {q, c, 0u, 0u};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  orc_philox4x32_10(ctr, key, x);
+  const double two_pi = 6.283185307179586476925286766559;
+  double u[4];
+  for (int a = 0; a < 4; ++a) u[a] = ((double)x[a] + 0.5) * 0x1p-32;
+  double r0 = sqrt(-2.0 * log(u[0]));
+  double r1 = sqrt(-2.0 * log(u[2]));
+  w[0] = r0 * cos(two_pi * u[1]);
+  w[1] = r0 * sin(two_pi * u[1]);
+  w[2] = r1 * cos(two_pi * u[3]);
+  w[3] = r1 * sin(two_pi * u[3]);
+}
+
+/* Omega block: out[c * m + i] = omega(c0 + c, i), c < w, i < m. */
+void orc_omega(uint64_t seed, int64_t c0, int64_t w, int64_t m, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < w; ++c) {
+    for (int64_t i = 0; i < m; i += 4) {
+      double v[4];
+      omega_quad(seed, (uint32_t)(i / 4), (uint32_t)(c0 + c), v);
+      for (int a = 0; a < 4 && i + a < m; ++a) out[c * m + i + a] = v[a];
+    }
+  }
+}
+
+/* Sketch (paper Sec. 2.4): Y(c, j) = sum_{i=0}^{m-1} omega(c0+c, i) * A(i, j),
+ * summed in ascending i.  Y is w x n row-major with leading dimension ldy.
+ * Each output column strip is owned by one thread. */
+void orc_sketch(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                int64_t c0, int64_t w, double* Y, int64_t ldy) {
+  double* om = (double*)malloc(sizeof(double) * (size_t)(w > 0 ? w : 1) * (size_t)(m > 0 ? m : 1));
+  orc_omega(seed, c0, w, m, om);
+  const int64_t strip = 256;
+  int64_t nstrips = (n + strip - 1) / strip;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t sidx = 0; sidx < nstrips; ++sidx) {
+    int64_t j0 = sidx * strip, j1 = j0 + strip < n ? j0 + strip : n;
+    for (int64_t c = 0; c < w; ++c)
+      for (int64_t j = j0; j < j1; ++j) Y[c * ldy + j] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+      const double* a = A + i * lda;
+      for (int64_t c = 0; c < w; ++c) {
+        double o = om[c * m + i];
+        double* y = Y + c * ldy;
+        for (int64_t j = j0; j < j1; ++j) y[j] = y[j] + o * a[j];
+      }
+    }
+  }
+  free(om);
+}
+
+/* Sum of squares of A in ascending (row, column) order. */
+static double frob2(const double* A, int64_t m, int64_t n, int64_t lda, int* nonfinite) {
+  double s = 0.0;
+  *nonfinite = 0;
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double v = A[i * lda + j];
+      if (!isfinite(v)) *nonfinite = 1;
+      s = s + v * v;
+    }
+  return s;
+}
+
+/* Result record returned to the caller. */
+typedef struct {
+  int64_t k;          /* rank of the returned ID (= number of skeletons)         */
+  double err_est;     /* Schur-complement estimate E for that rank (-1 if none)  */
+  int32_t status;     /* ORC_* code                                              */
+  int32_t nsteps;     /* number of estimates taken (length of the E history)    */
+  double min_gap;     /* min over pivot steps of (|1st| - |2nd|) / |1st|        */
+  int64_t min_gap_step;
+  double fro_a;       /* ||A||_F                                                 */
+} orc_result;
+
+/*
+ * Blocked LUPP interpolative decomposition on the sketch (paper Alg. 1 and
+ * Sec. 4.2), column form.
+ *
+ *   mode 0 (fixed rank, randLUPP): one block of k sketch vectors is factored
+ *     (k pivots), then one block of p vectors is drawn only to estimate the
+ *     error of that rank-k ID (Sec. 3.2, E_Schur on an independent sample).
+ *   mode 1 (adaptive, randLUPPadap): the first block of b vectors is always
+ *     factored; each later block of b vectors is first reduced by the current
+ *     factorization (U2 = L1^{-1} (P Y)(top), S = (P Y)(bottom) - L2 U2), its
+ *     Frobenius norm gives the estimate, and only if that misses the
+ *     tolerance is S factored and appended.
+ *
+ * Z (n x zc) holds P * [Y^(0) ... Y^(t)]^T with its LU factors in place:
+ * row r is candidate column perm[r]; for r < k the row holds U (columns
+ * >= r) and L1 (columns < r); for r >= k columns < k hold L2.
+ *
+ * Estimate scaling: Omega has unit variance, so E = ||S||_F / sqrt(w) is the
+ * unbiased estimate of the residual norm (E||X w||^2 = ||X||_F^2 per unit
+ * vector w).
+ *
+ * Outputs: J[0..k) pivot order (original column indices); T (k x (n-k),
+ * row-major, ldt) with column q belonging to the q-th non-skeleton column in
+ * ascending index; E history (up to hist_cap entries).
+ */
+int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                 int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
+                 uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
+                 int64_t hist_cap, orc_result* res) {
+  memset(res, 0, sizeof(*res));
+  res->err_est = -1.0;
+  res->min_gap = INFINITY;
+  res->min_gap_step = -1;
+  if (m < 1 || n < 1 || lda < n || k_or_b < 1 || p < 0 || (mode != 0 && mode != 1)) {
+    res->status = ORC_ERR_ARG;
+    return ORC_ERR_ARG;
+  }
+  const int64_t mn = m < n ? m : n;
+  int64_t kcap, first_w, later_w;
+  if (mode == 0) {
+    if (k_or_b > mn) {
+      res->status = ORC_ERR_ARG;
+      return ORC_ERR_ARG;
+    }
+    kcap = k_or_b;
+    first_w = k_or_b;
+    later_w = p;
+  } else {
+    if (kmax < 1) {
+      res->status = ORC_ERR_ARG;
+      return ORC_ERR_ARG;
+    }
+    kcap = kmax < mn ? kmax : mn;
+    first_w = k_or_b < kcap ? k_or_b : kcap;
+    later_w = k_or_b;
+  }
+
+  int nonfinite = 0;
+  double fa2 = frob2(A, m, n, lda, &nonfinite);
+  res->fro_a = sqrt(fa2);
+  if (nonfinite) {
+    res->status = ORC_ERR_NONFINITE;
+    return ORC_ERR_NONFINITE;
+  }
+  const double thr = tol_relative ? tol * sqrt(fa2) : tol;
+
+  const int64_t zc = kcap + (later_w > first_w ? later_w : first_w) + 1;
+  double* Z = (double*)calloc((size_t)n * (size_t)zc, sizeof(double));
+  int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  double* Ynew = (double*)malloc(sizeof(double) * (size_t)n * (size_t)(zc));
+  for (int64_t r = 0; r < n; ++r) perm[r] = r;
+
+  int64_t k = 0;        /* pivots taken so far */
+  int64_t cnext = 0;    /* next unused sketch vector */
+  double E = -1.0;
+  int status = ORC_OK;
+  int first = 1;
+
+  for (;;) {
+    int64_t w = first ? first_w : later_w;
+    if (w == 0) break; /* fixed rank with p = 0: no estimate */
+    /* Draw the next block and apply the current row permutation (P Y^T). */
+    orc_sketch(A, m, n, lda, seed, cnext, w, Ynew, n);
+    cnext += w;
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t q = 0; q < w; ++q) Z[r * zc + k + q] = Ynew[q * n + perm[r]];
+
+    if (k > 0) {
+      /* U2 = L1^{-1} (P Y)(0:k, new): forward substitution, ascending s. */
+      for (int64_t r = 0; r < k; ++r)
+        for (int64_t q = 0; q < w; ++q) {
+          double acc = Z[r * zc + k + q];
+          for (int64_t s = 0; s < r; ++s) acc = acc - Z[r * zc + s] * Z[s * zc + k + q];
+          Z[r * zc + k + q] = acc;
+        }
+      /* S = (P Y)(k:n, new) - L2 * U2, ascending s. */
+#pragma omp parallel for schedule(static)
+      for (int64_t r = k; r < n; ++r)
+        for (int64_t q = 0; q < w; ++q) {
+          double acc = Z[r * zc + k + q];
+          for (int64_t s = 0; s < k; ++s) acc = acc - Z[r * zc + s] * Z[s * zc + k + q];
+          Z[r * zc + k + q] = acc;
+        }
+    }
+
+    if (!first) {
+      /* E = ||S||_F / sqrt(w), rows k..n-1 in order, columns in order. */
+      double s2 = 0.0;
+      for (int64_t r = k; r < n; ++r)
+        for (int64_t q = 0; q < w; ++q) {
+          double v = Z[r * zc + k + q];
+          s2 = s2 + v * v;
+        }
+      E = sqrt(s2) / sqrt((double)w);
+      if (res->nsteps < hist_cap && E_hist) E_hist[res->nsteps] = E;
+      res->nsteps++;
+      if (mode == 0) break;                 /* fixed rank: estimate only */
+      if (E <= thr) break;                  /* certified at rank k */
+      if (k >= kcap) {                      /* cap reached, tolerance missed */
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+    }
+
+    /* LUPP on the block (paper eq. for the Schur update in Sec. 2.3.2). */
+    int64_t f = w < kcap - k ? w : kcap - k;
+    int deficient = 0;
+    for (int64_t s = k; s < k + f; ++s) {
+      /* pivot: largest |Z(r, s)| over r >= s; ties -> lowest original index */
+      int64_t piv = s;
+      double best = fabs(Z[s * zc + s]);
+      for (int64_t r = s + 1; r < n; ++r) {
+        double v = fabs(Z[r * zc + s]);
+        if (v > best || (v == best && perm[r] < perm[piv])) {
+          best = v;
+          piv = r;
+        }
+      }
+      /* diagnostic: relative gap between the best and the runner-up */
+      double second = -1.0;
+      for (int64_t r = s; r < n; ++r)
+        if (r != piv) {
+          double v = fabs(Z[r * zc + s]);
+          if (v > second) second = v;
+        }
+      if (best > 0.0 && second >= 0.0) {
+        double gap = (best - second) / best;
+        if (gap < res->min_gap) {
+          res->min_gap = gap;
+          res->min_gap_step = s;
+        }
+      }
+      if (best == 0.0) {
+        deficient = 1;
+        k = s;
+        break;
+      }
+      if (piv != s) { /* swap whole rows: this also permutes L2 (re-blocking) */
+        for (int64_t q = 0; q < zc; ++q) {
+          double tmp = Z[s * zc + q];
+          Z[s * zc + q] = Z[piv * zc + q];
+          Z[piv * zc + q] = tmp;
+        }
+        int64_t tp = perm[s];
+        perm[s] = perm[piv];
+        perm[piv] = tp;
+      }
+      double d = Z[s * zc + s];
+#pragma omp parallel for schedule(static)
+      for (int64_t r = s + 1; r < n; ++r) {
+        double l = Z[r * zc + s] / d;
+        Z[r * zc + s] = l;
+        for (int64_t q = s + 1; q < k + w; ++q) Z[r * zc + q] = Z[r * zc + q] - l * Z[s * zc + q];
+      }
+    }
+    if (deficient) {
+      status = ORC_RANK_DEFICIENT;
+      if (E < 0.0) E = 0.0;
+      break;
+    }
+    k += f;
+    first = 0;
+    if (mode == 1 && k == mn) { /* every column (or row) used: the ID is exact */
+      E = 0.0;
+      break;
+    }
+    if (mode == 0 && p == 0) break;
+  }
+
+  /* Outputs: skeletons in pivot order and T = L1^{-T} L2^T (paper eq. for the
+   * interpolation matrix in Sec. 3.2; last step of Alg. 1). */
+  for (int64_t s = 0; s < k; ++s) J[s] = perm[s];
+  int64_t nr = n - k;
+  /* rank[r - k] = position of candidate r among the non-skeletons in
+   * ascending original index */
+  int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nr > 0 ? nr : 1));
+  {
+    char* is_skel = (char*)calloc((size_t)n, 1);
+    int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t s = 0; s < k; ++s) is_skel[perm[s]] = 1;
+    int64_t q = 0;
+    for (int64_t j = 0; j < n; ++j)
+      if (!is_skel[j]) slot[j] = q++;
+    for (int64_t r = k; r < n; ++r) order[r - k] = slot[perm[r]];
+    free(is_skel);
+    free(slot);
+  }
+  if (T && k > 0) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = k; r < n; ++r) {
+      double* x = (double*)malloc(sizeof(double) * (size_t)k);
+      for (int64_t s = k - 1; s >= 0; --s) {
+        double acc = Z[r * zc + s];
+        for (int64_t s2 = s + 1; s2 < k; ++s2) acc = acc - Z[s2 * zc + s] * x[s2];
+        x[s] = acc;
+      }
+      int64_t q = order[r - k];
+      for (int64_t s = 0; s < k; ++s) T[s * ldt + q] = x[s];
+      free(x);
+    }
+  }
+  free(order);
+  free(Z);
+  free(perm);
+  free(Ynew);
+  res->k = k;
+  res->err_est = E;
+  res->status = status;
+  return status;
+}
+
+/*
+ * Fixed-rank LU factor dump for tests of the bound |L| <= 1 (paper
+ * Sec. 2.3.2): factors Y^T (n x l, built from the first l sketch vectors)
+ * with k pivot steps and returns L (n x k, rows in pivot order, unit
+ * diagonal) and U (k x l).
+ */
+int orc_lupp_factors(const double* A, int64_t m, int64_t n, int64_t lda, int64_t l,
+                     int64_t k, uint64_t seed, double* L, double* U, int64_t* perm_out) {
+  if (k > l || k > n) return ORC_ERR_ARG;
+  double* Y = (double*)malloc(sizeof(double) * (size_t)l * (size_t)n);
+  orc_sketch(A, m, n, lda, seed, 0, l, Y, n);
+  double* Z = (double*)malloc(sizeof(double) * (size_t)n * (size_t)l);
+  int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  for (int64_t r = 0; r < n; ++r) {
+    perm[r] = r;
+    for (int64_t q = 0; q < l; ++q) Z[r * l + q] = Y[q * n + r];
+  }
+  for (int64_t s = 0; s < k; ++s) {
+    int64_t piv = s;
+    double best = fabs(Z[s * l + s]);
+    for (int64_t r = s + 1; r < n; ++r) {
+      double v = fabs(Z[r * l + s]);
+      if (v > best || (v == best && perm[r] < perm[piv])) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (best == 0.0) {
+      free(Y); free(Z); free(perm);
+      return ORC_RANK_DEFICIENT;
+    }
+    if (piv != s) {
+      for (int64_t q = 0; q < l; ++q) {
+        double t = Z[s * l + q];
+        Z[s * l + q] = Z[piv * l + q];
+        Z[piv * l + q] = t;
+      }
+      int64_t tp = perm[s];
+      perm[s] = perm[piv];
+      perm[piv] = tp;
+    }
+    for (int64_t r = s + 1; r < n; ++r) {
+      double lv = Z[r * l + s] / Z[s * l + s];
+      Z[r * l + s] = lv;
+      for (int64_t q = s + 1; q < l; ++q) Z[r * l + q] = Z[r * l + q] - lv * Z[s * l + q];
+    }
+  }
+  for (int64_t r = 0; r < n; ++r) {
+    perm_out[r] = perm[r];
+    for (int64_t s = 0; s < k; ++s)
+      L[r * k + s] = (s < r) ? Z[r * l + s] : (s == r ? 1.0 : 0.0);
+  }
+  for (int64_t s = 0; s < k; ++s)
+    for (int64_t q = 0; q < l; ++q) U[s * l + q] = (q >= s) ? Z[s * l + q] : 0.0;
+  free(Y);
+  free(Z);
+  free(perm);
+  return ORC_OK;
+}

@@ -1,0 +1,95 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds no arithmetic of the decomposition itself: it only builds
+input matrices with known structure (spectrum, exact rank, pivot-adversarial
+patterns, kernel blocks) from seeded random numbers.
+
+Families (arXiv 2310.09417, Sec. 5.1 test matrices, plus the batched
+kernel-block workload):
+  * fast_decay / power_decay -- A = U diag(sigma) V^T with Haar-like U, V from
+    the QR of Gaussian matrices (R with positive diagonal); sigma chosen, so
+    the optimal rank-k error is known in closed form.
+  * kahan                    -- D_n K_n with zeta^2 + phi^2 = 1.
+  * exact_rank               -- B @ C with Gaussian B (m x r), C (r x n).
+  * kernel_block             -- K_ij = 1 / |x_i - y_j| for points in two unit
+    cubes whose centres are d apart.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _haar_columns(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    g = rng.standard_normal((rows, cols))
+    q, r = np.linalg.qr(g)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def sigma_geometric(n: int, decades: float) -> np.ndarray:
+    """sigma_j = 10^(-decades * (j-1)/(n-1)), j = 1..n (the paper's Fast Decay
+    uses beta = 10^-16, i.e. 16 decades)."""
+    j = np.arange(n, dtype=np.float64)
+    return 10.0 ** (-decades * j / max(n - 1, 1))
+
+
+def sigma_power(n: int, power: float = 2.0) -> np.ndarray:
+    """sigma_j = j^-power, j = 1..n."""
+    return np.arange(1, n + 1, dtype=np.float64) ** (-power)
+
+
+def svd_matrix(m: int, n: int, sigma: np.ndarray, seed: int) -> np.ndarray:
+    """A = U diag(sigma) V^T, U m x r and V n x r with orthonormal columns,
+    r = min(m, n) = len(sigma)."""
+    r = min(m, n)
+    assert len(sigma) == r
+    rng = np.random.default_rng(seed)
+    U = _haar_columns(rng, m, r)
+    V = _haar_columns(rng, n, r)
+    return (U * sigma[None, :]) @ V.T
+
+
+def fast_decay(m: int, n: int, decades: float = 16.0, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    s = sigma_geometric(min(m, n), decades)
+    return svd_matrix(m, n, s, seed), s
+
+
+def power_decay(m: int, n: int, power: float = 2.0, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    s = sigma_power(min(m, n), power)
+    return svd_matrix(m, n, s, seed), s
+
+
+def kahan(n: int, zeta: float = 0.99) -> np.ndarray:
+    """Kahan matrix D_n K_n: D = diag(zeta^i), K unit upper with -phi above."""
+    phi = math.sqrt(1.0 - zeta * zeta)
+    K = np.triu(-phi * np.ones((n, n)), 1) + np.eye(n)
+    return (zeta ** np.arange(n, dtype=np.float64))[:, None] * K
+
+
+def exact_rank(m: int, n: int, r: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+
+
+def kernel_block(m: int, n: int, sep: float, seed: int) -> np.ndarray:
+    """K_ij = 1/|x_i - y_j|, x uniform in the unit cube at the origin, y in a
+    unit cube centred sep * u for a uniformly random unit vector u."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-0.5, 0.5, size=(m, 3))
+    u = rng.standard_normal(3)
+    u /= np.linalg.norm(u)
+    y = rng.uniform(-0.5, 0.5, size=(n, 3)) + sep * u[None, :]
+    d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(-1))
+    return 1.0 / d
+
+
+def kernel_batch_shapes(nblk: int, seed: int, lo: int = 64, hi: int = 1024):
+    """Per-block (m, n, separation, block seed) for the batched workload:
+    m, n uniform integers in [lo, hi], separation uniform in [3, 6]."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(lo, hi + 1, size=nblk)
+    n = rng.integers(lo, hi + 1, size=nblk)
+    sep = rng.uniform(3.0, 6.0, size=nblk)
+    seeds = rng.integers(0, 2**62, size=nblk)
+    return [(int(m[i]), int(n[i]), float(sep[i]), int(seeds[i])) for i in range(nblk)]
