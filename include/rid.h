@@ -1,0 +1,134 @@
+/*
+ * rid.h -- randomized interpolative decomposition by LU with partial pivoting
+ * on a Gaussian sketch, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Pearce, Chen, Dong, Martinsson, "Adaptive parallelizable algorithms
+ * for interpolative decompositions via partially pivoted LU" (arXiv
+ * 2310.09417).  Column form: for A (m x n) the library selects k columns J
+ * and an interpolation matrix T (k x (n-k)) with
+ *     A(:, J^c) ~= A(:, J) * T ,
+ * i.e. A ~= A(:, J) X with X(:, J) = I_k and X(:, J^c) = T (Sec. 2.2.1,
+ * column ID).  The row ID of the paper is the column ID of A^T.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked (device) are device pointers; everything else is host.
+ *  - A is row-major with leading dimension lda >= n (element (i,j) at
+ *    A[i*lda + j]).  The library never writes A.
+ *  - J receives the skeleton columns in pivot order, 0-based.
+ *  - T is row-major with leading dimension ldt >= n; column q of T belongs to
+ *    the q-th non-skeleton column of A in ascending index order.
+ *  - The caller owns every buffer, including the device workspace `work` of
+ *    at least rid_workspace_bytes(...) bytes, exclusively for the duration of
+ *    the call.  The library allocates nothing.
+ *  - Calls are asynchronous on `stream` and never synchronize with the host.
+ *    The return value reports only argument / workspace / launch errors that
+ *    the host can see.  The numerical outcome (rank, estimate, status) is
+ *    written to the device scalars k_out, err_est, status and is valid once
+ *    the stream has completed.
+ *  - Not reentrant on one workspace; distinct workspaces may be used
+ *    concurrently.
+ */
+#ifndef RID_H
+#define RID_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RID_OK = 0,              /* tolerance met (or fixed rank done)                      */
+  RID_NOT_CONVERGED = 1,   /* maximum rank reached with the estimate above tolerance  */
+  RID_RANK_DEFICIENT = 2,  /* an exactly zero pivot: the sketch has rank k_out        */
+  RID_ERR_ARG = -1,        /* invalid argument (host-detected)                        */
+  RID_ERR_NONFINITE = -2,  /* A holds a NaN or an infinity (device-detected)          */
+  RID_ERR_HIP = -3,        /* a HIP launch failed, or a device wait ran out           */
+  RID_ERR_WORKSPACE = -4   /* workspace too small (host-detected)                     */
+} rid_status;
+
+typedef enum {
+  RID_F64 = 0,       /* double                                   */
+  RID_F32 = 1        /* float                                    */
+} rid_dtype;
+
+typedef struct {
+  rid_dtype dtype;      /* storage type of A and T; LUPP, Schur updates and the
+                           interpolation solve run in this precision; every norm
+                           and the stopping test accumulate in FP64            */
+  int tol_relative;     /* 1: stop when E <= tol * ||A||_F; 0: when E <= tol   */
+  uint64_t seed;        /* key of the Gaussian embedding: entry (c, i) of sketch
+                           vector c is a pure function of (seed, c, i)          */
+} rid_config;
+
+/*
+ * Workspace size in bytes for a call with these sizes.  kmax is the rank
+ * cap (fixed rank: k + p; adaptive: kmax), b the block width (fixed rank:
+ * pass p).  Returns 0 for invalid arguments.
+ */
+size_t rid_workspace_bytes(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg);
+
+/* Human-readable name of a status code (static storage). */
+const char* rid_status_string(int status);
+
+/*
+ * Fixed-rank randomized LUPP ID (randLUPP; Sec. 3.1 and Sec. 3.2).
+ *   Y = Omega A with Omega (k+p) x m Gaussian, generated on the fly and never
+ *   stored.  LU with partial pivoting on the first k columns of Y^T selects J
+ *   (|J| = k, ties to the lowest column index); T = L1^{-T} L2^T
+ *   (eq. (inty)).  The p remaining sketch vectors form an independent sample:
+ *   err_est = ||S||_F / sqrt(p) for the Schur block S of eq. (errSch), the
+ *   unbiased estimate of ||A - A(:,J) X||_F (0 <= p; p = 0 gives -1).
+ * Arguments: 1 <= k <= min(m, n); J (device, int64[k]); T (device, dtype,
+ *   k rows of ldt); k_out, status (device int32), err_est (device double).
+ * Errors: RID_ERR_ARG for bad sizes or null pointers, RID_ERR_WORKSPACE when
+ *   work_bytes is too small, RID_ERR_HIP when a launch fails.
+ */
+int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
+                        const rid_config* cfg, int64_t* J, void* T, int64_t ldt, int32_t* k_out,
+                        double* err_est, int32_t* status, void* work, size_t work_bytes,
+                        hipStream_t stream);
+
+/*
+ * Adaptive blocked randomized LUPP ID (randLUPPadap; Alg. 1, Sec. 4.2).
+ *   The first block of b sketch vectors is factored.  Each further block
+ *   Y^(t) is reduced by the current factors, U2 = L1^{-1} (P Y^(t))(top) and
+ *   S = (P Y^(t))(bottom) - L2 U2; E = ||S||_F / sqrt(b) (FP64 accumulation).
+ *   If E <= tol (times ||A||_F when relative) the call stops with rank k and
+ *   status RID_OK; otherwise S is factored with partial pivoting and appended.
+ *   At k = kmax (capped by min(m, n)) with E above tolerance the status is
+ *   RID_NOT_CONVERGED; at k = min(m, n) the ID is exact (E = 0, RID_OK).
+ * Arguments: 1 <= b <= 128; kmax >= 1; J (device, int64, capacity
+ *   min(kmax, m, n)); T (device, capacity min(kmax,m,n) rows of ldt).
+ * Errors: as rid_lupp_fixed_rank.
+ */
+int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t b, double tol,
+                      int64_t kmax, const rid_config* cfg, int64_t* J, void* T, int64_t ldt,
+                      int32_t* k_out, double* err_est, int32_t* status, void* work,
+                      size_t work_bytes, hipStream_t stream);
+
+/*
+ * Test export: materialises the Gaussian embedding block
+ *   out[c * m + i] = omega(c0 + c, i), 0 <= c < w, 0 <= i < m
+ * in the given dtype (device buffer).  The decomposition never stores Omega;
+ * this exists so the generator can be checked on its own.
+ */
+int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtype, void* out,
+                       hipStream_t stream);
+
+/*
+ * Test export: the sketch alone, Yt = (Omega(c0:c0+w, :) A)^T stored as an
+ * n x w row-major matrix with leading dimension ldy (device, dtype), using
+ * the same kernels as the decomposition.  Requires a workspace of
+ * rid_workspace_bytes(m, n, w, w, cfg) bytes.  w <= 128.
+ */
+int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c0, int64_t w,
+                     const rid_config* cfg, void* Yt, int64_t ldy, void* work, size_t work_bytes,
+                     hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RID_H */

@@ -1,0 +1,16 @@
+"""MI355X-native randomized interpolative decomposition by LU with partial
+pivoting on a Gaussian sketch (arXiv 2310.09417).
+
+Thin binding over the C ABI of ``librid.so`` (declared in include/rid.h).
+This module only marshals arguments: torch tensors provide device memory and
+the current stream; every step of the decomposition runs in the HIP kernels.
+Importing it never loads the library; the first call does, and raises if the
+library has not been built.
+"""
+from .binding import (  # noqa: F401
+    RID_OK, RID_NOT_CONVERGED, RID_RANK_DEFICIENT, RID_ERR_ARG, RID_ERR_NONFINITE, RID_ERR_HIP,
+    RID_ERR_WORKSPACE, RID_F64, RID_F32, RidError, IDOutput, library, workspace_bytes,
+    status_string, fixed_rank, adaptive, debug_gaussian, debug_sketch,
+    rid_lupp_fixed_rank, rid_lupp_adaptive, rid_workspace_bytes, rid_debug_gaussian,
+    rid_debug_sketch, rid_status_string)
+from .flops import flops_id  # noqa: F401

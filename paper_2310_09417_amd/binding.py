@@ -1,0 +1,227 @@
+"""ctypes binding of librid.so (C ABI in include/rid.h).
+
+The ``rid_*`` functions take raw pointers (ints) and sizes exactly like the
+C entry points.  The convenience wrappers (``fixed_rank``, ``adaptive``, ...)
+take torch tensors, allocate outputs and the workspace with torch on the
+tensor's device, pass ``data_ptr()`` values and the current HIP stream, and
+read the device scalars back after the stream completes.  No arithmetic of
+the decomposition happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librid.so")
+
+RID_OK, RID_NOT_CONVERGED, RID_RANK_DEFICIENT = 0, 1, 2
+RID_ERR_ARG, RID_ERR_NONFINITE, RID_ERR_HIP, RID_ERR_WORKSPACE = -1, -2, -3, -4
+RID_F64, RID_F32 = 0, 1
+
+
+class RidError(RuntimeError):
+    pass
+
+
+class RidConfig(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("tol_relative", ctypes.c_int),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load librid.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RidError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(hipcc, gfx950); there is no CPU fallback")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, dbl, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_size_t)
+        cfgp = ctypes.POINTER(RidConfig)
+        lib.rid_workspace_bytes.argtypes = [i64, i64, i64, i64, cfgp]
+        lib.rid_workspace_bytes.restype = sz
+        lib.rid_status_string.argtypes = [i32]
+        lib.rid_status_string.restype = ctypes.c_char_p
+        lib.rid_lupp_fixed_rank.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, P, i64, P, P, P,
+                                            P, sz, P]
+        lib.rid_lupp_fixed_rank.restype = i32
+        lib.rid_lupp_adaptive.argtypes = [P, i64, i64, i64, i64, dbl, i64, cfgp, P, P, i64, P, P,
+                                          P, P, sz, P]
+        lib.rid_lupp_adaptive.restype = i32
+        lib.rid_debug_gaussian.argtypes = [ctypes.c_uint64, i64, i64, i64, i32, P, P]
+        lib.rid_debug_gaussian.restype = i32
+        lib.rid_debug_sketch.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, i64, P, sz, P]
+        lib.rid_debug_sketch.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _cfg(dtype: int, seed: int, tol_relative: bool = True) -> RidConfig:
+    return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed)
+
+
+# ---- raw C-ABI mirrors (pointers as ints) ----------------------------------
+
+def rid_workspace_bytes(m, n, kmax, b, cfg: RidConfig) -> int:
+    return int(library().rid_workspace_bytes(m, n, kmax, b, ctypes.byref(cfg)))
+
+
+def rid_status_string(status: int) -> str:
+    return library().rid_status_string(status).decode()
+
+
+def rid_lupp_fixed_rank(A, m, n, lda, k, p, cfg, J, T, ldt, k_out, err_est, status, work,
+                        work_bytes, stream) -> int:
+    return int(library().rid_lupp_fixed_rank(A, m, n, lda, k, p, ctypes.byref(cfg), J, T, ldt,
+                                              k_out, err_est, status, work, work_bytes, stream))
+
+
+def rid_lupp_adaptive(A, m, n, lda, b, tol, kmax, cfg, J, T, ldt, k_out, err_est, status, work,
+                      work_bytes, stream) -> int:
+    return int(library().rid_lupp_adaptive(A, m, n, lda, b, tol, kmax, ctypes.byref(cfg), J, T,
+                                           ldt, k_out, err_est, status, work, work_bytes, stream))
+
+
+def rid_debug_gaussian(seed, c0, w, m, dtype, out, stream) -> int:
+    return int(library().rid_debug_gaussian(seed, c0, w, m, dtype, out, stream))
+
+
+def rid_debug_sketch(A, m, n, lda, c0, w, cfg, Yt, ldy, work, work_bytes, stream) -> int:
+    return int(library().rid_debug_sketch(A, m, n, lda, c0, w, ctypes.byref(cfg), Yt, ldy, work,
+                                          work_bytes, stream))
+
+
+# ---- torch-facing wrappers -------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return RID_F64
+    if t.dtype == torch.float32:
+        return RID_F32
+    raise RidError(f"unsupported dtype {t.dtype}")
+
+
+def _check(rc: int, what: str):
+    if rc != RID_OK:
+        raise RidError(f"{what} returned {rc} ({rid_status_string(rc)})")
+
+
+def status_string(status: int) -> str:
+    return rid_status_string(status)
+
+
+def workspace_bytes(m, n, kmax, b, dtype=RID_F64) -> int:
+    return rid_workspace_bytes(m, n, kmax, b, _cfg(dtype, 0))
+
+
+@dataclass
+class IDOutput:
+    J: "object"        # int64 device tensor [k]
+    T: "object"        # device tensor k x (n-k)
+    k: int
+    err_est: float
+    status: int
+
+
+class _Outputs:
+    def __init__(self, cap, n, dtype, device):
+        torch = _torch()
+        self.J = torch.zeros(max(cap, 1), dtype=torch.int64, device=device)
+        self.T = torch.zeros((max(cap, 1), n), dtype=dtype, device=device)
+        self.k = torch.zeros(1, dtype=torch.int32, device=device)
+        self.E = torch.zeros(1, dtype=torch.float64, device=device)
+        self.st = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def result(self, n) -> IDOutput:
+        torch = _torch()
+        torch.cuda.current_stream().synchronize()
+        k = int(self.k.item())
+        return IDOutput(J=self.J[:k], T=self.T[:k, : n - k], k=k, err_est=float(self.E.item()),
+                        status=int(self.st.item()))
+
+
+def _stream_ptr():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _work(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def fixed_rank(A, k: int, p: int, seed: int, work=None) -> IDOutput:
+    """randLUPP at rank k with p estimation vectors (A: m x n device tensor)."""
+    m, n = A.shape
+    lda = A.stride(0)
+    assert A.stride(1) == 1
+    dt = _dtype_code(A)
+    cfg = _cfg(dt, seed)
+    wb = rid_workspace_bytes(m, n, k + p, p, cfg)
+    if wb == 0:
+        raise RidError("invalid sizes")
+    if work is None:
+        work = _work(wb, A.device)
+    out = _Outputs(k, n, A.dtype, A.device)
+    rc = rid_lupp_fixed_rank(A.data_ptr(), m, n, lda, k, p, cfg, out.J.data_ptr(),
+                             out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
+                             out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
+    _check(rc, "rid_lupp_fixed_rank")
+    return out.result(n)
+
+
+def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
+             work=None) -> IDOutput:
+    """randLUPPadap with block size b, tolerance tol, rank cap kmax."""
+    m, n = A.shape
+    lda = A.stride(0)
+    assert A.stride(1) == 1
+    dt = _dtype_code(A)
+    cfg = _cfg(dt, seed, relative)
+    wb = rid_workspace_bytes(m, n, kmax, b, cfg)
+    if wb == 0:
+        raise RidError("invalid sizes")
+    if work is None:
+        work = _work(wb, A.device)
+    cap = min(kmax, m, n)
+    out = _Outputs(cap, n, A.dtype, A.device)
+    rc = rid_lupp_adaptive(A.data_ptr(), m, n, lda, b, tol, kmax, cfg, out.J.data_ptr(),
+                           out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
+                           out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
+    _check(rc, "rid_lupp_adaptive")
+    return out.result(n)
+
+
+def debug_gaussian(seed: int, c0: int, w: int, m: int, dtype, device="cuda"):
+    torch = _torch()
+    out = torch.empty((w, m), dtype=dtype, device=device)
+    code = RID_F64 if dtype == torch.float64 else RID_F32
+    _check(rid_debug_gaussian(seed, c0, w, m, code, out.data_ptr(), _stream_ptr()),
+           "rid_debug_gaussian")
+    torch.cuda.current_stream().synchronize()
+    return out
+
+
+def debug_sketch(A, seed: int, c0: int, w: int):
+    """(Omega(c0:c0+w) A)^T as an n x w tensor, computed by the sketch kernels."""
+    torch = _torch()
+    m, n = A.shape
+    cfg = _cfg(_dtype_code(A), seed)
+    wb = rid_workspace_bytes(m, n, w, w, cfg)
+    work = _work(wb, A.device)
+    Yt = torch.empty((n, w), dtype=A.dtype, device=A.device)
+    _check(rid_debug_sketch(A.data_ptr(), m, n, A.stride(0), c0, w, cfg, Yt.data_ptr(), w,
+                            work.data_ptr(), work.numel(), _stream_ptr()), "rid_debug_sketch")
+    torch.cuda.current_stream().synchronize()
+    return Yt

@@ -1,0 +1,506 @@
+// Host driver and C ABI of the randomized LUPP interpolative decomposition.
+// Every step of the decomposition runs in the kernels of rid_kernels.hpp; the
+// host only validates arguments, carves the caller's workspace, sizes the
+// launches and enqueues them on the caller's stream (no host synchronisation).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/rid.h"
+#include "rid_kernels.hpp"
+
+using namespace rid;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxW = 128;        // widest sketch block per pass / panel
+constexpr int kPanel = 64;        // panel width of the fixed-rank factorisation
+constexpr size_t kMaxLds = 160 * 1024;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct DeviceInfo {
+  int cu = 0;
+  bool ok = false;
+};
+
+DeviceInfo device_info() {
+  static std::mutex mu;
+  static DeviceInfo cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DeviceInfo{};
+  std::lock_guard<std::mutex> lk(mu);
+  if (!cache[dev].ok) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return DeviceInfo{};
+    cache[dev].cu = p.multiProcessorCount;
+    cache[dev].ok = true;
+  }
+  return cache[dev];
+}
+
+inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
+
+// Sketch launch geometry for a block of w vectors.
+struct SketchGeom {
+  int mt, nq, wp, kc, cols_per_wg;
+  int64_t ncolg, nsplit, rows_per_split;
+};
+
+SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
+  SketchGeom g;
+  g.mt = w <= 16 ? 1 : w <= 32 ? 2 : w <= 64 ? 4 : 8;
+  g.nq = g.mt == 8 ? 2 : 4;
+  g.wp = g.mt * 16;
+  g.kc = dt == RID_F64 ? 32 : 64;
+  g.cols_per_wg = 4 * g.nq * 16;
+  g.ncolg = ceil_div(n, g.cols_per_wg);
+  const int64_t target = 4 * (int64_t)cu;
+  int64_t ns = std::max<int64_t>(1, ceil_div(target, g.ncolg));
+  ns = std::min<int64_t>(ns, ceil_div(m, g.kc));
+  g.rows_per_split = ceil_div(ceil_div(m, ns), g.kc) * g.kc;
+  g.nsplit = ceil_div(m, g.rows_per_split);
+  return g;
+}
+
+// Everything a call needs, derived from its sizes.
+struct Plan {
+  int64_t m = 0, n = 0, kcap = 0, wmax = 0;
+  rid_dtype dt = RID_F64;
+  int64_t ldz = 0, ldu = 0;
+  int cu = 0;
+  int lupp_g = 0, lupp_rows = 0;
+  size_t lupp_lds = 0;
+  int nbars = 0;
+  size_t part_bytes = 0, fro_count = 0;
+  int64_t schur_wgs = 0;
+  // offsets
+  size_t o_ctrl, o_bars, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
+      o_slotrows, o_nonfinite, total;
+};
+
+bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, Plan& P) {
+  DeviceInfo di = device_info();
+  if (!di.ok) return false;
+  P.m = m;
+  P.n = n;
+  P.kcap = kcap;
+  P.wmax = wmax;
+  P.dt = dt;
+  P.cu = di.cu;
+  const size_t es = esize(dt);
+  P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
+  P.ldu = (int64_t)align_up((size_t)kcap, 16);
+  // panel factorisation: one workgroup per CU at most, at least 16 rows each
+  P.lupp_g = (int)std::max<int64_t>(1, std::min<int64_t>(di.cu, ceil_div(n, 16)));
+  P.lupp_rows = (int)ceil_div(n, P.lupp_g);
+  P.lupp_g = (int)ceil_div(n, P.lupp_rows);
+  P.lupp_lds = (size_t)P.lupp_rows * wmax * es + 128 * es + (size_t)P.lupp_rows * es +
+               (size_t)P.lupp_rows * 4;
+  P.nbars = (int)(kcap + 8);
+  // largest sketch partial buffer over the block widths used
+  size_t pb = 0, fc = 0;
+  for (int w = 1; w <= wmax; w = (w < 16 ? 16 : w * 2)) {
+    SketchGeom g = sketch_geom(m, n, std::min<int64_t>(w, wmax), dt, di.cu);
+    pb = std::max(pb, (size_t)g.nsplit * (size_t)n * g.wp * 8);
+    fc = std::max(fc, (size_t)(g.nsplit * g.ncolg));
+    if (w >= wmax) break;
+  }
+  {
+    SketchGeom g = sketch_geom(m, n, (int)wmax, dt, di.cu);
+    pb = std::max(pb, (size_t)g.nsplit * (size_t)n * g.wp * 8);
+    fc = std::max(fc, (size_t)(g.nsplit * g.ncolg));
+  }
+  P.part_bytes = pb;
+  P.fro_count = fc;
+  P.schur_wgs = ceil_div(n, 64);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, kAlign);
+    return at;
+  };
+  P.o_ctrl = take(sizeof(Ctrl));
+  P.o_bars = take((size_t)P.nbars * 4);
+  P.o_nonfinite = take(4);
+  P.o_pos = take((size_t)n * 4);
+  P.o_order = take((size_t)(kcap + 1) * 4);
+  P.o_nonpiv = take((size_t)n * 4);
+  P.o_z = take((size_t)n * P.ldz * es);
+  P.o_u2t = take((size_t)wmax * P.ldu * es);
+  P.o_part = take(P.part_bytes);
+  P.o_fro = take(P.fro_count * 8);
+  P.o_norm = take((size_t)P.schur_wgs * 8);
+  P.o_slots = take((size_t)2 * P.lupp_g * sizeof(Slot));
+  P.o_slotrows = take((size_t)2 * P.lupp_g * wmax * es);
+  P.total = o;
+  return true;
+}
+
+// Plan of a call with rank cap kmax and block width b (fixed rank: kmax = k + p,
+// b = p): kcap = min(kmax, m, n), widest block min(128, max(b, min(kcap, 128))).
+bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, rid_dtype dt, Plan& P) {
+  const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
+  const int64_t wmax =
+      std::min<int64_t>(kMaxW, std::max<int64_t>({b, std::min<int64_t>(kcap, kMaxW), 1}));
+  return make_plan(m, n, kcap, wmax, dt, P);
+}
+
+// Pointers into the caller's workspace.
+struct Ws {
+  Ctrl* ctrl;
+  unsigned* bars;
+  int* nonfinite;
+  int* pos;
+  int* order;
+  int* nonpiv;
+  void* z;
+  void* u2t;
+  double* part;
+  double* fro;
+  double* norm;
+  Slot* slots;
+  void* slotrows;
+};
+
+Ws carve(const Plan& P, void* work) {
+  char* b = static_cast<char*>(work);
+  Ws w;
+  w.ctrl = reinterpret_cast<Ctrl*>(b + P.o_ctrl);
+  w.bars = reinterpret_cast<unsigned*>(b + P.o_bars);
+  w.nonfinite = reinterpret_cast<int*>(b + P.o_nonfinite);
+  w.pos = reinterpret_cast<int*>(b + P.o_pos);
+  w.order = reinterpret_cast<int*>(b + P.o_order);
+  w.nonpiv = reinterpret_cast<int*>(b + P.o_nonpiv);
+  w.z = b + P.o_z;
+  w.u2t = b + P.o_u2t;
+  w.part = reinterpret_cast<double*>(b + P.o_part);
+  w.fro = reinterpret_cast<double*>(b + P.o_fro);
+  w.norm = reinterpret_cast<double*>(b + P.o_norm);
+  w.slots = reinterpret_cast<Slot*>(b + P.o_slots);
+  w.slotrows = b + P.o_slotrows;
+  return w;
+}
+
+#define RID_LAUNCH_CHECK()                          \
+  do {                                              \
+    if (hipGetLastError() != hipSuccess) return RID_ERR_HIP; \
+  } while (0)
+
+// ---- sketch dispatch -------------------------------------------------------
+template <typename TC, int MT, int NQ, int KC>
+int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                    int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
+                    hipStream_t st) {
+  dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  if (norm)
+    hipLaunchKernelGGL((k_sketch<TC, MT, NQ, 4, KC, true>), grid, dim3(256), 0, st,
+                       static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
+                       g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
+  else
+    hipLaunchKernelGGL((k_sketch<TC, MT, NQ, 4, KC, false>), grid, dim3(256), 0, st,
+                       static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
+                       g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+template <typename TC, int KC>
+int launch_sketch_mt(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                     int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
+                     hipStream_t st) {
+  switch (g.mt) {
+    case 1: return launch_sketch_t<TC, 1, 4, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    case 2: return launch_sketch_t<TC, 2, 4, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    case 4: return launch_sketch_t<TC, 4, 4, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    default: return launch_sketch_t<TC, 8, 2, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+  }
+}
+
+// Sketch vectors [c0, c0 + w) into columns [zcol, zcol + w) of `out`
+// (n x ldo, dtype of the plan).
+int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                 int64_t c0, int w, void* out, int64_t ldo, int zcol, bool first, bool use_ctrl,
+                 hipStream_t st) {
+  SketchGeom g = sketch_geom(P.m, P.n, w, P.dt, P.cu);
+  int rc = (P.dt == RID_F64)
+               ? launch_sketch_mt<double, 32>(P, W, A, lda, seed, c0, w, g, first, use_ctrl, st)
+               : launch_sketch_mt<float, 64>(P, W, A, lda, seed, c0, w, g, first, use_ctrl, st);
+  if (rc != RID_OK) return rc;
+  const int64_t tot = P.n * w;
+  const unsigned blocks = (unsigned)ceil_div(tot, 256);
+  Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  if (P.dt == RID_F64)
+    hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
+                       (int)g.nsplit, P.n, g.wp, w, static_cast<double*>(out), ldo, zcol, W.fro,
+                       (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, first ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
+                       (int)g.nsplit, P.n, g.wp, w, static_cast<float*>(out), ldo, zcol, W.fro,
+                       (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, first ? 1 : 0);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+// ---- block update: U2 (triangular solve) then S (Schur GEMM) --------------
+template <typename TF>
+int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, hipStream_t st) {
+  const size_t lds = (size_t)k * sizeof(TF);
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_trsm_u2<TF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return RID_ERR_HIP;
+  hipLaunchKernelGGL(k_trsm_u2<TF>, dim3(w), dim3(256), lds, st, static_cast<TF*>(W.z), P.ldz,
+                     W.order, k, zcol, w, static_cast<TF*>(W.u2t), P.ldu, W.ctrl);
+  RID_LAUNCH_CHECK();
+  const int nt = (w + 15) / 16;
+  dim3 grid((unsigned)P.schur_wgs);
+#define RID_SCHUR(NTV)                                                                         \
+  hipLaunchKernelGGL((k_schur<TF, NTV>), grid, dim3(256), 0, st, static_cast<TF*>(W.z), P.ldz, \
+                     P.n, W.pos, k, zcol, w, static_cast<const TF*>(W.u2t), P.ldu, W.norm,      \
+                     W.ctrl, norm ? 1 : 0)
+  switch (nt) {
+    case 1: RID_SCHUR(1); break;
+    case 2: RID_SCHUR(2); break;
+    case 3: RID_SCHUR(3); break;
+    case 4: RID_SCHUR(4); break;
+    case 5: RID_SCHUR(5); break;
+    case 6: RID_SCHUR(6); break;
+    case 7: RID_SCHUR(7); break;
+    default: RID_SCHUR(8); break;
+  }
+#undef RID_SCHUR
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int block_update(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, hipStream_t st) {
+  return P.dt == RID_F64 ? block_update_t<double>(P, W, k, zcol, w, norm, st)
+                         : block_update_t<float>(P, W, k, zcol, w, norm, st);
+}
+
+int estimate(const Plan& P, const Ws& W, int w, double tol, int rel, int k, bool fixed,
+             hipStream_t st) {
+  hipLaunchKernelGGL(k_estimate, dim3(1), dim3(1), 0, st, W.ctrl, W.norm, (int)P.schur_wgs, w,
+                     tol, rel, k, (int)P.kcap, fixed ? 1 : 0);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+// ---- panel factorisation ---------------------------------------------------
+template <typename TF>
+int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
+            hipStream_t st) {
+  const size_t es = sizeof(TF);
+  const size_t lds = (size_t)P.lupp_rows * w * es + 128 * es + (size_t)P.lupp_rows * es +
+                     (size_t)P.lupp_rows * 4;
+  if (lds > kMaxLds) return RID_ERR_ARG;
+  const void* fn = (const void*)k_panel_lupp<TF>;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return RID_ERR_HIP;
+  TF* z = static_cast<TF*>(W.z);
+  int64_t ldz = P.ldz, n = P.n, mn = std::min(P.m, P.n);
+  int* pos = W.pos;
+  int* order = W.order;
+  Ctrl* ctrl = W.ctrl;
+  Slot* slots = W.slots;
+  TF* slotrows = static_cast<TF*>(W.slotrows);
+  unsigned* bar = W.bars + bar_idx;
+  int rows = P.lupp_rows;
+  int sf = stop_full ? 1 : 0;
+  void* args[] = {&z, &ldz, &n, &zcol, &w, &f, &pos, &order, &ctrl,
+                  &slots, &slotrows, &bar, &rows, &mn, &sf};
+  if (hipLaunchCooperativeKernel(fn, dim3(P.lupp_g), dim3(256), args, (unsigned)lds, st) !=
+      hipSuccess)
+    return RID_ERR_HIP;
+  return RID_OK;
+}
+
+int panel(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
+          hipStream_t st) {
+  return P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, bar_idx, stop_full, st)
+                         : panel_t<float>(P, W, zcol, w, f, bar_idx, stop_full, st);
+}
+
+// ---- interpolation matrix and outputs --------------------------------------
+template <typename TF>
+int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32_t* k_out,
+             double* err_est, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_nonpiv, dim3(1), dim3(1024), 0, st, W.pos, P.n, W.nonpiv);
+  RID_LAUNCH_CHECK();
+  const int nblk = (int)ceil_div(P.kcap, 64);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(P.n, 64));
+  for (int beta = nblk - 1; beta >= 0; --beta) {
+    hipLaunchKernelGGL(k_tsolve<TF>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const TF*>(W.z), P.ldz, W.order, W.nonpiv, P.n, beta,
+                       static_cast<TF*>(T), ldt, W.ctrl);
+    RID_LAUNCH_CHECK();
+  }
+  const unsigned og = (unsigned)std::max<int64_t>(1, ceil_div(P.kcap, 256));
+  hipLaunchKernelGGL(k_outputs, dim3(og), dim3(256), 0, st, W.ctrl, W.order, J, k_out, err_est,
+                     status);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int finish(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32_t* k_out,
+           double* err_est, int32_t* status, hipStream_t st) {
+  return P.dt == RID_F64 ? finish_t<double>(P, W, T, ldt, J, k_out, err_est, status, st)
+                         : finish_t<float>(P, W, T, ldt, J, k_out, err_est, status, st);
+}
+
+int init(const Plan& P, const Ws& W, hipStream_t st) {
+  const int64_t cnt = std::max<int64_t>(P.n, P.nbars);
+  hipLaunchKernelGGL(k_init, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, W.ctrl, W.pos,
+                     P.n, W.bars, P.nbars, W.nonfinite);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+bool valid_cfg(const rid_config* cfg) {
+  return cfg && (cfg->dtype == RID_F64 || cfg->dtype == RID_F32);
+}
+
+int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }
+
+}  // namespace
+
+#define RID_TRY(expr)             \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != RID_OK) return rc_; \
+  } while (0)
+
+extern "C" {
+
+size_t rid_workspace_bytes(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg) {
+  if (m < 1 || n < 1 || kmax < 1 || b < 0 || !valid_cfg(cfg)) return 0;
+  Plan P;
+  if (!plan_for(m, n, kmax, b, cfg->dtype, P)) return 0;
+  return P.total;
+}
+
+const char* rid_status_string(int s) {
+  switch (s) {
+    case RID_OK: return "RID_OK";
+    case RID_NOT_CONVERGED: return "RID_NOT_CONVERGED";
+    case RID_RANK_DEFICIENT: return "RID_RANK_DEFICIENT";
+    case RID_ERR_ARG: return "RID_ERR_ARG";
+    case RID_ERR_NONFINITE: return "RID_ERR_NONFINITE";
+    case RID_ERR_HIP: return "RID_ERR_HIP";
+    case RID_ERR_WORKSPACE: return "RID_ERR_WORKSPACE";
+    default: return "RID_UNKNOWN";
+  }
+}
+
+int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
+                        const rid_config* cfg, int64_t* J, void* T, int64_t ldt, int32_t* k_out,
+                        double* err_est, int32_t* status, void* work, size_t work_bytes,
+                        hipStream_t stream) {
+  if (!A || !J || !T || !k_out || !err_est || !status || !work || !valid_cfg(cfg))
+    return RID_ERR_ARG;
+  if (m < 1 || n < 1 || lda < n || ldt < n || k < 1 || k > std::min(m, n) || p < 0 ||
+      p > kMaxW || m > INT32_MAX || n > INT32_MAX)
+    return RID_ERR_ARG;
+  if (k > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
+  Plan P;
+  if (!plan_for(m, n, k + p, p, cfg->dtype, P)) return RID_ERR_HIP;
+  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
+  Ws W = carve(P, work);
+  RID_TRY(init(P, W, stream));
+  // one pass per <= 128 sketch vectors: all k + p vectors up front
+  for (int64_t c = 0; c < k + p; c += P.wmax) {
+    const int w = (int)std::min<int64_t>(P.wmax, k + p - c);
+    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, c, w, W.z, P.ldz, (int)c, c == 0, true, stream));
+  }
+  int bar = 0;
+  for (int64_t k0 = 0; k0 < k; k0 += kPanel) {
+    const int f = (int)std::min<int64_t>(kPanel, k - k0);
+    if (k0 > 0) RID_TRY(block_update(P, W, (int)k0, (int)k0, f, false, stream));
+    RID_TRY(panel(P, W, (int)k0, f, f, bar++, false, stream));
+  }
+  if (p > 0) {
+    RID_TRY(block_update(P, W, (int)k, (int)k, (int)p, true, stream));
+    RID_TRY(estimate(P, W, (int)p, 0.0, 0, (int)k, true, stream));
+  }
+  return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+}
+
+int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t b, double tol,
+                      int64_t kmax, const rid_config* cfg, int64_t* J, void* T, int64_t ldt,
+                      int32_t* k_out, double* err_est, int32_t* status, void* work,
+                      size_t work_bytes, hipStream_t stream) {
+  if (!A || !J || !T || !k_out || !err_est || !status || !work || !valid_cfg(cfg))
+    return RID_ERR_ARG;
+  if (m < 1 || n < 1 || lda < n || ldt < n || b < 1 || b > kMaxW || kmax < 1 || !(tol >= 0.0) ||
+      m > INT32_MAX || n > INT32_MAX)
+    return RID_ERR_ARG;
+  const int64_t mn = std::min(m, n);
+  const int64_t kcap = std::min(kmax, mn);
+  if (kcap > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
+  Plan P;
+  if (!plan_for(m, n, kmax, b, cfg->dtype, P)) return RID_ERR_HIP;
+  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
+  Ws W = carve(P, work);
+  RID_TRY(init(P, W, stream));
+  const int w0 = (int)std::min<int64_t>(b, kcap);
+  RID_TRY(sketch_block(P, W, A, lda, cfg->seed, 0, w0, W.z, P.ldz, 0, true, true, stream));
+  int bar = 0;
+  RID_TRY(panel(P, W, 0, w0, w0, bar++, true, stream));
+  int64_t k = w0, cnext = w0;
+  while (k < mn) {
+    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false, true,
+                         stream));
+    cnext += b;
+    RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, true, stream));
+    RID_TRY(estimate(P, W, (int)b, tol, cfg->tol_relative, (int)k, false, stream));
+    if (k >= kcap) break;
+    const int f = (int)std::min<int64_t>(b, kcap - k);
+    RID_TRY(panel(P, W, (int)k, (int)b, f, bar++, true, stream));
+    k += f;
+  }
+  return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+}
+
+int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtype, void* out,
+                       hipStream_t stream) {
+  if (!out || w < 1 || m < 1 || c0 < 0 || (dtype != RID_F64 && dtype != RID_F32))
+    return RID_ERR_ARG;
+  const int64_t nq = (m + 3) / 4;
+  const unsigned blocks = (unsigned)ceil_div(nq * w, 256);
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  if (dtype == RID_F64)
+    hipLaunchKernelGGL(k_gaussian<double>, dim3(blocks), dim3(256), 0, stream, k0, k1, c0, w, m,
+                       static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(k_gaussian<float>, dim3(blocks), dim3(256), 0, stream, k0, k1, c0, w, m,
+                       static_cast<float*>(out));
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c0, int64_t w,
+                     const rid_config* cfg, void* Yt, int64_t ldy, void* work, size_t work_bytes,
+                     hipStream_t stream) {
+  if (!A || !Yt || !work || !valid_cfg(cfg) || m < 1 || n < 1 || lda < n || w < 1 ||
+      w > kMaxW || ldy < w || c0 < 0)
+    return RID_ERR_ARG;
+  Plan P;
+  if (!plan_for(m, n, w, w, cfg->dtype, P)) return RID_ERR_HIP;
+  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  Ws W = carve(P, work);
+  RID_TRY(init(P, W, stream));
+  return sketch_block(P, W, A, lda, cfg->seed, c0, (int)w, Yt, ldy, 0, true, true, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Device-side building blocks for gfx950 (CDNA4): the counter-based Gaussian
+// generator, MFMA wrappers and wave64 reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rid {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One round maps
+// (x0,x1,x2,x3) under key (k0,k1) to
+//   (hi(B*x2) ^ x1 ^ k0, lo(B*x2), hi(A*x0) ^ x3 ^ k1, lo(A*x0)),
+// A = 0xD2511F53, B = 0xCD9E8D57; the key advances by the Weyl increments
+// 0x9E3779B9 / 0xBB67AE85 between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                                              uint32_t& x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t a = 0xD2511F53u, b = 0xCD9E8D57u;
+    uint32_t hi_a = __umulhi(a, x0), lo_a = a * x0;
+    uint32_t hi_b = __umulhi(b, x2), lo_b = b * x2;
+    uint32_t y0 = hi_b ^ x1 ^ k0;
+    uint32_t y2 = hi_a ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo_b;
+    x2 = y2;
+    x3 = lo_a;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Gaussian embedding entries omega(c, 4q .. 4q+3) of sketch vector c: Philox
+// with counter (q, c, 0, 0) and key (seed lo, seed hi); each word x gives the
+// uniform (x + 1/2) 2^-32; Box-Muller on the pairs (x0,x1) and (x2,x3).
+// The double version evaluates in FP64, the float version in FP32 (the FP32
+// sketch consumes FP32 operands, so the generator works at that precision).
+template <typename T>
+__device__ __forceinline__ void gauss4(uint32_t k0, uint32_t k1, uint32_t q, uint32_t c, T out[4]);
+
+template <>
+__device__ __forceinline__ void gauss4<double>(uint32_t k0, uint32_t k1, uint32_t q, uint32_t c,
+                                               double out[4]) {
+  uint32_t x0 = q, x1 = c, x2 = 0u, x3 = 0u;
+  philox4x32_10(x0, x1, x2, x3, k0, k1);
+  const double two_pi = 6.283185307179586476925286766559;
+  double u0 = ((double)x0 + 0.5) * 0x1p-32, u1 = ((double)x1 + 0.5) * 0x1p-32;
+  double u2 = ((double)x2 + 0.5) * 0x1p-32, u3 = ((double)x3 + 0.5) * 0x1p-32;
+  double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+  double s0, c0v, s1, c1v;
+  sincos(two_pi * u1, &s0, &c0v);
+  sincos(two_pi * u3, &s1, &c1v);
+  out[0] = r0 * c0v;
+  out[1] = r0 * s0;
+  out[2] = r1 * c1v;
+  out[3] = r1 * s1;
+}
+
+template <>
+__device__ __forceinline__ void gauss4<float>(uint32_t k0, uint32_t k1, uint32_t q, uint32_t c,
+                                              float out[4]) {
+  uint32_t x0 = q, x1 = c, x2 = 0u, x3 = 0u;
+  philox4x32_10(x0, x1, x2, x3, k0, k1);
+  const float two_pi = 6.28318530717958647692f;
+  float u0 = ((float)x0 + 0.5f) * 0x1p-32f, u1 = ((float)x1 + 0.5f) * 0x1p-32f;
+  float u2 = ((float)x2 + 0.5f) * 0x1p-32f, u3 = ((float)x3 + 0.5f) * 0x1p-32f;
+  float r0 = sqrtf(-2.0f * logf(u0)), r1 = sqrtf(-2.0f * logf(u2));
+  float s0, c0v, s1, c1v;
+  sincosf(two_pi * u1, &s0, &c0v);
+  sincosf(two_pi * u3, &s1, &c1v);
+  out[0] = r0 * c0v;
+  out[1] = r0 * s0;
+  out[2] = r1 * c1v;
+  out[3] = r1 * s1;
+}
+
+// ---------------------------------------------------------------------------
+// 16x16x4 MFMA tiles.  Operand layout (wave64): lane l supplies
+// A[i = l%16][k = l/16] and B[k = l/16][j = l%16].  Accumulator element r of
+// lane l holds D[row(l, r)][l%16] with row = 4*(l/16) + r for the FP32
+// instruction and row = l/16 + 4*r for the FP64 one.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  using acc_t = floatx4;
+  __device__ __forceinline__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ __forceinline__ static acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <>
+struct Mfma<double> {
+  using acc_t = doublex4;
+  __device__ __forceinline__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ __forceinline__ static acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// ---------------------------------------------------------------------------
+// Wave64 / workgroup reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// (value, index) arg-max: larger value wins, equal values go to the lower
+// index; index < 0 marks "no candidate".
+__device__ __forceinline__ void argmax_merge(double& v, long long& i, double v2, long long i2) {
+  if (i2 < 0) return;
+  if (i < 0 || v2 > v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, long long& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double v2 = __shfl_xor(v, off, 64);
+    long long i2 = __shfl_xor(i, off, 64);
+    argmax_merge(v, i, v2, i2);
+  }
+}
+
+// Agent-scope release / acquire, used around the cross-workgroup hand-off of
+// the cooperative panel factorisation.
+__device__ __forceinline__ void fence_release_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+__device__ __forceinline__ void fence_acquire_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+}  // namespace rid

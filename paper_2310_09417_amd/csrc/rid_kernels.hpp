@@ -1,0 +1,668 @@
+// HIP kernels for the randomized LUPP interpolative decomposition on gfx950.
+//
+// Storage of the factorisation (column form, A is m x n):
+//   Z  (n x ldz, row-major, dtype TF): row r belongs to candidate column r of
+//      A and is never moved.  Column c < k of a pivot row holds L1 (c < its
+//      pivot step) or U (c >= its pivot step); columns c < k of a non-pivot
+//      row hold L2; the columns of the block being processed hold the sketch
+//      values, then U2 / S after the block update.
+//   pos[r]   pivot step of candidate r, or -1 while r is not a skeleton.
+//   order[s] candidate chosen at pivot step s.
+// Row swaps of the paper's P are therefore bookkeeping (pos / order) rather
+// than data movement: "P Y" is read through order[], "L2" is the set of rows
+// with pos < 0, and the re-blocking of Alg. 1 costs nothing.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rid_device.hpp"
+
+namespace rid {
+
+// Device-resident control block of one decomposition.
+struct Ctrl {
+  int32_t k;          // pivots taken so far
+  int32_t done;       // 1 once the result is final (later kernels return at once)
+  int32_t status;     // rid_status value
+  int32_t nonfinite;  // set by the sketch when A holds NaN / Inf
+  double E;           // latest estimate E = ||S||_F / sqrt(w), -1 before the first
+  double frob2;       // ||A||_F^2 accumulated in FP64 during the first sketch pass
+  int32_t pad[8];
+};
+
+enum : int32_t {
+  ST_OK = 0,
+  ST_NOT_CONVERGED = 1,
+  ST_RANK_DEFICIENT = 2,
+  ST_ERR_NONFINITE = -2,
+  ST_ERR_HIP = -3
+};
+
+struct Slot {
+  double v;       // |candidate| of one workgroup at one pivot step
+  long long row;  // its candidate index, -1 if the workgroup has none left
+};
+
+// ---------------------------------------------------------------------------
+// Initialisation of the control block, the pivot map and barrier counters.
+// ---------------------------------------------------------------------------
+__global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, unsigned* bars, int nbars,
+                       int* nonfinite) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    *nonfinite = 0;
+    ctrl->k = 0;
+    ctrl->done = 0;
+    ctrl->status = ST_OK;
+    ctrl->nonfinite = 0;
+    ctrl->E = -1.0;
+    ctrl->frob2 = 0.0;
+  }
+  if (t < n) pos[t] = -1;
+  if (t < nbars) bars[t] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Sketch: partial sums of Y(c, j) = sum_i omega(c0 + c, i) A(i, j) over one
+// row range ("split") per grid row, for a strip of columns per grid column.
+//   * Omega for KC rows x WP vectors is generated into LDS once per chunk and
+//     shared by the WAVES*NQ*16 columns of the workgroup (never stored in HBM).
+//   * The A tile is read once, straight into MFMA B operands.
+//   * FP32: each KC-row chunk is accumulated by MFMA in FP32 and folded into
+//     FP64 accumulators, so rounding grows with KC, not with m.
+//   * Partials part[split][j][c] (FP64) are summed in split order by
+//     k_sketch_reduce, so the result does not depend on scheduling.
+//   * NORM: also accumulates sum A^2 (FP64) and flags non-finite entries.
+// ---------------------------------------------------------------------------
+template <typename TC, int MT, int NQ, int WAVES, int KC, bool NORM>
+__global__ __launch_bounds__(WAVES * 64) void k_sketch(
+    const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, uint32_t key0, uint32_t key1,
+    uint32_t c0, int w, int64_t rows_per_split, double* __restrict__ part,
+    double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  constexpr int WP = MT * 16;
+  constexpr int LDO = WP + 16;
+  constexpr int NT = WAVES * 64;
+  using M = Mfma<TC>;
+  using acc_t = typename M::acc_t;
+  __shared__ TC om[KC * LDO];
+  __shared__ double red[WAVES];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t colw = (int64_t)blockIdx.x * (WAVES * NQ * 16) + wave * (NQ * 16);
+  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+
+  acc_t acc[MT][NQ];
+  double acc64[MT][NQ][4];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NQ; ++b) {
+      acc[a][b] = M::zero();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+    }
+  double fro = 0.0;
+  bool bad = false;
+
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
+    __syncthreads();
+    for (int it = tid; it < (KC / 4) * WP; it += NT) {
+      const int c = it % WP, qd = it / WP;
+      const int64_t row4 = r0 + 4 * qd;
+      TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
+      if (c < w && row4 < r_end) gauss4<TC>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) om[(4 * qd + a) * LDO + c] = (row4 + a < r_end) ? v[a] : TC(0);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int krow = kk + (lane >> 4);
+      const int64_t row = r0 + krow;
+      TC bv[NQ];
+#pragma unroll
+      for (int b = 0; b < NQ; ++b) {
+        const int64_t col = colw + b * 16 + (lane & 15);
+        bv[b] = (row < r_end && col < n) ? A[row * lda + col] : TC(0);
+      }
+      TC av[MT];
+#pragma unroll
+      for (int a = 0; a < MT; ++a) av[a] = om[krow * LDO + a * 16 + (lane & 15)];
+      if (NORM) {
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) {
+          fro += (double)bv[b] * (double)bv[b];
+          bad |= !__builtin_isfinite((double)bv[b]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) acc[a][b] = M::op(av[a], bv[b], acc[a][b]);
+    }
+    if (sizeof(TC) == 4) {
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+          acc[a][b] = M::zero();
+        }
+    }
+  }
+  if (sizeof(TC) == 8) {
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < NQ; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[a][b][r] = (double)acc[a][b][r];
+  }
+  const int64_t split = blockIdx.y;
+#pragma unroll
+  for (int b = 0; b < NQ; ++b) {
+    const int64_t col = colw + b * 16 + (lane & 15);
+    if (col < n) {
+      double* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP;
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = acc64[a][b][r];
+    }
+  }
+  if (NORM) {
+    fro = wave_sum(fro);
+    if (lane == 0) red[wave] = fro;
+    if (bad) atomicOr(nonfinite, 1);
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int i = 0; i < WAVES; ++i) s += red[i];
+      fro_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// Sum of the split partials in split order; writes Y^T into Z columns
+// [zcol, zcol + w) in the factor type.  With `first`, also finishes ||A||_F^2
+// and the non-finite check.
+template <typename TF>
+__global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int64_t n, int WP,
+                                int w, TF* __restrict__ Z, int64_t ldz, int zcol,
+                                const double* __restrict__ fro_part, int nfro,
+                                const int* __restrict__ nonfinite, Ctrl* ctrl, int first) {
+  if (ctrl && ctrl->done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * w) {
+    const int64_t j = t / w;
+    const int c = (int)(t % w);
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[((size_t)sp * (size_t)n + (size_t)j) * WP + c];
+    Z[j * ldz + zcol + c] = (TF)s;
+  }
+  if (first && t == 0 && ctrl) {
+    double f = 0.0;
+    for (int i = 0; i < nfro; ++i) f += fro_part[i];
+    ctrl->frob2 = f;
+    if (*nonfinite) {
+      ctrl->status = ST_ERR_NONFINITE;
+      ctrl->done = 1;
+      ctrl->k = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// U2 = L1^{-1} (P Y)(0:k, block): one workgroup per right-hand side column.
+// L1 is read from the pivot rows of Z through order[].  Blocked forward
+// substitution: wave 0 solves each 64 x 64 diagonal block from registers
+// (lane i holds row i of the block), then all threads update the rows below.
+// Results go to U2T (w x ldu, column-major U2) and back into the pivot rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_f(double v, int l) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_trsm_u2(TF* __restrict__ Z, int64_t ldz,
+                                                 const int* __restrict__ order, int k, int zcol,
+                                                 int w, TF* __restrict__ U2T, int64_t ldu,
+                                                 const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  TF* x = reinterpret_cast<TF*>(smem_raw);
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  for (int s = tid; s < k; s += 256) x[s] = Z[(int64_t)order[s] * ldz + zcol + c];
+  __syncthreads();
+  for (int s0 = 0; s0 < k; s0 += 64) {
+    const int nb = (k - s0 < 64) ? k - s0 : 64;
+    if (tid < 64) {
+      TF lrow[64];
+      const TF* src = Z + (int64_t)order[s0 + (lane < nb ? lane : 0)] * ldz + s0;
+#pragma unroll
+      for (int j = 0; j < 64; ++j) lrow[j] = (lane < nb && j < lane) ? src[j] : TF(0);
+      TF xi = lane < nb ? x[s0 + lane] : TF(0);
+#pragma unroll
+      for (int j = 0; j < 63; ++j) {
+        TF xj = readlane_f(xi, j);
+        if (lane > j) xi -= lrow[j] * xj;
+      }
+      if (lane < nb) x[s0 + lane] = xi;
+    }
+    __syncthreads();
+    for (int s2 = s0 + nb + tid; s2 < k; s2 += 256) {
+      const TF* lr = Z + (int64_t)order[s2] * ldz + s0;
+      TF acc = TF(0);
+      for (int j = 0; j < nb; ++j) acc += lr[j] * x[s0 + j];
+      x[s2] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int s = tid; s < k; s += 256) {
+    U2T[(int64_t)c * ldu + s] = x[s];
+    Z[(int64_t)order[s] * ldz + zcol + c] = x[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Schur block S = (P Y)(non-pivots, block) - L2 U2 (MFMA, K = k), written in
+// place for every non-pivot row; with `want_norm` each workgroup also leaves
+// its FP64 sum of S^2 in normpart[blockIdx.x].  Each wave owns 16 rows and
+// all NT 16-column tiles of the block.  The K index is walked in chunks of
+// 16: a lane loads 4 consecutive K values of its A row and of its U2 column
+// and feeds them to 4 MFMAs (a consistent relabelling of K inside the chunk).
+// FP32: the MFMA accumulator is folded into FP64 every 64 K values.
+// ---------------------------------------------------------------------------
+template <typename TF>
+__device__ __forceinline__ void load4(const TF* p, int64_t base, int kidx, int k, bool ok,
+                                      TF out[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = (ok && kidx + j < k) ? p[base + kidx + j] : TF(0);
+}
+
+template <typename TF, int NT>
+__global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, int64_t n,
+                                               const int* __restrict__ pos, int k, int zcol, int w,
+                                               const TF* __restrict__ U2T, int64_t ldu,
+                                               double* __restrict__ normpart, const Ctrl* ctrl,
+                                               int want_norm) {
+  if (ctrl->done) return;
+  using M = Mfma<TF>;
+  using acc_t = typename M::acc_t;
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t rbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t arow = rbase + (lane & 15);
+  const bool arow_ok = arow < n;
+  acc_t acc[NT];
+  double acc64[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
+  }
+  for (int s0 = 0; s0 < k; s0 += 16) {
+    const int kidx = s0 + 4 * (lane >> 4);
+    TF a4[4];
+    load4(Z, arow * ldz, kidx, k, arow_ok, a4);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 16 + (lane & 15);
+      TF b4[4];
+      load4(U2T, (int64_t)col * ldu, kidx, k, col < w, b4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[t] = M::op(a4[j], b4[j], acc[t]);
+    }
+    if (sizeof(TF) == 4 && ((s0 >> 4) & 3) == 3) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[t][r] += (double)acc[t][r];
+        acc[t] = M::zero();
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[t][r] += (double)acc[t][r];
+  double ss = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rbase + M::row(lane, r);
+      if (row < n && col < w && pos[row] < 0) {
+        TF* zp = Z + row * ldz + zcol + col;
+        TF s = (TF)((double)(*zp) - acc64[t][r]);
+        *zp = s;
+        ss += (double)s * (double)s;
+      }
+    }
+  }
+  if (want_norm) {
+    ss = wave_sum(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) normpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
+// Estimate and stopping test (one thread): E = sqrt(sum S^2) / sqrt(w) with
+// the partials summed in workgroup order.
+__global__ void k_estimate(Ctrl* ctrl, const double* __restrict__ normpart, int nparts, int w,
+                           double tol, int rel, int k, int kcap, int fixed_mode) {
+  if (ctrl->done) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += normpart[i];
+  const double E = sqrt(s) / sqrt((double)w);
+  ctrl->E = E;
+  if (fixed_mode) {
+    ctrl->done = 1;
+    ctrl->status = ST_OK;
+    return;
+  }
+  const double thr = rel ? tol * sqrt(ctrl->frob2) : tol;
+  if (E <= thr) {
+    ctrl->done = 1;
+    ctrl->status = ST_OK;
+  } else if (k >= kcap) {
+    ctrl->done = 1;
+    ctrl->status = ST_NOT_CONVERGED;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panel LUPP (cooperative launch, all workgroups resident).  Workgroup g owns
+// candidate rows [g*R, (g+1)*R) and keeps their w panel values in LDS.  Per
+// pivot step: local arg-max of |value| (ties -> lower candidate index) ->
+// publish (value, candidate, full row) to a double-buffered slot -> one grid
+// barrier -> every workgroup reduces the same slots to the same winner, reads
+// its row, scales its own rows and applies the rank-1 update.  Rows are never
+// swapped: the winner's pos/order entries record the permutation.  An exactly
+// zero winner stops the factorisation (rank of the sketch reached).
+// ---------------------------------------------------------------------------
+constexpr long long kSpinLimit = 1ll << 26;
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t ldz, int64_t n,
+                                                    int zcol, int w, int f, int* __restrict__ pos,
+                                                    int* __restrict__ order, Ctrl* ctrl,
+                                                    Slot* slots, TF* slotrows, unsigned* bar,
+                                                    int rows_per_wg, int64_t mn, int stop_full) {
+  if (ctrl->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  TF* P = reinterpret_cast<TF*>(smem_raw);  // [rows_per_wg][w]
+  TF* prow = P + (size_t)rows_per_wg * w;    // [128]
+  TF* lmul = prow + 128;                     // [rows_per_wg]
+  int* act = reinterpret_cast<int*>(lmul + rows_per_wg);
+  __shared__ double red_v[4];
+  __shared__ long long red_i[4];
+  __shared__ double s_val;
+  __shared__ long long s_row;
+  __shared__ int s_timeout;
+
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)g * rows_per_wg;
+  int64_t r1 = r0 + rows_per_wg;
+  if (r1 > n) r1 = n;
+  const int R = r1 > r0 ? (int)(r1 - r0) : 0;
+
+  for (int i = tid; i < R * w; i += 256) {
+    const int rr = i / w, q = i % w;
+    P[i] = Z[(r0 + rr) * ldz + zcol + q];
+  }
+  for (int rr = tid; rr < R; rr += 256) act[rr] = (pos[r0 + rr] < 0) ? 1 : 0;
+  if (tid == 0) s_timeout = 0;
+  __syncthreads();
+
+  int steps = f;
+  bool deficient = false;
+  for (int s = 0; s < f; ++s) {
+    double bv = -1.0;
+    long long bi = -1;
+    for (int rr = tid; rr < R; rr += 256)
+      if (act[rr] == 1) argmax_merge(bv, bi, fabs((double)P[rr * w + s]), r0 + rr);
+    wave_argmax(bv, bi);
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = 1; i < 4; ++i) argmax_merge(bv, bi, red_v[i], red_i[i]);
+      s_val = bv;
+      s_row = bi;
+    }
+    __syncthreads();
+    const int buf = s & 1;
+    Slot* sl = slots + (size_t)buf * G;
+    TF* srow = slotrows + (size_t)buf * G * w;
+    if (tid == 0) {
+      sl[g].v = s_val;
+      sl[g].row = s_row;
+    }
+    if (s_row >= 0)
+      for (int q = tid; q < w; q += 256) srow[(size_t)g * w + q] = P[(s_row - r0) * w + q];
+    fence_release_agent();
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = (unsigned)(s + 1) * (unsigned)G;
+      long long spins = 0;
+      while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > kSpinLimit) {
+          s_timeout = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    fence_acquire_agent();
+    if (s_timeout) {
+      if (tid == 0) {
+        ctrl->status = ST_ERR_HIP;
+        ctrl->done = 1;
+      }
+      return;
+    }
+    bv = -1.0;
+    bi = -1;
+    for (int t = tid; t < G; t += 256) argmax_merge(bv, bi, sl[t].v, sl[t].row);
+    wave_argmax(bv, bi);
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = 1; i < 4; ++i) argmax_merge(bv, bi, red_v[i], red_i[i]);
+      s_val = bv;
+      s_row = bi;
+    }
+    __syncthreads();
+    const long long prow_idx = s_row;
+    if (prow_idx < 0 || s_val == 0.0) {
+      deficient = true;
+      steps = s;
+      break;
+    }
+    const int owner = (int)(prow_idx / rows_per_wg);
+    for (int q = tid; q < w; q += 256) prow[q] = srow[(size_t)owner * w + q];
+    if (tid == 0) {
+      if (owner == g) {
+        act[prow_idx - r0] = 2;
+        pos[prow_idx] = zcol + s;
+      }
+      if (g == 0) order[zcol + s] = (int)prow_idx;
+    }
+    __syncthreads();
+    const TF d = prow[s];
+    for (int rr = tid; rr < R; rr += 256)
+      if (act[rr] == 1) {
+        const TF l = P[rr * w + s] / d;
+        lmul[rr] = l;
+        P[rr * w + s] = l;
+      }
+    __syncthreads();
+    const int nq = w - s - 1;
+    if (nq > 0)
+      for (int i = tid; i < R * nq; i += 256) {
+        const int rr = i / nq, q = s + 1 + i % nq;
+        if (act[rr] == 1) P[rr * w + q] -= lmul[rr] * prow[q];
+      }
+    __syncthreads();
+  }
+  for (int i = tid; i < R * w; i += 256) {
+    const int rr = i / w, q = i % w;
+    if (act[rr] != 0) Z[(r0 + rr) * ldz + zcol + q] = P[i];
+  }
+  if (g == 0 && tid == 0) {
+    if (deficient) {
+      ctrl->k = zcol + steps;
+      ctrl->status = ST_RANK_DEFICIENT;
+      ctrl->done = 1;
+      if (ctrl->E < 0.0) ctrl->E = 0.0;
+    } else {
+      ctrl->k = zcol + f;
+      if (stop_full && (int64_t)(zcol + f) == mn) {
+        ctrl->done = 1;
+        ctrl->status = ST_OK;
+        ctrl->E = 0.0;
+      }
+    }
+  }
+}
+
+// Non-skeleton candidates in ascending index (one workgroup, 1024 threads):
+// nonpiv[q] = q-th candidate r with pos[r] < 0.
+__global__ __launch_bounds__(1024) void k_nonpiv(const int* __restrict__ pos, int64_t n,
+                                                 int* __restrict__ nonpiv) {
+  __shared__ int cnt[1024];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t a = tid * chunk, b = (a + chunk < n) ? a + chunk : n;
+  int c = 0;
+  for (int64_t r = a; r < b; ++r) c += (pos[r] < 0);
+  cnt[tid] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = (tid >= off) ? cnt[tid - off] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
+  }
+  int q = cnt[tid] - c;
+  for (int64_t r = a; r < b; ++r)
+    if (pos[r] < 0) nonpiv[q++] = (int)r;
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation matrix T = L1^{-T} L2^T, one 64-row block [s0, s1) of T per
+// launch, launched from the last block to the first.  Each workgroup owns 64
+// non-skeleton candidates (columns of T):
+//   acc(s, q) = L2(q, s) - sum_{s' >= s1} L1(s', s) T(s', q)     (MFMA)
+// then back substitution with the 64 x 64 diagonal block of L1 in LDS.
+// ---------------------------------------------------------------------------
+template <typename TF>
+__global__ __launch_bounds__(256) void k_tsolve(const TF* __restrict__ Z, int64_t ldz,
+                                                const int* __restrict__ order,
+                                                const int* __restrict__ nonpiv, int64_t n,
+                                                int beta, TF* __restrict__ T, int64_t ldt,
+                                                const Ctrl* ctrl) {
+  if (ctrl->status < 0) return;
+  const int k = ctrl->k;
+  const int s0 = beta * 64;
+  if (s0 >= k) return;
+  const int s1 = (s0 + 64 < k) ? s0 + 64 : k, nb = s1 - s0;
+  const int64_t nn = n - k;
+  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  if (q0 >= nn) return;
+  using M = Mfma<TF>;
+  using acc_t = typename M::acc_t;
+  __shared__ TF xs[64][65];
+  __shared__ TF Ld[64][65];
+  __shared__ int rq[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < 64) rq[tid] = (q0 + tid < nn) ? nonpiv[q0 + tid] : -1;
+  for (int idx = tid; idx < nb * nb; idx += 256) {
+    const int a = idx / nb, b = idx % nb;
+    Ld[a][b] = (b < a) ? Z[(int64_t)order[s0 + a] * ldz + s0 + b] : TF(0);
+  }
+  acc_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = M::zero();
+  const int irow = wave * 16 + (lane & 15);
+  for (int s2 = s1; s2 < k; s2 += 4) {
+    const int kidx = s2 + (lane >> 4);
+    const TF a = (kidx < k && irow < nb) ? Z[(int64_t)order[kidx] * ldz + s0 + irow] : TF(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t qj = q0 + t * 16 + (lane & 15);
+      const TF b = (kidx < k && qj < nn) ? T[(int64_t)kidx * ldt + qj] : TF(0);
+      acc[t] = M::op(a, b, acc[t]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = wave * 16 + M::row(lane, r), j = t * 16 + (lane & 15);
+      if (i < nb && rq[j] >= 0) xs[i][j] = Z[(int64_t)rq[j] * ldz + s0 + i] - acc[t][r];
+    }
+  __syncthreads();
+  if (tid < 64 && rq[tid] >= 0) {
+    for (int i = nb - 1; i >= 0; --i) {
+      TF v = xs[i][tid];
+      for (int a = i + 1; a < nb; ++a) v -= Ld[a][i] * xs[a][tid];
+      xs[i][tid] = v;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * 64; idx += 256) {
+    const int i = idx / 64, j = idx % 64;
+    if (q0 + j < nn) T[(int64_t)(s0 + i) * ldt + q0 + j] = xs[i][j];
+  }
+}
+
+// Final outputs: J (int64, pivot order), rank, estimate, status.
+__global__ void k_outputs(const Ctrl* ctrl, const int* __restrict__ order, int64_t* __restrict__ J,
+                          int32_t* k_out, double* err_est, int32_t* status) {
+  const int k = ctrl->status < 0 ? 0 : ctrl->k;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < k; s += gridDim.x * blockDim.x)
+    J[s] = order[s];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *k_out = k;
+    *err_est = ctrl->E;
+    *status = ctrl->status;
+  }
+}
+
+// Test export: materialised Gaussian block out[c*m + i] = omega(c0 + c, i).
+template <typename T>
+__global__ void k_gaussian(uint32_t key0, uint32_t key1, int64_t c0, int64_t w, int64_t m,
+                           T* __restrict__ out) {
+  const int64_t nq = (m + 3) / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq * w) return;
+  const int64_t c = t / nq, q = t % nq;
+  T v[4];
+  gauss4<T>(key0, key1, (uint32_t)q, (uint32_t)(c0 + c), v);
+  for (int a = 0; a < 4; ++a)
+    if (4 * q + a < m) out[c * m + 4 * q + a] = v[a];
+}
+
+}  // namespace rid
