@@ -128,6 +128,19 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
                      const rid_config* cfg, void* Yt, int64_t ldy, void* work, size_t work_bytes,
                      hipStream_t stream);
 
+/*
+ * Optional timing.  After rid_profile_start(), every kernel launch of the
+ * library is bracketed by two HIP events on the call's stream (host-side
+ * event objects are created on first use and reused).  rid_profile_stop()
+ * waits for the recorded events and returns, per kernel class, the summed
+ * elapsed milliseconds and the number of launches; it also ends recording.
+ * Classes: 0 sketch, 1 sketch reduction, 2 U2 triangular solve,
+ * 3 Schur update, 4 panel LUPP, 5 interpolation solve.  Process-wide state:
+ * not for concurrent use from several host threads.
+ */
+int rid_profile_start(void);
+int rid_profile_stop(double* ms, int64_t* launches, int nclass);
+
 #ifdef __cplusplus
 }
 #endif

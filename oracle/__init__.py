@@ -68,8 +68,15 @@ def _load():
         lib.orc_rid_lupp.restype = cint
         lib.orc_lupp_factors.argtypes = [P, i64, i64, i64, i64, i64, u64, P, P, P]
         lib.orc_lupp_factors.restype = cint
+        lib.orc_num_threads.argtypes = []
+        lib.orc_num_threads.restype = cint
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().orc_num_threads())
 
 
 def _ptr(a: np.ndarray):

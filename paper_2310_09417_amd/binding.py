@@ -58,6 +58,10 @@ def library() -> ctypes.CDLL:
         lib.rid_debug_gaussian.restype = i32
         lib.rid_debug_sketch.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, i64, P, sz, P]
         lib.rid_debug_sketch.restype = i32
+        lib.rid_profile_start.argtypes = []
+        lib.rid_profile_start.restype = i32
+        lib.rid_profile_stop.argtypes = [P, P, i32]
+        lib.rid_profile_stop.restype = i32
         _lib = lib
     return _lib
 
@@ -95,6 +99,25 @@ def rid_debug_gaussian(seed, c0, w, m, dtype, out, stream) -> int:
 def rid_debug_sketch(A, m, n, lda, c0, w, cfg, Yt, ldy, work, work_bytes, stream) -> int:
     return int(library().rid_debug_sketch(A, m, n, lda, c0, w, ctypes.byref(cfg), Yt, ldy, work,
                                           work_bytes, stream))
+
+
+KERNEL_CLASSES = ("sketch", "sketch_reduce", "trsm_u2", "schur", "panel_lupp", "tsolve")
+
+
+def rid_profile_start() -> int:
+    return int(library().rid_profile_start())
+
+
+def rid_profile_stop() -> dict:
+    """{class: (total_ms, launches)} for the launches since rid_profile_start."""
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    rc = int(library().rid_profile_stop(ctypes.cast(ms, ctypes.c_void_p),
+                                         ctypes.cast(cnt, ctypes.c_void_p), n))
+    if rc != RID_OK:
+        raise RidError(f"rid_profile_stop returned {rc}")
+    return {KERNEL_CLASSES[i]: (ms[i], int(cnt[i])) for i in range(n)}
 
 
 # ---- torch-facing wrappers -------------------------------------------------

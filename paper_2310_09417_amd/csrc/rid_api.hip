@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "../../include/rid.h"
 #include "rid_kernels.hpp"
@@ -45,6 +47,39 @@ DeviceInfo device_info() {
 }
 
 inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
+
+// ---- optional per-kernel-class timing (HIP events on the call's stream) ----
+enum KClass { KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_OTHER, KC_N };
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+
+// Records a start event before a launch of class c; returns the slot to close.
+inline long prof_begin(int c, hipStream_t st) {
+  Profiler& p = prof();
+  if (!p.on) return -1;
+  while (p.used + 2 > p.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    p.pool.push_back(e);
+  }
+  const size_t at = p.used;
+  p.used += 2;
+  if (hipEventRecord(p.pool[at], st) != hipSuccess) return -1;
+  p.marks.emplace_back(c, at);
+  return (long)at;
+}
+inline void prof_end(long at, hipStream_t st) {
+  if (at >= 0) (void)hipEventRecord(prof().pool[(size_t)at + 1], st);
+}
 
 // Sketch launch geometry for a block of w vectors.
 struct SketchGeom {
@@ -200,6 +235,7 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  const long pm = prof_begin(KC_SKETCH, st);
   if (norm)
     hipLaunchKernelGGL((k_sketch<TC, MT, NQ, 4, KC, true>), grid, dim3(256), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
@@ -208,6 +244,7 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
     hipLaunchKernelGGL((k_sketch<TC, MT, NQ, 4, KC, false>), grid, dim3(256), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
                        g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
+  prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }
@@ -237,6 +274,7 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
   const int64_t tot = P.n * w;
   const unsigned blocks = (unsigned)ceil_div(tot, 256);
   Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  const long pm = prof_begin(KC_REDUCE, st);
   if (P.dt == RID_F64)
     hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
                        (int)g.nsplit, P.n, g.wp, w, static_cast<double*>(out), ldo, zcol, W.fro,
@@ -245,6 +283,7 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
     hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
                        (int)g.nsplit, P.n, g.wp, w, static_cast<float*>(out), ldo, zcol, W.fro,
                        (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, first ? 1 : 0);
+  prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }
@@ -257,9 +296,12 @@ int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm
       hipFuncSetAttribute((const void*)k_trsm_u2<TF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds) != hipSuccess)
     return RID_ERR_HIP;
+  long pm = prof_begin(KC_TRSM, st);
   hipLaunchKernelGGL(k_trsm_u2<TF>, dim3(w), dim3(256), lds, st, static_cast<TF*>(W.z), P.ldz,
                      W.order, k, zcol, w, static_cast<TF*>(W.u2t), P.ldu, W.ctrl);
+  prof_end(pm, st);
   RID_LAUNCH_CHECK();
+  pm = prof_begin(KC_SCHUR, st);
   const int nt = (w + 15) / 16;
   dim3 grid((unsigned)P.schur_wgs);
 #define RID_SCHUR(NTV)                                                                         \
@@ -277,6 +319,7 @@ int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm
     default: RID_SCHUR(8); break;
   }
 #undef RID_SCHUR
+  prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }
@@ -318,10 +361,11 @@ int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, boo
   int sf = stop_full ? 1 : 0;
   void* args[] = {&z, &ldz, &n, &zcol, &w, &f, &pos, &order, &ctrl,
                   &slots, &slotrows, &bar, &rows, &mn, &sf};
-  if (hipLaunchCooperativeKernel(fn, dim3(P.lupp_g), dim3(256), args, (unsigned)lds, st) !=
-      hipSuccess)
-    return RID_ERR_HIP;
-  return RID_OK;
+  const long pm = prof_begin(KC_LUPP, st);
+  const hipError_t e =
+      hipLaunchCooperativeKernel(fn, dim3(P.lupp_g), dim3(256), args, (unsigned)lds, st);
+  prof_end(pm, st);
+  return e == hipSuccess ? RID_OK : RID_ERR_HIP;
 }
 
 int panel(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
@@ -339,9 +383,11 @@ int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32
   const int nblk = (int)ceil_div(P.kcap, 64);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(P.n, 64));
   for (int beta = nblk - 1; beta >= 0; --beta) {
+    const long pm = prof_begin(KC_TSOLVE, st);
     hipLaunchKernelGGL(k_tsolve<TF>, dim3(grid), dim3(256), 0, st,
                        static_cast<const TF*>(W.z), P.ldz, W.order, W.nonpiv, P.n, beta,
                        static_cast<TF*>(T), ldt, W.ctrl);
+    prof_end(pm, st);
     RID_LAUNCH_CHECK();
   }
   const unsigned og = (unsigned)std::max<int64_t>(1, ceil_div(P.kcap, 256));
@@ -501,6 +547,37 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
   Ws W = carve(P, work);
   RID_TRY(init(P, W, stream));
   return sketch_block(P, W, A, lda, cfg->seed, c0, (int)w, Yt, ldy, 0, true, true, stream);
+}
+
+int rid_profile_start(void) {
+  Profiler& p = prof();
+  p.on = true;
+  p.used = 0;
+  p.marks.clear();
+  return RID_OK;
+}
+
+int rid_profile_stop(double* ms, int64_t* launches, int nclass) {
+  Profiler& p = prof();
+  p.on = false;
+  if (!ms || !launches || nclass < 1) return RID_ERR_ARG;
+  for (int c = 0; c < nclass; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (auto& mk : p.marks) {
+    if (hipEventSynchronize(p.pool[mk.second + 1]) != hipSuccess) return RID_ERR_HIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p.pool[mk.second], p.pool[mk.second + 1]) != hipSuccess)
+      return RID_ERR_HIP;
+    if (mk.first < nclass) {
+      ms[mk.first] += t;
+      launches[mk.first] += 1;
+    }
+  }
+  p.marks.clear();
+  p.used = 0;
+  return RID_OK;
 }
 
 }  // extern "C"

@@ -93,3 +93,26 @@ def kernel_batch_shapes(nblk: int, seed: int, lo: int = 64, hi: int = 1024):
     sep = rng.uniform(3.0, 6.0, size=nblk)
     seeds = rng.integers(0, 2**62, size=nblk)
     return [(int(m[i]), int(n[i]), float(sep[i]), int(seeds[i])) for i in range(nblk)]
+
+
+def svd_matrix_device(m: int, n: int, sigma, seed: int, device="cuda", dtype=None):
+    """Device-side version of svd_matrix for sizes where host QR is too slow
+    (torch's Gaussian generator and QR on the GPU, FP64).  Same construction,
+    different random stream from the host version; returns an FP64 tensor."""
+    import torch
+    r = min(m, n)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    s = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+    U = torch.randn((m, r), generator=g, dtype=torch.float64, device=device)
+    U, R = torch.linalg.qr(U)
+    U *= torch.sign(torch.diagonal(R))[None, :]
+    del R
+    V = torch.randn((n, r), generator=g, dtype=torch.float64, device=device)
+    V, R = torch.linalg.qr(V)
+    V *= torch.sign(torch.diagonal(R))[None, :]
+    del R
+    U *= s[None, :]
+    A = U @ V.T
+    del U, V
+    return A if dtype is None else A.to(dtype)
