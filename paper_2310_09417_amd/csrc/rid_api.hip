@@ -81,20 +81,19 @@ inline void prof_end(long at, hipStream_t st) {
   if (at >= 0) (void)hipEventRecord(prof().pool[(size_t)at + 1], st);
 }
 
-// Sketch launch geometry for a block of w vectors.
+// Sketch launch geometry for a block of w <= 64 vectors: 256 columns per
+// workgroup, enough row splits for ~4 workgroups per CU.
 struct SketchGeom {
-  int mt, nq, wp, kc, cols_per_wg;
+  int mt, wp, kc;
   int64_t ncolg, nsplit, rows_per_split;
 };
 
 SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   SketchGeom g;
-  g.mt = w <= 16 ? 1 : w <= 32 ? 2 : w <= 64 ? 4 : 8;
-  g.nq = g.mt == 8 ? 2 : 4;
+  g.mt = w <= 16 ? 1 : w <= 32 ? 2 : 4;
   g.wp = g.mt * 16;
   g.kc = dt == RID_F64 ? 32 : 64;
-  g.cols_per_wg = 4 * g.nq * 16;
-  g.ncolg = ceil_div(n, g.cols_per_wg);
+  g.ncolg = ceil_div(n, 256);
   const int64_t target = 4 * (int64_t)cu;
   int64_t ns = std::max<int64_t>(1, ceil_div(target, g.ncolg));
   ns = std::min<int64_t>(ns, ceil_div(m, g.kc));
@@ -135,21 +134,14 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, P
   P.lupp_g = (int)std::max<int64_t>(1, std::min<int64_t>(di.cu, ceil_div(n, 16)));
   P.lupp_rows = (int)ceil_div(n, P.lupp_g);
   P.lupp_g = (int)ceil_div(n, P.lupp_rows);
-  P.lupp_lds = (size_t)P.lupp_rows * wmax * es + 128 * es + (size_t)P.lupp_rows * es +
-               (size_t)P.lupp_rows * 4;
+  P.lupp_lds = (size_t)P.lupp_rows * (wmax + 1) * es + 128 * es + (size_t)P.lupp_rows * 4;
   P.nbars = (int)(kcap + 8);
-  // largest sketch partial buffer over the block widths used
+  // sketch partials: every launch covers <= 64 vectors with the same split
   size_t pb = 0, fc = 0;
-  for (int w = 1; w <= wmax; w = (w < 16 ? 16 : w * 2)) {
-    SketchGeom g = sketch_geom(m, n, std::min<int64_t>(w, wmax), dt, di.cu);
-    pb = std::max(pb, (size_t)g.nsplit * (size_t)n * g.wp * 8);
-    fc = std::max(fc, (size_t)(g.nsplit * g.ncolg));
-    if (w >= wmax) break;
-  }
   {
-    SketchGeom g = sketch_geom(m, n, (int)wmax, dt, di.cu);
-    pb = std::max(pb, (size_t)g.nsplit * (size_t)n * g.wp * 8);
-    fc = std::max(fc, (size_t)(g.nsplit * g.ncolg));
+    SketchGeom g = sketch_geom(m, n, (int)std::min<int64_t>(wmax, 64), dt, di.cu);
+    pb = (size_t)g.nsplit * (size_t)n * g.wp * 8;
+    fc = (size_t)(g.nsplit * g.ncolg);
   }
   P.part_bytes = pb;
   P.fro_count = fc;
@@ -228,7 +220,7 @@ Ws carve(const Plan& P, void* work) {
   } while (0)
 
 // ---- sketch dispatch -------------------------------------------------------
-template <typename TC, int MT, int NQ, int KC>
+template <typename TC, int MT, int KC, bool VEC>
 int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                     int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
                     hipStream_t st) {
@@ -237,11 +229,11 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
   const long pm = prof_begin(KC_SKETCH, st);
   if (norm)
-    hipLaunchKernelGGL((k_sketch<TC, MT, NQ, 4, KC, true>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((k_sketch<TC, MT, KC, true, VEC>), grid, dim3(256), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
                        g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
   else
-    hipLaunchKernelGGL((k_sketch<TC, MT, NQ, 4, KC, false>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((k_sketch<TC, MT, KC, false, VEC>), grid, dim3(256), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
                        g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
   prof_end(pm, st);
@@ -249,42 +241,56 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   return RID_OK;
 }
 
-template <typename TC, int KC>
+template <typename TC, int KC, bool VEC>
 int launch_sketch_mt(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                      int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
                      hipStream_t st) {
   switch (g.mt) {
-    case 1: return launch_sketch_t<TC, 1, 4, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
-    case 2: return launch_sketch_t<TC, 2, 4, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
-    case 4: return launch_sketch_t<TC, 4, 4, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
-    default: return launch_sketch_t<TC, 8, 2, KC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    case 1: return launch_sketch_t<TC, 1, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    case 2: return launch_sketch_t<TC, 2, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    default: return launch_sketch_t<TC, 4, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
   }
 }
 
+template <typename TC, int KC>
+int launch_sketch(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                  int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
+                  hipStream_t st) {
+  // 16-byte vector loads of 4 consecutive entries need lda % 4 == 0 and an
+  // aligned base
+  const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+  return vec ? launch_sketch_mt<TC, KC, true>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st)
+             : launch_sketch_mt<TC, KC, false>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+}
+
 // Sketch vectors [c0, c0 + w) into columns [zcol, zcol + w) of `out`
-// (n x ldo, dtype of the plan).
+// (n x ldo, dtype of the plan), in launches of at most 64 vectors.
 int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                  int64_t c0, int w, void* out, int64_t ldo, int zcol, bool first, bool use_ctrl,
                  hipStream_t st) {
-  SketchGeom g = sketch_geom(P.m, P.n, w, P.dt, P.cu);
-  int rc = (P.dt == RID_F64)
-               ? launch_sketch_mt<double, 32>(P, W, A, lda, seed, c0, w, g, first, use_ctrl, st)
-               : launch_sketch_mt<float, 64>(P, W, A, lda, seed, c0, w, g, first, use_ctrl, st);
-  if (rc != RID_OK) return rc;
-  const int64_t tot = P.n * w;
-  const unsigned blocks = (unsigned)ceil_div(tot, 256);
-  Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
-  const long pm = prof_begin(KC_REDUCE, st);
-  if (P.dt == RID_F64)
-    hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
-                       (int)g.nsplit, P.n, g.wp, w, static_cast<double*>(out), ldo, zcol, W.fro,
-                       (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, first ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
-                       (int)g.nsplit, P.n, g.wp, w, static_cast<float*>(out), ldo, zcol, W.fro,
-                       (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, first ? 1 : 0);
-  prof_end(pm, st);
-  RID_LAUNCH_CHECK();
+  for (int off = 0; off < w; off += 64) {
+    const int wc = std::min(64, w - off);
+    const bool norm = first && off == 0;
+    SketchGeom g = sketch_geom(P.m, P.n, wc, P.dt, P.cu);
+    int rc = (P.dt == RID_F64)
+                 ? launch_sketch<double, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st)
+                 : launch_sketch<float, 64>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st);
+    if (rc != RID_OK) return rc;
+    const int64_t tot = P.n * wc;
+    const unsigned blocks = (unsigned)ceil_div(tot, 256);
+    Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+    const long pm = prof_begin(KC_REDUCE, st);
+    if (P.dt == RID_F64)
+      hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
+                         (int)g.nsplit, P.n, g.wp, wc, static_cast<double*>(out), ldo, zcol + off,
+                         W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, norm ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
+                         (int)g.nsplit, P.n, g.wp, wc, static_cast<float*>(out), ldo, zcol + off,
+                         W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, norm ? 1 : 0);
+    prof_end(pm, st);
+    RID_LAUNCH_CHECK();
+  }
   return RID_OK;
 }
 
@@ -342,8 +348,7 @@ template <typename TF>
 int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
             hipStream_t st) {
   const size_t es = sizeof(TF);
-  const size_t lds = (size_t)P.lupp_rows * w * es + 128 * es + (size_t)P.lupp_rows * es +
-                     (size_t)P.lupp_rows * 4;
+  const size_t lds = (size_t)P.lupp_rows * (w + 1) * es + 128 * es + (size_t)P.lupp_rows * 4;
   if (lds > kMaxLds) return RID_ERR_ARG;
   const void* fn = (const void*)k_panel_lupp<TF>;
   if (lds > 64 * 1024 &&

@@ -64,113 +64,167 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, unsigned* bars, int nbar
 
 // ---------------------------------------------------------------------------
 // Sketch: partial sums of Y(c, j) = sum_i omega(c0 + c, i) A(i, j) over one
-// row range ("split") per grid row, for a strip of columns per grid column.
-//   * Omega for KC rows x WP vectors is generated into LDS once per chunk and
-//     shared by the WAVES*NQ*16 columns of the workgroup (never stored in HBM).
-//   * The A tile is read once, straight into MFMA B operands.
-//   * FP32: each KC-row chunk is accumulated by MFMA in FP32 and folded into
-//     FP64 accumulators, so rounding grows with KC, not with m.
+// row range ("split") per grid row, for a strip of 256 columns per grid
+// column (4 waves x 64 columns).
+//   * A is streamed once.  Each lane loads 4 consecutive columns of one row
+//     (one 16- or 32-byte load) and feeds them to 4 different MFMAs, so MFMA
+//     q, output column j covers matrix column 4 j + q of the wave's strip.
+//   * The A operands of the next KC-row chunk are loaded into registers while
+//     the current chunk is multiplied (register double buffering).
+//   * Omega is generated into LDS, double buffered: the next chunk's entries
+//     are produced between the current chunk's MFMAs.  It is never stored in
+//     HBM and each entry is generated once per 256-column strip.
+//   * FP32: each chunk is accumulated by MFMA in FP32 and folded into FP64
+//     registers, so rounding grows with KC, not with m.
 //   * Partials part[split][j][c] (FP64) are summed in split order by
 //     k_sketch_reduce, so the result does not depend on scheduling.
 //   * NORM: also accumulates sum A^2 (FP64) and flags non-finite entries.
 // ---------------------------------------------------------------------------
-template <typename TC, int MT, int NQ, int WAVES, int KC, bool NORM>
-__global__ __launch_bounds__(WAVES * 64) void k_sketch(
+template <typename TC, bool VEC>
+__device__ __forceinline__ void load_row4(const TC* __restrict__ A, int64_t row, int64_t r_end,
+                                          int64_t col, int64_t n, int64_t lda, TC out[4]) {
+  if (row < r_end && col + 3 < n) {
+    const TC* p = A + row * lda + col;
+    if (VEC) {
+      if (sizeof(TC) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2*>(p);
+        const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+        out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[e] = p[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      out[e] = (row < r_end && col + e < n) ? A[row * lda + col + e] : TC(0);
+  }
+}
+
+template <typename TC, int MT, int KC, bool NORM, bool VEC>
+__global__ __launch_bounds__(256) void k_sketch(
     const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, uint32_t key0, uint32_t key1,
     uint32_t c0, int w, int64_t rows_per_split, double* __restrict__ part,
     double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
   if (ctrl && ctrl->done) return;
-  constexpr int WP = MT * 16;
-  constexpr int LDO = WP + 16;
-  constexpr int NT = WAVES * 64;
+  constexpr int WP = MT * 16;            // padded number of sketch vectors
+  constexpr int LDO = WP + 16;           // LDS row pitch of Omega
+  constexpr int KS = KC / 4;             // MFMA k-steps (and row quads) per chunk
+  constexpr int NGEN = (KS * WP + 255) / 256;  // gauss4 calls per thread per chunk
+  constexpr int GSTEP = KS / NGEN;             // k-steps between two of them
+  static_assert(NGEN >= 1 && KS % NGEN == 0, "chunk geometry");
   using M = Mfma<TC>;
   using acc_t = typename M::acc_t;
-  __shared__ TC om[KC * LDO];
-  __shared__ double red[WAVES];
+  __shared__ TC om[2][KC * LDO];
+  __shared__ double red[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t colw = (int64_t)blockIdx.x * (WAVES * NQ * 16) + wave * (NQ * 16);
+  const int64_t col4 = (int64_t)blockIdx.x * 256 + wave * 64 + 4 * (lane & 15);
   const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+  const int nch = (int)((r_end - r_begin + KC - 1) / KC);
 
-  acc_t acc[MT][NQ];
-  double acc64[MT][NQ][4];
+  acc_t acc[MT][4];
+  double acc64[MT][4][4];
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < NQ; ++b) {
-      acc[a][b] = M::zero();
+    for (int q = 0; q < 4; ++q) {
+      acc[a][q] = M::zero();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+      for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
     }
   double fro = 0.0;
   bool bad = false;
 
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
-    __syncthreads();
-    for (int it = tid; it < (KC / 4) * WP; it += NT) {
-      const int c = it % WP, qd = it / WP;
-      const int64_t row4 = r0 + 4 * qd;
-      TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
-      if (c < w && row4 < r_end) gauss4<TC>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
+  // Omega entries for row quads of chunk starting at r0, call index g
+  auto gen = [&](TC* omb, int64_t r0, int g) {
+    const int it = tid + g * 256;
+    if (it >= KS * WP) return;
+    const int c = it % WP, qd = it / WP;
+    const int64_t row4 = r0 + 4 * qd;
+    TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
+    if (c < w && row4 < r_end) gauss4<TC>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) om[(4 * qd + a) * LDO + c] = (row4 + a < r_end) ? v[a] : TC(0);
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int krow = kk + (lane >> 4);
-      const int64_t row = r0 + krow;
-      TC bv[NQ];
+    for (int a = 0; a < 4; ++a) omb[(4 * qd + a) * LDO + c] = (row4 + a < r_end) ? v[a] : TC(0);
+  };
+  auto loadB = [&](TC (&buf)[KS][4], int64_t r0) {
 #pragma unroll
-      for (int b = 0; b < NQ; ++b) {
-        const int64_t col = colw + b * 16 + (lane & 15);
-        bv[b] = (row < r_end && col < n) ? A[row * lda + col] : TC(0);
-      }
+    for (int j = 0; j < KS; ++j) load_row4<TC, VEC>(A, r0 + 4 * j + (lane >> 4), r_end, col4, n, lda, buf[j]);
+  };
+  // multiply one chunk (Omega in omc, A operands in buf) while generating the
+  // next chunk's Omega into omn
+  auto compute = [&](const TC* omc, TC (&buf)[KS][4], TC* omn, int64_t rnext, bool has_next) {
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      if (has_next && (j % GSTEP) == 0) gen(omn, rnext, j / GSTEP);
       TC av[MT];
 #pragma unroll
-      for (int a = 0; a < MT; ++a) av[a] = om[krow * LDO + a * 16 + (lane & 15)];
+      for (int a = 0; a < MT; ++a) av[a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
       if (NORM) {
 #pragma unroll
-        for (int b = 0; b < NQ; ++b) {
-          fro += (double)bv[b] * (double)bv[b];
-          bad |= !__builtin_isfinite((double)bv[b]);
+        for (int q = 0; q < 4; ++q) {
+          fro += (double)buf[j][q] * (double)buf[j][q];
+          bad |= !__builtin_isfinite((double)buf[j][q]);
         }
       }
 #pragma unroll
       for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int b = 0; b < NQ; ++b) acc[a][b] = M::op(av[a], bv[b], acc[a][b]);
+        for (int q = 0; q < 4; ++q) acc[a][q] = M::op(av[a], buf[j][q], acc[a][q]);
     }
     if (sizeof(TC) == 4) {
 #pragma unroll
       for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int b = 0; b < NQ; ++b) {
+        for (int q = 0; q < 4; ++q) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
-          acc[a][b] = M::zero();
+          for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
+          acc[a][q] = M::zero();
         }
     }
+  };
+
+  TC bA[KS][4], bB[KS][4];
+  if (nch > 0) {
+#pragma unroll
+    for (int g = 0; g < NGEN; ++g) gen(om[0], r_begin, g);
+    loadB(bA, r_begin);
+  }
+  __syncthreads();
+  for (int ci = 0; ci < nch; ci += 2) {
+    const int64_t r0 = r_begin + (int64_t)ci * KC;
+    const bool n1 = ci + 1 < nch, n2 = ci + 2 < nch;
+    if (n1) loadB(bB, r0 + KC);
+    compute(om[0], bA, om[1], r0 + KC, n1);
+    __syncthreads();
+    if (!n1) break;
+    if (n2) loadB(bA, r0 + 2 * KC);
+    compute(om[1], bB, om[0], r0 + 2 * KC, n2);
+    __syncthreads();
   }
   if (sizeof(TC) == 8) {
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-      for (int b = 0; b < NQ; ++b)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc64[a][b][r] = (double)acc[a][b][r];
+        for (int r = 0; r < 4; ++r) acc64[a][q][r] = (double)acc[a][q][r];
   }
   const int64_t split = blockIdx.y;
 #pragma unroll
-  for (int b = 0; b < NQ; ++b) {
-    const int64_t col = colw + b * 16 + (lane & 15);
+  for (int q = 0; q < 4; ++q) {
+    const int64_t col = col4 + q;
     if (col < n) {
       double* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP;
 #pragma unroll
       for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = acc64[a][b][r];
+        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = acc64[a][q][r];
     }
   }
   if (NORM) {
@@ -178,11 +232,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sketch(
     if (lane == 0) red[wave] = fro;
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int i = 0; i < WAVES; ++i) s += red[i];
-      fro_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
-    }
+    if (tid == 0) fro_part[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
   }
 }
 
@@ -285,6 +335,18 @@ __global__ __launch_bounds__(256) void k_trsm_u2(TF* __restrict__ Z, int64_t ldz
 template <typename TF>
 __device__ __forceinline__ void load4(const TF* p, int64_t base, int kidx, int k, bool ok,
                                       TF out[4]) {
+  if (ok && kidx + 3 < k) {
+    // 16-byte aligned: base and kidx are multiples of 4 elements
+    if (sizeof(TF) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p + base + kidx);
+      out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+      const double2 v0 = *reinterpret_cast<const double2*>(p + base + kidx);
+      const double2 v1 = *reinterpret_cast<const double2*>(p + base + kidx + 2);
+      out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) out[j] = (ok && kidx + j < k) ? p[base + kidx + j] : TF(0);
 }
@@ -385,15 +447,46 @@ __global__ void k_estimate(Ctrl* ctrl, const double* __restrict__ normpart, int 
 
 // ---------------------------------------------------------------------------
 // Panel LUPP (cooperative launch, all workgroups resident).  Workgroup g owns
-// candidate rows [g*R, (g+1)*R) and keeps their w panel values in LDS.  Per
-// pivot step: local arg-max of |value| (ties -> lower candidate index) ->
-// publish (value, candidate, full row) to a double-buffered slot -> one grid
-// barrier -> every workgroup reduces the same slots to the same winner, reads
-// its row, scales its own rows and applies the rank-1 update.  Rows are never
-// swapped: the winner's pos/order entries record the permutation.  An exactly
-// zero winner stops the factorisation (rank of the sketch reached).
+// candidate rows [g*R, (g+1)*R) and keeps their w panel values in LDS (row
+// pitch w+1, so column reads across rows are free of bank conflicts).  Per
+// pivot step, wave 0 alone carries the critical path:
+//   local arg-max of |value| over active rows (ties -> lower candidate index)
+//   -> publish (value, candidate) and the candidate's row to a
+//      double-buffered slot -> grid barrier (one counter per launch)
+//   -> reduce all slots to the winner (every workgroup reaches the same one)
+//   -> fetch the winner's row;
+// then every thread updates the rows it owns (scale by the pivot, rank-1
+// update).  Rows are never swapped: pos/order record the permutation.  An
+// exactly zero winner stops the factorisation (rank of the sketch reached).
+// Cross-workgroup data goes through agent-scope relaxed atomics (coherent
+// across XCDs without cache write-back or invalidation); a writer waits for
+// its stores to complete before the barrier counter is incremented.
 // ---------------------------------------------------------------------------
 constexpr long long kSpinLimit = 1ll << 26;
+
+template <typename TF>
+struct Bits;
+template <>
+struct Bits<float> {
+  using U = uint32_t;
+  __device__ static U to(float v) { return __float_as_uint(v); }
+  __device__ static float from(U u) { return __uint_as_float(u); }
+};
+template <>
+struct Bits<double> {
+  using U = unsigned long long;
+  __device__ static U to(double v) { return (U)__double_as_longlong(v); }
+  __device__ static double from(U u) { return __longlong_as_double((long long)u); }
+};
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <typename TF>
 __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t ldz, int64_t n,
@@ -402,16 +495,16 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
                                                     Slot* slots, TF* slotrows, unsigned* bar,
                                                     int rows_per_wg, int64_t mn, int stop_full) {
   if (ctrl->done) return;
+  using B = Bits<TF>;
+  using U = typename B::U;
   extern __shared__ unsigned char smem_raw[];
-  TF* P = reinterpret_cast<TF*>(smem_raw);  // [rows_per_wg][w]
-  TF* prow = P + (size_t)rows_per_wg * w;    // [128]
-  TF* lmul = prow + 128;                     // [rows_per_wg]
-  int* act = reinterpret_cast<int*>(lmul + rows_per_wg);
-  __shared__ double red_v[4];
-  __shared__ long long red_i[4];
+  const int pitch = w + 1;
+  TF* P = reinterpret_cast<TF*>(smem_raw);       // [rows_per_wg][pitch]
+  TF* prow = P + (size_t)rows_per_wg * pitch;     // [128]
+  int* act = reinterpret_cast<int*>(prow + 128);  // [rows_per_wg]
   __shared__ double s_val;
   __shared__ long long s_row;
-  __shared__ int s_timeout;
+  __shared__ int s_stop;  // 0 run, 1 deficient, 2 timeout
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = (int64_t)g * rows_per_wg;
@@ -421,116 +514,101 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
 
   for (int i = tid; i < R * w; i += 256) {
     const int rr = i / w, q = i % w;
-    P[i] = Z[(r0 + rr) * ldz + zcol + q];
+    P[rr * pitch + q] = Z[(r0 + rr) * ldz + zcol + q];
   }
   for (int rr = tid; rr < R; rr += 256) act[rr] = (pos[r0 + rr] < 0) ? 1 : 0;
-  if (tid == 0) s_timeout = 0;
+  if (tid == 0) s_stop = 0;
   __syncthreads();
 
   int steps = f;
-  bool deficient = false;
   for (int s = 0; s < f; ++s) {
-    double bv = -1.0;
-    long long bi = -1;
-    for (int rr = tid; rr < R; rr += 256)
-      if (act[rr] == 1) argmax_merge(bv, bi, fabs((double)P[rr * w + s]), r0 + rr);
-    wave_argmax(bv, bi);
-    if (lane == 0) {
-      red_v[wave] = bv;
-      red_i[wave] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int i = 1; i < 4; ++i) argmax_merge(bv, bi, red_v[i], red_i[i]);
-      s_val = bv;
-      s_row = bi;
-    }
-    __syncthreads();
-    const int buf = s & 1;
-    Slot* sl = slots + (size_t)buf * G;
-    TF* srow = slotrows + (size_t)buf * G * w;
-    if (tid == 0) {
-      sl[g].v = s_val;
-      sl[g].row = s_row;
-    }
-    if (s_row >= 0)
-      for (int q = tid; q < w; q += 256) srow[(size_t)g * w + q] = P[(s_row - r0) * w + q];
-    fence_release_agent();
-    __syncthreads();
-    if (tid == 0) {
-      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned target = (unsigned)(s + 1) * (unsigned)G;
-      long long spins = 0;
-      while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > kSpinLimit) {
-          s_timeout = 1;
-          break;
+    if (wave == 0) {
+      double bv = -1.0;
+      long long bi = -1;
+      for (int rr = lane; rr < R; rr += 64)
+        if (act[rr] == 1) argmax_merge(bv, bi, fabs((double)P[rr * pitch + s]), r0 + rr);
+      wave_argmax(bv, bi);
+      const int buf = s & 1;
+      Slot* sl = slots + (size_t)buf * G;
+      U* srow = reinterpret_cast<U*>(slotrows) + (size_t)buf * G * w;
+      if (lane == 0) {
+        st_agent(reinterpret_cast<unsigned long long*>(&sl[g].v),
+                 (unsigned long long)__double_as_longlong(bv));
+        st_agent(&sl[g].row, bi);
+      }
+      if (bi >= 0)
+        for (int q = lane; q < w; q += 64) st_agent(&srow[(size_t)g * w + q], B::to(P[(bi - r0) * pitch + q]));
+      __builtin_amdgcn_s_waitcnt(0);  // slot stores performed before the counter moves
+      int timeout = 0;
+      if (lane == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (unsigned)(s + 1) * (unsigned)G;
+        long long spins = 0;
+        while (ld_agent(bar) < target) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            timeout = 1;
+            break;
+          }
+        }
+      }
+      timeout = __shfl(timeout, 0, 64);
+      bv = -1.0;
+      bi = -1;
+      if (!timeout) {
+        for (int t = lane; t < G; t += 64) {
+          const double v = __longlong_as_double(
+              (long long)ld_agent(reinterpret_cast<const unsigned long long*>(&sl[t].v)));
+          argmax_merge(bv, bi, v, ld_agent(&sl[t].row));
+        }
+        wave_argmax(bv, bi);
+      }
+      if (timeout) {
+        if (lane == 0) s_stop = 2;
+      } else if (bi < 0 || bv == 0.0) {
+        if (lane == 0) s_stop = 1;
+      } else {
+        const int owner = (int)(bi / rows_per_wg);
+        for (int q = lane; q < w; q += 64) prow[q] = B::from(ld_agent(&srow[(size_t)owner * w + q]));
+        if (lane == 0) {
+          s_val = bv;
+          s_row = bi;
+          if (owner == g) {
+            act[bi - r0] = 2;
+            pos[bi] = zcol + s;
+          }
+          if (g == 0) order[zcol + s] = (int)bi;
         }
       }
     }
     __syncthreads();
-    fence_acquire_agent();
-    if (s_timeout) {
-      if (tid == 0) {
-        ctrl->status = ST_ERR_HIP;
-        ctrl->done = 1;
+    if (s_stop) {
+      if (s_stop == 2) {
+        if (tid == 0) {
+          ctrl->status = ST_ERR_HIP;
+          ctrl->done = 1;
+        }
+        return;
       }
-      return;
-    }
-    bv = -1.0;
-    bi = -1;
-    for (int t = tid; t < G; t += 256) argmax_merge(bv, bi, sl[t].v, sl[t].row);
-    wave_argmax(bv, bi);
-    if (lane == 0) {
-      red_v[wave] = bv;
-      red_i[wave] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int i = 1; i < 4; ++i) argmax_merge(bv, bi, red_v[i], red_i[i]);
-      s_val = bv;
-      s_row = bi;
-    }
-    __syncthreads();
-    const long long prow_idx = s_row;
-    if (prow_idx < 0 || s_val == 0.0) {
-      deficient = true;
       steps = s;
       break;
     }
-    const int owner = (int)(prow_idx / rows_per_wg);
-    for (int q = tid; q < w; q += 256) prow[q] = srow[(size_t)owner * w + q];
-    if (tid == 0) {
-      if (owner == g) {
-        act[prow_idx - r0] = 2;
-        pos[prow_idx] = zcol + s;
-      }
-      if (g == 0) order[zcol + s] = (int)prow_idx;
-    }
-    __syncthreads();
     const TF d = prow[s];
-    for (int rr = tid; rr < R; rr += 256)
-      if (act[rr] == 1) {
-        const TF l = P[rr * w + s] / d;
-        lmul[rr] = l;
-        P[rr * w + s] = l;
-      }
-    __syncthreads();
-    const int nq = w - s - 1;
-    if (nq > 0)
-      for (int i = tid; i < R * nq; i += 256) {
-        const int rr = i / nq, q = s + 1 + i % nq;
-        if (act[rr] == 1) P[rr * w + q] -= lmul[rr] * prow[q];
-      }
+    for (int rr = tid; rr < R; rr += 256) {
+      if (act[rr] != 1) continue;
+      TF* row = P + rr * pitch;
+      const TF l = row[s] / d;
+      row[s] = l;
+      for (int q = s + 1; q < w; ++q) row[q] -= l * prow[q];
+    }
     __syncthreads();
   }
   for (int i = tid; i < R * w; i += 256) {
     const int rr = i / w, q = i % w;
-    if (act[rr] != 0) Z[(r0 + rr) * ldz + zcol + q] = P[i];
+    if (act[rr] != 0) Z[(r0 + rr) * ldz + zcol + q] = P[rr * pitch + q];
   }
   if (g == 0 && tid == 0) {
-    if (deficient) {
+    if (steps < f) {
       ctrl->k = zcol + steps;
       ctrl->status = ST_RANK_DEFICIENT;
       ctrl->done = 1;
