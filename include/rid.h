@@ -134,8 +134,8 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
  * event objects are created on first use and reused).  rid_profile_stop()
  * waits for the recorded events and returns, per kernel class, the summed
  * elapsed milliseconds and the number of launches; it also ends recording.
- * Classes: 0 sketch, 1 sketch reduction, 2 U2 triangular solve,
- * 3 Schur update, 4 panel LUPP, 5 interpolation solve.  Process-wide state:
+ * Classes: 0 sketch, 1 sketch reduction, 2 U2 = L1^{-1} (P Y)(top),
+ * 3 Schur update, 4 panel LUPP, 5 interpolation matrix, 6 update of L1^{-1}.  Process-wide state:
  * not for concurrent use from several host threads.
  */
 int rid_profile_start(void);

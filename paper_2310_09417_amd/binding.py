@@ -101,7 +101,7 @@ def rid_debug_sketch(A, m, n, lda, c0, w, cfg, Yt, ldy, work, work_bytes, stream
                                           work_bytes, stream))
 
 
-KERNEL_CLASSES = ("sketch", "sketch_reduce", "trsm_u2", "schur", "panel_lupp", "tsolve")
+KERNEL_CLASSES = ("sketch", "sketch_reduce", "u2", "schur", "panel_lupp", "tgemm", "linv_update")
 
 
 def rid_profile_start() -> int:

@@ -49,7 +49,7 @@ DeviceInfo device_info() {
 inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
 
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
-enum KClass { KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_OTHER, KC_N };
+enum KClass { KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_N };
 
 struct Profiler {
   bool on = false;
@@ -94,10 +94,25 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   g.wp = g.mt * 16;
   g.kc = dt == RID_F64 ? 32 : 64;
   g.ncolg = ceil_div(n, 256);
-  const int64_t target = 4 * (int64_t)cu;
-  int64_t ns = std::max<int64_t>(1, ceil_div(target, g.ncolg));
-  ns = std::min<int64_t>(ns, ceil_div(m, g.kc));
-  g.rows_per_split = ceil_div(ceil_div(m, ns), g.kc) * g.kc;
+  // One resident workgroup per CU (the kernel holds ~440 registers per
+  // lane): pick the number of row splits whose workgroup count fills the
+  // last round best, between ~2 and ~8 rounds, preferring fewer splits.
+  const int64_t maxsplit = ceil_div(m, g.kc);
+  const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(2 * cu, g.ncolg)));
+  const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(maxsplit, ceil_div(8 * cu, g.ncolg)));
+  double best = -1.0;
+  int64_t best_ns = lo;
+  for (int64_t ns = lo; ns <= hi; ++ns) {
+    const int64_t rps = ceil_div(ceil_div(m, ns), g.kc) * g.kc;
+    const int64_t real_ns = ceil_div(m, rps);
+    const int64_t items = g.ncolg * real_ns;
+    const double eff = (double)items / (double)(ceil_div(items, cu) * cu);
+    if (eff > best + 1e-3) {
+      best = eff;
+      best_ns = ns;
+    }
+  }
+  g.rows_per_split = ceil_div(ceil_div(m, best_ns), g.kc) * g.kc;
   g.nsplit = ceil_div(m, g.rows_per_split);
   return g;
 }
@@ -106,7 +121,7 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
 struct Plan {
   int64_t m = 0, n = 0, kcap = 0, wmax = 0;
   rid_dtype dt = RID_F64;
-  int64_t ldz = 0, ldu = 0;
+  int64_t ldz = 0, ldu = 0, ldl = 0;
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
   size_t lupp_lds = 0;
@@ -115,7 +130,7 @@ struct Plan {
   int64_t schur_wgs = 0;
   // offsets
   size_t o_ctrl, o_bars, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
-      o_slotrows, o_nonfinite, total;
+      o_slotrows, o_nonfinite, o_linv, o_mtmp, total;
 };
 
 bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, Plan& P) {
@@ -130,6 +145,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, P
   const size_t es = esize(dt);
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
   P.ldu = (int64_t)align_up((size_t)kcap, 16);
+  P.ldl = (int64_t)align_up((size_t)kcap, 64);
   // panel factorisation: one workgroup per CU at most, at least 16 rows each
   P.lupp_g = (int)std::max<int64_t>(1, std::min<int64_t>(di.cu, ceil_div(n, 16)));
   P.lupp_rows = (int)ceil_div(n, P.lupp_g);
@@ -165,6 +181,8 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, P
   P.o_norm = take((size_t)P.schur_wgs * 8);
   P.o_slots = take((size_t)2 * P.lupp_g * sizeof(Slot));
   P.o_slotrows = take((size_t)2 * P.lupp_g * wmax * es);
+  P.o_linv = take((size_t)kcap * P.ldl * es);
+  P.o_mtmp = take((size_t)wmax * P.ldl * es);
   P.total = o;
   return true;
 }
@@ -193,6 +211,8 @@ struct Ws {
   double* norm;
   Slot* slots;
   void* slotrows;
+  void* linv;
+  void* mtmp;
 };
 
 Ws carve(const Plan& P, void* work) {
@@ -211,6 +231,8 @@ Ws carve(const Plan& P, void* work) {
   w.norm = reinterpret_cast<double*>(b + P.o_norm);
   w.slots = reinterpret_cast<Slot*>(b + P.o_slots);
   w.slotrows = b + P.o_slotrows;
+  w.linv = b + P.o_linv;
+  w.mtmp = b + P.o_mtmp;
   return w;
 }
 
@@ -297,14 +319,11 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
 // ---- block update: U2 (triangular solve) then S (Schur GEMM) --------------
 template <typename TF>
 int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, hipStream_t st) {
-  const size_t lds = (size_t)k * sizeof(TF);
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_trsm_u2<TF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds) != hipSuccess)
-    return RID_ERR_HIP;
   long pm = prof_begin(KC_TRSM, st);
-  hipLaunchKernelGGL(k_trsm_u2<TF>, dim3(w), dim3(256), lds, st, static_cast<TF*>(W.z), P.ldz,
-                     W.order, k, zcol, w, static_cast<TF*>(W.u2t), P.ldu, W.ctrl);
+  hipLaunchKernelGGL(k_u2<TF>, dim3((unsigned)ceil_div(k, 16), (unsigned)ceil_div(w, 64)),
+                     dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz, W.order, k, zcol, w,
+                     static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
+                     W.ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   pm = prof_begin(KC_SCHUR, st);
@@ -373,10 +392,40 @@ int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, boo
   return e == hipSuccess ? RID_OK : RID_ERR_HIP;
 }
 
+// Linv grows by the block row of the pivots just taken at k0 (at most f;
+// the kernels read the actual count from the control block).
+template <typename TF>
+int linv_update_t(const Plan& P, const Ws& W, int k0, int f, hipStream_t st) {
+  const long pm = prof_begin(KC_LINV, st);
+  const size_t lds = (size_t)f * (f + 1) * sizeof(TF);
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_linv_diag<TF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return RID_ERR_HIP;
+  hipLaunchKernelGGL(k_linv_diag<TF>, dim3(1), dim3(128), lds, st, static_cast<const TF*>(W.z),
+                     P.ldz, W.order, k0, static_cast<TF*>(W.linv), P.ldl, W.ctrl);
+  RID_LAUNCH_CHECK();
+  if (k0 > 0) {
+    dim3 grid((unsigned)ceil_div(f, 16), (unsigned)ceil_div(k0, 64));
+    hipLaunchKernelGGL(k_linv_b1<TF>, grid, dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz,
+                       W.order, k0, static_cast<const TF*>(W.linv), P.ldl,
+                       static_cast<TF*>(W.mtmp), W.ctrl);
+    RID_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_linv_b2<TF>, grid, dim3(256), 0, st, static_cast<const TF*>(W.mtmp), k0,
+                       static_cast<TF*>(W.linv), P.ldl, W.ctrl);
+    RID_LAUNCH_CHECK();
+  }
+  prof_end(pm, st);
+  return RID_OK;
+}
+
 int panel(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
           hipStream_t st) {
-  return P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, bar_idx, stop_full, st)
-                         : panel_t<float>(P, W, zcol, w, f, bar_idx, stop_full, st);
+  int rc = P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, bar_idx, stop_full, st)
+                           : panel_t<float>(P, W, zcol, w, f, bar_idx, stop_full, st);
+  if (rc != RID_OK) return rc;
+  return P.dt == RID_F64 ? linv_update_t<double>(P, W, zcol, f, st)
+                         : linv_update_t<float>(P, W, zcol, f, st);
 }
 
 // ---- interpolation matrix and outputs --------------------------------------
@@ -385,12 +434,12 @@ int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32
              double* err_est, int32_t* status, hipStream_t st) {
   hipLaunchKernelGGL(k_nonpiv, dim3(1), dim3(1024), 0, st, W.pos, P.n, W.nonpiv);
   RID_LAUNCH_CHECK();
-  const int nblk = (int)ceil_div(P.kcap, 64);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(P.n, 64));
-  for (int beta = nblk - 1; beta >= 0; --beta) {
+  {
     const long pm = prof_begin(KC_TSOLVE, st);
-    hipLaunchKernelGGL(k_tsolve<TF>, dim3(grid), dim3(256), 0, st,
-                       static_cast<const TF*>(W.z), P.ldz, W.order, W.nonpiv, P.n, beta,
+    dim3 grid((unsigned)std::max<int64_t>(1, ceil_div(P.n, 64)),
+              (unsigned)std::max<int64_t>(1, ceil_div(P.kcap, 64)));
+    hipLaunchKernelGGL(k_tgemm<TF>, grid, dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz,
+                       W.nonpiv, P.n, static_cast<const TF*>(W.linv), P.ldl,
                        static_cast<TF*>(T), ldt, W.ctrl);
     prof_end(pm, st);
     RID_LAUNCH_CHECK();
@@ -412,6 +461,10 @@ int init(const Plan& P, const Ws& W, hipStream_t st) {
   const int64_t cnt = std::max<int64_t>(P.n, P.nbars);
   hipLaunchKernelGGL(k_init, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, W.ctrl, W.pos,
                      P.n, W.bars, P.nbars, W.nonfinite);
+  RID_LAUNCH_CHECK();
+  const int64_t words = P.kcap * P.ldl * (int64_t)esize(P.dt) / 4;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, ceil_div(words, 256))), dim3(256),
+                     0, st, static_cast<unsigned int*>(W.linv), words);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }

@@ -266,64 +266,6 @@ __global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int
 }
 
 // ---------------------------------------------------------------------------
-// U2 = L1^{-1} (P Y)(0:k, block): one workgroup per right-hand side column.
-// L1 is read from the pivot rows of Z through order[].  Blocked forward
-// substitution: wave 0 solves each 64 x 64 diagonal block from registers
-// (lane i holds row i of the block), then all threads update the rows below.
-// Results go to U2T (w x ldu, column-major U2) and back into the pivot rows.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float readlane_f(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double readlane_f(double v, int l) {
-  long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-template <typename TF>
-__global__ __launch_bounds__(256) void k_trsm_u2(TF* __restrict__ Z, int64_t ldz,
-                                                 const int* __restrict__ order, int k, int zcol,
-                                                 int w, TF* __restrict__ U2T, int64_t ldu,
-                                                 const Ctrl* ctrl) {
-  if (ctrl->done) return;
-  extern __shared__ unsigned char smem_raw[];
-  TF* x = reinterpret_cast<TF*>(smem_raw);
-  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-  for (int s = tid; s < k; s += 256) x[s] = Z[(int64_t)order[s] * ldz + zcol + c];
-  __syncthreads();
-  for (int s0 = 0; s0 < k; s0 += 64) {
-    const int nb = (k - s0 < 64) ? k - s0 : 64;
-    if (tid < 64) {
-      TF lrow[64];
-      const TF* src = Z + (int64_t)order[s0 + (lane < nb ? lane : 0)] * ldz + s0;
-#pragma unroll
-      for (int j = 0; j < 64; ++j) lrow[j] = (lane < nb && j < lane) ? src[j] : TF(0);
-      TF xi = lane < nb ? x[s0 + lane] : TF(0);
-#pragma unroll
-      for (int j = 0; j < 63; ++j) {
-        TF xj = readlane_f(xi, j);
-        if (lane > j) xi -= lrow[j] * xj;
-      }
-      if (lane < nb) x[s0 + lane] = xi;
-    }
-    __syncthreads();
-    for (int s2 = s0 + nb + tid; s2 < k; s2 += 256) {
-      const TF* lr = Z + (int64_t)order[s2] * ldz + s0;
-      TF acc = TF(0);
-      for (int j = 0; j < nb; ++j) acc += lr[j] * x[s0 + j];
-      x[s2] -= acc;
-    }
-    __syncthreads();
-  }
-  for (int s = tid; s < k; s += 256) {
-    U2T[(int64_t)c * ldu + s] = x[s];
-    Z[(int64_t)order[s] * ldz + zcol + c] = x[s];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Schur block S = (P Y)(non-pivots, block) - L2 U2 (MFMA, K = k), written in
 // place for every non-pivot row; with `want_norm` each workgroup also leaves
 // its FP64 sum of S^2 in normpart[blockIdx.x].  Each wave owns 16 rows and
@@ -648,72 +590,275 @@ __global__ __launch_bounds__(1024) void k_nonpiv(const int* __restrict__ pos, in
 }
 
 // ---------------------------------------------------------------------------
-// Interpolation matrix T = L1^{-T} L2^T, one 64-row block [s0, s1) of T per
-// launch, launched from the last block to the first.  Each workgroup owns 64
-// non-skeleton candidates (columns of T):
-//   acc(s, q) = L2(q, s) - sum_{s' >= s1} L1(s', s) T(s', q)     (MFMA)
-// then back substitution with the 64 x 64 diagonal block of L1 in LDS.
+// Products with the inverse of L1.  Linv (kcap x ldl, row-major, zero above
+// the diagonal) holds L1^{-1} for the pivots taken so far; it grows by one
+// block row per panel:
+//   [L1 0; L21 L22]^{-1} = [L1^{-1} 0; -L22^{-1} L21 L1^{-1}  L22^{-1}].
+// With it the triangular solves of the method become MFMA products:
+//   U2 = L1^{-1} (P Y)(top)            (block update, before the Schur GEMM)
+//   T^T = L2 L1^{-1}                   (interpolation matrix, at the end).
+// All of them use one wave-level tile routine: a wave accumulates a 16 x 64
+// tile C(i, j) += sum_p A(i, p) B(p, j) over p in [kb, ke).  Lane l holds A
+// row l%16 and loads 4 consecutive p of it; for each of those p it loads 4
+// consecutive columns of the B row, which feed 4 MFMAs (MFMA q, column j of
+// its output covers tile column 4 j + q).  FP32 accumulators are folded into
+// FP64 every 64 values of p.
 // ---------------------------------------------------------------------------
 template <typename TF>
-__global__ __launch_bounds__(256) void k_tsolve(const TF* __restrict__ Z, int64_t ldz,
-                                                const int* __restrict__ order,
-                                                const int* __restrict__ nonpiv, int64_t n,
-                                                int beta, TF* __restrict__ T, int64_t ldt,
-                                                const Ctrl* ctrl) {
-  if (ctrl->status < 0) return;
-  const int k = ctrl->k;
-  const int s0 = beta * 64;
-  if (s0 >= k) return;
-  const int s1 = (s0 + 64 < k) ? s0 + 64 : k, nb = s1 - s0;
-  const int64_t nn = n - k;
-  const int64_t q0 = (int64_t)blockIdx.x * 64;
-  if (q0 >= nn) return;
-  using M = Mfma<TF>;
-  using acc_t = typename M::acc_t;
-  __shared__ TF xs[64][65];
-  __shared__ TF Ld[64][65];
-  __shared__ int rq[64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid < 64) rq[tid] = (q0 + tid < nn) ? nonpiv[q0 + tid] : -1;
-  for (int idx = tid; idx < nb * nb; idx += 256) {
-    const int a = idx / nb, b = idx % nb;
-    Ld[a][b] = (b < a) ? Z[(int64_t)order[s0 + a] * ldz + s0 + b] : TF(0);
+__device__ __forceinline__ void ld4_masked(const TF* p, int e0, int lim, TF out[4]) {
+  // entries p[0..3] with index e0+e < lim; one 16-byte-aligned vector access
+  // when all four are present and the address allows it
+  if (e0 + 3 < lim && (reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+    if (sizeof(TF) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+      const double2 v0 = *reinterpret_cast<const double2*>(p);
+      const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+      out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+    }
+    return;
   }
-  acc_t acc[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = M::zero();
-  const int irow = wave * 16 + (lane & 15);
-  for (int s2 = s1; s2 < k; s2 += 4) {
-    const int kidx = s2 + (lane >> 4);
-    const TF a = (kidx < k && irow < nb) ? Z[(int64_t)order[kidx] * ldz + s0 + irow] : TF(0);
+  for (int e = 0; e < 4; ++e) out[e] = (e0 + e < lim) ? p[e] : TF(0);
+}
+
+template <typename TF, typename BRow>
+__device__ __forceinline__ void wave_tile(const TF* arow, BRow brow, int kb, int ke, int bcols,
+                                          typename Mfma<TF>::acc_t acc[4],
+                                          double acc64[4][4]) {
+  using M = Mfma<TF>;
+  const int lane = threadIdx.x & 63;
+  const int bc = 4 * (lane & 15);
+  int chunk = 0;
+  for (int p0 = kb & ~15; p0 < ke; p0 += 16, ++chunk) {
+    const int pa = p0 + 4 * (lane >> 4);
+    TF a4[4];
+    if (arow && pa >= kb && pa + 3 < ke) {
+      ld4_masked(arow + pa, 0, 4, a4);
+    } else {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t qj = q0 + t * 16 + (lane & 15);
-      const TF b = (kidx < k && qj < nn) ? T[(int64_t)kidx * ldt + qj] : TF(0);
-      acc[t] = M::op(a, b, acc[t]);
+      for (int e = 0; e < 4; ++e) a4[e] = (arow && pa + e >= kb && pa + e < ke) ? arow[pa + e] : TF(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int pp = pa + j;
+      TF b4[4] = {TF(0), TF(0), TF(0), TF(0)};
+      if (pp >= kb && pp < ke) {
+        const TF* br = brow(pp);
+        if (br) ld4_masked(br + bc, bc, bcols, b4);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = M::op(a4[j], b4[q], acc[q]);
+    }
+    if (sizeof(TF) == 4 && (chunk & 3) == 3) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[q][r] += (double)acc[q][r];
+        acc[q] = M::zero();
+      }
     }
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[q][r] += (double)acc[q][r];
+    acc[q] = M::zero();
+  }
+}
+
+// The four waves of a workgroup split [kb, ke) and their 16 x 64 partial
+// tiles are summed (fixed order) into red (LDS, 16 x 64 doubles) by wave 0's
+// lanes; returns with red complete after a barrier.
+template <typename TF, typename BRow>
+__device__ __forceinline__ void wg_tile_ksplit(const TF* arow, BRow brow, int kb, int ke, int bcols,
+                                               double* red) {
+  using M = Mfma<TF>;
+  typename M::acc_t acc[4];
+  double acc64[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[q] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[q][r] = 0.0;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // split on 16-aligned boundaries
+  const int kb16 = kb & ~15;
+  const int nchunks = (ke - kb16 + 15) / 16;
+  const int per = (nchunks + 3) / 4;
+  const int c0 = wave * per, c1 = (c0 + per < nchunks) ? c0 + per : nchunks;
+  if (c0 < c1) {
+    const int lo = (kb16 + 16 * c0 > kb) ? kb16 + 16 * c0 : kb;
+    const int hi = (kb16 + 16 * c1 < ke) ? kb16 + 16 * c1 : ke;
+    wave_tile<TF>(arow, brow, lo, hi, bcols, acc, acc64);
+  }
+  // deterministic reduction: wave order 0,1,2,3
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = M::row(lane, r), j = 4 * (lane & 15) + q;
+          if (wv == 0) red[i * 64 + j] = acc64[q][r];
+          else red[i * 64 + j] += acc64[q][r];
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// U2 = L1^{-1} (P Y)(0:k, block) for the w block columns starting at zcol.
+// Grid (ceil(k/16), ceil(w/64)); output U2T (w x ldu, column-major U2).
+template <typename TF>
+__global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ Z, int64_t ldz,
+                                            const int* __restrict__ order, int k, int zcol, int w,
+                                            const TF* __restrict__ Linv, int64_t ldl,
+                                            TF* __restrict__ U2T, int64_t ldu, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  __shared__ double red[16 * 64];
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 64;
+  const int lane = threadIdx.x & 63;
+  const int i = i0 + (lane & 15);
+  const TF* arow = (i < k) ? Linv + (int64_t)i * ldl : nullptr;
+  const int bcols = (w - j0 < 64) ? w - j0 : 64;
+  auto brow = [&](int p) -> const TF* { return Z + (int64_t)order[p] * ldz + zcol + j0; };
+  const int ke = (i0 + 16 < k) ? i0 + 16 : k;  // lower triangular: p <= i
+  wg_tile_ksplit<TF>(arow, brow, 0, ke, bcols, red);
+  for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+    const int ii = t % 16, jj = t / 16;
+    if (i0 + ii < k && j0 + jj < w) U2T[(int64_t)(j0 + jj) * ldu + i0 + ii] = (TF)red[ii * 64 + jj];
+  }
+}
+
+// Diagonal block of Linv for the f_act pivots of the panel at k0:
+// Linv[k0:k0+f, k0:k0+f] = L22^{-1} (one workgroup; column j solved by thread
+// j).  f_act = ctrl->k - k0 (0 when the panel did not run).
+template <typename TF>
+__global__ __launch_bounds__(128) void k_linv_diag(const TF* __restrict__ Z, int64_t ldz,
+                                                   const int* __restrict__ order, int k0,
+                                                   TF* __restrict__ Linv, int64_t ldl,
+                                                   const Ctrl* ctrl) {
+  if (ctrl->status < 0) return;
+  const int f = ctrl->k - k0;
+  if (f <= 0) return;
+  extern __shared__ unsigned char smem_raw[];
+  TF* L = reinterpret_cast<TF*>(smem_raw);  // f x (f+1)
+  const int pitch = f + 1;
+  for (int t = threadIdx.x; t < f * f; t += blockDim.x) {
+    const int a = t / f, b = t % f;
+    L[a * pitch + b] = (b < a) ? Z[(int64_t)order[k0 + a] * ldz + k0 + b] : TF(0);
+  }
   __syncthreads();
+  const int j = threadIdx.x;
+  if (j < f) {
+    // column j of X = L22^{-1}: X[j][j] = 1, X[i][j] = -sum_{j<=p<i} L[i][p] X[p][j]
+    TF* out = Linv + (int64_t)k0 * ldl + k0;
+    out[(int64_t)j * ldl + j] = TF(1);
+    for (int i = j + 1; i < f; ++i) {
+      TF acc = L[i * pitch + j];
+      for (int p = j + 1; p < i; ++p) acc += L[i * pitch + p] * out[(int64_t)p * ldl + j];
+      out[(int64_t)i * ldl + j] = -acc;
+    }
+  }
+}
+
+// Mtmp = L21 L1^{-1}_old: rows i < f_act (new pivots), columns s < k0.
+// Grid (ceil(fmax/16), ceil(k0/64)).
+template <typename TF>
+__global__ __launch_bounds__(256) void k_linv_b1(const TF* __restrict__ Z, int64_t ldz,
+                                                 const int* __restrict__ order, int k0,
+                                                 const TF* __restrict__ Linv, int64_t ldl,
+                                                 TF* __restrict__ Mtmp, const Ctrl* ctrl) {
+  if (ctrl->status < 0) return;
+  const int f = ctrl->k - k0;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 64;
+  if (f <= 0 || i0 >= f) return;
+  __shared__ double red[16 * 64];
+  const int lane = threadIdx.x & 63;
+  const int i = i0 + (lane & 15);
+  const TF* arow = (i < f) ? Z + (int64_t)order[k0 + i] * ldz : nullptr;
+  const int bcols = (k0 - j0 < 64) ? k0 - j0 : 64;
+  auto brow = [&](int p) -> const TF* { return Linv + (int64_t)p * ldl + j0; };
+  // Linv_old[p][s] = 0 for p < s: p runs over [j0, k0)
+  wg_tile_ksplit<TF>(arow, brow, j0, k0, bcols, red);
+  for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+    const int ii = t / 64, jj = t % 64;
+    if (i0 + ii < f && j0 + jj < k0) Mtmp[(int64_t)(i0 + ii) * ldl + j0 + jj] = (TF)red[ii * 64 + jj];
+  }
+}
+
+// Linv[k0+i, 0:k0] = -L22^{-1} Mtmp.  Grid (ceil(fmax/16), ceil(k0/64)).
+template <typename TF>
+__global__ __launch_bounds__(256) void k_linv_b2(const TF* __restrict__ Mtmp, int k0,
+                                                 TF* __restrict__ Linv, int64_t ldl,
+                                                 const Ctrl* ctrl) {
+  if (ctrl->status < 0) return;
+  const int f = ctrl->k - k0;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 64;
+  if (f <= 0 || i0 >= f) return;
+  __shared__ double red[16 * 64];
+  const int lane = threadIdx.x & 63;
+  const int i = i0 + (lane & 15);
+  const TF* arow = (i < f) ? Linv + (int64_t)(k0 + i) * ldl + k0 : nullptr;
+  const int bcols = (k0 - j0 < 64) ? k0 - j0 : 64;
+  auto brow = [&](int p) -> const TF* { return Mtmp + (int64_t)p * ldl + j0; };
+  const int ke = (i0 + 16 < f) ? i0 + 16 : f;  // L22^{-1} is lower triangular
+  wg_tile_ksplit<TF>(arow, brow, 0, ke, bcols, red);
+  for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+    const int ii = t / 64, jj = t % 64;
+    if (i0 + ii < f && j0 + jj < k0)
+      Linv[(int64_t)(k0 + i0 + ii) * ldl + j0 + jj] = (TF)(-red[ii * 64 + jj]);
+  }
+}
+
+// T(s, q) = sum_{p >= s} L2(q, p) L1^{-1}(p, s): T^T = L2 L1^{-1}.  Each wave
+// owns 16 candidates (rows of T^T) and the workgroup a 64 x 64 tile.
+// Grid (ceil(n/64), ceil(kcap/64)); tiles beyond the final k or n-k exit.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t ldz,
+                                               const int* __restrict__ nonpiv, int64_t n,
+                                               const TF* __restrict__ Linv, int64_t ldl,
+                                               TF* __restrict__ T, int64_t ldt, const Ctrl* ctrl) {
+  if (ctrl->status < 0) return;
+  const int k = ctrl->k;
+  const int64_t nn = n - k;
+  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  if (q0 >= nn || j0 >= k) return;
+  using M = Mfma<TF>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = q0 + wave * 16 + (lane & 15);
+  const TF* arow = (q < nn) ? Z + (int64_t)nonpiv[q] * ldz : nullptr;
+  const int bcols = (k - j0 < 64) ? k - j0 : 64;
+  auto brow = [&](int p) -> const TF* { return Linv + (int64_t)p * ldl + j0; };
+  typename M::acc_t acc[4];
+  double acc64[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    acc[t] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
+  }
+  // Linv[p][s] = 0 for p < s: p runs over [j0, k)
+  wave_tile<TF>(arow, brow, j0, k, bcols, acc, acc64);
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = wave * 16 + M::row(lane, r), j = t * 16 + (lane & 15);
-      if (i < nb && rq[j] >= 0) xs[i][j] = Z[(int64_t)rq[j] * ldz + s0 + i] - acc[t][r];
+      const int64_t qq = q0 + wave * 16 + M::row(lane, r);
+      const int s = j0 + 4 * (lane & 15) + t;
+      if (qq < nn && s < k) T[(int64_t)s * ldt + qq] = (TF)acc64[t][r];
     }
-  __syncthreads();
-  if (tid < 64 && rq[tid] >= 0) {
-    for (int i = nb - 1; i >= 0; --i) {
-      TF v = xs[i][tid];
-      for (int a = i + 1; a < nb; ++a) v -= Ld[a][i] * xs[a][tid];
-      xs[i][tid] = v;
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < nb * 64; idx += 256) {
-    const int i = idx / 64, j = idx % 64;
-    if (q0 + j < nn) T[(int64_t)(s0 + i) * ldt + q0 + j] = xs[i][j];
-  }
+}
+
+// Zero fill (graph-safe replacement for a memset).
+__global__ void k_zero(unsigned int* __restrict__ p, int64_t words) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < words;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = 0u;
 }
 
 // Final outputs: J (int64, pivot order), rank, estimate, status.
