@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-kmax", type=int, default=64,
                     help="rank cap of the bounded oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the decomposition is built and timed on a single "
@@ -121,6 +123,14 @@ def main():
                 raise RuntimeError(f"rid_lupp_adaptive -> {rc}")
 
         return run, (J, T, ko, eo, so), wb
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
 
     run32, out32, wb32 = make_run(A32, rid.RID_F32)
     for i in range(args.warmup):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librid.so")
-SOURCES = [os.path.join(CSRC, "rid_api.hip")]
+SOURCES = [os.path.join(CSRC, "rid_api.hip")]  # the library (the driver below links it)
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + [
     os.path.join(ROOT, "include", "rid.h")]
 
@@ -23,6 +23,24 @@ FLAGS = [
 ]
 
 
+NATIVE = os.path.join(HERE, "rid_bench_native")
+NATIVE_SRC = os.path.join(CSRC, "rid_bench_native.hip")
+
+
+def build_native(verbose: bool = False) -> str:
+    """Native profiling driver linked against librid.so (no Python)."""
+    tmp = NATIVE + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), "-o", tmp, NATIVE_SRC,
+           "-L", HERE, "-lrid", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.check_call(cmd)
+    os.replace(tmp, NATIVE)
+    return NATIVE
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB) and all(
             os.path.getmtime(LIB) >= os.path.getmtime(d) for d in DEPS):
@@ -33,6 +51,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_native(verbose)
     return LIB
 
 

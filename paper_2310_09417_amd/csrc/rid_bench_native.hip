@@ -1,0 +1,108 @@
+// Native driver for profiling the library without Python: runs, through the
+// C ABI, the sketch of one block and the whole adaptive decomposition on an
+// m x n FP32 matrix resident in HBM, plus one plain device copy of a known
+// size (the reference for hardware traffic counters).
+//
+// usage: rid_bench_native [m n b kmax iters]   (defaults 50000 20000 64 2048 3)
+// The matrix holds Gaussian entries produced by rid_debug_gaussian; traffic
+// and timing of the kernels do not depend on the values.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "../../include/rid.h"
+
+#define CHECK(x)                                                             \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) {                                                  \
+      std::fprintf(stderr, "%s:%d %s\n", __FILE__, __LINE__, hipGetErrorString(e_)); \
+      return 1;                                                              \
+    }                                                                        \
+  } while (0)
+
+__global__ void calib_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n4) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+int main(int argc, char** argv) {
+  const int64_t m = argc > 1 ? atoll(argv[1]) : 50000;
+  const int64_t n = argc > 2 ? atoll(argv[2]) : 20000;
+  const int64_t b = argc > 3 ? atoll(argv[3]) : 64;
+  const int64_t kmax = argc > 4 ? atoll(argv[4]) : 2048;
+  const int iters = argc > 5 ? atoi(argv[5]) : 3;
+  hipStream_t st;
+  CHECK(hipStreamCreate(&st));
+
+  // calibration copy: 1 GiB read, 1 GiB written
+  const size_t cbytes = (size_t)1 << 30;
+  float *csrc = nullptr, *cdst = nullptr;
+  CHECK(hipMalloc(&csrc, cbytes));
+  CHECK(hipMalloc(&cdst, cbytes));
+  CHECK(hipMemsetAsync(csrc, 0, cbytes, st));
+  hipLaunchKernelGGL(calib_copy, dim3(4096), dim3(256), 0, st, (const float4*)csrc, (float4*)cdst,
+                     cbytes / 16);
+  CHECK(hipStreamSynchronize(st));
+  CHECK(hipFree(csrc));
+  CHECK(hipFree(cdst));
+  std::printf("[native] calibration copy: %zu bytes read, %zu written\n", cbytes, cbytes);
+
+  float* A = nullptr;
+  CHECK(hipMalloc(&A, (size_t)m * n * sizeof(float)));
+  if (rid_debug_gaussian(7, 0, m, n, RID_F32, A, st) != RID_OK) return 2;
+  rid_config cfg{RID_F32, 1, 1};
+  const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
+  const size_t wb = rid_workspace_bytes(m, n, kmax, b, &cfg);
+  void* work = nullptr;
+  CHECK(hipMalloc(&work, wb));
+  float *Yt = nullptr, *T = nullptr;
+  int64_t* J = nullptr;
+  int32_t *ko = nullptr, *so = nullptr;
+  double* eo = nullptr;
+  CHECK(hipMalloc(&Yt, (size_t)n * b * sizeof(float)));
+  CHECK(hipMalloc(&T, (size_t)kcap * n * sizeof(float)));
+  CHECK(hipMalloc(&J, (size_t)kcap * sizeof(int64_t)));
+  CHECK(hipMalloc(&ko, 4));
+  CHECK(hipMalloc(&so, 4));
+  CHECK(hipMalloc(&eo, 8));
+  const size_t wbs = rid_workspace_bytes(m, n, b, b, &cfg);
+  void* works = nullptr;
+  CHECK(hipMalloc(&works, wbs));
+
+  for (int it = 0; it < iters; ++it) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (rid_debug_sketch(A, m, n, n, b, b, &cfg, Yt, b, works, wbs, st) != RID_OK) return 3;
+    CHECK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    if (rid_lupp_adaptive(A, m, n, n, b, 1e-6, kmax, &cfg, J, T, n, ko, eo, so, work, wb, st) !=
+        RID_OK)
+      return 4;
+    CHECK(hipStreamSynchronize(st));
+    auto t2 = std::chrono::steady_clock::now();
+    int32_t k = 0, s = 0;
+    double e = 0;
+    CHECK(hipMemcpy(&k, ko, 4, hipMemcpyDeviceToHost));
+    CHECK(hipMemcpy(&s, so, 4, hipMemcpyDeviceToHost));
+    CHECK(hipMemcpy(&e, eo, 8, hipMemcpyDeviceToHost));
+    std::printf("[native] iter %d: sketch block %.3f ms, adaptive %.3f ms, k=%d status=%s E=%.3e\n",
+                it, std::chrono::duration<double, std::milli>(t1 - t0).count(),
+                std::chrono::duration<double, std::milli>(t2 - t1).count(), k,
+                rid_status_string(s), e);
+  }
+  CHECK(hipFree(A));
+  CHECK(hipFree(work));
+  CHECK(hipFree(works));
+  CHECK(hipFree(Yt));
+  CHECK(hipFree(T));
+  CHECK(hipFree(J));
+  CHECK(hipFree(ko));
+  CHECK(hipFree(so));
+  CHECK(hipFree(eo));
+  std::printf("[native] done\n");
+  return 0;
+}
