@@ -356,7 +356,7 @@ int block_update(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, 
 
 int estimate(const Plan& P, const Ws& W, int w, double tol, int rel, int k, bool fixed,
              hipStream_t st) {
-  hipLaunchKernelGGL(k_estimate, dim3(1), dim3(1), 0, st, W.ctrl, W.norm, (int)P.schur_wgs, w,
+  hipLaunchKernelGGL(k_estimate, dim3(1), dim3(256), 0, st, W.ctrl, W.norm, (int)P.schur_wgs, w,
                      tol, rel, k, (int)P.kcap, fixed ? 1 : 0);
   RID_LAUNCH_CHECK();
   return RID_OK;
@@ -397,13 +397,15 @@ int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, boo
 template <typename TF>
 int linv_update_t(const Plan& P, const Ws& W, int k0, int f, hipStream_t st) {
   const long pm = prof_begin(KC_LINV, st);
-  const size_t lds = (size_t)f * (f + 1) * sizeof(TF);
+  const size_t lds1 = (size_t)f * (f + 1) * sizeof(TF);
+  const int x_in_lds = (2 * lds1 <= kMaxLds) ? 1 : 0;
+  const size_t lds = x_in_lds ? 2 * lds1 : lds1;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k_linv_diag<TF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds) != hipSuccess)
     return RID_ERR_HIP;
   hipLaunchKernelGGL(k_linv_diag<TF>, dim3(1), dim3(128), lds, st, static_cast<const TF*>(W.z),
-                     P.ldz, W.order, k0, static_cast<TF*>(W.linv), P.ldl, W.ctrl);
+                     P.ldz, W.order, k0, static_cast<TF*>(W.linv), P.ldl, W.ctrl, x_in_lds);
   RID_LAUNCH_CHECK();
   if (k0 > 0) {
     dim3 grid((unsigned)ceil_div(f, 16), (unsigned)ceil_div(k0, 64));

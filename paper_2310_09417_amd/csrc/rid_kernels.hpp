@@ -363,14 +363,23 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
   }
 }
 
-// Estimate and stopping test (one thread): E = sqrt(sum S^2) / sqrt(w) with
-// the partials summed in workgroup order.
-__global__ void k_estimate(Ctrl* ctrl, const double* __restrict__ normpart, int nparts, int w,
-                           double tol, int rel, int k, int kcap, int fixed_mode) {
+// Estimate and stopping test (one workgroup of 256): E = sqrt(sum S^2) /
+// sqrt(w); thread t sums partials t, t+256, ... in order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_estimate(Ctrl* ctrl, const double* __restrict__ normpart,
+                                                  int nparts, int w, double tol, int rel, int k,
+                                                  int kcap, int fixed_mode) {
   if (ctrl->done) return;
+  __shared__ double red[256];
   double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += normpart[i];
-  const double E = sqrt(s) / sqrt((double)w);
+  for (int i = threadIdx.x; i < nparts; i += 256) s += normpart[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double E = sqrt(red[0]) / sqrt((double)w);
   ctrl->E = E;
   if (fixed_mode) {
     ctrl->done = 1;
@@ -735,32 +744,44 @@ __global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ Z, int64_t ld
 
 // Diagonal block of Linv for the f_act pivots of the panel at k0:
 // Linv[k0:k0+f, k0:k0+f] = L22^{-1} (one workgroup; column j solved by thread
-// j).  f_act = ctrl->k - k0 (0 when the panel did not run).
+// j, with L22 and, when it fits, the result kept in LDS).  f_act = ctrl->k -
+// k0 (0 when the panel did not run).
 template <typename TF>
 __global__ __launch_bounds__(128) void k_linv_diag(const TF* __restrict__ Z, int64_t ldz,
                                                    const int* __restrict__ order, int k0,
                                                    TF* __restrict__ Linv, int64_t ldl,
-                                                   const Ctrl* ctrl) {
+                                                   const Ctrl* ctrl, int x_in_lds) {
   if (ctrl->status < 0) return;
   const int f = ctrl->k - k0;
   if (f <= 0) return;
   extern __shared__ unsigned char smem_raw[];
-  TF* L = reinterpret_cast<TF*>(smem_raw);  // f x (f+1)
   const int pitch = f + 1;
+  TF* L = reinterpret_cast<TF*>(smem_raw);  // f x pitch
+  TF* X = L + (size_t)f * pitch;              // f x pitch when x_in_lds
   for (int t = threadIdx.x; t < f * f; t += blockDim.x) {
     const int a = t / f, b = t % f;
     L[a * pitch + b] = (b < a) ? Z[(int64_t)order[k0 + a] * ldz + k0 + b] : TF(0);
   }
   __syncthreads();
   const int j = threadIdx.x;
+  TF* out = Linv + (int64_t)k0 * ldl + k0;
   if (j < f) {
-    // column j of X = L22^{-1}: X[j][j] = 1, X[i][j] = -sum_{j<=p<i} L[i][p] X[p][j]
-    TF* out = Linv + (int64_t)k0 * ldl + k0;
-    out[(int64_t)j * ldl + j] = TF(1);
-    for (int i = j + 1; i < f; ++i) {
-      TF acc = L[i * pitch + j];
-      for (int p = j + 1; p < i; ++p) acc += L[i * pitch + p] * out[(int64_t)p * ldl + j];
-      out[(int64_t)i * ldl + j] = -acc;
+    // column j of L22^{-1}: X[j][j] = 1, X[i][j] = -sum_{j<=p<i} L[i][p] X[p][j]
+    if (x_in_lds) {
+      X[j * pitch + j] = TF(1);
+      for (int i = j + 1; i < f; ++i) {
+        TF acc = L[i * pitch + j];
+        for (int p = j + 1; p < i; ++p) acc += L[i * pitch + p] * X[p * pitch + j];
+        X[i * pitch + j] = -acc;
+      }
+      for (int i = j; i < f; ++i) out[(int64_t)i * ldl + j] = X[i * pitch + j];
+    } else {
+      out[(int64_t)j * ldl + j] = TF(1);
+      for (int i = j + 1; i < f; ++i) {
+        TF acc = L[i * pitch + j];
+        for (int p = j + 1; p < i; ++p) acc += L[i * pitch + p] * out[(int64_t)p * ldl + j];
+        out[(int64_t)i * ldl + j] = -acc;
+      }
     }
   }
 }
