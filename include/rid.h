@@ -110,6 +110,36 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
                       size_t work_bytes, hipStream_t stream);
 
 /*
+ * Batched adaptive LUPP IDs of many independent blocks in one persistent
+ * launch (the batch extension named as future work in the paper's
+ * conclusions, applied to Alg. 1 per block).  Every array argument is a
+ * DEVICE array of length nblk:
+ *   A[i]  (device pointer, dtype)  block i, m[i] x n[i], row-major, ld lda[i]
+ *   kmax[i]  rank cap;  k_hint[i] (nullable array; entries <= 0 mean none):
+ *            width of the first factored block, e.g. a predicted rank, so
+ *            that the first pass can certify it; otherwise the first block
+ *            has b vectors (Alg. 1);
+ *   J[i]  (device pointer, int32, capacity min(kmax[i], m[i], n[i]))
+ *   T[i]  (device pointer, dtype, capacity min(kmax, m, n) rows of ldt[i])
+ *   k_out, err_est, status, passes (nullable): per-block results, with
+ *   passes[i] = number of sketch passes over block i.
+ *   order (nullable): processing order (a permutation of 0..nblk-1), e.g.
+ *   largest blocks first.
+ * Block i uses the Gaussian stream of seed cfg->seed + i.  b <= 32; every n[i]
+ * must be <= max_n <= 1024 (blocks outside the plan get status RID_ERR_ARG);
+ * ranks are capped at min(max_kmax, max_n).  Workspace:
+ * rid_batched_workspace_bytes(max_n, max_kmax, b, cfg).
+ */
+size_t rid_batched_workspace_bytes(int32_t max_n, int32_t max_kmax, int32_t b,
+                                   const rid_config* cfg);
+int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, const int32_t* m,
+                     const int32_t* n, int32_t b, double tol, const int32_t* kmax,
+                     const int32_t* k_hint, const rid_config* cfg, int32_t* const* J,
+                     void* const* T, const int64_t* ldt, int32_t* k_out, double* err_est,
+                     int32_t* status, int32_t* passes, const int32_t* order, int32_t max_n,
+                     int32_t max_kmax, void* work, size_t work_bytes, hipStream_t stream);
+
+/*
  * Test export: materialises the Gaussian embedding block
  *   out[c * m + i] = omega(c0 + c, i), 0 <= c < w, 0 <= i < m
  * in the given dtype (device buffer).  The decomposition never stores Omega;
@@ -135,7 +165,8 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
  * waits for the recorded events and returns, per kernel class, the summed
  * elapsed milliseconds and the number of launches; it also ends recording.
  * Classes: 0 sketch, 1 sketch reduction, 2 U2 = L1^{-1} (P Y)(top),
- * 3 Schur update, 4 panel LUPP, 5 interpolation matrix, 6 update of L1^{-1}.  Process-wide state:
+ * 3 Schur update, 4 panel LUPP, 5 interpolation matrix, 6 update of L1^{-1},
+ * 7 batched persistent kernel.  Process-wide state:
  * not for concurrent use from several host threads.
  */
 int rid_profile_start(void);

@@ -44,7 +44,7 @@ class _Result(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("err_est", ctypes.c_double),
                 ("status", ctypes.c_int32), ("nsteps", ctypes.c_int32),
                 ("min_gap", ctypes.c_double), ("min_gap_step", ctypes.c_int64),
-                ("fro_a", ctypes.c_double)]
+                ("fro_a", ctypes.c_double), ("robust_k", ctypes.c_int64)]
 
 
 _lib = None
@@ -68,6 +68,9 @@ def _load():
         lib.orc_rid_lupp.restype = cint
         lib.orc_lupp_factors.argtypes = [P, i64, i64, i64, i64, i64, u64, P, P, P]
         lib.orc_lupp_factors.restype = cint
+        lib.orc_rid_adaptive_first.argtypes = [P, i64, i64, i64, i64, i64, dbl, cint, i64, u64,
+                                               P, P, i64, P, i64, ctypes.POINTER(_Result)]
+        lib.orc_rid_adaptive_first.restype = cint
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = cint
         _lib = lib
@@ -122,6 +125,7 @@ class IDResult:
     min_gap: float = float("inf")
     min_gap_step: int = -1
     fro_a: float = 0.0
+    robust_k: int = 0       # leading pivots decided above the FP64 rounding floor
 
     def X(self, n: int) -> np.ndarray:
         """Column interpolation matrix (k x n) with X[:, J] = I."""
@@ -133,7 +137,7 @@ class IDResult:
         return X
 
 
-def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096) -> IDResult:
+def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0) -> IDResult:
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
@@ -142,13 +146,18 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096) -> IDResult:
     T = np.zeros((cap, n), dtype=np.float64)
     hist = np.zeros(hist_cap, dtype=np.float64)
     res = _Result()
-    lib.orc_rid_lupp(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
-                     _ptr(J), _ptr(T), n, _ptr(hist), hist_cap, ctypes.byref(res))
+    if first_w > 0:
+        lib.orc_rid_adaptive_first(_ptr(A), m, n, n, k_or_b, first_w, tol, 1 if rel else 0, kmax,
+                                   seed, _ptr(J), _ptr(T), n, _ptr(hist), hist_cap,
+                                   ctypes.byref(res))
+    else:
+        lib.orc_rid_lupp(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
+                         _ptr(J), _ptr(T), n, _ptr(hist), hist_cap, ctypes.byref(res))
     k = int(res.k)
     return IDResult(J=J[:k].copy(), T=T[:k, : n - k].copy(), k=k, err_est=float(res.err_est),
                     status=int(res.status), E_hist=hist[: res.nsteps].copy(),
                     min_gap=float(res.min_gap), min_gap_step=int(res.min_gap_step),
-                    fro_a=float(res.fro_a))
+                    fro_a=float(res.fro_a), robust_k=int(res.robust_k))
 
 
 def rid_fixed_rank(A, k: int, p: int, seed: int) -> IDResult:
@@ -156,9 +165,12 @@ def rid_fixed_rank(A, k: int, p: int, seed: int) -> IDResult:
     return _run(A, 0, k, p, 0.0, False, k, seed)
 
 
-def rid_adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True) -> IDResult:
-    """randLUPPadap (Alg. 1): blocks of b sketch vectors until E <= tol."""
-    return _run(A, 1, b, 0, tol, relative, kmax, seed)
+def rid_adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
+                 first_width: int = 0) -> IDResult:
+    """randLUPPadap (Alg. 1): blocks of b sketch vectors until E <= tol.
+    first_width > 0 makes the first factored block that wide (a rank known
+    or predicted beforehand); the rest of the method is unchanged."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed, first_w=first_width)
 
 
 def lupp_factors(A, l: int, k: int, seed: int):

@@ -161,6 +161,10 @@ typedef struct {
   double min_gap;     /* min over pivot steps of (|1st| - |2nd|) / |1st|        */
   int64_t min_gap_step;
   double fro_a;       /* ||A||_F                                                 */
+  int64_t robust_k;   /* leading pivots decided by more than the rounding floor: */
+                      /* (|1st| - |2nd|) > 64 u sqrt(s+1) max|Y| at every step   */
+                      /* s < robust_k; later ones may legitimately differ in     */
+                      /* any other correct evaluation order                      */
 } orc_result;
 
 /*
@@ -188,10 +192,34 @@ typedef struct {
  * row-major, ldt) with column q belonging to the q-th non-skeleton column in
  * ascending index; E history (up to hist_cap entries).
  */
+static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                         int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
+                         int64_t first_width, uint64_t seed, int64_t* J, double* T, int64_t ldt,
+                         double* E_hist, int64_t hist_cap, orc_result* res);
+
 int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                  int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                  uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                  int64_t hist_cap, orc_result* res) {
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, J, T, ldt,
+                       E_hist, hist_cap, res);
+}
+
+/* Adaptive variant whose first factored block has first_width vectors
+ * (instead of b), e.g. a rank predicted beforehand; the blocks after it have b
+ * vectors and the stopping rule is unchanged. */
+int orc_rid_adaptive_first(const double* A, int64_t m, int64_t n, int64_t lda, int64_t b,
+                           int64_t first_width, double tol, int tol_relative, int64_t kmax,
+                           uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
+                           int64_t hist_cap, orc_result* res) {
+  return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, J, T,
+                       ldt, E_hist, hist_cap, res);
+}
+
+static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                         int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
+                         int64_t first_width, uint64_t seed, int64_t* J, double* T, int64_t ldt,
+                         double* E_hist, int64_t hist_cap, orc_result* res) {
   memset(res, 0, sizeof(*res));
   res->err_est = -1.0;
   res->min_gap = INFINITY;
@@ -216,7 +244,8 @@ int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
       return ORC_ERR_ARG;
     }
     kcap = kmax < mn ? kmax : mn;
-    first_w = k_or_b < kcap ? k_or_b : kcap;
+    first_w = first_width > 0 ? first_width : k_or_b;
+    if (first_w > kcap) first_w = kcap;
     later_w = k_or_b;
   }
 
@@ -237,6 +266,8 @@ int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
 
   int64_t k = 0;        /* pivots taken so far */
   int64_t cnext = 0;    /* next unused sketch vector */
+  double ymax = 0.0;    /* largest |Y| entry drawn so far (scale of the rounding floor) */
+  res->robust_k = -1;
   double E = -1.0;
   int status = ORC_OK;
   int first = 1;
@@ -247,6 +278,8 @@ int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
     /* Draw the next block and apply the current row permutation (P Y^T). */
     orc_sketch(A, m, n, lda, seed, cnext, w, Ynew, n);
     cnext += w;
+    for (int64_t t = 0; t < w * n; ++t)
+      if (fabs(Ynew[t]) > ymax) ymax = fabs(Ynew[t]);
     for (int64_t r = 0; r < n; ++r)
       for (int64_t q = 0; q < w; ++q) Z[r * zc + k + q] = Ynew[q * n + perm[r]];
 
@@ -314,6 +347,8 @@ int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
           res->min_gap = gap;
           res->min_gap_step = s;
         }
+        const double floor_s = 64.0 * 0x1p-52 * sqrt((double)(s + 1)) * ymax;
+        if (res->robust_k < 0 && best - second <= floor_s) res->robust_k = s;
       }
       if (best == 0.0) {
         deficient = 1;
@@ -391,6 +426,7 @@ int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
   res->k = k;
   res->err_est = E;
   res->status = status;
+  if (res->robust_k < 0 || res->robust_k > k) res->robust_k = k;
   return status;
 }
 

@@ -12,5 +12,6 @@ from .binding import (  # noqa: F401
     RID_ERR_WORKSPACE, RID_F64, RID_F32, RidError, IDOutput, library, workspace_bytes,
     status_string, fixed_rank, adaptive, debug_gaussian, debug_sketch,
     rid_lupp_fixed_rank, rid_lupp_adaptive, rid_workspace_bytes, rid_debug_gaussian,
-    rid_debug_sketch, rid_status_string, rid_profile_start, rid_profile_stop, KERNEL_CLASSES)
+    rid_debug_sketch, rid_status_string, rid_profile_start, rid_profile_stop, KERNEL_CLASSES,
+    rid_batched_workspace_bytes, rid_lupp_batched, BatchPlan, BatchOutput, batched)
 from .flops import flops_id  # noqa: F401

@@ -58,6 +58,11 @@ def library() -> ctypes.CDLL:
         lib.rid_debug_gaussian.restype = i32
         lib.rid_debug_sketch.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, i64, P, sz, P]
         lib.rid_debug_sketch.restype = i32
+        lib.rid_batched_workspace_bytes.argtypes = [i32, i32, i32, cfgp]
+        lib.rid_batched_workspace_bytes.restype = sz
+        lib.rid_lupp_batched.argtypes = [i32, P, P, P, P, i32, dbl, P, P, cfgp, P, P, P, P, P, P,
+                                         P, P, i32, i32, P, sz, P]
+        lib.rid_lupp_batched.restype = i32
         lib.rid_profile_start.argtypes = []
         lib.rid_profile_start.restype = i32
         lib.rid_profile_stop.argtypes = [P, P, i32]
@@ -101,7 +106,20 @@ def rid_debug_sketch(A, m, n, lda, c0, w, cfg, Yt, ldy, work, work_bytes, stream
                                           work_bytes, stream))
 
 
-KERNEL_CLASSES = ("sketch", "sketch_reduce", "u2", "schur", "panel_lupp", "tgemm", "linv_update")
+def rid_batched_workspace_bytes(max_n, max_kmax, b, cfg: RidConfig) -> int:
+    return int(library().rid_batched_workspace_bytes(max_n, max_kmax, b, ctypes.byref(cfg)))
+
+
+def rid_lupp_batched(nblk, A, lda, m, n, b, tol, kmax, k_hint, cfg, J, T, ldt, k_out, err_est,
+                     status, passes, order, max_n, max_kmax, work, work_bytes, stream) -> int:
+    return int(library().rid_lupp_batched(nblk, A, lda, m, n, b, tol, kmax, k_hint,
+                                          ctypes.byref(cfg), J, T, ldt, k_out, err_est, status,
+                                          passes, order, max_n, max_kmax, work, work_bytes,
+                                          stream))
+
+
+KERNEL_CLASSES = ("sketch", "sketch_reduce", "u2", "schur", "panel_lupp", "tgemm", "linv_update",
+                  "batched")
 
 
 def rid_profile_start() -> int:
@@ -248,3 +266,90 @@ def debug_sketch(A, seed: int, c0: int, w: int):
                             work.data_ptr(), work.numel(), _stream_ptr()), "rid_debug_sketch")
     torch.cuda.current_stream().synchronize()
     return Yt
+
+
+@dataclass
+class BatchOutput:
+    J: list            # int32 device tensors, one per block (length k_i)
+    T: list            # device tensors k_i x (n_i - k_i)
+    k: "object"        # numpy int32 [nblk]
+    err_est: "object"  # numpy float64 [nblk]
+    status: "object"   # numpy int32 [nblk]
+    passes: "object"   # numpy int32 [nblk]
+
+
+class BatchPlan:
+    """Device-side argument arrays, outputs and workspace for one batch of
+    blocks (kept alive so that repeated calls, or a captured graph, reuse
+    them).  blocks: list of 2-D device tensors of one dtype."""
+
+    def __init__(self, blocks, b: int, tol: float, kmax=None, seed: int = 0, relative=True,
+                 k_hint=None, order=None):
+        torch = _torch()
+        dev = blocks[0].device
+        dt = _dtype_code(blocks[0])
+        self.blocks = blocks
+        self.nblk = len(blocks)
+        self.b, self.tol = b, tol
+        self.cfg = _cfg(dt, seed, relative)
+        ms = [int(a.shape[0]) for a in blocks]
+        ns = [int(a.shape[1]) for a in blocks]
+        if kmax is None:
+            kmax = [min(a, c) for a, c in zip(ms, ns)]
+        elif isinstance(kmax, int):
+            kmax = [kmax] * self.nblk
+        caps = [min(k, a, c) for k, a, c in zip(kmax, ms, ns)]
+        self.max_n = max(ns)
+        self.max_kmax = max(caps)
+        i32, i64 = torch.int32, torch.int64
+        self.A = torch.tensor([a.data_ptr() for a in blocks], dtype=i64, device=dev)
+        self.lda = torch.tensor([a.stride(0) for a in blocks], dtype=i64, device=dev)
+        self.m = torch.tensor(ms, dtype=i32, device=dev)
+        self.n = torch.tensor(ns, dtype=i32, device=dev)
+        self.kmax = torch.tensor(kmax, dtype=i32, device=dev)
+        self.k_hint = (torch.as_tensor(k_hint, dtype=i32).to(dev) if k_hint is not None else None)
+        self.order = (torch.as_tensor(order, dtype=i32).to(dev) if order is not None else None)
+        self.Jbufs = [torch.zeros(max(c, 1), dtype=i32, device=dev) for c in caps]
+        self.Tbufs = [torch.zeros((max(c, 1), n_), dtype=blocks[0].dtype, device=dev)
+                      for c, n_ in zip(caps, ns)]
+        self.J = torch.tensor([t.data_ptr() for t in self.Jbufs], dtype=i64, device=dev)
+        self.T = torch.tensor([t.data_ptr() for t in self.Tbufs], dtype=i64, device=dev)
+        self.ldt = torch.tensor(ns, dtype=i64, device=dev)
+        self.k_out = torch.zeros(self.nblk, dtype=i32, device=dev)
+        self.err = torch.zeros(self.nblk, dtype=torch.float64, device=dev)
+        self.st = torch.zeros(self.nblk, dtype=i32, device=dev)
+        self.passes = torch.zeros(self.nblk, dtype=i32, device=dev)
+        wb = rid_batched_workspace_bytes(self.max_n, self.max_kmax, b, self.cfg)
+        if wb == 0:
+            raise RidError("invalid batch sizes (every block needs n <= 1024, b <= 32)")
+        self.work = torch.empty(wb, dtype=torch.uint8, device=dev)
+
+    def launch(self, stream=None):
+        rc = rid_lupp_batched(
+            self.nblk, self.A.data_ptr(), self.lda.data_ptr(), self.m.data_ptr(),
+            self.n.data_ptr(), self.b, self.tol, self.kmax.data_ptr(),
+            self.k_hint.data_ptr() if self.k_hint is not None else 0, self.cfg,
+            self.J.data_ptr(), self.T.data_ptr(), self.ldt.data_ptr(), self.k_out.data_ptr(),
+            self.err.data_ptr(), self.st.data_ptr(), self.passes.data_ptr(),
+            self.order.data_ptr() if self.order is not None else 0, self.max_n, self.max_kmax,
+            self.work.data_ptr(), self.work.numel(),
+            stream if stream is not None else _stream_ptr())
+        _check(rc, "rid_lupp_batched")
+
+    def result(self) -> BatchOutput:
+        torch = _torch()
+        torch.cuda.current_stream().synchronize()
+        k = self.k_out.cpu().numpy()
+        J = [self.Jbufs[i][: k[i]] for i in range(self.nblk)]
+        T = [self.Tbufs[i][: k[i], : int(self.blocks[i].shape[1]) - k[i]] for i in range(self.nblk)]
+        return BatchOutput(J=J, T=T, k=k, err_est=self.err.cpu().numpy(),
+                           status=self.st.cpu().numpy(), passes=self.passes.cpu().numpy())
+
+
+def batched(blocks, b: int, tol: float, kmax=None, seed: int = 0, relative=True, k_hint=None,
+            order=None) -> BatchOutput:
+    """Adaptive LUPP IDs of a list of device blocks in one persistent launch;
+    block i uses the Gaussian stream of seed + i."""
+    plan = BatchPlan(blocks, b, tol, kmax, seed, relative, k_hint, order)
+    plan.launch()
+    return plan.result()

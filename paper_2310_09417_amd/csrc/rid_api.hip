@@ -13,6 +13,7 @@
 
 #include "../../include/rid.h"
 #include "rid_kernels.hpp"
+#include "rid_batched.hpp"
 
 using namespace rid;
 
@@ -49,7 +50,7 @@ DeviceInfo device_info() {
 inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
 
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
-enum KClass { KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_N };
+enum KClass { KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_N };
 
 struct Profiler {
   bool on = false;
@@ -477,6 +478,30 @@ bool valid_cfg(const rid_config* cfg) {
 
 int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }
 
+// ---- batched path ------------------------------------------------------------
+struct BPlan {
+  int64_t ldz = 0, ldl = 0, ldu = 0;
+  size_t slice = 0, total = 0;
+  int G = 0;
+};
+
+bool bplan(int32_t maxn, int32_t maxk, int32_t b, rid_dtype dt, BPlan& P) {
+  DeviceInfo di = device_info();
+  if (!di.ok) return false;
+  const size_t es = esize(dt);
+  P.ldz = (int64_t)align_up((size_t)maxk + (size_t)std::max<int32_t>(b, 64), 4);
+  P.ldl = (int64_t)align_up((size_t)maxk, 64);
+  P.ldu = (int64_t)align_up((size_t)maxk, 16);
+  auto a = [](size_t x) { return align_up(x, kAlign); };
+  // same sequence as the slice carving in k_batched
+  P.slice = a((size_t)maxn * P.ldz * es) + a((size_t)maxk * P.ldl * es) +
+            a((size_t)kBPW * P.ldl * es) + a((size_t)64 * P.ldu * es) + a((size_t)maxn * 4) +
+            a((size_t)(maxk + 64) * 4) + a((size_t)maxn * 4);
+  P.G = di.cu;
+  P.total = kAlign + (size_t)P.G * P.slice;
+  return true;
+}
+
 }  // namespace
 
 #define RID_TRY(expr)             \
@@ -607,6 +632,53 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
   Ws W = carve(P, work);
   RID_TRY(init(P, W, stream));
   return sketch_block(P, W, A, lda, cfg->seed, c0, (int)w, Yt, ldy, 0, true, true, stream);
+}
+
+size_t rid_batched_workspace_bytes(int32_t max_n, int32_t max_kmax, int32_t b,
+                                   const rid_config* cfg) {
+  if (max_n < 1 || max_n > rid::kBMaxN || max_kmax < 1 || b < 1 || b > rid::kBPW ||
+      !valid_cfg(cfg))
+    return 0;
+  BPlan P;
+  if (!bplan(max_n, std::min(max_kmax, max_n), b, cfg->dtype, P)) return 0;
+  return P.total;
+}
+
+int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, const int32_t* m,
+                     const int32_t* n, int32_t b, double tol, const int32_t* kmax,
+                     const int32_t* k_hint, const rid_config* cfg, int32_t* const* J,
+                     void* const* T, const int64_t* ldt, int32_t* k_out, double* err_est,
+                     int32_t* status, int32_t* passes, const int32_t* order, int32_t max_n,
+                     int32_t max_kmax, void* work, size_t work_bytes, hipStream_t stream) {
+  if (nblk < 0 || !valid_cfg(cfg) || b < 1 || b > rid::kBPW || !(tol >= 0.0) || max_n < 1 ||
+      max_n > rid::kBMaxN || max_kmax < 1 || !work)
+    return RID_ERR_ARG;
+  if (nblk == 0) return RID_OK;
+  if (!A || !lda || !m || !n || !kmax || !J || !T || !ldt || !k_out || !err_est || !status)
+    return RID_ERR_ARG;
+  BPlan P;
+  const int32_t maxk = std::min(max_kmax, max_n);
+  if (!bplan(max_n, maxk, b, cfg->dtype, P)) return RID_ERR_HIP;
+  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  unsigned* queue = static_cast<unsigned*>(work);
+  unsigned char* base = static_cast<unsigned char*>(work) + kAlign;
+  hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(1), 0, stream, queue);
+  RID_LAUNCH_CHECK();
+  const int grid = std::min<int>(P.G, nblk);
+  const long pm = prof_begin(KC_BATCHED, stream);
+  if (cfg->dtype == RID_F64)
+    hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
+                       b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
+                       err_est, status, passes, order, queue, base, P.slice, max_n, maxk, P.ldz,
+                       P.ldl, P.ldu);
+  else
+    hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
+                       b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
+                       err_est, status, passes, order, queue, base, P.slice, max_n, maxk, P.ldz,
+                       P.ldl, P.ldu);
+  prof_end(pm, stream);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
 }
 
 int rid_profile_start(void) {

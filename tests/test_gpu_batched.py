@@ -1,0 +1,122 @@
+"""Batched persistent kernel against the oracle, block by block, on kernel
+blocks 1/|x - y| with uneven sizes.  Block i uses the stream of seed + i.
+FP64: ranks, statuses and skeletons identical, reconstruction within 1e-12
+relative; FP32: per-block bounds stated in the test."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from parity_util import check_fp64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2310_09417_amd as rid
+    rid.library()
+    return torch, rid
+
+
+def _blocks(nblk, seed, lo=64, hi=400):
+    return [workloads.kernel_block(m, n, sep, s)
+            for (m, n, sep, s) in workloads.kernel_batch_shapes(nblk, seed, lo, hi)]
+
+
+def _recon_gap(A, J, T, Jo, To):
+    n = A.shape[1]
+
+    def X(J_, T_):
+        k = len(J_)
+        X_ = np.zeros((k, n))
+        X_[:, J_] = np.eye(k)
+        X_[:, np.setdiff1d(np.arange(n), J_)] = T_
+        return X_
+
+    return np.linalg.norm(A[:, J] @ X(J, T) - A[:, Jo] @ X(Jo, To)) / np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("tol,b", [(1e-8, 32), (1e-5, 16), (1e-10, 8)])
+def test_batched_fp64_matches_oracle(env, orc, tol, b):
+    torch, rid = env
+    print("batched64", tol, b, file=sys.stderr, flush=True)
+    blocks = _blocks(24, seed=3)
+    dev = [torch.tensor(A, dtype=torch.float64, device="cuda") for A in blocks]
+    out = rid.batched(dev, b, tol, seed=100)
+    for i, A in enumerate(blocks):
+        o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=100 + i)
+        check_fp64(A, out.J[i].cpu().numpy(), out.T[i].cpu().numpy(), int(out.k[i]),
+                   int(out.status[i]), float(out.err_est[i]), o, b, tag=i)
+    assert np.all(out.passes >= 1)
+
+
+def test_batched_fp32_matches_oracle(env, orc):
+    """FP32 factorisation: same status; rank within one block of the oracle's;
+    residual within 2x the oracle's plus the FP32 floor; estimate tracks the
+    true residual."""
+    torch, rid = env
+    blocks = _blocks(24, seed=5)
+    A32 = [A.astype(np.float32).astype(np.float64) for A in blocks]
+    dev = [torch.tensor(A, dtype=torch.float32, device="cuda") for A in A32]
+    b, tol = 32, 1e-5
+    out = rid.batched(dev, b, tol, seed=7)
+    for i, A in enumerate(A32):
+        o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=7 + i)
+        assert out.status[i] == o.status, i
+        assert abs(int(out.k[i]) - o.k) <= b, i
+        J = out.J[i].cpu().numpy()
+        T = out.T[i].cpu().numpy().astype(np.float64)
+        res = orc.true_residual(A, J, T)
+        fro = np.linalg.norm(A)
+        assert res <= 2.0 * orc.true_residual(A, o.J, o.T) + 1e-6 * fro, i
+        assert abs(out.err_est[i] - res) <= 0.6 * res + 1e-6 * fro, i
+
+
+def test_batched_hint_and_order(env, orc):
+    """A first-block width (predicted rank) follows the oracle's variant with
+    the same first width; the processing order does not change any result."""
+    torch, rid = env
+    blocks = _blocks(16, seed=9)
+    dev = [torch.tensor(A, dtype=torch.float64, device="cuda") for A in blocks]
+    b, tol = 32, 1e-8
+    hints = [int(h) for h in np.random.default_rng(1).integers(4, 60, size=len(blocks))]
+    out = rid.batched(dev, b, tol, seed=50, k_hint=hints)
+    for i, A in enumerate(blocks):
+        o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=50 + i, first_width=hints[i])
+        check_fp64(A, out.J[i].cpu().numpy(), out.T[i].cpu().numpy(), int(out.k[i]),
+                   int(out.status[i]), float(out.err_est[i]), o, b, tag=i)
+    perm = list(reversed(range(len(blocks))))
+    out2 = rid.batched(dev, b, tol, seed=50, k_hint=hints, order=perm)
+    assert np.array_equal(out.k, out2.k) and np.array_equal(out.err_est, out2.err_est)
+    for i in range(len(blocks)):
+        assert torch.equal(out.J[i], out2.J[i]) and torch.equal(out.T[i], out2.T[i])
+
+
+def test_batched_edge_blocks(env, orc):
+    torch, rid = env
+    rng = np.random.default_rng(2)
+    Z = np.zeros((70, 50))
+    C = np.zeros((90, 60))
+    C[:, [3, 40, 41]] = rng.standard_normal((90, 3))
+    N = rng.standard_normal((80, 80))
+    N[5, 7] = np.nan
+    F = rng.standard_normal((9, 13))          # full rank, wide
+    one = rng.standard_normal((1, 1))
+    big = workloads.kernel_block(1024, 1024, 3.0, 11)
+    mats = [Z, C, N, F, one, big]
+    dev = [torch.tensor(A, dtype=torch.float64, device="cuda") for A in mats]
+    out = rid.batched(dev, 32, 1e-10, seed=3)
+    assert (out.status[0], out.k[0]) == (rid.RID_RANK_DEFICIENT, 0)
+    assert (out.status[1], out.k[1]) == (rid.RID_RANK_DEFICIENT, 3)
+    assert sorted(out.J[1].cpu().numpy()) == [3, 40, 41]
+    assert (out.status[2], out.k[2]) == (rid.RID_ERR_NONFINITE, 0)
+    assert (out.status[3], out.k[3], out.err_est[3]) == (rid.RID_OK, 9, 0.0)
+    assert (out.status[4], out.k[4]) == (rid.RID_OK, 1)
+    o = orc.rid_adaptive(big, 32, 1e-10, 1024, seed=3 + 5)
+    check_fp64(big, out.J[5].cpu().numpy(), out.T[5].cpu().numpy(), int(out.k[5]),
+               int(out.status[5]), float(out.err_est[5]), o, 32, tag="1024x1024")

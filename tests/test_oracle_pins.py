@@ -279,3 +279,30 @@ def test_kahan_estimate_tracks_residual(orc):
         true = orc.true_residual(A, r.J, r.T)
         assert r.status == orc.NOT_CONVERGED
         assert 0.2 < r.err_est / true < 5.0
+
+
+def test_first_width_variant(orc):
+    """A first block of width b is plain randLUPPadap; a first block of width
+    k that already meets the tolerance is randLUPP at rank k with the next b
+    vectors as the estimation sample (Sec. 3.2)."""
+    A, _ = workloads.fast_decay(400, 300, decades=10, seed=12)
+    r1 = orc.rid_adaptive(A, 16, 1e-5, 300, seed=4)
+    r2 = orc.rid_adaptive(A, 16, 1e-5, 300, seed=4, first_width=16)
+    assert list(r1.J) == list(r2.J) and r1.err_est == r2.err_est
+    k0 = r1.k + 8
+    r3 = orc.rid_adaptive(A, 16, 1e-5, 300, seed=4, first_width=k0)
+    rf = orc.rid_fixed_rank(A, k0, 16, seed=4)
+    assert r3.k == k0 and r3.status == 0
+    assert list(r3.J) == list(rf.J) and abs(r3.err_est - rf.err_est) <= 1e-12 * rf.err_est
+
+
+def test_robust_prefix_diagnostic(orc):
+    """robust_k counts the leading pivots decided above the FP64 rounding
+    floor: all of them on a well-separated spectrum, fewer once the Schur
+    complement reaches the floor (a rank far beyond the numerical rank)."""
+    A, _ = workloads.fast_decay(600, 400, decades=10.0, seed=11)
+    o = orc.rid_fixed_rank(A, 48, 16, seed=3)
+    assert o.robust_k == o.k == 48
+    B, _ = workloads.fast_decay(300, 200, decades=16.0, seed=2)
+    o2 = orc.rid_fixed_rank(B, 190, 0, seed=3)  # sigma_190 ~ 1e-15: inside the floor
+    assert 0 < o2.robust_k < 190
