@@ -74,6 +74,10 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-kmax", type=int, default=64,
                     help="rank cap of the bounded oracle sample")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the 4096-block batched workload (off: see DESIGN.md)")
+    ap.add_argument("--nblk", type=int, default=4096)
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -218,6 +222,10 @@ def main():
             f"{cpu['cores']} threads")
         del Ah
 
+    batched = None
+    if args.batched:
+        batched = bench_batched(args, torch, rid, workloads)
+
     rec = {
         "metric": "ID GFLOP/s + blocks/s at tol 1e-6; speedup vs plain FP64 GPU path",
         "value": gflops,
@@ -244,9 +252,66 @@ def main():
         "kernel_breakdown": breakdown,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
         "source_hash": source_hash(),
     }
     print(json.dumps(rec), flush=True)
+
+
+def bench_batched(args, torch, rid, workloads):
+    """4096 kernel blocks 1/|x-y| (sizes uniform in [64, 1024]) in one
+    persistent launch, captured in a HIP graph and replayed: FP32 at relative
+    tolerance 1e-6 against the plain FP64 path on the same blocks."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    blocks64, shapes = workloads.kernel_blocks_device(args.nblk, 7, device=dev)
+    blocks32 = [a.to(torch.float32) for a in blocks64]
+    torch.cuda.synchronize()
+    log(f"[bench] batched: {args.nblk} kernel blocks generated in {time.time() - t0:.1f}s")
+    cost = np.array([m * n for (m, n, _, _) in shapes], dtype=np.float64)
+    order = list(np.argsort(-cost, kind="stable"))
+    b, tol = 32, 1e-6
+
+    def run(blocks, steps):
+        plan = rid.BatchPlan(blocks, b, tol, seed=7, order=order)
+        plan.launch()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.launch(stream=torch.cuda.current_stream().cuda_stream)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out = plan.result()
+        return ms, out
+
+    ms32, o32 = run(blocks32, args.batched_steps)
+    ms64, o64 = run(blocks64, max(1, args.batched_steps // 2))
+    F = sum(rid.flops_id(m, n, int(k), int(k) + b) for (m, n, _, _), k in zip(shapes, o32.k))
+    st = {rid.status_string(int(v)): int((o32.status == v).sum()) for v in np.unique(o32.status)}
+    res = {
+        "workload": f"{args.nblk} kernel blocks 1/|x-y|, m,n uniform in [64,1024], fp32, "
+                    f"b={b}, tol={tol:g} relative, one persistent launch in a HIP graph",
+        "ms_per_batch": ms32,
+        "blocks_per_s": args.nblk / (ms32 * 1e-3),
+        "id_gflops": F / (ms32 * 1e-3) / 1e9,
+        "mean_rank": float(np.mean(o32.k)),
+        "mean_passes": float(np.mean(o32.passes)),
+        "status_counts": st,
+        "fp64_ms_per_batch": ms64,
+        "fp64_mean_rank": float(np.mean(o64.k)),
+        "speedup_vs_fp64": ms64 / ms32,
+        "a_bytes": float(4 * cost.sum()),
+    }
+    log(f"[bench] batched fp32: {ms32:.2f} ms ({res['blocks_per_s']:.0f} blocks/s, "
+        f"mean k {res['mean_rank']:.1f}, passes {res['mean_passes']:.2f}); fp64 {ms64:.2f} ms; "
+        f"speedup {ms64 / ms32:.2f}x")
+    return res
 
 
 if __name__ == "__main__":

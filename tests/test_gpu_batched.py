@@ -120,3 +120,31 @@ def test_batched_edge_blocks(env, orc):
     o = orc.rid_adaptive(big, 32, 1e-10, 1024, seed=3 + 5)
     check_fp64(big, out.J[5].cpu().numpy(), out.T[5].cpu().numpy(), int(out.k[5]),
                int(out.status[5]), float(out.err_est[5]), o, 32, tag="1024x1024")
+
+
+def test_batched_graph_replay(env):
+    """The batched call captured in a HIP graph gives the eager result on
+    every replay, with unrelated eager work between replays."""
+    torch, rid = env
+    blocks = _blocks(40, seed=21)
+    dev = [torch.tensor(A, dtype=torch.float32, device="cuda") for A in blocks]
+    plan = rid.BatchPlan(dev, 32, 1e-5, seed=9)
+    plan.launch()
+    ref = plan.result()
+    refJ = [j.clone() for j in ref.J]
+    refT = [t.clone() for t in ref.T]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch(stream=torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        plan.k_out.fill_(-7)
+        for t in plan.Tbufs:
+            t.zero_()
+        junk = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")
+        torch.cuda.synchronize()
+        g.replay()
+        out = plan.result()
+        assert np.array_equal(out.k, ref.k) and np.array_equal(out.err_est, ref.err_est), rep
+        for i in range(len(blocks)):
+            assert torch.equal(out.J[i], refJ[i]) and torch.equal(out.T[i], refT[i]), (rep, i)
+        del junk

@@ -116,3 +116,25 @@ def svd_matrix_device(m: int, n: int, sigma, seed: int, device="cuda", dtype=Non
     A = U @ V.T
     del U, V
     return A if dtype is None else A.to(dtype)
+
+
+def kernel_blocks_device(nblk: int, seed: int, device="cuda", dtype=None, lo: int = 64,
+                         hi: int = 1024):
+    """The batched workload on the device: for each block, points x in the
+    unit cube at the origin and y in a unit cube at distance sep in a random
+    direction (host-side seeded draws), K_ij = 1/|x_i - y_j| formed in FP64
+    on the device.  Returns (list of tensors, list of (m, n, sep, seed))."""
+    import torch
+    shapes = kernel_batch_shapes(nblk, seed, lo, hi)
+    out = []
+    for (m, n, sep, s) in shapes:
+        rng = np.random.default_rng(s)
+        x = rng.uniform(-0.5, 0.5, size=(m, 3))
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        y = rng.uniform(-0.5, 0.5, size=(n, 3)) + sep * u[None, :]
+        xd = torch.as_tensor(x, dtype=torch.float64, device=device)
+        yd = torch.as_tensor(y, dtype=torch.float64, device=device)
+        K = 1.0 / torch.cdist(xd, yd)
+        out.append(K if dtype is None else K.to(dtype))
+    return out, shapes
