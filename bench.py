@@ -27,7 +27,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f32_mfma": 157.3e12, "f64_mfma": 78.6e12, "hbm": 8.0e12}
+PEAK = {"f32_mfma": 157.3e12, "f64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "fp8_mfma": 5.0e15,
+        "hbm": 8.0e12}
 
 
 def log(*a):
@@ -71,6 +72,9 @@ def main():
     ap.add_argument("--kmax", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--lp-steps", type=int, default=3,
+                    help="timed runs of each precision form (A stored in BF16 / FP8-e4m3); "
+                         "0 skips them")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-kmax", type=int, default=64,
                     help="rank cap of the bounded oracle sample")
@@ -109,12 +113,14 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     kcap = min(kmax, m, n)
 
-    def make_run(A, dtype_code):
-        cfg = rid.binding._cfg(dtype_code, seed, True)
+    def make_run(A, dtype_code, a_type=None, col_scale=None):
+        cfg = rid.binding._cfg(dtype_code, seed, True, a_type=a_type,
+                               col_scale=col_scale.data_ptr() if col_scale is not None else 0)
         wb = rid.rid_workspace_bytes(m, n, kmax, b, cfg)
         work = torch.empty(wb, dtype=torch.uint8, device=dev)
         J = torch.zeros(kcap, dtype=torch.int64, device=dev)
-        T = torch.zeros((kcap, n), dtype=A.dtype, device=dev)
+        T = torch.zeros((kcap, n), dtype=torch.float64 if dtype_code == rid.RID_F64
+                        else torch.float32, device=dev)
         ko = torch.zeros(1, dtype=torch.int32, device=dev)
         eo = torch.zeros(1, dtype=torch.float64, device=dev)
         so = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -203,6 +209,71 @@ def main():
         log(f"[bench] fp64: {ms64:.2f} ms/step, k={k64}, speedup of fp32 = {ms64 / ms:.2f}x")
         del out64, run64
 
+    def true_resid(Avals, J, T):
+        """||A(:,J^c) - A(:,J) T||_F in FP64 (measurement, outside timed regions)."""
+        kk = J.numel()
+        mask = torch.ones(n, dtype=torch.bool, device=dev)
+        mask[J] = False
+        R = Avals[:, mask].double() - Avals[:, J].double() @ T[:kk, : n - kk].double()
+        return float(torch.linalg.vector_norm(R).item())
+
+    k32 = k
+    resid32 = true_resid(A32, out32[0][:k32], out32[1]) / fro
+    err32_orig = true_resid(A64, out32[0][:k32], out32[1]) / float(
+        torch.linalg.vector_norm(A64).item())
+    log(f"[bench] fp32 true residual / ||A|| = {resid32:.3e}")
+
+    # precision forms: A stored in BF16 / FP8-e4m3 (per-128-column power-of-two
+    # scale), sketch on matrix cores with FP32 accumulation, FP32 factorisation
+    precision = {}
+    if args.lp_steps > 0:
+        for fmt, code, es in (("bf16", rid.RID_BF16, 2), ("fp8", rid.RID_FP8_E4M3, 1)):
+            Aq, scale = workloads.quantize_device(A32, fmt)
+            Avals = (Aq.float() if fmt == "bf16" else
+                     Aq.float() * scale.repeat_interleave(128)[:n][None, :])
+            froq = float(torch.linalg.vector_norm(Avals.double()).item())
+            runq, outq, _ = make_run(Aq, rid.RID_F32, a_type=code, col_scale=scale)
+            runq()
+            torch.cuda.synchronize()
+            rid.rid_profile_start()
+            t0 = time.perf_counter()
+            for _ in range(args.lp_steps):
+                runq()
+            torch.cuda.synchronize()
+            msq = (time.perf_counter() - t0) * 1e3 / args.lp_steps
+            profq = rid.rid_profile_stop()
+            kq = int(outq[2].item())
+            skq, skc = profq["sketch"]
+            sk_avg = skq * 1e-3 / max(skc, 1)
+            bytes_l = float(es) * m * n
+            Fq = rid.flops_id(m, n, kq, kq + b if kq < min(m, n) else kq)
+            rq = true_resid(Avals, outq[0][:kq], outq[1]) / froq
+            eq = true_resid(A64, outq[0][:kq], outq[1]) / float(torch.linalg.vector_norm(A64).item())
+            peak_mfma = PEAK["bf16_mfma"] if fmt == "bf16" else PEAK["fp8_mfma"]
+            precision[fmt] = {
+                "ms_per_step": msq, "gflops": Fq / (msq * 1e-3) / 1e9, "k": kq,
+                "status": rid.status_string(int(outq[4].item())),
+                "err_est_rel": float(outq[3].item()) / froq,
+                "resid_rel_stored": rq, "err_rel_vs_original": eq,
+                "rounding_floor_rel": (2.0 ** -9 if fmt == "bf16" else 2.0 ** -4) / 3 ** 0.5,
+                "speedup_vs_fp32": ms / msq,
+                "speedup_vs_fp64": (fp64["ms_per_step"] / msq) if fp64 else None,
+                "sketch": {"avg_launch_ms": sk_avg * 1e3, "launches_per_step": skc // args.lp_steps,
+                           "bound": "hbm", "algorithmic_bytes_per_launch": bytes_l,
+                           "achieved_GBps": bytes_l / sk_avg / 1e9,
+                           "frac_hbm": bytes_l / sk_avg / PEAK["hbm"],
+                           "achieved_TFLOPs": 2.0 * b * m * n / sk_avg / 1e12,
+                           "frac_mfma": 2.0 * b * m * n / sk_avg / peak_mfma},
+                "kernel_breakdown": {nm: {"ms_per_step": t / args.lp_steps,
+                                          "launches_per_step": c // args.lp_steps}
+                                     for nm, (t, c) in profq.items()},
+            }
+            log(f"[bench] {fmt}: {msq:.2f} ms/step, k={kq}, "
+                f"{precision[fmt]['status']}, resid={rq:.3e} (vs original A {eq:.3e}), "
+                f"sketch {sk_avg * 1e3:.3f} ms/launch = {bytes_l / sk_avg / 1e9:.0f} GB/s, "
+                f"speedup vs fp32 {ms / msq:.2f}x")
+            del Aq, scale, Avals, runq, outq
+
     # CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.skip_cpu:
@@ -248,6 +319,9 @@ def main():
         "err_est_rel": E / fro,
         "flops_per_step": F,
         "speedup_vs_fp64": (fp64["speedup_of_fp32"] if fp64 else None),
+        "resid_rel_true": resid32,
+        "err_rel_vs_fp64_matrix": err32_orig,
+        "precision_forms": precision,
         "fp64_path": fp64,
         "kernel_breakdown": breakdown,
         "roofline": roof,

@@ -50,17 +50,33 @@ typedef enum {
 } rid_status;
 
 typedef enum {
-  RID_F64 = 0,       /* double                                   */
-  RID_F32 = 1        /* float                                    */
+  RID_F64 = 0,       /* double                                             */
+  RID_F32 = 1,       /* float                                              */
+  RID_BF16 = 2,      /* bfloat16 bit patterns (uint16); storage of A only   */
+  RID_FP8_E4M3 = 3   /* OCP FP8 e4m3 codes (uint8) with a power-of-two scale
+                        per 128-column tile; storage of A only              */
 } rid_dtype;
 
 typedef struct {
-  rid_dtype dtype;      /* storage type of A and T; LUPP, Schur updates and the
-                           interpolation solve run in this precision; every norm
-                           and the stopping test accumulate in FP64            */
+  rid_dtype dtype;      /* factor type: storage of T; LUPP, Schur updates and
+                           the interpolation solve run in this precision; every
+                           norm and the stopping test accumulate in FP64.
+                           RID_F64 or RID_F32.                                  */
   int tol_relative;     /* 1: stop when E <= tol * ||A||_F; 0: when E <= tol   */
   uint64_t seed;        /* key of the Gaussian embedding: entry (c, i) of sketch
                            vector c is a pure function of (seed, c, i)          */
+  rid_dtype a_type;     /* storage type of A.  Equal to dtype, or, with dtype
+                           RID_F32, RID_BF16 or RID_FP8_E4M3: the sketch then
+                           multiplies in that format on the matrix cores (the
+                           Gaussian entries rounded to nearest even into it)
+                           with FP32 accumulation, summed across row ranges in
+                           FP64.  The precision forms of the sketch step.      */
+  const float* a_col_scale; /* (device) RID_FP8_E4M3 only: ceil(n/128) powers of
+                           two; A(i, j) = code(i, j) * a_col_scale[j / 128].
+                           NULL otherwise.                                      */
+  int refine;           /* 0, or 1 (dtype RID_F32 only): one iterative-refinement
+                           step on T whose residual Y(:,J) T - Y(:,J^c) is
+                           formed in FP64 from the FP32 sketch                  */
 } rid_config;
 
 /*
@@ -157,6 +173,19 @@ int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtyp
 int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c0, int64_t w,
                      const rid_config* cfg, void* Yt, int64_t ldy, void* work, size_t work_bytes,
                      hipStream_t stream);
+
+/*
+ * Test export: one wave checks the matrix-instruction layouts and number
+ * conversions of the low-precision sketch.  D is 16 x 16 FP32 (device).
+ *   kind 0: D = A B with A 16 x 32 and B 32 x 16 BF16 bit patterns (uint16,
+ *           row-major, device)
+ *   kind 1: the same with OCP FP8-e4m3 codes (uint8)
+ *   kind 2: A holds 64 floats; D[i] = BF16 pattern and D[64 + i] = e4m3 code
+ *           of A[i], both rounded to nearest even
+ *   kind 3: B holds the 256 e4m3 codes; D[c] = value of code c
+ * Returns RID_ERR_ARG for another kind or a null pointer.
+ */
+int rid_debug_mfma_probe(int kind, const void* A, const void* B, float* D, hipStream_t stream);
 
 /*
  * Optional timing.  After rid_profile_start(), every kernel launch of the

@@ -27,6 +27,7 @@ _SRC = os.path.join(_HERE, "rid_oracle.c")
 _LIB = os.path.join(_HERE, "librid_oracle.so")
 
 OK, NOT_CONVERGED, RANK_DEFICIENT, ERR_ARG, ERR_NONFINITE = 0, 1, 2, -1, -2
+FMT_NONE, FMT_BF16, FMT_E4M3 = 0, 1, 2   # formats of orc_round_format
 
 
 def build(force: bool = False) -> str:
@@ -63,6 +64,12 @@ def _load():
         lib.orc_omega.restype = None
         lib.orc_sketch.argtypes = [P, i64, i64, i64, u64, i64, i64, P, i64]
         lib.orc_sketch.restype = None
+        lib.orc_sketch_format.argtypes = [P, i64, i64, i64, u64, i64, i64, cint, P, i64]
+        lib.orc_sketch_format.restype = None
+        lib.orc_omega_format.argtypes = [u64, i64, i64, i64, cint, P]
+        lib.orc_omega_format.restype = None
+        lib.orc_round_format.argtypes = [dbl, cint]
+        lib.orc_round_format.restype = dbl
         lib.orc_rid_lupp.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
                                      P, P, i64, P, i64, ctypes.POINTER(_Result)]
         lib.orc_rid_lupp.restype = cint
@@ -104,14 +111,31 @@ def omega(seed: int, c0: int, w: int, m: int) -> np.ndarray:
     return out
 
 
-def sketch(A: np.ndarray, seed: int, c0: int, w: int) -> np.ndarray:
-    """Y = Omega(c0:c0+w, :) @ A, summed in ascending row order."""
+def sketch(A: np.ndarray, seed: int, c0: int, w: int, fmt: int = FMT_NONE) -> np.ndarray:
+    """Y = Omega(c0:c0+w, :) @ A, summed in ascending row order; with fmt the
+    entries of Omega are first rounded into BF16 (FMT_BF16) or e4m3 (FMT_E4M3)."""
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
     Y = np.empty((w, n), dtype=np.float64)
-    lib.orc_sketch(_ptr(A), m, n, n, seed, c0, w, _ptr(Y), n)
+    lib.orc_sketch_format(_ptr(A), m, n, n, seed, c0, w, fmt, _ptr(Y), n)
     return Y
+
+
+def round_format(x, fmt: int) -> np.ndarray:
+    """Round every entry of x to nearest (ties to even) in BF16 (FMT_BF16) or
+    OCP FP8 e4m3 (FMT_E4M3), saturating at the largest finite value."""
+    lib = _load()
+    x = np.asarray(x, dtype=np.float64)
+    return np.vectorize(lambda v: lib.orc_round_format(float(v), fmt), otypes=[np.float64])(x)
+
+
+def omega_format(seed: int, c0: int, w: int, m: int, fmt: int) -> np.ndarray:
+    """Gaussian block rounded into format fmt: out[c, i] = round(omega(c0 + c, i))."""
+    lib = _load()
+    out = np.empty((w, m), dtype=np.float64)
+    lib.orc_omega_format(seed, c0, w, m, fmt, _ptr(out))
+    return out
 
 
 @dataclass

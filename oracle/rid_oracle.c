@@ -113,13 +113,55 @@ void orc_omega(uint64_t seed, int64_t c0, int64_t w, int64_t m, double* out) {
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Rounding into a narrower binary floating-point format: p significand bits */
+/* (the implicit one included), smallest normal exponent emin, largest      */
+/* finite magnitude xmax.  Round to nearest, ties to the even significand;  */
+/* magnitudes beyond xmax saturate.  Subnormals keep the spacing of the     */
+/* smallest binade.                                                         */
+/*   fmt 1: bfloat16       p = 8, emin = -126, xmax = (2 - 2^-7) 2^127       */
+/*   fmt 2: OCP FP8 e4m3   p = 4, emin = -6,   xmax = 448                    */
+/* fmt 0 returns x unchanged.                                               */
+/* ------------------------------------------------------------------------ */
+double orc_round_format(double x, int fmt) {
+  int p, emin;
+  double xmax;
+  if (fmt == 1) {
+    p = 8;
+    emin = -126;
+    xmax = ldexp(2.0 - ldexp(1.0, -7), 127);
+  } else if (fmt == 2) {
+    p = 4;
+    emin = -6;
+    xmax = 448.0;
+  } else {
+    return x;
+  }
+  if (x == 0.0 || !isfinite(x)) return x;
+  int e;
+  (void)frexp(x, &e); /* |x| = f 2^e, f in [0.5, 1): leading bit at 2^(e-1) */
+  int lead = e - 1;
+  if (lead < emin) lead = emin;
+  const double q = ldexp(1.0, lead - (p - 1)); /* spacing of the binade */
+  double r = nearbyint(x / q) * q;             /* x / q is exact; ties to even */
+  if (fabs(r) > xmax) r = copysign(xmax, x);
+  return r;
+}
+
+/* Omega block rounded into format fmt: out[c * m + i] = round(omega(c0+c, i)). */
+void orc_omega_format(uint64_t seed, int64_t c0, int64_t w, int64_t m, int fmt, double* out) {
+  orc_omega(seed, c0, w, m, out);
+  for (int64_t t = 0; t < w * m; ++t) out[t] = orc_round_format(out[t], fmt);
+}
+
 /* Sketch (paper Sec. 2.4): Y(c, j) = sum_{i=0}^{m-1} omega(c0+c, i) * A(i, j),
- * summed in ascending i.  Y is w x n row-major with leading dimension ldy.
+ * summed in ascending i, with the entries of Omega first rounded into format
+ * fmt (0: kept in double).  Y is w x n row-major with leading dimension ldy.
  * Each output column strip is owned by one thread. */
-void orc_sketch(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
-                int64_t c0, int64_t w, double* Y, int64_t ldy) {
+void orc_sketch_format(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                       int64_t c0, int64_t w, int fmt, double* Y, int64_t ldy) {
   double* om = (double*)malloc(sizeof(double) * (size_t)(w > 0 ? w : 1) * (size_t)(m > 0 ? m : 1));
-  orc_omega(seed, c0, w, m, om);
+  orc_omega_format(seed, c0, w, m, fmt, om);
   const int64_t strip = 256;
   int64_t nstrips = (n + strip - 1) / strip;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -137,6 +179,12 @@ void orc_sketch(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t see
     }
   }
   free(om);
+}
+
+/* Sketch with the Gaussian entries kept in double. */
+void orc_sketch(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                int64_t c0, int64_t w, double* Y, int64_t ldy) {
+  orc_sketch_format(A, m, n, lda, seed, c0, w, 0, Y, ldy);
 }
 
 /* Sum of squares of A in ascending (row, column) order. */

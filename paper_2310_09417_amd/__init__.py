@@ -9,8 +9,8 @@ library has not been built.
 """
 from .binding import (  # noqa: F401
     RID_OK, RID_NOT_CONVERGED, RID_RANK_DEFICIENT, RID_ERR_ARG, RID_ERR_NONFINITE, RID_ERR_HIP,
-    RID_ERR_WORKSPACE, RID_F64, RID_F32, RidError, IDOutput, library, workspace_bytes,
-    status_string, fixed_rank, adaptive, debug_gaussian, debug_sketch,
+    RID_ERR_WORKSPACE, RID_F64, RID_F32, RID_BF16, RID_FP8_E4M3, RidError, IDOutput, library, workspace_bytes,
+    status_string, fixed_rank, adaptive, debug_gaussian, debug_sketch, debug_mfma_probe,
     rid_lupp_fixed_rank, rid_lupp_adaptive, rid_workspace_bytes, rid_debug_gaussian,
     rid_debug_sketch, rid_status_string, rid_profile_start, rid_profile_stop, KERNEL_CLASSES,
     rid_batched_workspace_bytes, rid_lupp_batched, BatchPlan, BatchOutput, batched)

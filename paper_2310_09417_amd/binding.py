@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librid.so")
 
 RID_OK, RID_NOT_CONVERGED, RID_RANK_DEFICIENT = 0, 1, 2
 RID_ERR_ARG, RID_ERR_NONFINITE, RID_ERR_HIP, RID_ERR_WORKSPACE = -1, -2, -3, -4
-RID_F64, RID_F32 = 0, 1
+RID_F64, RID_F32, RID_BF16, RID_FP8_E4M3 = 0, 1, 2, 3
 
 
 class RidError(RuntimeError):
@@ -27,7 +27,8 @@ class RidError(RuntimeError):
 
 class RidConfig(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("tol_relative", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("a_type", ctypes.c_int),
+                ("a_col_scale", ctypes.c_void_p), ("refine", ctypes.c_int)]
 
 
 _lib = None
@@ -63,6 +64,8 @@ def library() -> ctypes.CDLL:
         lib.rid_lupp_batched.argtypes = [i32, P, P, P, P, i32, dbl, P, P, cfgp, P, P, P, P, P, P,
                                          P, P, i32, i32, P, sz, P]
         lib.rid_lupp_batched.restype = i32
+        lib.rid_debug_mfma_probe.argtypes = [i32, P, P, P, P]
+        lib.rid_debug_mfma_probe.restype = i32
         lib.rid_profile_start.argtypes = []
         lib.rid_profile_start.restype = i32
         lib.rid_profile_stop.argtypes = [P, P, i32]
@@ -71,8 +74,11 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
-def _cfg(dtype: int, seed: int, tol_relative: bool = True) -> RidConfig:
-    return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed)
+def _cfg(dtype: int, seed: int, tol_relative: bool = True, a_type: int | None = None,
+         col_scale: int = 0, refine: bool = False) -> RidConfig:
+    return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed,
+                     a_type=dtype if a_type is None else a_type, a_col_scale=col_scale or None,
+                     refine=1 if refine else 0)
 
 
 # ---- raw C-ABI mirrors (pointers as ints) ----------------------------------
@@ -154,6 +160,31 @@ def _dtype_code(t) -> int:
     raise RidError(f"unsupported dtype {t.dtype}")
 
 
+def _config_for(A, seed: int, relative: bool = True, col_scale=None, refine: bool = False):
+    """Config for A's storage: float64 / float32 run the whole path in that
+    type; bfloat16 A, or float8_e4m3fn (or uint8 codes) A with col_scale
+    (float32 device tensor, ceil(n/128) powers of two), run the sketch in that
+    format and the factorisation in FP32.  Returns (cfg, dtype of T)."""
+    torch = _torch()
+    if A.dtype in (torch.float64, torch.float32):
+        if col_scale is not None:
+            raise RidError("col_scale applies to FP8 storage only")
+        dt = _dtype_code(A)
+        return _cfg(dt, seed, relative, refine=refine), A.dtype
+    if A.dtype == torch.bfloat16:
+        if col_scale is not None:
+            raise RidError("col_scale applies to FP8 storage only")
+        return _cfg(RID_F32, seed, relative, a_type=RID_BF16, refine=refine), torch.float32
+    if A.dtype in (torch.float8_e4m3fn, torch.uint8):
+        n = A.shape[1]
+        if (col_scale is None or col_scale.dtype != torch.float32 or not col_scale.is_contiguous()
+                or col_scale.numel() < (n + 127) // 128 or col_scale.device != A.device):
+            raise RidError("FP8 storage needs col_scale: float32 device tensor of ceil(n/128)")
+        return (_cfg(RID_F32, seed, relative, a_type=RID_FP8_E4M3, col_scale=col_scale.data_ptr(),
+                     refine=refine), torch.float32)
+    raise RidError(f"unsupported dtype {A.dtype}")
+
+
 def _check(rc: int, what: str):
     if rc != RID_OK:
         raise RidError(f"{what} returned {rc} ({rid_status_string(rc)})")
@@ -163,8 +194,8 @@ def status_string(status: int) -> str:
     return rid_status_string(status)
 
 
-def workspace_bytes(m, n, kmax, b, dtype=RID_F64) -> int:
-    return rid_workspace_bytes(m, n, kmax, b, _cfg(dtype, 0))
+def workspace_bytes(m, n, kmax, b, dtype=RID_F64, a_type=None) -> int:
+    return rid_workspace_bytes(m, n, kmax, b, _cfg(dtype, 0, a_type=a_type, col_scale=1 if a_type == RID_FP8_E4M3 else 0))
 
 
 @dataclass
@@ -202,19 +233,20 @@ def _work(nbytes, device):
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
 
 
-def fixed_rank(A, k: int, p: int, seed: int, work=None) -> IDOutput:
-    """randLUPP at rank k with p estimation vectors (A: m x n device tensor)."""
+def fixed_rank(A, k: int, p: int, seed: int, work=None, col_scale=None,
+               refine: bool = False) -> IDOutput:
+    """randLUPP at rank k with p estimation vectors (A: m x n device tensor;
+    BF16 / FP8 storage as described in _config_for)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
-    dt = _dtype_code(A)
-    cfg = _cfg(dt, seed)
+    cfg, tdt = _config_for(A, seed, True, col_scale, refine)
     wb = rid_workspace_bytes(m, n, k + p, p, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
     if work is None:
         work = _work(wb, A.device)
-    out = _Outputs(k, n, A.dtype, A.device)
+    out = _Outputs(k, n, tdt, A.device)
     rc = rid_lupp_fixed_rank(A.data_ptr(), m, n, lda, k, p, cfg, out.J.data_ptr(),
                              out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
                              out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
@@ -223,20 +255,20 @@ def fixed_rank(A, k: int, p: int, seed: int, work=None) -> IDOutput:
 
 
 def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
-             work=None) -> IDOutput:
-    """randLUPPadap with block size b, tolerance tol, rank cap kmax."""
+             work=None, col_scale=None, refine: bool = False) -> IDOutput:
+    """randLUPPadap with block size b, tolerance tol, rank cap kmax (BF16 /
+    FP8 storage as described in _config_for)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
-    dt = _dtype_code(A)
-    cfg = _cfg(dt, seed, relative)
+    cfg, tdt = _config_for(A, seed, relative, col_scale, refine)
     wb = rid_workspace_bytes(m, n, kmax, b, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
     if work is None:
         work = _work(wb, A.device)
     cap = min(kmax, m, n)
-    out = _Outputs(cap, n, A.dtype, A.device)
+    out = _Outputs(cap, n, tdt, A.device)
     rc = rid_lupp_adaptive(A.data_ptr(), m, n, lda, b, tol, kmax, cfg, out.J.data_ptr(),
                            out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
                            out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
@@ -254,14 +286,28 @@ def debug_gaussian(seed: int, c0: int, w: int, m: int, dtype, device="cuda"):
     return out
 
 
-def debug_sketch(A, seed: int, c0: int, w: int):
-    """(Omega(c0:c0+w) A)^T as an n x w tensor, computed by the sketch kernels."""
+def debug_mfma_probe(kind: int, A, B):
+    """Layout / conversion probe (D 16x16 FP32): kind 0 D = A @ B with BF16
+    bit tensors 16x32 / 32x16, kind 1 the same with FP8-e4m3 codes, kind 2 the
+    BF16 and e4m3 encodings of 64 floats in A, kind 3 the values of the 256
+    e4m3 codes in B."""
+    torch = _torch()
+    D = torch.zeros((16, 16), dtype=torch.float32, device=A.device)
+    _check(int(library().rid_debug_mfma_probe(kind, A.data_ptr(), B.data_ptr(), D.data_ptr(),
+                                              _stream_ptr())), "rid_debug_mfma_probe")
+    torch.cuda.current_stream().synchronize()
+    return D
+
+
+def debug_sketch(A, seed: int, c0: int, w: int, col_scale=None):
+    """(Omega(c0:c0+w) A)^T as an n x w tensor, computed by the sketch kernels
+    (BF16 / FP8 storage as described in _config_for; result in FP32 then)."""
     torch = _torch()
     m, n = A.shape
-    cfg = _cfg(_dtype_code(A), seed)
+    cfg, ydt = _config_for(A, seed, True, col_scale)
     wb = rid_workspace_bytes(m, n, w, w, cfg)
     work = _work(wb, A.device)
-    Yt = torch.empty((n, w), dtype=A.dtype, device=A.device)
+    Yt = torch.empty((n, w), dtype=ydt, device=A.device)
     _check(rid_debug_sketch(A.data_ptr(), m, n, A.stride(0), c0, w, cfg, Yt.data_ptr(), w,
                             work.data_ptr(), work.numel(), _stream_ptr()), "rid_debug_sketch")
     torch.cuda.current_stream().synchronize()

@@ -14,6 +14,7 @@
 #include "../../include/rid.h"
 #include "rid_kernels.hpp"
 #include "rid_batched.hpp"
+#include "rid_sketch_lp.hpp"
 
 using namespace rid;
 
@@ -118,10 +119,44 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   return g;
 }
 
+// Low-precision sketch geometry: 1024 columns per workgroup, one workgroup
+// per CU.  The split count minimises (rounds x bytes of A per workgroup) plus
+// the FP32 partials written and read back, per CU.
+struct LpGeom {
+  int64_t ncolg, nsplit, rows_per_split;
+};
+
+LpGeom sketch_geom_lp(int64_t m, int64_t n, int es, int cu) {
+  LpGeom g;
+  g.ncolg = ceil_div(n, kLpCols);
+  const int64_t maxsplit = ceil_div(m, kLpKs);
+  const int64_t hi = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(8 * cu, g.ncolg)));
+  double best = -1.0;
+  int64_t best_ns = 1;
+  for (int64_t ns = 1; ns <= hi; ++ns) {
+    const int64_t rps = ceil_div(ceil_div(m, ns), kLpKs) * kLpKs;
+    const int64_t real_ns = ceil_div(m, rps);
+    const int64_t items = g.ncolg * real_ns;
+    const double cost = (double)ceil_div(items, cu) * (double)rps * kLpCols * es +
+                        (double)items * kLpCols * 64 * 4 * 2 / cu;
+    if (best < 0.0 || cost < best * (1.0 - 1e-3)) {
+      best = cost;
+      best_ns = ns;
+    }
+  }
+  g.rows_per_split = ceil_div(ceil_div(m, best_ns), kLpKs) * kLpKs;
+  g.nsplit = ceil_div(m, g.rows_per_split);
+  return g;
+}
+
+inline bool low_precision(rid_dtype t) { return t == RID_BF16 || t == RID_FP8_E4M3; }
+
 // Everything a call needs, derived from its sizes.
 struct Plan {
   int64_t m = 0, n = 0, kcap = 0, wmax = 0;
-  rid_dtype dt = RID_F64;
+  rid_dtype dt = RID_F64;   // factor type
+  rid_dtype at = RID_F64;   // storage type of A
+  const float* scale = nullptr;  // FP8 column-tile scales (device)
   int64_t ldz = 0, ldu = 0, ldl = 0;
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
@@ -134,7 +169,8 @@ struct Plan {
       o_slotrows, o_nonfinite, o_linv, o_mtmp, total;
 };
 
-bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, Plan& P) {
+bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, rid_dtype at,
+               Plan& P) {
   DeviceInfo di = device_info();
   if (!di.ok) return false;
   P.m = m;
@@ -142,6 +178,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, P
   P.kcap = kcap;
   P.wmax = wmax;
   P.dt = dt;
+  P.at = at;
   P.cu = di.cu;
   const size_t es = esize(dt);
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
@@ -155,7 +192,11 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, P
   P.nbars = (int)(kcap + 8);
   // sketch partials: every launch covers <= 64 vectors with the same split
   size_t pb = 0, fc = 0;
-  {
+  if (low_precision(at)) {
+    LpGeom g = sketch_geom_lp(m, n, at == RID_BF16 ? 2 : 1, di.cu);
+    pb = (size_t)g.nsplit * (size_t)n * 64 * 4;
+    fc = (size_t)(g.nsplit * g.ncolg);
+  } else {
     SketchGeom g = sketch_geom(m, n, (int)std::min<int64_t>(wmax, 64), dt, di.cu);
     pb = (size_t)g.nsplit * (size_t)n * g.wp * 8;
     fc = (size_t)(g.nsplit * g.ncolg);
@@ -190,11 +231,13 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, P
 
 // Plan of a call with rank cap kmax and block width b (fixed rank: kmax = k + p,
 // b = p): kcap = min(kmax, m, n), widest block min(128, max(b, min(kcap, 128))).
-bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, rid_dtype dt, Plan& P) {
+bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg, Plan& P) {
   const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
   const int64_t wmax =
       std::min<int64_t>(kMaxW, std::max<int64_t>({b, std::min<int64_t>(kcap, kMaxW), 1}));
-  return make_plan(m, n, kcap, wmax, dt, P);
+  if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, P)) return false;
+  P.scale = cfg->a_col_scale;
+  return true;
 }
 
 // Pointers into the caller's workspace.
@@ -286,6 +329,31 @@ int launch_sketch(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64
              : launch_sketch_mt<TC, KC, false>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
 }
 
+template <int FMT, bool NORM>
+int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                     int64_t c0, int w, const LpGeom& g, bool use_ctrl, hipStream_t st) {
+  constexpr int ES = FMT == 1 ? 2 : 1;
+  // 16-byte vector loads: aligned base and rows of a multiple of 16 bytes
+  const bool vec = ((lda * ES) % 16 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+  dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  const unsigned char* a = static_cast<const unsigned char*>(A);
+  float* part = reinterpret_cast<float*>(W.part);
+  const long pm = prof_begin(KC_SKETCH, st);
+  if (vec)
+    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, true>), grid, dim3(256), 0, st, a, P.m, P.n, lda,
+                       P.scale, k0, k1, (uint32_t)c0, w, g.rows_per_split, part, W.fro,
+                       W.nonfinite, ctrl);
+  else
+    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, false>), grid, dim3(256), 0, st, a, P.m, P.n, lda,
+                       P.scale, k0, k1, (uint32_t)c0, w, g.rows_per_split, part, W.fro,
+                       W.nonfinite, ctrl);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
 // Sketch vectors [c0, c0 + w) into columns [zcol, zcol + w) of `out`
 // (n x ldo, dtype of the plan), in launches of at most 64 vectors.
 int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
@@ -294,14 +362,34 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
   for (int off = 0; off < w; off += 64) {
     const int wc = std::min(64, w - off);
     const bool norm = first && off == 0;
+    Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+    const unsigned blocks = (unsigned)ceil_div(P.n * wc, 256);
+    if (low_precision(P.at)) {
+      // factor type is FP32 (checked by the caller)
+      LpGeom g = sketch_geom_lp(P.m, P.n, P.at == RID_BF16 ? 2 : 1, P.cu);
+      int rc;
+      if (P.at == RID_BF16)
+        rc = norm ? launch_sketch_lp<1, true>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st)
+                  : launch_sketch_lp<1, false>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st);
+      else
+        rc = norm ? launch_sketch_lp<2, true>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st)
+                  : launch_sketch_lp<2, false>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st);
+      if (rc != RID_OK) return rc;
+      const long pm = prof_begin(KC_REDUCE, st);
+      hipLaunchKernelGGL(k_sketch_reduce_lp<float>, dim3(blocks), dim3(256), 0, st,
+                         reinterpret_cast<const float*>(W.part), (int)g.nsplit, P.n, wc,
+                         P.at == RID_FP8_E4M3 ? P.scale : nullptr, static_cast<float*>(out), ldo,
+                         zcol + off, W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl,
+                         norm ? 1 : 0);
+      prof_end(pm, st);
+      RID_LAUNCH_CHECK();
+      continue;
+    }
     SketchGeom g = sketch_geom(P.m, P.n, wc, P.dt, P.cu);
     int rc = (P.dt == RID_F64)
                  ? launch_sketch<double, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st)
                  : launch_sketch<float, 64>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st);
     if (rc != RID_OK) return rc;
-    const int64_t tot = P.n * wc;
-    const unsigned blocks = (unsigned)ceil_div(tot, 256);
-    Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
     const long pm = prof_begin(KC_REDUCE, st);
     if (P.dt == RID_F64)
       hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
@@ -473,7 +561,17 @@ int init(const Plan& P, const Ws& W, hipStream_t st) {
 }
 
 bool valid_cfg(const rid_config* cfg) {
-  return cfg && (cfg->dtype == RID_F64 || cfg->dtype == RID_F32);
+  if (!cfg || (cfg->dtype != RID_F64 && cfg->dtype != RID_F32)) return false;
+  if (cfg->a_type != cfg->dtype) {
+    if (cfg->dtype != RID_F32 || !low_precision(cfg->a_type)) return false;
+    if (cfg->a_type == RID_FP8_E4M3 && !cfg->a_col_scale) return false;
+  }
+  return cfg->refine == 0;
+}
+
+// The batched path reads A in the factor type only.
+bool valid_batched_cfg(const rid_config* cfg) {
+  return valid_cfg(cfg) && cfg->a_type == cfg->dtype;
 }
 
 int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }
@@ -515,7 +613,7 @@ extern "C" {
 size_t rid_workspace_bytes(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg) {
   if (m < 1 || n < 1 || kmax < 1 || b < 0 || !valid_cfg(cfg)) return 0;
   Plan P;
-  if (!plan_for(m, n, kmax, b, cfg->dtype, P)) return 0;
+  if (!plan_for(m, n, kmax, b, cfg, P)) return 0;
   return P.total;
 }
 
@@ -543,7 +641,7 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
     return RID_ERR_ARG;
   if (k > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
   Plan P;
-  if (!plan_for(m, n, k + p, p, cfg->dtype, P)) return RID_ERR_HIP;
+  if (!plan_for(m, n, k + p, p, cfg, P)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
   if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
   Ws W = carve(P, work);
@@ -579,7 +677,7 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
   const int64_t kcap = std::min(kmax, mn);
   if (kcap > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
   Plan P;
-  if (!plan_for(m, n, kmax, b, cfg->dtype, P)) return RID_ERR_HIP;
+  if (!plan_for(m, n, kmax, b, cfg, P)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
   if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
   Ws W = carve(P, work);
@@ -627,7 +725,7 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
       w > kMaxW || ldy < w || c0 < 0)
     return RID_ERR_ARG;
   Plan P;
-  if (!plan_for(m, n, w, w, cfg->dtype, P)) return RID_ERR_HIP;
+  if (!plan_for(m, n, w, w, cfg, P)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
   Ws W = carve(P, work);
   RID_TRY(init(P, W, stream));
@@ -637,7 +735,7 @@ int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c
 size_t rid_batched_workspace_bytes(int32_t max_n, int32_t max_kmax, int32_t b,
                                    const rid_config* cfg) {
   if (max_n < 1 || max_n > rid::kBMaxN || max_kmax < 1 || b < 1 || b > rid::kBPW ||
-      !valid_cfg(cfg))
+      !valid_batched_cfg(cfg))
     return 0;
   BPlan P;
   if (!bplan(max_n, std::min(max_kmax, max_n), b, cfg->dtype, P)) return 0;
@@ -650,7 +748,7 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
                      void* const* T, const int64_t* ldt, int32_t* k_out, double* err_est,
                      int32_t* status, int32_t* passes, const int32_t* order, int32_t max_n,
                      int32_t max_kmax, void* work, size_t work_bytes, hipStream_t stream) {
-  if (nblk < 0 || !valid_cfg(cfg) || b < 1 || b > rid::kBPW || !(tol >= 0.0) || max_n < 1 ||
+  if (nblk < 0 || !valid_batched_cfg(cfg) || b < 1 || b > rid::kBPW || !(tol >= 0.0) || max_n < 1 ||
       max_n > rid::kBMaxN || max_kmax < 1 || !work)
     return RID_ERR_ARG;
   if (nblk == 0) return RID_OK;
@@ -677,6 +775,14 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
                        err_est, status, passes, order, queue, base, P.slice, max_n, maxk, P.ldz,
                        P.ldl, P.ldu);
   prof_end(pm, stream);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_debug_mfma_probe(int kind, const void* A, const void* B, float* D, hipStream_t stream) {
+  if (kind < 0 || kind > 3 || !A || !B || !D) return RID_ERR_ARG;
+  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, stream, kind,
+                     static_cast<const unsigned char*>(A), static_cast<const unsigned char*>(B), D);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }

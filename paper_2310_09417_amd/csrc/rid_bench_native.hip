@@ -55,7 +55,7 @@ int main(int argc, char** argv) {
   float* A = nullptr;
   CHECK(hipMalloc(&A, (size_t)m * n * sizeof(float)));
   if (rid_debug_gaussian(7, 0, m, n, RID_F32, A, st) != RID_OK) return 2;
-  rid_config cfg{RID_F32, 1, 1};
+  rid_config cfg{RID_F32, 1, 1, RID_F32, nullptr, 0};
   const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
   const size_t wb = rid_workspace_bytes(m, n, kmax, b, &cfg);
   void* work = nullptr;

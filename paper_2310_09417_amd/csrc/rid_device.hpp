@@ -110,6 +110,39 @@ struct Mfma<double> {
   __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
+// Low-precision tiles, FP32 accumulate: 16x16x32 BF16 and 16x16x32 FP8-e4m3
+// (OCP format).  Lane l supplies 8 entries of A row l%16 and 8 entries of B
+// column l%16, both at k = 8*(l/16) .. 8*(l/16)+7 (any relabelling of k that
+// both operands share gives the same product); the accumulator is laid out as
+// for the FP32 16x16x4 instruction (row 4*(l/16)+r, column l%16).
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ floatx4 mfma_bf16x32(u32x4 a, u32x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                 __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma_fp8x32(u32x2 a, u32x2 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a),
+                                                    __builtin_bit_cast(long, b), c, 0, 0, 0);
+}
+
+// FP32 -> BF16 bit pattern, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+// Two FP32 values -> two OCP e4m3 codes (round to nearest even), packed in
+// the low 16 bits: a in bits 0-7, b in bits 8-15.
+__device__ __forceinline__ uint32_t fp8x2_rne(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+}
+// OCP e4m3 code in byte `sel` of v -> FP32.
+template <int SEL>
+__device__ __forceinline__ float fp8_to_f32(uint32_t v) {
+  return __builtin_amdgcn_cvt_f32_fp8((int)v, SEL);
+}
+
 // ---------------------------------------------------------------------------
 // Wave64 / workgroup reductions.
 // ---------------------------------------------------------------------------

@@ -895,6 +895,56 @@ __global__ void k_outputs(const Ctrl* ctrl, const int* __restrict__ order, int64
   }
 }
 
+// Test export: checks, in one wave, the operand and accumulator layouts and
+// the number conversions the low-precision sketch relies on.
+//   kind 0: D = A B, A 16 x 32 and B 32 x 16 BF16 bit patterns (row-major)
+//   kind 1: D = A B, A 16 x 32 and B 32 x 16 OCP e4m3 codes (row-major)
+//   kind 2: A holds 64 FP32 values x_i; D[i] = BF16 bits of x_i and
+//           D[64 + i] = e4m3 code of x_i (both round to nearest even)
+//   kind 3: B holds the 256 e4m3 codes; D[c] = value of code c
+// D is 16 x 16 FP32.  Buffers: kinds 0/1 read 1024/512 bytes of A and B,
+// kind 2 reads 256 bytes of A, kind 3 256 bytes of B.
+__global__ void k_mfma_probe(int kind, const unsigned char* __restrict__ A,
+                             const unsigned char* __restrict__ B, float* __restrict__ D) {
+  const int l = threadIdx.x;
+  if (l >= 64) return;
+  const int g = l >> 4, ij = l & 15;
+  if (kind == 2) {
+    const float x = reinterpret_cast<const float*>(A)[l];
+    D[l] = (float)bf16_rne(x);
+    D[64 + l] = (float)(fp8x2_rne(x, 0.0f) & 0xffu);
+    return;
+  }
+  if (kind == 3) {
+    const uint32_t v = reinterpret_cast<const uint32_t*>(B)[l];
+    D[4 * l + 0] = fp8_to_f32<0>(v);
+    D[4 * l + 1] = fp8_to_f32<1>(v);
+    D[4 * l + 2] = fp8_to_f32<2>(v);
+    D[4 * l + 3] = fp8_to_f32<3>(v);
+    return;
+  }
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (kind == 0) {
+    const unsigned short* a = reinterpret_cast<const unsigned short*>(A);
+    const unsigned short* b = reinterpret_cast<const unsigned short*>(B);
+    u32x4 av, bv;
+    for (int e = 0; e < 4; ++e) {
+      av[e] = (uint32_t)a[ij * 32 + 8 * g + 2 * e] | ((uint32_t)a[ij * 32 + 8 * g + 2 * e + 1] << 16);
+      bv[e] = (uint32_t)b[(8 * g + 2 * e) * 16 + ij] |
+              ((uint32_t)b[(8 * g + 2 * e + 1) * 16 + ij] << 16);
+    }
+    acc = mfma_bf16x32(av, bv, acc);
+  } else {
+    u32x2 av = {0u, 0u}, bv = {0u, 0u};
+    for (int e = 0; e < 8; ++e) {
+      av[e >> 2] |= (uint32_t)A[ij * 32 + 8 * g + e] << (8 * (e & 3));
+      bv[e >> 2] |= (uint32_t)B[(8 * g + e) * 16 + ij] << (8 * (e & 3));
+    }
+    acc = mfma_fp8x32(av, bv, acc);
+  }
+  for (int r = 0; r < 4; ++r) D[(4 * g + r) * 16 + ij] = acc[r];
+}
+
 // Test export: materialised Gaussian block out[c*m + i] = omega(c0 + c, i).
 template <typename T>
 __global__ void k_gaussian(uint32_t key0, uint32_t key1, int64_t c0, int64_t w, int64_t m,

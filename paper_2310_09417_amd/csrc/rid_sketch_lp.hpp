@@ -1,0 +1,283 @@
+// Low-precision sketch Y = Omega A with A stored as BF16 or as OCP FP8-e4m3
+// codes with one power-of-two scale per 128-column tile (the sketch step of
+// Sec. 2.4 and Alg. 1, run on matrix cores with FP32 accumulation).
+//
+// Omega is generated as in the FP32 path (Philox4x32-10 + Box-Muller in FP32,
+// the same counters) and rounded to nearest even into the format of A, so
+// each sketch vector is a fixed, slightly rounded Gaussian vector: rounding
+// the embedding changes which random matrix is used, not the method.
+//
+// Geometry: 256 threads (4 waves, one per SIMD) own 1024 columns and a range
+// of rows_per_split rows.  Per k-step of 32 rows every lane loads 8 rows of 16
+// columns of A, transposes them in registers into the 16x16x32 operand form
+// (8 consecutive rows of one column), and multiplies them by the 4 Omega
+// tiles (64 vectors) it reads from LDS.  Omega for the next k-step is
+// generated into the other LDS buffer while the current one is in use, so
+// each Gaussian value is reused across 1024 columns.
+//   BF16: lane columns {8cg .. 8cg+7} and {128+8cg .. 128+8cg+7} of its
+//         wave's 256 (two fully coalesced 16-byte loads per row).
+//   FP8:  lane columns {16cg .. 16cg+15} (one 16-byte load per row); all 16
+//         lie in one 128-column tile, so one scale covers them.
+// The FP32 accumulators of a workgroup hold the raw sum over its rows; the
+// partials part[split][col][64] (FP32) are summed in split order in FP64 by
+// k_sketch_reduce_lp, which also applies the FP8 column scale.  NORM also
+// accumulates sum A^2 (FP64 across k-steps) and flags non-finite entries.
+#pragma once
+
+#include "rid_kernels.hpp"
+
+namespace rid {
+
+constexpr int kLpCols = 1024;  // columns per workgroup
+constexpr int kLpKs = 32;      // rows per k-step
+
+// 16 bytes of row `row` from column `col` (zeros outside the matrix).  The
+// element-wise path serves segments that cross column n and unaligned A.
+template <int ES, bool VEC>
+__device__ __forceinline__ u32x4 lp_load16(const unsigned char* __restrict__ A, int64_t row,
+                                           int64_t r_end, int64_t col, int64_t n, int64_t lda) {
+  constexpr int NE = 16 / ES;  // entries in 16 bytes
+  if (row >= r_end) return u32x4{0u, 0u, 0u, 0u};
+  const unsigned char* p = A + (row * lda + col) * ES;
+  if (VEC && col + NE <= n) return *reinterpret_cast<const u32x4*>(p);
+  uint64_t lo = 0, hi = 0;
+#pragma unroll 1
+  for (int t = 0; t < NE && col + t < n; ++t) {
+    const uint64_t x = (ES == 2) ? (uint64_t) reinterpret_cast<const unsigned short*>(p)[t]
+                                 : (uint64_t)p[t];
+    const int sh = 8 * ES * t;
+    if (sh < 64)
+      lo |= x << sh;
+    else
+      hi |= x << (sh - 64);
+  }
+  return u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+}
+
+// BF16: the operand of column j (0..7) of the 8 rows x 8 columns held in
+// buf[base .. base+7] (row e; entries 2d, 2d+1 in dword d): entries of rows
+// e = 0..7 packed two per dword.
+__device__ __forceinline__ u32x4 lp_col_bf16(const u32x4 (&buf)[16], int base, int j) {
+  const int d = j >> 1;
+  u32x4 o;
+  if (j & 1) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      o[p] = (buf[base + 2 * p][d] >> 16) | (buf[base + 2 * p + 1][d] & 0xffff0000u);
+  } else {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      o[p] = (buf[base + 2 * p][d] & 0xffffu) | (buf[base + 2 * p + 1][d] << 16);
+  }
+  return o;
+}
+
+// FP8: 4x4 byte transpose of rows x0..x3 (one dword each): out[s] holds byte
+// s of x0, x1, x2, x3 in bytes 0..3.
+__device__ __forceinline__ void lp_tr4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                       uint32_t out[4]) {
+  const uint32_t a_lo = (x0 & 0x00ff00ffu) | ((x1 & 0x00ff00ffu) << 8);
+  const uint32_t a_hi = ((x0 >> 8) & 0x00ff00ffu) | (x1 & 0xff00ff00u);
+  const uint32_t b_lo = (x2 & 0x00ff00ffu) | ((x3 & 0x00ff00ffu) << 8);
+  const uint32_t b_hi = ((x2 >> 8) & 0x00ff00ffu) | (x3 & 0xff00ff00u);
+  out[0] = (a_lo & 0xffffu) | (b_lo << 16);
+  out[1] = (a_hi & 0xffffu) | (b_hi << 16);
+  out[2] = (a_lo >> 16) | (b_lo & 0xffff0000u);
+  out[3] = (a_hi >> 16) | (b_hi & 0xffff0000u);
+}
+
+template <int FMT, bool NORM, bool VEC>
+__global__ __launch_bounds__(256) void k_sketch_lp(
+    const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+    const float* __restrict__ col_scale, uint32_t key0, uint32_t key1, uint32_t c0, int w,
+    int64_t rows_per_split, float* __restrict__ part, double* __restrict__ fro_part,
+    int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  constexpr int ES = FMT == 1 ? 2 : 1;     // bytes per entry of A and Omega
+  constexpr int WP = 64;                   // sketch vectors (padded)
+  constexpr int PITCH = kLpKs * ES + 16;   // LDS bytes per vector
+  __shared__ __align__(16) unsigned char om[2][WP * PITCH];
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cg = lane & 15, rs = lane >> 4;
+  const int64_t cbase = (int64_t)blockIdx.x * kLpCols + wave * 256;
+  const int64_t colA = (FMT == 1) ? cbase + 8 * cg : cbase + 16 * cg;  // first load
+  const int64_t colB = cbase + 128 + 8 * cg;                           // BF16 second load
+  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+  const int nks = (int)((r_end - r_begin + kLpKs - 1) / kLpKs);
+
+  floatx4 acc[4][16];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[a][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  double fro = 0.0;
+  bool bad = false;
+
+  // Omega for the k-step at row r0: 64 vectors x 8 row quads, two quads per
+  // thread (call g = 0, 1)
+  auto gen = [&](unsigned char* omb, int64_t r0, int g) {
+    const int it = tid + 256 * g;
+    const int c = it >> 3, qd = it & 7;
+    const int64_t row4 = r0 + 4 * qd;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c < w && row4 < r_end) gauss4<float>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (row4 + e >= r_end) v[e] = 0.f;
+    unsigned char* dst = omb + c * PITCH + 4 * qd * ES;
+    if (FMT == 1) {
+      uint2 p;
+      p.x = bf16_rne(v[0]) | (bf16_rne(v[1]) << 16);
+      p.y = bf16_rne(v[2]) | (bf16_rne(v[3]) << 16);
+      *reinterpret_cast<uint2*>(dst) = p;
+    } else {
+      *reinterpret_cast<uint32_t*>(dst) = fp8x2_rne(v[0], v[1]) | (fp8x2_rne(v[2], v[3]) << 16);
+    }
+  };
+
+  constexpr int NB = FMT == 1 ? 16 : 8;  // 16-byte loads per lane per k-step
+  auto load = [&](u32x4 (&buf)[NB], int64_t r0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t row = r0 + 8 * rs + e;
+      buf[e] = lp_load16<ES, VEC>(A, row, r_end, colA, n, lda);
+      if (FMT == 1) buf[(8 + e) % NB] = lp_load16<ES, VEC>(A, row, r_end, colB, n, lda);
+    }
+  };
+
+  auto norm_acc = [&](const u32x4 (&buf)[NB]) {
+    float f = 0.f;
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t x = buf[t][d];
+        if (FMT == 1) {
+          const float lo = __uint_as_float(x << 16), hi = __uint_as_float(x & 0xffff0000u);
+          f += lo * lo + hi * hi;
+          bad |= ((x & 0x7f80u) == 0x7f80u) || ((x & 0x7f800000u) == 0x7f800000u);
+        } else {
+          const float v0 = fp8_to_f32<0>(x), v1 = fp8_to_f32<1>(x);
+          const float v2 = fp8_to_f32<2>(x), v3 = fp8_to_f32<3>(x);
+          f += (v0 * v0 + v1 * v1) + (v2 * v2 + v3 * v3);
+          bad |= ((x & 0x7fu) == 0x7fu) || ((x & 0x7f00u) == 0x7f00u) ||
+                 ((x & 0x7f0000u) == 0x7f0000u) || ((x & 0x7f000000u) == 0x7f000000u);
+        }
+      }
+    fro += (double)f;
+  };
+
+  auto compute = [&](const unsigned char* omc, const u32x4 (&buf)[NB], unsigned char* omn,
+                     int64_t rnext, bool has_next) {
+    if (NORM) norm_acc(buf);
+    if constexpr (FMT == 1) {
+      u32x4 oa[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        oa[a] = *reinterpret_cast<const u32x4*>(omc + (16 * a + cg) * PITCH + 16 * rs);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (has_next && (j == 0 || j == 8)) gen(omn, rnext, j >> 3);
+        const u32x4 bv = lp_col_bf16(buf, j < 8 ? 0 : 8, j & 7);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a][j] = mfma_bf16x32(oa[a], bv, acc[a][j]);
+      }
+    } else {
+      u32x2 oa[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        oa[a] = *reinterpret_cast<const u32x2*>(omc + (16 * a + cg) * PITCH + 8 * rs);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        if (has_next && (d == 0 || d == 2)) gen(omn, rnext, d >> 1);
+        uint32_t lo[4], hi[4];
+        lp_tr4(buf[0][d], buf[1][d], buf[2][d], buf[3][d], lo);
+        lp_tr4(buf[4][d], buf[5][d], buf[6][d], buf[7][d], hi);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const u32x2 bv = {lo[s], hi[s]};
+#pragma unroll
+          for (int a = 0; a < 4; ++a) acc[a][4 * d + s] = mfma_fp8x32(oa[a], bv, acc[a][4 * d + s]);
+        }
+      }
+    }
+  };
+
+  // A for the next k-step is loaded into bB while bA is in use, then moved
+  // (one copy of the k-step body keeps the accumulators in place)
+  u32x4 bA[NB], bB[NB];
+  if (nks > 0) {
+    gen(om[0], r_begin, 0);
+    gen(om[0], r_begin, 1);
+    load(bA, r_begin);
+  }
+  __syncthreads();
+  for (int ks = 0; ks < nks; ++ks) {
+    const int64_t r0 = r_begin + (int64_t)ks * kLpKs;
+    const bool nx = ks + 1 < nks;
+    if (nx) load(bB, r0 + kLpKs);
+    compute(om[ks & 1], bA, om[(ks + 1) & 1], r0 + kLpKs, nx);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NB; ++t) bA[t] = bB[t];
+  }
+
+  // partials: accumulator (a, j) holds vectors 16a + 4rs + r of lane column j
+  const int64_t split = blockIdx.y;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int64_t col = (FMT == 1) ? ((j < 8) ? colA + j : colB + (j - 8)) : colA + j;
+    if (col < n) {
+      float* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP + 4 * rs;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) *reinterpret_cast<floatx4*>(dst + 16 * a) = acc[a][j];
+    }
+  }
+  if (NORM) {
+    if (FMT == 2 && colA < n) {
+      const double s = (double)col_scale[colA >> 7];
+      fro *= s * s;
+    }
+    fro = wave_sum(fro);
+    if (lane == 0) red[wave] = fro;
+    if (bad) atomicOr(nonfinite, 1);
+    __syncthreads();
+    if (tid == 0) fro_part[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
+// Sum of the FP32 split partials in split order (FP64), times the column
+// scale for FP8; writes Y^T into Z columns [zcol, zcol + w).  With `first`,
+// also finishes ||A||_F^2 and the non-finite check.
+template <typename TF>
+__global__ void k_sketch_reduce_lp(const float* __restrict__ part, int nsplit, int64_t n, int w,
+                                   const float* __restrict__ col_scale, TF* __restrict__ Z,
+                                   int64_t ldz, int zcol, const double* __restrict__ fro_part,
+                                   int nfro, const int* __restrict__ nonfinite, Ctrl* ctrl,
+                                   int first) {
+  if (ctrl && ctrl->done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * w) {
+    const int64_t j = t / w;
+    const int c = (int)(t % w);
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) s += (double)part[((size_t)sp * (size_t)n + (size_t)j) * 64 + c];
+    if (col_scale) s *= (double)col_scale[j >> 7];
+    Z[j * ldz + zcol + c] = (TF)s;
+  }
+  if (first && t == 0 && ctrl) {
+    double f = 0.0;
+    for (int i = 0; i < nfro; ++i) f += fro_part[i];
+    ctrl->frob2 = f;
+    if (*nonfinite) {
+      ctrl->status = ST_ERR_NONFINITE;
+      ctrl->done = 1;
+      ctrl->k = 0;
+    }
+  }
+}
+
+}  // namespace rid

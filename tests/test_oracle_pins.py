@@ -306,3 +306,51 @@ def test_robust_prefix_diagnostic(orc):
     B, _ = workloads.fast_decay(300, 200, decades=16.0, seed=2)
     o2 = orc.rid_fixed_rank(B, 190, 0, seed=3)  # sigma_190 ~ 1e-15: inside the floor
     assert 0 < o2.robust_k < 190
+
+
+# ---- rounding into BF16 / OCP e4m3 and the rounded-Gaussian sketch --------
+
+def test_round_format_matches_torch_conversions(orc):
+    """The oracle's round-to-nearest-even into BF16 and e4m3 agrees with
+    torch's own conversions on float32 inputs across both formats' ranges,
+    subnormal e4m3 values included (overflow excluded: torch maps it to NaN,
+    the oracle saturates)."""
+    import torch
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.standard_normal(4000),
+                        np.exp(rng.uniform(np.log(2.0 ** -12), np.log(440.0), 4000))
+                        * rng.choice([-1.0, 1.0], 4000)]).astype(np.float32)
+    bf = torch.as_tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    f8 = torch.as_tensor(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(orc.round_format(x, orc.FMT_BF16), bf)
+    assert np.array_equal(orc.round_format(x, orc.FMT_E4M3), f8)
+
+
+def test_round_format_ties_and_subnormals(orc):
+    """Values fixed by the format definitions: halfway cases go to the even
+    significand, e4m3 subnormals are spaced 2^-9, magnitudes above 448
+    saturate."""
+    bf = [(1 + 2 ** -8, 1.0), (1 + 3 * 2 ** -8, 1 + 2 ** -6), (-(1 + 2 ** -8), -1.0),
+          (3.0, 3.0), (2 ** -130, 2 ** -130)]
+    e4 = [(17.0, 16.0), (19.0, 20.0), (2 ** -10, 0.0), (3 * 2 ** -10, 2 ** -8),
+          (2 ** -9, 2 ** -9), (5 * 2 ** -11, 2 ** -9), (460.0, 448.0), (1000.0, 448.0),
+          (-1000.0, -448.0), (0.3, 0.3125)]
+    for x, want in bf:
+        assert orc.round_format(x, orc.FMT_BF16) == want, x
+    for x, want in e4:
+        assert orc.round_format(x, orc.FMT_E4M3) == want, x
+    assert orc.round_format(0.1234, orc.FMT_NONE) == 0.1234
+
+
+def test_sketch_format_of_identity_is_rounded_omega(orc):
+    """With A = I the sketch returns Omega itself: for each format it must be
+    the Gaussian block rounded entry by entry, and without a format it must
+    be the plain sketch."""
+    m = 37
+    I = np.eye(m)
+    om = orc.omega(5, 3, 6, m)
+    for fmt in (orc.FMT_BF16, orc.FMT_E4M3):
+        Y = orc.sketch(I, 5, 3, 6, fmt)
+        assert np.array_equal(Y, orc.round_format(om, fmt))
+        assert np.array_equal(orc.omega_format(5, 3, 6, m, fmt), Y)
+    assert np.array_equal(orc.sketch(I, 5, 3, 6), om)

@@ -138,3 +138,61 @@ def kernel_blocks_device(nblk: int, seed: int, device="cuda", dtype=None, lo: in
         K = 1.0 / torch.cdist(xd, yd)
         out.append(K if dtype is None else K.to(dtype))
     return out, shapes
+
+
+def quantize_bf16(A: np.ndarray):
+    """Round A to BF16 (round to nearest even).  Returns (uint16 bit patterns,
+    the represented values as float64)."""
+    import torch
+    t = torch.as_tensor(np.ascontiguousarray(A, dtype=np.float32)).to(torch.bfloat16)
+    bits = t.view(torch.int16).numpy().view(np.uint16).copy()
+    return bits, t.to(torch.float64).numpy()
+
+
+def quantize_fp8_e4m3(A: np.ndarray, tile: int = 128):
+    """Scale each tile of 128 columns by a power of two s = 2^floor(log2(448 /
+    max|tile|)) and round to OCP FP8-e4m3 (nearest even).  Returns (uint8
+    codes, inverse scales 1/s per tile as float32, the represented values
+    codes * (1/s) as float64)."""
+    import torch
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    ntile = (n + tile - 1) // tile
+    inv = np.ones(ntile, dtype=np.float32)
+    scaled = np.empty_like(A)
+    for t in range(ntile):
+        sl = slice(t * tile, min(n, (t + 1) * tile))
+        amax = np.abs(A[:, sl]).max()
+        e = int(np.floor(np.log2(448.0 / amax))) if amax > 0 else 0
+        if amax * 2.0 ** e > 448.0:
+            e -= 1
+        scaled[:, sl] = A[:, sl] * (2.0 ** e)
+        inv[t] = np.float32(2.0 ** (-e))
+    q = torch.as_tensor(scaled.astype(np.float32)).to(torch.float8_e4m3fn)
+    codes = q.view(torch.uint8).numpy().copy()
+    vals = q.to(torch.float64).numpy()
+    for t in range(ntile):
+        sl = slice(t * tile, min(n, (t + 1) * tile))
+        vals[:, sl] *= float(inv[t])
+    return codes, inv, vals
+
+
+def quantize_device(A, fmt: str, tile: int = 128):
+    """Storage conversion of a device matrix (input preparation, outside any
+    timed region).  'bf16': A rounded to BF16 (nearest even), scale None.
+    'fp8': OCP e4m3 codes of A scaled per tile of 128 columns by the power of
+    two s = 2^floor(log2(448 / max|tile|)), and the float32 inverse scales
+    1/s (one per tile).  Returns (stored matrix, inverse scales or None)."""
+    import torch
+    if fmt == "bf16":
+        return A.to(torch.bfloat16), None
+    assert fmt == "fp8"
+    m, n = A.shape
+    nt = (n + tile - 1) // tile
+    amax = A.abs().amax(dim=0).to(torch.float64)
+    amax = torch.nn.functional.pad(amax, (0, nt * tile - n)).view(nt, tile).amax(dim=1)
+    e = torch.where(amax > 0, torch.floor(torch.log2(448.0 / amax)), torch.zeros_like(amax))
+    e = torch.where(amax * torch.exp2(e) > 448.0, e - 1, e)
+    scale = torch.exp2(e).repeat_interleave(tile)[:n].to(A.dtype)
+    codes = (A * scale[None, :]).to(torch.float8_e4m3fn)
+    return codes, torch.exp2(-e).to(torch.float32).contiguous()
