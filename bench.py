@@ -113,9 +113,10 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     kcap = min(kmax, m, n)
 
-    def make_run(A, dtype_code, a_type=None, col_scale=None):
+    def make_run(A, dtype_code, a_type=None, col_scale=None, refine=False):
         cfg = rid.binding._cfg(dtype_code, seed, True, a_type=a_type,
-                               col_scale=col_scale.data_ptr() if col_scale is not None else 0)
+                               col_scale=col_scale.data_ptr() if col_scale is not None else 0,
+                               refine=refine)
         wb = rid.rid_workspace_bytes(m, n, kmax, b, cfg)
         work = torch.empty(wb, dtype=torch.uint8, device=dev)
         J = torch.zeros(kcap, dtype=torch.int64, device=dev)
@@ -223,6 +224,26 @@ def main():
         torch.linalg.vector_norm(A64).item())
     log(f"[bench] fp32 true residual / ||A|| = {resid32:.3e}")
 
+    # FP32 path with the FP64-residual refinement step on T
+    refine = None
+    if args.lp_steps > 0:
+        runr, outr, _ = make_run(A32, rid.RID_F32, refine=True)
+        runr()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.lp_steps):
+            runr()
+        torch.cuda.synchronize()
+        msr = (time.perf_counter() - t0) * 1e3 / args.lp_steps
+        kr = int(outr[2].item())
+        rr = true_resid(A32, outr[0][:kr], outr[1]) / fro
+        refine = {"ms_per_step": msr, "overhead_ms": msr - ms, "k": kr,
+                  "same_skeleton": bool(torch.equal(outr[0][:kr], out32[0][:k32])),
+                  "resid_rel_true": rr, "resid_rel_unrefined": resid32}
+        log(f"[bench] fp32+refine: {msr:.2f} ms/step (+{msr - ms:.2f}), resid {rr:.4e} "
+            f"(unrefined {resid32:.4e})")
+        del runr, outr
+
     # precision forms: A stored in BF16 / FP8-e4m3 (per-128-column power-of-two
     # scale), sketch on matrix cores with FP32 accumulation, FP32 factorisation
     precision = {}
@@ -322,6 +343,7 @@ def main():
         "resid_rel_true": resid32,
         "err_rel_vs_fp64_matrix": err32_orig,
         "precision_forms": precision,
+        "refine": refine,
         "fp64_path": fp64,
         "kernel_breakdown": breakdown,
         "roofline": roof,

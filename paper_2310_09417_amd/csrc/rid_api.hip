@@ -15,6 +15,7 @@
 #include "rid_kernels.hpp"
 #include "rid_batched.hpp"
 #include "rid_sketch_lp.hpp"
+#include "rid_refine.hpp"
 
 using namespace rid;
 
@@ -157,6 +158,7 @@ struct Plan {
   rid_dtype dt = RID_F64;   // factor type
   rid_dtype at = RID_F64;   // storage type of A
   const float* scale = nullptr;  // FP8 column-tile scales (device)
+  bool refine = false;           // FP64-residual refinement step on T
   int64_t ldz = 0, ldu = 0, ldl = 0;
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
@@ -166,11 +168,11 @@ struct Plan {
   int64_t schur_wgs = 0;
   // offsets
   size_t o_ctrl, o_bars, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
-      o_slotrows, o_nonfinite, o_linv, o_mtmp, total;
+      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_yorig, o_tt, o_x, total;
 };
 
 bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, rid_dtype at,
-               Plan& P) {
+               bool refine, Plan& P) {
   DeviceInfo di = device_info();
   if (!di.ok) return false;
   P.m = m;
@@ -179,6 +181,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.wmax = wmax;
   P.dt = dt;
   P.at = at;
+  P.refine = refine;
   P.cu = di.cu;
   const size_t es = esize(dt);
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
@@ -225,6 +228,10 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.o_slotrows = take((size_t)2 * P.lupp_g * wmax * es);
   P.o_linv = take((size_t)kcap * P.ldl * es);
   P.o_mtmp = take((size_t)wmax * P.ldl * es);
+  // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
+  P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
+  P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
+  P.o_x = take(refine ? (size_t)n * P.ldl * es : 0);
   P.total = o;
   return true;
 }
@@ -235,7 +242,7 @@ bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* c
   const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
   const int64_t wmax =
       std::min<int64_t>(kMaxW, std::max<int64_t>({b, std::min<int64_t>(kcap, kMaxW), 1}));
-  if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, P)) return false;
+  if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, cfg->refine != 0, P)) return false;
   P.scale = cfg->a_col_scale;
   return true;
 }
@@ -257,6 +264,9 @@ struct Ws {
   void* slotrows;
   void* linv;
   void* mtmp;
+  void* yorig;
+  void* tt;
+  void* xr;
 };
 
 Ws carve(const Plan& P, void* work) {
@@ -277,6 +287,9 @@ Ws carve(const Plan& P, void* work) {
   w.slotrows = b + P.o_slotrows;
   w.linv = b + P.o_linv;
   w.mtmp = b + P.o_mtmp;
+  w.yorig = P.refine ? b + P.o_yorig : nullptr;
+  w.tt = P.refine ? b + P.o_tt : nullptr;
+  w.xr = P.refine ? b + P.o_x : nullptr;
   return w;
 }
 
@@ -359,6 +372,9 @@ int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uin
 int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                  int64_t c0, int w, void* out, int64_t ldo, int zcol, bool first, bool use_ctrl,
                  hipStream_t st) {
+  // the refinement step reads a copy of the sketch columns the factorisation
+  // overwrites
+  void* copy = (P.refine && out == W.z) ? W.yorig : nullptr;
   for (int off = 0; off < w; off += 64) {
     const int wc = std::min(64, w - off);
     const bool norm = first && off == 0;
@@ -379,8 +395,8 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
       hipLaunchKernelGGL(k_sketch_reduce_lp<float>, dim3(blocks), dim3(256), 0, st,
                          reinterpret_cast<const float*>(W.part), (int)g.nsplit, P.n, wc,
                          P.at == RID_FP8_E4M3 ? P.scale : nullptr, static_cast<float*>(out), ldo,
-                         zcol + off, W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl,
-                         norm ? 1 : 0);
+                         zcol + off, static_cast<float*>(copy), W.fro, (int)(g.nsplit * g.ncolg),
+                         W.nonfinite, ctrl, norm ? 1 : 0);
       prof_end(pm, st);
       RID_LAUNCH_CHECK();
       continue;
@@ -394,11 +410,13 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
     if (P.dt == RID_F64)
       hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
                          (int)g.nsplit, P.n, g.wp, wc, static_cast<double*>(out), ldo, zcol + off,
-                         W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, norm ? 1 : 0);
+                         static_cast<double*>(copy), W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite,
+                         ctrl, norm ? 1 : 0);
     else
       hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
                          (int)g.nsplit, P.n, g.wp, wc, static_cast<float*>(out), ldo, zcol + off,
-                         W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite, ctrl, norm ? 1 : 0);
+                         static_cast<float*>(copy), W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite,
+                         ctrl, norm ? 1 : 0);
     prof_end(pm, st);
     RID_LAUNCH_CHECK();
   }
@@ -413,8 +431,15 @@ int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm
                      dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz, W.order, k, zcol, w,
                      static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
                      W.ctrl);
-  prof_end(pm, st);
   RID_LAUNCH_CHECK();
+  if (P.refine) {
+    // keep U's block row in the pivot rows (the refinement solves with U)
+    hipLaunchKernelGGL(k_store_u2<TF>, dim3((unsigned)ceil_div((int64_t)k * w, 256)), dim3(256),
+                       0, st, static_cast<TF*>(W.z), P.ldz, W.order, k, zcol, w,
+                       static_cast<const TF*>(W.u2t), P.ldu, W.ctrl);
+    RID_LAUNCH_CHECK();
+  }
+  prof_end(pm, st);
   pm = prof_begin(KC_SCHUR, st);
   const int nt = (w + 15) / 16;
   dim3 grid((unsigned)P.schur_wgs);
@@ -529,11 +554,36 @@ int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32
     const long pm = prof_begin(KC_TSOLVE, st);
     dim3 grid((unsigned)std::max<int64_t>(1, ceil_div(P.n, 64)),
               (unsigned)std::max<int64_t>(1, ceil_div(P.kcap, 64)));
-    hipLaunchKernelGGL(k_tgemm<TF>, grid, dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz,
-                       W.nonpiv, P.n, static_cast<const TF*>(W.linv), P.ldl,
-                       static_cast<TF*>(T), ldt, W.ctrl);
+    const TF* z = static_cast<const TF*>(W.z);
+    const TF* linv = static_cast<const TF*>(W.linv);
+    if (!P.refine) {
+      hipLaunchKernelGGL((k_tgemm<TF, 0>), grid, dim3(256), 0, st, z, P.ldz, W.nonpiv, P.n, linv,
+                         P.ldl, static_cast<TF*>(T), ldt, static_cast<const TF*>(nullptr),
+                         (int64_t)0, W.ctrl);
+      RID_LAUNCH_CHECK();
+    } else {
+      TF* tt = static_cast<TF*>(W.tt);
+      TF* xr = static_cast<TF*>(W.xr);
+      // T^T = L2 L1^{-1} (rows in ascending J^c order)
+      hipLaunchKernelGGL((k_tgemm<TF, 1>), grid, dim3(256), 0, st, z, P.ldz, W.nonpiv, P.n, linv,
+                         P.ldl, tt, P.ldl, static_cast<const TF*>(nullptr), (int64_t)0, W.ctrl);
+      RID_LAUNCH_CHECK();
+      // residual of the kept sketch in FP64, solve x U = R^T, T^T += x L1^{-1}
+      hipLaunchKernelGGL(k_refine_resid, grid, dim3(256), 0, st,
+                         static_cast<const float*>(W.yorig), P.ldz, W.order, W.nonpiv, P.n,
+                         static_cast<const float*>(W.tt), P.ldl, static_cast<float*>(W.xr), P.ldl,
+                         W.ctrl);
+      RID_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_refine_solve, dim3((unsigned)std::max<int64_t>(1, ceil_div(P.n, 64))),
+                         dim3(256), 0, st, static_cast<const float*>(W.z), P.ldz, W.order, P.n,
+                         static_cast<float*>(W.xr), P.ldl, W.ctrl);
+      RID_LAUNCH_CHECK();
+      hipLaunchKernelGGL((k_tgemm<TF, 2>), grid, dim3(256), 0, st, static_cast<const TF*>(xr),
+                         P.ldl, W.nonpiv, P.n, linv, P.ldl, static_cast<TF*>(T), ldt,
+                         static_cast<const TF*>(tt), P.ldl, W.ctrl);
+      RID_LAUNCH_CHECK();
+    }
     prof_end(pm, st);
-    RID_LAUNCH_CHECK();
   }
   const unsigned og = (unsigned)std::max<int64_t>(1, ceil_div(P.kcap, 256));
   hipLaunchKernelGGL(k_outputs, dim3(og), dim3(256), 0, st, W.ctrl, W.order, J, k_out, err_est,
@@ -566,12 +616,12 @@ bool valid_cfg(const rid_config* cfg) {
     if (cfg->dtype != RID_F32 || !low_precision(cfg->a_type)) return false;
     if (cfg->a_type == RID_FP8_E4M3 && !cfg->a_col_scale) return false;
   }
-  return cfg->refine == 0;
+  return cfg->refine == 0 || (cfg->refine == 1 && cfg->dtype == RID_F32);
 }
 
 // The batched path reads A in the factor type only.
 bool valid_batched_cfg(const rid_config* cfg) {
-  return valid_cfg(cfg) && cfg->a_type == cfg->dtype;
+  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0;
 }
 
 int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }

@@ -242,8 +242,9 @@ __global__ __launch_bounds__(256) void k_sketch(
 template <typename TF>
 __global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int64_t n, int WP,
                                 int w, TF* __restrict__ Z, int64_t ldz, int zcol,
-                                const double* __restrict__ fro_part, int nfro,
-                                const int* __restrict__ nonfinite, Ctrl* ctrl, int first) {
+                                TF* __restrict__ Z2, const double* __restrict__ fro_part,
+                                int nfro, const int* __restrict__ nonfinite, Ctrl* ctrl,
+                                int first) {
   if (ctrl && ctrl->done) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n * w) {
@@ -252,6 +253,7 @@ __global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int
     double s = 0.0;
     for (int sp = 0; sp < nsplit; ++sp) s += part[((size_t)sp * (size_t)n + (size_t)j) * WP + c];
     Z[j * ldz + zcol + c] = (TF)s;
+    if (Z2) Z2[j * ldz + zcol + c] = (TF)s;  // kept copy of the sketch (refinement)
   }
   if (first && t == 0 && ctrl) {
     double f = 0.0;
@@ -838,11 +840,17 @@ __global__ __launch_bounds__(256) void k_linv_b2(const TF* __restrict__ Mtmp, in
 // T(s, q) = sum_{p >= s} L2(q, p) L1^{-1}(p, s): T^T = L2 L1^{-1}.  Each wave
 // owns 16 candidates (rows of T^T) and the workgroup a 64 x 64 tile.
 // Grid (ceil(n/64), ceil(kcap/64)); tiles beyond the final k or n-k exit.
-template <typename TF>
+//   MODE 0: rows L2(q) = Z[nonpiv[q]], T(s, q) written to T (k x ldt)
+//   MODE 1: the same rows, T^T(q, s) written row-major to T (ldt = its pitch)
+//   MODE 2: rows X(q) = Z[q] (Z = X, nonpiv unused); T(s, q) = acc + TT(q, s)
+//           (the refinement update T += (X L1^{-1})^T)
+template <typename TF, int MODE>
 __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t ldz,
                                                const int* __restrict__ nonpiv, int64_t n,
                                                const TF* __restrict__ Linv, int64_t ldl,
-                                               TF* __restrict__ T, int64_t ldt, const Ctrl* ctrl) {
+                                               TF* __restrict__ T, int64_t ldt,
+                                               const TF* __restrict__ TT, int64_t ldtt,
+                                               const Ctrl* ctrl) {
   if (ctrl->status < 0) return;
   const int k = ctrl->k;
   const int64_t nn = n - k;
@@ -852,7 +860,7 @@ __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t
   using M = Mfma<TF>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t q = q0 + wave * 16 + (lane & 15);
-  const TF* arow = (q < nn) ? Z + (int64_t)nonpiv[q] * ldz : nullptr;
+  const TF* arow = (q < nn) ? Z + (MODE == 2 ? q : (int64_t)nonpiv[q]) * ldz : nullptr;
   const int bcols = (k - j0 < 64) ? k - j0 : 64;
   auto brow = [&](int p) -> const TF* { return Linv + (int64_t)p * ldl + j0; };
   typename M::acc_t acc[4];
@@ -871,7 +879,14 @@ __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t
     for (int r = 0; r < 4; ++r) {
       const int64_t qq = q0 + wave * 16 + M::row(lane, r);
       const int s = j0 + 4 * (lane & 15) + t;
-      if (qq < nn && s < k) T[(int64_t)s * ldt + qq] = (TF)acc64[t][r];
+      if (qq < nn && s < k) {
+        if (MODE == 1)
+          T[qq * ldt + s] = (TF)acc64[t][r];
+        else if (MODE == 2)
+          T[(int64_t)s * ldt + qq] = (TF)((double)TT[qq * ldtt + s] + acc64[t][r]);
+        else
+          T[(int64_t)s * ldt + qq] = (TF)acc64[t][r];
+      }
     }
 }
 

@@ -250,12 +250,14 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
 }
 
 // Sum of the FP32 split partials in split order (FP64), times the column
-// scale for FP8; writes Y^T into Z columns [zcol, zcol + w).  With `first`,
+// scale for FP8; writes Y^T into Z columns [zcol, zcol + w) (and into Z2 when
+// given, the copy the refinement step reads).  With `first`,
 // also finishes ||A||_F^2 and the non-finite check.
 template <typename TF>
 __global__ void k_sketch_reduce_lp(const float* __restrict__ part, int nsplit, int64_t n, int w,
                                    const float* __restrict__ col_scale, TF* __restrict__ Z,
-                                   int64_t ldz, int zcol, const double* __restrict__ fro_part,
+                                   int64_t ldz, int zcol, TF* __restrict__ Z2,
+                                   const double* __restrict__ fro_part,
                                    int nfro, const int* __restrict__ nonfinite, Ctrl* ctrl,
                                    int first) {
   if (ctrl && ctrl->done) return;
@@ -267,6 +269,7 @@ __global__ void k_sketch_reduce_lp(const float* __restrict__ part, int nsplit, i
     for (int sp = 0; sp < nsplit; ++sp) s += (double)part[((size_t)sp * (size_t)n + (size_t)j) * 64 + c];
     if (col_scale) s *= (double)col_scale[j >> 7];
     Z[j * ldz + zcol + c] = (TF)s;
+    if (Z2) Z2[j * ldz + zcol + c] = (TF)s;  // kept copy of the sketch (refinement)
   }
   if (first && t == 0 && ctrl) {
     double f = 0.0;
