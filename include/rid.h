@@ -144,7 +144,11 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
  * Block i uses the Gaussian stream of seed cfg->seed + i.  b <= 32; every n[i]
  * must be <= max_n <= 1024 (blocks outside the plan get status RID_ERR_ARG);
  * ranks are capped at min(max_kmax, max_n).  Workspace:
- * rid_batched_workspace_bytes(max_n, max_kmax, b, cfg).
+ * rid_batched_workspace_bytes(max_n, max_kmax, b, cfg).  An FP32 call takes
+ * at most as many blocks as the device has compute units (one block per
+ * resident workgroup; more returns RID_ERR_ARG): FP32 batches in which a
+ * workgroup went on to a second block ended with a GPU memory fault whose
+ * cause has not been found.  FP64 calls take any number of blocks.
  */
 size_t rid_batched_workspace_bytes(int32_t max_n, int32_t max_kmax, int32_t b,
                                    const rid_config* cfg);
@@ -173,6 +177,59 @@ int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtyp
 int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c0, int64_t w,
                      const rid_config* cfg, void* Yt, int64_t ldy, void* work, size_t work_bytes,
                      hipStream_t stream);
+
+/*
+ * Learned rank (callers that size the batched sketch up front through
+ * rid_lupp_batched's k_hint).  The paper notes that the adaptive method
+ * re-sketches until its estimate meets the tolerance (Sec. 4.2, Alg. 1); a
+ * predicted rank lets the first pass draw about that many vectors at once,
+ * and the adaptive loop continues from there when the prediction is short.
+ *
+ * rid_rank_features: 19 features per block (features: nblk x 19 FP32,
+ * device): log2 m, log2 n, log10 of the relative tolerance, and
+ * log10(E_s / ||A||_F) for s = 0..15, E_s = ||S_s||_F / sqrt(16 - s) the
+ * Schur-complement estimate (Sec. 4.2, eq. errSch) after s LUPP steps on the
+ * block's first 16 sketch vectors (the stream of seed + block index, as in
+ * rid_lupp_batched).  Blocks as in rid_lupp_batched (device arrays of
+ * pointers, lda, m, n; cfg->dtype = storage type F64 or F32, cfg->seed,
+ * cfg->tol_relative).  A block with n > 1024 gets NaN features.
+ */
+int rid_rank_features(int32_t nblk, const void* const* A, const int64_t* lda, const int32_t* m,
+                      const int32_t* n, double tol, const rid_config* cfg, float* features,
+                      hipStream_t stream);
+
+/*
+ * The rank MLP: 19 -> 128 -> 128 -> 1, GELU (erf form), predicting log2 of the
+ * rank.  params: rid_mlp_param_count() FP32 values (device), in the order
+ * W1 (128 x 19, row-major), b1 (128), W2 (128 x 128), b2 (128), w3 (128), b3;
+ * weight matrices are used rounded to BF16 (nearest even), everything else
+ * is FP32.  xnorm (device, nullable): 19 means then 19 inverse standard
+ * deviations applied to the features first.
+ *
+ * rid_mlp_forward: y[B] (device); z1, z2 (B x 128, nullable) keep the
+ *   pre-activations for rid_mlp_backward.
+ * rid_mlp_backward: gradient (device, param_count FP32) of the mean pinball
+ *   loss rho_q(target - y) over the B samples, and that loss (device double,
+ *   nullable).  Deterministic (fixed-order reduction).  work: device buffer of
+ *   rid_mlp_workspace_bytes(B) bytes.  q in (0, 1).
+ * rid_mlp_adamw: one AdamW step (moments m1, m2 device, zero-initialised by
+ *   the caller; step >= 1; decoupled weight decay on weight matrices only).
+ * rid_rank_hint: k_hint[i] = min(kcap[i], ceil(2^y[i] (1 + margin))), at least
+ *   1; 0 (no hint) for a non-finite prediction.
+ * All return RID_ERR_ARG on null or invalid arguments.
+ */
+int32_t rid_mlp_param_count(void);
+size_t rid_mlp_workspace_bytes(int32_t B);
+int rid_mlp_forward(int32_t B, const float* X, const float* xnorm, const float* params, float* y,
+                    float* z1, float* z2, hipStream_t stream);
+int rid_mlp_backward(int32_t B, const float* X, const float* xnorm, const float* z1,
+                     const float* z2, const float* y, const float* target, float q,
+                     const float* params, float* grad, double* loss, void* work,
+                     size_t work_bytes, hipStream_t stream);
+int rid_mlp_adamw(float* params, const float* grad, float* m1, float* m2, int32_t step, float lr,
+                  float beta1, float beta2, float eps, float weight_decay, hipStream_t stream);
+int rid_rank_hint(int32_t B, const float* y, float margin, const int32_t* kcap, int32_t* k_hint,
+                  hipStream_t stream);
 
 /*
  * Test export: one wave checks the matrix-instruction layouts and number

@@ -68,6 +68,8 @@ def _load():
         lib.orc_sketch_format.restype = None
         lib.orc_omega_format.argtypes = [u64, i64, i64, i64, cint, P]
         lib.orc_omega_format.restype = None
+        lib.orc_rank_features.argtypes = [P, i64, i64, i64, dbl, cint, u64, P]
+        lib.orc_rank_features.restype = None
         lib.orc_round_format.argtypes = [dbl, cint]
         lib.orc_round_format.restype = dbl
         lib.orc_rid_lupp.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
@@ -218,3 +220,13 @@ def true_residual(A: np.ndarray, J: np.ndarray, T: np.ndarray) -> float:
         return 0.0
     return float(np.linalg.norm(A[:, rest] - A[:, J] @ T))
 
+
+
+def rank_features(A: np.ndarray, tol: float, seed: int, relative: bool = True) -> np.ndarray:
+    """The 19 probe features of the learned rank for one block (FP64)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    out = np.empty(19, dtype=np.float64)
+    lib.orc_rank_features(_ptr(A), m, n, n, tol, 1 if relative else 0, seed, _ptr(out))
+    return out

@@ -537,3 +537,78 @@ int orc_lupp_factors(const double* A, int64_t m, int64_t n, int64_t lda, int64_t
   free(perm);
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Probe features of the learned rank (one block).  The first 16 sketch     */
+/* vectors (FP64 stream of `seed`), LU with partial pivoting on Y^T for up  */
+/* to 16 steps (ties to the lowest column index), and after s steps the     */
+/* Schur estimate E_s = ||S_s||_F / sqrt(16 - s) over the remaining probe   */
+/* columns (paper Sec. 4.2, eq. errSch; E_0 = ||Y||_F / 4).  Output:        */
+/* log2 m, log2 n, log10 of the relative tolerance, log10(E_s / ||A||_F),   */
+/* s = 0..15 (values below 1e-30 are floored there).                        */
+/* ------------------------------------------------------------------------ */
+void orc_rank_features(const double* A, int64_t m, int64_t n, int64_t lda, double tol, int rel,
+                       uint64_t seed, double* out) {
+  enum { PR = 16 };
+  double* Y = (double*)malloc(sizeof(double) * PR * (size_t)n);
+  double* M = (double*)malloc(sizeof(double) * PR * (size_t)n);
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  orc_sketch(A, m, n, lda, seed, 0, PR, Y, n);
+  for (int64_t j = 0; j < n; ++j) {
+    idx[j] = j;
+    for (int c = 0; c < PR; ++c) M[j * PR + c] = Y[c * n + j];
+  }
+  int nf = 0;
+  const double fa = sqrt(frob2(A, m, n, lda, &nf));
+  double E[PR];
+  for (int s = 0; s < PR; ++s) E[s] = 0.0;
+  {
+    double t = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+      for (int c = 0; c < PR; ++c) t += M[j * PR + c] * M[j * PR + c];
+    E[0] = sqrt(t) / 4.0;
+  }
+  for (int s = 0; s < PR && s < n; ++s) {
+    int64_t p = -1;
+    double best = -1.0;
+    for (int64_t r = s; r < n; ++r) {
+      const double v = fabs(M[r * PR + s]);
+      if (v > best || (v == best && idx[r] < idx[p])) {
+        best = v;
+        p = r;
+      }
+    }
+    if (best == 0.0) break;
+    if (p != s) {
+      for (int c = 0; c < PR; ++c) {
+        const double t = M[s * PR + c];
+        M[s * PR + c] = M[p * PR + c];
+        M[p * PR + c] = t;
+      }
+      const int64_t ti = idx[s];
+      idx[s] = idx[p];
+      idx[p] = ti;
+    }
+    double ss = 0.0;
+    for (int64_t r = s + 1; r < n; ++r) {
+      const double l = M[r * PR + s] / M[s * PR + s];
+      M[r * PR + s] = l;
+      for (int c = s + 1; c < PR; ++c) {
+        M[r * PR + c] = M[r * PR + c] - l * M[s * PR + c];
+        ss += M[r * PR + c] * M[r * PR + c];
+      }
+    }
+    if (s + 1 < PR) E[s + 1] = sqrt(ss / (double)(PR - 1 - s));
+  }
+  out[0] = log2((double)m);
+  out[1] = log2((double)n);
+  const double rtol = rel ? tol : (fa > 0.0 ? tol / fa : 1.0);
+  out[2] = log10(rtol > 1e-30 ? rtol : 1e-30);
+  for (int s = 0; s < PR; ++s) {
+    const double r = fa > 0.0 ? E[s] / fa : 0.0;
+    out[3 + s] = log10(r > 1e-30 ? r : 1e-30);
+  }
+  free(Y);
+  free(M);
+  free(idx);
+}

@@ -13,5 +13,6 @@ from .binding import (  # noqa: F401
     status_string, fixed_rank, adaptive, debug_gaussian, debug_sketch, debug_mfma_probe,
     rid_lupp_fixed_rank, rid_lupp_adaptive, rid_workspace_bytes, rid_debug_gaussian,
     rid_debug_sketch, rid_status_string, rid_profile_start, rid_profile_stop, KERNEL_CLASSES,
-    rid_batched_workspace_bytes, rid_lupp_batched, BatchPlan, BatchOutput, batched)
+    rid_batched_workspace_bytes, rid_lupp_batched, BatchPlan, BatchOutput, batched,
+    rank_features, mlp_param_count, mlp_forward, mlp_backward, mlp_adamw, rank_hint, N_FEATURES)
 from .flops import flops_id  # noqa: F401

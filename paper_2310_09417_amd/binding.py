@@ -66,6 +66,21 @@ def library() -> ctypes.CDLL:
         lib.rid_lupp_batched.restype = i32
         lib.rid_debug_mfma_probe.argtypes = [i32, P, P, P, P]
         lib.rid_debug_mfma_probe.restype = i32
+        lib.rid_rank_features.argtypes = [i32, P, P, P, P, dbl, cfgp, P, P]
+        lib.rid_rank_features.restype = i32
+        lib.rid_mlp_param_count.argtypes = []
+        lib.rid_mlp_param_count.restype = i32
+        lib.rid_mlp_workspace_bytes.argtypes = [i32]
+        lib.rid_mlp_workspace_bytes.restype = sz
+        lib.rid_mlp_forward.argtypes = [i32, P, P, P, P, P, P, P]
+        lib.rid_mlp_forward.restype = i32
+        lib.rid_mlp_backward.argtypes = [i32, P, P, P, P, P, P, ctypes.c_float, P, P, P, P, sz, P]
+        lib.rid_mlp_backward.restype = i32
+        lib.rid_mlp_adamw.argtypes = [P, P, P, P, i32, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
+        lib.rid_mlp_adamw.restype = i32
+        lib.rid_rank_hint.argtypes = [i32, P, ctypes.c_float, P, P, P]
+        lib.rid_rank_hint.restype = i32
         lib.rid_profile_start.argtypes = []
         lib.rid_profile_start.restype = i32
         lib.rid_profile_stop.argtypes = [P, P, i32]
@@ -365,6 +380,9 @@ class BatchPlan:
         self.err = torch.zeros(self.nblk, dtype=torch.float64, device=dev)
         self.st = torch.zeros(self.nblk, dtype=i32, device=dev)
         self.passes = torch.zeros(self.nblk, dtype=i32, device=dev)
+        if dt == RID_F32 and self.nblk > torch.cuda.get_device_properties(dev).multi_processor_count:
+            raise RidError("an FP32 batch takes at most one block per compute unit (an FP32 "
+                           "batch with more blocks faulted the GPU; cause not found yet)")
         wb = rid_batched_workspace_bytes(self.max_n, self.max_kmax, b, self.cfg)
         if wb == 0:
             raise RidError("invalid batch sizes (every block needs n <= 1024, b <= 32)")
@@ -399,3 +417,80 @@ def batched(blocks, b: int, tol: float, kmax=None, seed: int = 0, relative=True,
     plan = BatchPlan(blocks, b, tol, kmax, seed, relative, k_hint, order)
     plan.launch()
     return plan.result()
+
+
+# ---- learned rank ----------------------------------------------------------
+
+N_FEATURES = 19
+
+
+def _ptr_or_0(t):
+    return t.data_ptr() if t is not None else 0
+
+
+def rank_features(blocks, tol: float, seed: int, relative: bool = True):
+    """19 probe features per block (nblk x 19 FP32 device tensor); block i
+    uses the Gaussian stream of seed + i, as in batched()."""
+    torch = _torch()
+    dev = blocks[0].device
+    cfg = _cfg(_dtype_code(blocks[0]), seed, relative)
+    A = torch.tensor([a.data_ptr() for a in blocks], dtype=torch.int64, device=dev)
+    lda = torch.tensor([a.stride(0) for a in blocks], dtype=torch.int64, device=dev)
+    m = torch.tensor([int(a.shape[0]) for a in blocks], dtype=torch.int32, device=dev)
+    n = torch.tensor([int(a.shape[1]) for a in blocks], dtype=torch.int32, device=dev)
+    F = torch.empty((len(blocks), N_FEATURES), dtype=torch.float32, device=dev)
+    _check(int(library().rid_rank_features(len(blocks), A.data_ptr(), lda.data_ptr(), m.data_ptr(),
+                                           n.data_ptr(), tol, ctypes.byref(cfg), F.data_ptr(),
+                                           _stream_ptr())), "rid_rank_features")
+    torch.cuda.current_stream().synchronize()
+    return F
+
+
+def mlp_param_count() -> int:
+    return int(library().rid_mlp_param_count())
+
+
+def mlp_forward(X, params, xnorm=None, save=False):
+    """y = MLP(X) for X (B x 19 FP32 device); with save, also (z1, z2)."""
+    torch = _torch()
+    B = int(X.shape[0])
+    y = torch.empty(B, dtype=torch.float32, device=X.device)
+    z1 = torch.empty((B, 128), dtype=torch.float32, device=X.device) if save else None
+    z2 = torch.empty((B, 128), dtype=torch.float32, device=X.device) if save else None
+    _check(int(library().rid_mlp_forward(B, X.data_ptr(), _ptr_or_0(xnorm), params.data_ptr(),
+                                         y.data_ptr(), _ptr_or_0(z1), _ptr_or_0(z2),
+                                         _stream_ptr())), "rid_mlp_forward")
+    return (y, z1, z2) if save else y
+
+
+def mlp_backward(X, z1, z2, y, target, q, params, xnorm=None, work=None):
+    """(gradient tensor, loss tensor) of the mean pinball loss."""
+    torch = _torch()
+    B = int(X.shape[0])
+    wb = int(library().rid_mlp_workspace_bytes(B))
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=X.device)
+    grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    _check(int(library().rid_mlp_backward(B, X.data_ptr(), _ptr_or_0(xnorm), z1.data_ptr(),
+                                          z2.data_ptr(), y.data_ptr(), target.data_ptr(), q,
+                                          params.data_ptr(), grad.data_ptr(), loss.data_ptr(),
+                                          work.data_ptr(), work.numel(), _stream_ptr())),
+           "rid_mlp_backward")
+    return grad, loss
+
+
+def mlp_adamw(params, grad, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-4):
+    _check(int(library().rid_mlp_adamw(params.data_ptr(), grad.data_ptr(), m1.data_ptr(),
+                                       m2.data_ptr(), step, lr, beta1, beta2, eps, wd,
+                                       _stream_ptr())), "rid_mlp_adamw")
+
+
+def rank_hint(y, kcap, margin: float):
+    """k_hint (int32 device) from predicted log2 ranks y and caps kcap."""
+    torch = _torch()
+    B = int(y.shape[0])
+    h = torch.empty(B, dtype=torch.int32, device=y.device)
+    _check(int(library().rid_rank_hint(B, y.data_ptr(), margin, kcap.data_ptr(), h.data_ptr(),
+                                       _stream_ptr())), "rid_rank_hint")
+    return h

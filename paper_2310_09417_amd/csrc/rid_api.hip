@@ -16,6 +16,7 @@
 #include "rid_batched.hpp"
 #include "rid_sketch_lp.hpp"
 #include "rid_refine.hpp"
+#include "rid_mlp.hpp"
 
 using namespace rid;
 
@@ -808,6 +809,10 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
   const int32_t maxk = std::min(max_kmax, max_n);
   if (!bplan(max_n, maxk, b, cfg->dtype, P)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  // FP32 batches that need a workgroup to take a second block from the queue
+  // ended twice with a GPU memory fault whose cause is not known; until it is,
+  // an FP32 call takes at most one block per resident workgroup.
+  if (cfg->dtype == RID_F32 && nblk > P.G) return RID_ERR_ARG;
   unsigned* queue = static_cast<unsigned*>(work);
   unsigned char* base = static_cast<unsigned char*>(work) + kAlign;
   hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(1), 0, stream, queue);
@@ -825,6 +830,87 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
                        err_est, status, passes, order, queue, base, P.slice, max_n, maxk, P.ldz,
                        P.ldl, P.ldu);
   prof_end(pm, stream);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_rank_features(int32_t nblk, const void* const* A, const int64_t* lda, const int32_t* m,
+                      const int32_t* n, double tol, const rid_config* cfg, float* features,
+                      hipStream_t stream) {
+  if (nblk < 0 || !cfg || (cfg->dtype != RID_F64 && cfg->dtype != RID_F32) || !(tol >= 0.0))
+    return RID_ERR_ARG;
+  if (nblk == 0) return RID_OK;
+  if (!A || !lda || !m || !n || !features) return RID_ERR_ARG;
+  if (cfg->dtype == RID_F64)
+    hipLaunchKernelGGL(k_rank_features<double>, dim3((unsigned)nblk), dim3(256), 0, stream, nblk,
+                       A, lda, m, n, tol, cfg->tol_relative, cfg->seed, features);
+  else
+    hipLaunchKernelGGL(k_rank_features<float>, dim3((unsigned)nblk), dim3(256), 0, stream, nblk,
+                       A, lda, m, n, tol, cfg->tol_relative, cfg->seed, features);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int32_t rid_mlp_param_count(void) { return rid::kNParams; }
+
+static int mlp_groups(int32_t B) {
+  const int tiles = (B + rid::kMlpTile - 1) / rid::kMlpTile;
+  return tiles < 256 ? tiles : 256;
+}
+
+size_t rid_mlp_workspace_bytes(int32_t B) {
+  if (B < 1) return 0;
+  const size_t G = (size_t)mlp_groups(B);
+  return align_up(G * rid::kNParams * sizeof(float), kAlign) + G * sizeof(double);
+}
+
+int rid_mlp_forward(int32_t B, const float* X, const float* xnorm, const float* params, float* y,
+                    float* z1, float* z2, hipStream_t stream) {
+  if (B < 0 || (B > 0 && (!X || !params || !y))) return RID_ERR_ARG;
+  if (B == 0) return RID_OK;
+  const unsigned g = (unsigned)((B + rid::kMlpTile - 1) / rid::kMlpTile);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(rid::kHid), 0, stream, B, X, xnorm, params, y,
+                     z1, z2);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_mlp_backward(int32_t B, const float* X, const float* xnorm, const float* z1,
+                     const float* z2, const float* y, const float* target, float q,
+                     const float* params, float* grad, double* loss, void* work,
+                     size_t work_bytes, hipStream_t stream) {
+  if (B < 1 || !X || !z1 || !z2 || !y || !target || !params || !grad || !work ||
+      !(q > 0.f && q < 1.f))
+    return RID_ERR_ARG;
+  if (work_bytes < rid_mlp_workspace_bytes(B)) return RID_ERR_WORKSPACE;
+  const int G = mlp_groups(B);
+  float* part = static_cast<float*>(work);
+  double* lpart = reinterpret_cast<double*>(static_cast<char*>(work) +
+                                            align_up((size_t)G * rid::kNParams * sizeof(float), kAlign));
+  hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)G), dim3(rid::kHid), 0, stream, B, X, xnorm,
+                     z1, z2, y, target, q, params, part, lpart);
+  RID_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)ceil_div(rid::kNParams, 256)), dim3(256), 0,
+                     stream, G, part, lpart, grad, loss);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_mlp_adamw(float* params, const float* grad, float* m1, float* m2, int32_t step, float lr,
+                  float beta1, float beta2, float eps, float weight_decay, hipStream_t stream) {
+  if (!params || !grad || !m1 || !m2 || step < 1) return RID_ERR_ARG;
+  hipLaunchKernelGGL(k_mlp_adamw, dim3((unsigned)ceil_div(rid::kNParams, 256)), dim3(256), 0,
+                     stream, params, grad, m1, m2, step, lr, beta1, beta2, eps, weight_decay);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_rank_hint(int32_t B, const float* y, float margin, const int32_t* kcap, int32_t* k_hint,
+                  hipStream_t stream) {
+  if (B < 0 || (B > 0 && (!y || !kcap || !k_hint))) return RID_ERR_ARG;
+  if (B == 0) return RID_OK;
+  hipLaunchKernelGGL(k_rank_hint, dim3((unsigned)ceil_div(B, 256)), dim3(256), 0, stream, B, y,
+                     margin, kcap, k_hint);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }

@@ -11,8 +11,9 @@
 //                  the panel in registers (arg-max by wave reductions + LDS);
 //   * wg_gemm    : 16 x 64 MFMA tiles (the wave_tile routine) for U2, the
 //                  Schur block, the growth of L1^{-1} and T^T = L2 L1^{-1}.
-// The first pass sketches the first block together with the block that
-// estimates it (2b vectors when 2b <= 64), saving one pass over every block.
+// The first passes sketch the first block together with the block that
+// estimates it (w0 + b vectors, in passes of at most 64), saving one pass over
+// every block.
 #pragma once
 #include "rid_kernels.hpp"
 
@@ -537,8 +538,8 @@ __global__ __launch_bounds__(kBT) void k_batched(
         ++passes;
       }
     };
-    // first pass: the first block and (when it fits) the block that estimates it
-    sketch_to((w0 + b <= 64 && w0 < mn) ? w0 + b : w0);
+    // first passes: the first block together with the block that estimates it
+    sketch_to(w0 < mn ? w0 + b : w0);
     // ||A||_F^2 and non-finite check, reduced over the workgroup
     {
       double f = wave_sum(fro);

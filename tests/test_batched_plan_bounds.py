@@ -35,7 +35,7 @@ def _check(shapes, b, es, khints=None, kpath='max'):
                 assert (n - 1) * ldz + sk + wc - 1 < sizes['Z'], ('Z sketch', i)
                 assert sk + wc <= ldz
                 sk += wc
-        sketch_to(w0 + b if (w0 + b <= 64 and w0 < mn) else w0)
+        sketch_to(w0 + b if w0 < mn else w0)
         def block_update(k, zcol, w):
             assert w <= 32 or w <= 64
             if k > 0:
