@@ -82,6 +82,8 @@ def main():
                     help="also time the 4096-block batched workload (off: see DESIGN.md)")
     ap.add_argument("--nblk", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--learned-blocks", type=int, default=1536,
+                    help="training blocks of the learned-rank section (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -318,6 +320,10 @@ def main():
     if args.batched:
         batched = bench_batched(args, torch, rid, workloads)
 
+    learned = None
+    if args.learned_blocks > 0:
+        learned = bench_learned(args, torch, rid, workloads)
+
     rec = {
         "metric": "ID GFLOP/s + blocks/s at tol 1e-6; speedup vs plain FP64 GPU path",
         "value": gflops,
@@ -349,9 +355,51 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
+        "learned_rank": learned,
         "source_hash": source_hash(),
     }
     print(json.dumps(rec), flush=True)
+
+
+def bench_learned(args, torch, rid, workloads):
+    """Learned rank: train the rank MLP on the GPU (labels from the FP64
+    batched path) and compare FP64 batched runs with and without its hints
+    on held-out kernel blocks (64-384 per side, tol 1e-10, b = 8)."""
+    import numpy as np
+    from paper_2310_09417_amd import learned_rank as lr
+    dev = torch.device("cuda:0")
+    tol, b, seed = 1e-10, 8, 100
+    t0 = time.time()
+    tr, _ = workloads.kernel_blocks_device(args.learned_blocks, 21, device=dev, lo=64, hi=384)
+    k, _ = lr.labels(tr, b, tol, seed)
+    F = rid.rank_features(tr, tol, seed)
+    t1 = time.time()
+    model, hist = lr.fit(F, k, epochs=40, batch=256, seed=0)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    del tr, F
+    te, _ = workloads.kernel_blocks_device(512, 77, device=dev, lo=64, hi=384)
+    res = lr.evaluate(te, model, b, tol, seed)
+    a, l = res["adaptive"], res["learned"]
+    out = {
+        "workload": "FP64 kernel blocks 1/|x-y| (cube separation 3-6), m,n uniform in "
+                    f"[64,384], tol {tol:g} relative, b={b}; {args.learned_blocks} training "
+                    "blocks, 512 held out",
+        "train_blocks": args.learned_blocks, "label_and_feature_s": t1 - t0,
+        "train_s": t2 - t1, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+        "adaptive": {"ms": a["ms"], "mean_passes": float(a["passes"].mean()),
+                     "mean_k": float(a["k"].mean()),
+                     "all_ok": bool(np.all(a["status"] == rid.RID_OK))},
+        "learned": {"ms": l["ms"], "mean_passes": float(l["passes"].mean()),
+                    "mean_k": float(l["k"].mean()), "fallback": l["fallback"],
+                    "all_ok": bool(np.all(l["status"] == rid.RID_OK))},
+        "speedup": a["ms"] / l["ms"],
+    }
+    log(f"[bench] learned rank: adaptive {a['ms']:.2f} ms ({out['adaptive']['mean_passes']:.2f} "
+        f"passes), learned {l['ms']:.2f} ms ({out['learned']['mean_passes']:.2f} passes, "
+        f"fallback {l['fallback']}/512), mean k {out['adaptive']['mean_k']:.1f} -> "
+        f"{out['learned']['mean_k']:.1f}")
+    return out
 
 
 def bench_batched(args, torch, rid, workloads):
