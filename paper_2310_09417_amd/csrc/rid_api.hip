@@ -86,7 +86,7 @@ inline void prof_end(long at, hipStream_t st) {
 }
 
 // Sketch launch geometry for a block of w <= 64 vectors: 256 columns per
-// workgroup, enough row splits for ~4 workgroups per CU.
+// workgroup, enough row splits for 2-8 rounds of workgroups.
 struct SketchGeom {
   int mt, wp, kc;
   int64_t ncolg, nsplit, rows_per_split;
@@ -98,9 +98,9 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   g.wp = g.mt * 16;
   g.kc = dt == RID_F64 ? 32 : 64;
   g.ncolg = ceil_div(n, 256);
-  // One resident workgroup per CU (the kernel holds ~440 registers per
-  // lane): pick the number of row splits whose workgroup count fills the
-  // last round best, between ~2 and ~8 rounds, preferring fewer splits.
+  // One resident workgroup per CU (FP32: 4 waves of ~440 registers; FP64:
+  // 8 waves of ~250): pick the number of row splits whose workgroup count
+  // fills the last round best, between ~2 and ~8 rounds, preferring fewer.
   const int64_t maxsplit = ceil_div(m, g.kc);
   const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(2 * cu, g.ncolg)));
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(maxsplit, ceil_div(8 * cu, g.ncolg)));
@@ -309,11 +309,11 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
   const long pm = prof_begin(KC_SKETCH, st);
   if (norm)
-    hipLaunchKernelGGL((k_sketch<TC, MT, KC, true, VEC>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((k_sketch<TC, MT, KC, true, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
                        g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
   else
-    hipLaunchKernelGGL((k_sketch<TC, MT, KC, false, VEC>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((k_sketch<TC, MT, KC, false, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
                        g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
   prof_end(pm, st);
@@ -336,9 +336,10 @@ template <typename TC, int KC>
 int launch_sketch(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                   int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
                   hipStream_t st) {
-  // 16-byte vector loads of 4 consecutive entries need lda % 4 == 0 and an
-  // aligned base
-  const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+  // vector loads of NQ consecutive entries need lda % NQ == 0 and a base
+  // aligned to 16 bytes (FP32: one 16-byte load; FP64: 16-byte pairs)
+  constexpr int NQ = SketchShape<TC>::NQ;
+  const bool vec = (lda % NQ == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
   return vec ? launch_sketch_mt<TC, KC, true>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st)
              : launch_sketch_mt<TC, KC, false>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
 }

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "rid_device.hpp"
 
 namespace rid {
@@ -65,10 +67,10 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, unsigned* bars, int nbar
 // ---------------------------------------------------------------------------
 // Sketch: partial sums of Y(c, j) = sum_i omega(c0 + c, i) A(i, j) over one
 // row range ("split") per grid row, for a strip of 256 columns per grid
-// column (4 waves x 64 columns).
-//   * A is streamed once.  Each lane loads 4 consecutive columns of one row
-//     (one 16- or 32-byte load) and feeds them to 4 different MFMAs, so MFMA
-//     q, output column j covers matrix column 4 j + q of the wave's strip.
+// column (FP32: 4 waves x 64 columns; FP64: 8 waves x 32 columns).
+//   * A is streamed once.  Each lane loads NQ consecutive columns of one row
+//     (one 16- or 32-byte load) and feeds them to NQ different MFMAs, so MFMA
+//     q, output column j covers matrix column NQ j + q of the wave's strip.
 //   * The A operands of the next KC-row chunk are loaded into registers while
 //     the current chunk is multiplied (register double buffering).
 //   * Omega is generated into LDS, double buffered: the next chunk's entries
@@ -79,6 +81,8 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, unsigned* bars, int nbar
 //   * Partials part[split][j][c] (FP64) are summed in split order by
 //     k_sketch_reduce, so the result does not depend on scheduling.
 //   * NORM: also accumulates sum A^2 (FP64) and flags non-finite entries.
+//   * Workgroups away from the matrix edges run the same loop without any
+//     bounds test (see `fast` below).
 // ---------------------------------------------------------------------------
 template <typename TC, bool VEC>
 __device__ __forceinline__ void load_row4(const TC* __restrict__ A, int64_t row, int64_t r_end,
@@ -105,35 +109,80 @@ __device__ __forceinline__ void load_row4(const TC* __restrict__ A, int64_t row,
   }
 }
 
+template <typename TC, bool VEC>
+__device__ __forceinline__ void load_row2(const TC* __restrict__ A, int64_t row, int64_t r_end,
+                                          int64_t col, int64_t n, int64_t lda, TC out[2]) {
+  if (row < r_end && col + 1 < n) {
+    const TC* p = A + row * lda + col;
+    if (VEC) {
+      if (sizeof(TC) == 4) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        out[0] = v.x; out[1] = v.y;
+      } else {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        out[0] = v.x; out[1] = v.y;
+      }
+    } else {
+      out[0] = p[0];
+      out[1] = p[1];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      out[e] = (row < r_end && col + e < n) ? A[row * lda + col + e] : TC(0);
+  }
+}
+
+// Threads per sketch workgroup: FP32 uses 4 columns per lane and one wave
+// per SIMD (256 threads); FP64 uses 2 columns per lane and two waves per SIMD
+// (512 threads), which lets one wave's Gaussian generation overlap the other's
+// MFMAs (measured 153 -> 141 ms per FP64 decomposition of the 50000 x 20000
+// matrix, while the FP32 variant was slower that way: 1.65 -> 1.93 ms/pass).
+template <typename TC>
+struct SketchShape {
+  static constexpr int NQ = sizeof(TC) == 4 ? 4 : 2;  // columns per lane
+  static constexpr int NT = 64 * 256 / (16 * NQ);     // 256 columns per workgroup
+};
+
 template <typename TC, int MT, int KC, bool NORM, bool VEC>
-__global__ __launch_bounds__(256) void k_sketch(
+__global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
     const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, uint32_t key0, uint32_t key1,
     uint32_t c0, int w, int64_t rows_per_split, double* __restrict__ part,
     double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
   if (ctrl && ctrl->done) return;
+  constexpr int NQ = SketchShape<TC>::NQ;
+  constexpr int NT = SketchShape<TC>::NT;
+  constexpr int NW = NT / 64;
   constexpr int WP = MT * 16;            // padded number of sketch vectors
   constexpr int LDO = WP + 16;           // LDS row pitch of Omega
   constexpr int KS = KC / 4;             // MFMA k-steps (and row quads) per chunk
-  constexpr int NGEN = (KS * WP + 255) / 256;  // gauss4 calls per thread per chunk
-  constexpr int GSTEP = KS / NGEN;             // k-steps between two of them
+  constexpr int NGEN = (KS * WP + NT - 1) / NT;  // gauss4 calls per thread per chunk
+  constexpr int GSTEP = KS / NGEN;               // k-steps between two of them
   static_assert(NGEN >= 1 && KS % NGEN == 0, "chunk geometry");
   using M = Mfma<TC>;
   using acc_t = typename M::acc_t;
   __shared__ TC om[2][KC * LDO];
-  __shared__ double red[4];
+  __shared__ double red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t col4 = (int64_t)blockIdx.x * 256 + wave * 64 + 4 * (lane & 15);
+  // a wave owns 16 NQ columns; lane l loads NQ consecutive columns from NQ (l % 16)
+  const int64_t colq = (int64_t)blockIdx.x * 256 + wave * 16 * NQ + NQ * (lane & 15);
   const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
   const int nch = (int)((r_end - r_begin + KC - 1) / KC);
+  // Interior workgroups (all 256 columns, all WP vectors, whole chunks, and
+  // one more chunk of rows after the range so that prefetching it stays
+  // inside A) run a loop without bounds tests.
+  const bool fast = VEC && (KS * WP) % NT == 0 && w == WP &&
+                    (int64_t)blockIdx.x * 256 + 256 <= n &&
+                    (r_end - r_begin) % KC == 0 && r_end + KC <= m;
 
-  acc_t acc[MT][4];
-  double acc64[MT][4][4];
+  acc_t acc[MT][NQ];
+  double acc64[MT][NQ][4];
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       acc[a][q] = M::zero();
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
@@ -141,84 +190,125 @@ __global__ __launch_bounds__(256) void k_sketch(
   double fro = 0.0;
   bool bad = false;
 
-  // Omega entries for row quads of chunk starting at r0, call index g
-  auto gen = [&](TC* omb, int64_t r0, int g) {
-    const int it = tid + g * 256;
-    if (it >= KS * WP) return;
-    const int c = it % WP, qd = it / WP;
-    const int64_t row4 = r0 + 4 * qd;
-    TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
-    if (c < w && row4 < r_end) gauss4<TC>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
+  auto body = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    // Omega entries for row quads of chunk starting at r0, call index g
+    auto gen = [&](TC* omb, int64_t r0, int g) {
+      const int it = tid + g * NT;
+      if (!FAST && it >= KS * WP) return;
+      const int c = it % WP, qd = it / WP;
+      const int64_t row4 = r0 + 4 * qd;
+      TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
+      if (FAST || (c < w && row4 < r_end))
+        gauss4<TC>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) omb[(4 * qd + a) * LDO + c] = (row4 + a < r_end) ? v[a] : TC(0);
-  };
-  auto loadB = [&](TC (&buf)[KS][4], int64_t r0) {
+      for (int a = 0; a < 4; ++a)
+        omb[(4 * qd + a) * LDO + c] = (FAST || row4 + a < r_end) ? v[a] : TC(0);
+    };
+    auto loadB = [&](TC (&buf)[KS][NQ], int64_t r0) {
 #pragma unroll
-    for (int j = 0; j < KS; ++j) load_row4<TC, VEC>(A, r0 + 4 * j + (lane >> 4), r_end, col4, n, lda, buf[j]);
-  };
-  // multiply one chunk (Omega in omc, A operands in buf) while generating the
-  // next chunk's Omega into omn
-  auto compute = [&](const TC* omc, TC (&buf)[KS][4], TC* omn, int64_t rnext, bool has_next) {
-#pragma unroll
-    for (int j = 0; j < KS; ++j) {
-      if (has_next && (j % GSTEP) == 0) gen(omn, rnext, j / GSTEP);
-      TC av[MT];
-#pragma unroll
-      for (int a = 0; a < MT; ++a) av[a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
-      if (NORM) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          fro += (double)buf[j][q] * (double)buf[j][q];
-          bad |= !__builtin_isfinite((double)buf[j][q]);
+      for (int j = 0; j < KS; ++j) {
+        const int64_t row = r0 + 4 * j + (lane >> 4);
+        if constexpr (NQ == 4) {
+          if (FAST) {
+            const TC* p = A + row * lda + colq;
+            if (sizeof(TC) == 4) {
+              const float4 v = *reinterpret_cast<const float4*>(p);
+              buf[j][0] = v.x; buf[j][1] = v.y; buf[j][2] = v.z; buf[j][3] = v.w;
+            } else {
+              const double2 v0 = *reinterpret_cast<const double2*>(p);
+              const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+              buf[j][0] = v0.x; buf[j][1] = v0.y; buf[j][2] = v1.x; buf[j][3] = v1.y;
+            }
+          } else {
+            load_row4<TC, VEC>(A, row, r_end, colq, n, lda, buf[j]);
+          }
+        } else {
+          if (FAST) {
+            const TC* p = A + row * lda + colq;
+            if (sizeof(TC) == 4) {
+              const float2 v = *reinterpret_cast<const float2*>(p);
+              buf[j][0] = v.x; buf[j][1] = v.y;
+            } else {
+              const double2 v = *reinterpret_cast<const double2*>(p);
+              buf[j][0] = v.x; buf[j][1] = v.y;
+            }
+          } else {
+            load_row2<TC, VEC>(A, row, r_end, colq, n, lda, buf[j]);
+          }
         }
       }
+    };
+    // multiply one chunk (Omega in omc, A operands in buf) while generating
+    // the next chunk's Omega into omn
+    auto compute = [&](const TC* omc, TC (&buf)[KS][NQ], TC* omn, int64_t rnext, bool has_next) {
 #pragma unroll
-      for (int a = 0; a < MT; ++a)
+      for (int j = 0; j < KS; ++j) {
+        if ((FAST || has_next) && (j % GSTEP) == 0) gen(omn, rnext, j / GSTEP);
+        TC av[MT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[a][q] = M::op(av[a], buf[j][q], acc[a][q]);
-    }
-    if (sizeof(TC) == 4) {
+        for (int a = 0; a < MT; ++a)
+          av[a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
+        if (NORM) {
 #pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
-          acc[a][q] = M::zero();
+          for (int q = 0; q < NQ; ++q) {
+            fro += (double)buf[j][q] * (double)buf[j][q];
+            bad |= !__builtin_isfinite((double)buf[j][q]);
+          }
         }
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc[a][q] = M::op(av[a], buf[j][q], acc[a][q]);
+      }
+      if (sizeof(TC) == 4) {
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
+            acc[a][q] = M::zero();
+          }
+      }
+    };
+
+    TC bA[KS][NQ], bB[KS][NQ];
+    if (nch > 0) {
+#pragma unroll
+      for (int g = 0; g < NGEN; ++g) gen(om[0], r_begin, g);
+      loadB(bA, r_begin);
+    }
+    __syncthreads();
+    for (int ci = 0; ci < nch; ci += 2) {
+      const int64_t r0 = r_begin + (int64_t)ci * KC;
+      const bool n1 = ci + 1 < nch, n2 = ci + 2 < nch;
+      if (n1) loadB(bB, r0 + KC);
+      compute(om[0], bA, om[1], r0 + KC, n1);
+      __syncthreads();
+      if (!n1) break;
+      if (n2) loadB(bA, r0 + 2 * KC);
+      compute(om[1], bB, om[0], r0 + 2 * KC, n2);
+      __syncthreads();
     }
   };
+  if (fast)
+    body(std::true_type{});
+  else
+    body(std::false_type{});
 
-  TC bA[KS][4], bB[KS][4];
-  if (nch > 0) {
-#pragma unroll
-    for (int g = 0; g < NGEN; ++g) gen(om[0], r_begin, g);
-    loadB(bA, r_begin);
-  }
-  __syncthreads();
-  for (int ci = 0; ci < nch; ci += 2) {
-    const int64_t r0 = r_begin + (int64_t)ci * KC;
-    const bool n1 = ci + 1 < nch, n2 = ci + 2 < nch;
-    if (n1) loadB(bB, r0 + KC);
-    compute(om[0], bA, om[1], r0 + KC, n1);
-    __syncthreads();
-    if (!n1) break;
-    if (n2) loadB(bA, r0 + 2 * KC);
-    compute(om[1], bB, om[0], r0 + 2 * KC, n2);
-    __syncthreads();
-  }
   if (sizeof(TC) == 8) {
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc64[a][q][r] = (double)acc[a][q][r];
   }
   const int64_t split = blockIdx.y;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t col = col4 + q;
+  for (int q = 0; q < NQ; ++q) {
+    const int64_t col = colq + q;
     if (col < n) {
       double* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP;
 #pragma unroll
@@ -232,7 +322,11 @@ __global__ __launch_bounds__(256) void k_sketch(
     if (lane == 0) red[wave] = fro;
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
-    if (tid == 0) fro_part[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (tid == 0) {
+      double t = 0.0;
+      for (int wv = 0; wv < NW; ++wv) t += red[wv];
+      fro_part[blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
   }
 }
 
