@@ -348,8 +348,10 @@ template <int FMT, bool NORM>
 int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                      int64_t c0, int w, const LpGeom& g, bool use_ctrl, hipStream_t st) {
   constexpr int ES = FMT == 1 ? 2 : 1;
-  // 16-byte vector loads: aligned base and rows of a multiple of 16 bytes
-  const bool vec = ((lda * ES) % 16 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+  // vector loads of 8 entries (16 bytes BF16, 8 bytes FP8): base and row
+  // pitch aligned to that size
+  const bool vec = ((lda * ES) % (8 * ES) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(A) & (size_t)(8 * ES - 1)) == 0);
   dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
@@ -357,11 +359,11 @@ int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uin
   float* part = reinterpret_cast<float*>(W.part);
   const long pm = prof_begin(KC_SKETCH, st);
   if (vec)
-    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, true>), grid, dim3(256), 0, st, a, P.m, P.n, lda,
+    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, true>), grid, dim3(kLpThreads), 0, st, a, P.m, P.n, lda,
                        P.scale, k0, k1, (uint32_t)c0, w, g.rows_per_split, part, W.fro,
                        W.nonfinite, ctrl);
   else
-    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, false>), grid, dim3(256), 0, st, a, P.m, P.n, lda,
+    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, false>), grid, dim3(kLpThreads), 0, st, a, P.m, P.n, lda,
                        P.scale, k0, k1, (uint32_t)c0, w, g.rows_per_split, part, W.fro,
                        W.nonfinite, ctrl);
   prof_end(pm, st);

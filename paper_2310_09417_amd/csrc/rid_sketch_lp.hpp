@@ -7,22 +7,24 @@
 // each sketch vector is a fixed, slightly rounded Gaussian vector: rounding
 // the embedding changes which random matrix is used, not the method.
 //
-// Geometry: 256 threads (4 waves, one per SIMD) own 1024 columns and a range
-// of rows_per_split rows.  Per k-step of 32 rows every lane loads 8 rows of 16
+// Geometry: 512 threads (8 waves, two per SIMD, so that one wave's loads and
+// Gaussian generation overlap the other's) own 1024 columns and a range of
+// rows_per_split rows.  Per k-step of 32 rows every lane loads 8 rows of 8
 // columns of A, transposes them in registers into the 16x16x32 operand form
 // (8 consecutive rows of one column), and multiplies them by the 4 Omega
 // tiles (64 vectors) it reads from LDS.  Omega for the next k-step is
 // generated into the other LDS buffer while the current one is in use, so
 // each Gaussian value is reused across 1024 columns.
-//   BF16: lane columns {8cg .. 8cg+7} and {128+8cg .. 128+8cg+7} of its
-//         wave's 256 (two fully coalesced 16-byte loads per row).
-//   FP8:  lane columns {16cg .. 16cg+15} (one 16-byte load per row); all 16
-//         lie in one 128-column tile, so one scale covers them.
+//   lane columns {8cg .. 8cg+7} of its wave's 128 (one 16-byte BF16 or 8-byte
+//   FP8 load per row, contiguous over the 16 lanes of a row); a wave's 128
+//   columns are one FP8 scale tile.
 // The FP32 accumulators of a workgroup hold the raw sum over its rows; the
 // partials part[split][col][64] (FP32) are summed in split order in FP64 by
 // k_sketch_reduce_lp, which also applies the FP8 column scale.  NORM also
 // accumulates sum A^2 (FP64 across k-steps) and flags non-finite entries.
 #pragma once
+
+#include <type_traits>
 
 #include "rid_kernels.hpp"
 
@@ -54,10 +56,24 @@ __device__ __forceinline__ u32x4 lp_load16(const unsigned char* __restrict__ A, 
   return u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
 }
 
+// 8 bytes of row `row` from column `col` (FP8 codes; zeros outside A).
+template <bool VEC>
+__device__ __forceinline__ u32x2 lp_load8(const unsigned char* __restrict__ A, int64_t row,
+                                          int64_t r_end, int64_t col, int64_t n, int64_t lda) {
+  if (row >= r_end) return u32x2{0u, 0u};
+  const unsigned char* p = A + row * lda + col;
+  if (VEC && col + 8 <= n) return *reinterpret_cast<const u32x2*>(p);
+  uint64_t v = 0;
+#pragma unroll 1
+  for (int t = 0; t < 8 && col + t < n; ++t) v |= (uint64_t)p[t] << (8 * t);
+  return u32x2{(uint32_t)v, (uint32_t)(v >> 32)};
+}
+
 // BF16: the operand of column j (0..7) of the 8 rows x 8 columns held in
 // buf[base .. base+7] (row e; entries 2d, 2d+1 in dword d): entries of rows
 // e = 0..7 packed two per dword.
-__device__ __forceinline__ u32x4 lp_col_bf16(const u32x4 (&buf)[16], int base, int j) {
+template <int NB>
+__device__ __forceinline__ u32x4 lp_col_bf16(const u32x4 (&buf)[NB], int base, int j) {
   const int d = j >> 1;
   u32x4 o;
   if (j & 1) {
@@ -86,8 +102,10 @@ __device__ __forceinline__ void lp_tr4(uint32_t x0, uint32_t x1, uint32_t x2, ui
   out[3] = (a_hi >> 16) | (b_hi & 0xffff0000u);
 }
 
+constexpr int kLpThreads = 512;
+
 template <int FMT, bool NORM, bool VEC>
-__global__ __launch_bounds__(256) void k_sketch_lp(
+__global__ __launch_bounds__(kLpThreads) void k_sketch_lp(
     const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda,
     const float* __restrict__ col_scale, uint32_t key0, uint32_t key1, uint32_t c0, int w,
     int64_t rows_per_split, float* __restrict__ part, double* __restrict__ fro_part,
@@ -96,31 +114,29 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
   constexpr int ES = FMT == 1 ? 2 : 1;     // bytes per entry of A and Omega
   constexpr int WP = 64;                   // sketch vectors (padded)
   constexpr int PITCH = kLpKs * ES + 16;   // LDS bytes per vector
+  constexpr int NW = kLpThreads / 64;
   __shared__ __align__(16) unsigned char om[2][WP * PITCH];
-  __shared__ double red[4];
+  __shared__ double red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cg = lane & 15, rs = lane >> 4;
-  const int64_t cbase = (int64_t)blockIdx.x * kLpCols + wave * 256;
-  const int64_t colA = (FMT == 1) ? cbase + 8 * cg : cbase + 16 * cg;  // first load
-  const int64_t colB = cbase + 128 + 8 * cg;                           // BF16 second load
+  const int64_t colA = (int64_t)blockIdx.x * kLpCols + wave * 128 + 8 * cg;  // 8 columns
   const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
   const int nks = (int)((r_end - r_begin + kLpKs - 1) / kLpKs);
 
-  floatx4 acc[4][16];
+  floatx4 acc[4][8];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[a][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 8; ++j) acc[a][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   double fro = 0.0;
   bool bad = false;
 
-  // Omega for the k-step at row r0: 64 vectors x 8 row quads, two quads per
-  // thread (call g = 0, 1)
-  auto gen = [&](unsigned char* omb, int64_t r0, int g) {
-    const int it = tid + 256 * g;
-    const int c = it >> 3, qd = it & 7;
+  // Omega for the k-step at row r0: 64 vectors x 8 row quads, one quad per
+  // thread
+  auto gen = [&](unsigned char* omb, int64_t r0) {
+    const int c = tid >> 3, qd = tid & 7;
     const int64_t row4 = r0 + 4 * qd;
     float v[4] = {0.f, 0.f, 0.f, 0.f};
     if (c < w && row4 < r_end) gauss4<float>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
@@ -138,22 +154,26 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
     }
   };
 
-  constexpr int NB = FMT == 1 ? 16 : 8;  // 16-byte loads per lane per k-step
-  auto load = [&](u32x4 (&buf)[NB], int64_t r0) {
+  // one k-step of A: 8 rows of the lane's 8 columns
+  using BufT = typename std::conditional<FMT == 1, u32x4, u32x2>::type;
+  auto load = [&](BufT (&buf)[8], int64_t r0) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int64_t row = r0 + 8 * rs + e;
-      buf[e] = lp_load16<ES, VEC>(A, row, r_end, colA, n, lda);
-      if (FMT == 1) buf[(8 + e) % NB] = lp_load16<ES, VEC>(A, row, r_end, colB, n, lda);
+      if constexpr (FMT == 1)
+        buf[e] = lp_load16<ES, VEC>(A, row, r_end, colA, n, lda);
+      else
+        buf[e] = lp_load8<VEC>(A, row, r_end, colA, n, lda);
     }
   };
 
-  auto norm_acc = [&](const u32x4 (&buf)[NB]) {
+  auto norm_acc = [&](const BufT (&buf)[8]) {
     float f = 0.f;
+    constexpr int ND = FMT == 1 ? 4 : 2;
 #pragma unroll
-    for (int t = 0; t < NB; ++t)
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
+      for (int d = 0; d < ND; ++d) {
         const uint32_t x = buf[t][d];
         if (FMT == 1) {
           const float lo = __uint_as_float(x << 16), hi = __uint_as_float(x & 0xffff0000u);
@@ -170,18 +190,18 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
     fro += (double)f;
   };
 
-  auto compute = [&](const unsigned char* omc, const u32x4 (&buf)[NB], unsigned char* omn,
+  auto compute = [&](const unsigned char* omc, const BufT (&buf)[8], unsigned char* omn,
                      int64_t rnext, bool has_next) {
     if (NORM) norm_acc(buf);
+    if (has_next) gen(omn, rnext);
     if constexpr (FMT == 1) {
       u32x4 oa[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         oa[a] = *reinterpret_cast<const u32x4*>(omc + (16 * a + cg) * PITCH + 16 * rs);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (has_next && (j == 0 || j == 8)) gen(omn, rnext, j >> 3);
-        const u32x4 bv = lp_col_bf16(buf, j < 8 ? 0 : 8, j & 7);
+      for (int j = 0; j < 8; ++j) {
+        const u32x4 bv = lp_col_bf16<8>(buf, 0, j);
 #pragma unroll
         for (int a = 0; a < 4; ++a) acc[a][j] = mfma_bf16x32(oa[a], bv, acc[a][j]);
       }
@@ -191,8 +211,7 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
       for (int a = 0; a < 4; ++a)
         oa[a] = *reinterpret_cast<const u32x2*>(omc + (16 * a + cg) * PITCH + 8 * rs);
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        if (has_next && (d == 0 || d == 2)) gen(omn, rnext, d >> 1);
+      for (int d = 0; d < 2; ++d) {
         uint32_t lo[4], hi[4];
         lp_tr4(buf[0][d], buf[1][d], buf[2][d], buf[3][d], lo);
         lp_tr4(buf[4][d], buf[5][d], buf[6][d], buf[7][d], hi);
@@ -208,10 +227,9 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
 
   // A for the next k-step is loaded into bB while bA is in use, then moved
   // (one copy of the k-step body keeps the accumulators in place)
-  u32x4 bA[NB], bB[NB];
+  BufT bA[8], bB[8];
   if (nks > 0) {
-    gen(om[0], r_begin, 0);
-    gen(om[0], r_begin, 1);
+    gen(om[0], r_begin);
     load(bA, r_begin);
   }
   __syncthreads();
@@ -222,14 +240,14 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
     compute(om[ks & 1], bA, om[(ks + 1) & 1], r0 + kLpKs, nx);
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < NB; ++t) bA[t] = bB[t];
+    for (int t = 0; t < 8; ++t) bA[t] = bB[t];
   }
 
-  // partials: accumulator (a, j) holds vectors 16a + 4rs + r of lane column j
+  // partials: accumulator (a, j) holds vectors 16a + 4rs + r of column colA + j
   const int64_t split = blockIdx.y;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int64_t col = (FMT == 1) ? ((j < 8) ? colA + j : colB + (j - 8)) : colA + j;
+  for (int j = 0; j < 8; ++j) {
+    const int64_t col = colA + j;
     if (col < n) {
       float* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP + 4 * rs;
 #pragma unroll
@@ -238,14 +256,18 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
   }
   if (NORM) {
     if (FMT == 2 && colA < n) {
-      const double s = (double)col_scale[colA >> 7];
-      fro *= s * s;
+      const double sc = (double)col_scale[colA >> 7];
+      fro *= sc * sc;
     }
     fro = wave_sum(fro);
     if (lane == 0) red[wave] = fro;
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
-    if (tid == 0) fro_part[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (tid == 0) {
+      double t = 0.0;
+      for (int wv = 0; wv < NW; ++wv) t += red[wv];
+      fro_part[blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
   }
 }
 
