@@ -188,8 +188,14 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
   P.ldu = (int64_t)align_up((size_t)kcap, 16);
   P.ldl = (int64_t)align_up((size_t)kcap, 64);
-  // panel factorisation: one workgroup per CU at most, at least 16 rows each
-  P.lupp_g = (int)std::max<int64_t>(1, std::min<int64_t>(di.cu, ceil_div(n, 16)));
+  // Panel factorisation: each workgroup keeps up to 256 candidate rows in LDS
+  // (fewer when wide FP64 panels would not fit).  Fewer, fuller workgroups
+  // mean fewer slots to publish and read at every pivot step.
+  {
+    const int64_t cap = (int64_t)((kMaxLds - 128 * es) / ((size_t)(wmax + 1) * es + 4));
+    const int64_t target = std::max<int64_t>(16, std::min<int64_t>(256, cap));
+    P.lupp_g = (int)std::max<int64_t>(1, std::min<int64_t>(di.cu, ceil_div(n, target)));
+  }
   P.lupp_rows = (int)ceil_div(n, P.lupp_g);
   P.lupp_g = (int)ceil_div(n, P.lupp_rows);
   P.lupp_lds = (size_t)P.lupp_rows * (wmax + 1) * es + 128 * es + (size_t)P.lupp_rows * 4;
