@@ -44,18 +44,24 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, launches_units: float):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken from the current kernel sources; else None."""
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
+    of known size) from the committed counter summary, if it was taken from
+    the current sources of that kernel; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != source_hash():
-        return None
     ent = d.get("kernels", {}).get(kernel)
     if not ent:
+        return None
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2310_09417_amd", "csrc")
+    for f in ent.get("sources", []):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    if h.hexdigest()[:16] != ent.get("source_hash"):
         return None
     return ent.get("hbm_bytes_per_launch")
 
@@ -188,7 +194,7 @@ def main():
         "avg_launch_ms": sk_avg_s * 1e3,
         "algorithmic_flops_per_launch": sk_flops,
         "algorithmic_bytes_per_launch": 4.0 * m * n,
-        "traffic": traffic_from_profiles("k_sketch", 1.0),
+        "traffic": traffic_from_profiles("k_sketch"),
     }
     breakdown = {name: {"ms_per_step": tms / args.steps, "launches_per_step": cnt // args.steps}
                  for name, (tms, cnt) in prof.items()}
@@ -283,6 +289,7 @@ def main():
                 "speedup_vs_fp64": (fp64["ms_per_step"] / msq) if fp64 else None,
                 "sketch": {"avg_launch_ms": sk_avg * 1e3, "launches_per_step": skc // args.lp_steps,
                            "bound": "hbm", "algorithmic_bytes_per_launch": bytes_l,
+                           "traffic": traffic_from_profiles(f"k_sketch_lp_{fmt}"),
                            "achieved_GBps": bytes_l / sk_avg / 1e9,
                            "frac_hbm": bytes_l / sk_avg / PEAK["hbm"],
                            "achieved_TFLOPs": 2.0 * b * m * n / sk_avg / 1e12,

@@ -3,7 +3,9 @@
 // m x n FP32 matrix resident in HBM, plus one plain device copy of a known
 // size (the reference for hardware traffic counters).
 //
-// usage: rid_bench_native [m n b kmax iters]   (defaults 50000 20000 64 2048 3)
+// usage: rid_bench_native [m n b kmax iters fmt]   (defaults 50000 20000 64 2048 3 0)
+// fmt 0: A in FP32; 1: A stored as BF16; 2: A stored as FP8-e4m3 (scale 1 per
+// 128-column tile; the Gaussian entries fit the format unscaled).
 // The matrix holds Gaussian entries produced by rid_debug_gaussian; traffic
 // and timing of the kernels do not depend on the values.
 #include <hip/hip_runtime.h>
@@ -30,12 +32,33 @@ __global__ void calib_copy(const float4* __restrict__ src, float4* __restrict__ 
     dst[i] = src[i];
 }
 
+// FP32 -> BF16 bits (nearest even) or e4m3 codes, one entry per thread.
+__global__ void to_format(const float* __restrict__ src, unsigned char* __restrict__ dst,
+                          size_t count, int fmt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float x = src[i];
+  if (fmt == 1) {
+    const unsigned u = __float_as_uint(x);
+    reinterpret_cast<unsigned short*>(dst)[i] = (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  } else {
+    dst[i] = (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xff);
+  }
+}
+
+__global__ void fill_ones(float* p, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 1.0f;
+}
+
 int main(int argc, char** argv) {
   const int64_t m = argc > 1 ? atoll(argv[1]) : 50000;
   const int64_t n = argc > 2 ? atoll(argv[2]) : 20000;
   const int64_t b = argc > 3 ? atoll(argv[3]) : 64;
   const int64_t kmax = argc > 4 ? atoll(argv[4]) : 2048;
   const int iters = argc > 5 ? atoi(argv[5]) : 3;
+  const int fmt = argc > 6 ? atoi(argv[6]) : 0;
+  if (fmt < 0 || fmt > 2) return 5;
   hipStream_t st;
   CHECK(hipStreamCreate(&st));
 
@@ -56,6 +79,25 @@ int main(int argc, char** argv) {
   CHECK(hipMalloc(&A, (size_t)m * n * sizeof(float)));
   if (rid_debug_gaussian(7, 0, m, n, RID_F32, A, st) != RID_OK) return 2;
   rid_config cfg{RID_F32, 1, 1, RID_F32, nullptr, 0};
+  void* Aop = A;  // the matrix the calls read
+  float* scale = nullptr;
+  if (fmt != 0) {
+    const size_t count = (size_t)m * n;
+    unsigned char* Aq = nullptr;
+    CHECK(hipMalloc(&Aq, count * (fmt == 1 ? 2 : 1)));
+    hipLaunchKernelGGL(to_format, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, A, Aq,
+                       count, fmt);
+    const size_t ntile = (size_t)((n + 127) / 128);
+    CHECK(hipMalloc(&scale, ntile * sizeof(float)));
+    hipLaunchKernelGGL(fill_ones, dim3((unsigned)((ntile + 255) / 256)), dim3(256), 0, st, scale,
+                       ntile);
+    CHECK(hipStreamSynchronize(st));
+    CHECK(hipFree(A));
+    A = nullptr;
+    Aop = Aq;
+    cfg.a_type = fmt == 1 ? RID_BF16 : RID_FP8_E4M3;
+    cfg.a_col_scale = fmt == 2 ? scale : nullptr;
+  }
   const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
   const size_t wb = rid_workspace_bytes(m, n, kmax, b, &cfg);
   void* work = nullptr;
@@ -76,10 +118,10 @@ int main(int argc, char** argv) {
 
   for (int it = 0; it < iters; ++it) {
     auto t0 = std::chrono::steady_clock::now();
-    if (rid_debug_sketch(A, m, n, n, b, b, &cfg, Yt, b, works, wbs, st) != RID_OK) return 3;
+    if (rid_debug_sketch(Aop, m, n, n, b, b, &cfg, Yt, b, works, wbs, st) != RID_OK) return 3;
     CHECK(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
-    if (rid_lupp_adaptive(A, m, n, n, b, 1e-6, kmax, &cfg, J, T, n, ko, eo, so, work, wb, st) !=
+    if (rid_lupp_adaptive(Aop, m, n, n, b, 1e-6, kmax, &cfg, J, T, n, ko, eo, so, work, wb, st) !=
         RID_OK)
       return 4;
     CHECK(hipStreamSynchronize(st));
@@ -94,7 +136,8 @@ int main(int argc, char** argv) {
                 std::chrono::duration<double, std::milli>(t2 - t1).count(), k,
                 rid_status_string(s), e);
   }
-  CHECK(hipFree(A));
+  CHECK(hipFree(Aop));
+  if (scale) CHECK(hipFree(scale));
   CHECK(hipFree(work));
   CHECK(hipFree(works));
   CHECK(hipFree(Yt));
