@@ -27,6 +27,12 @@ constexpr int kMaxW = 128;        // widest sketch block per pass / panel
 constexpr int kPanel = 64;        // panel width of the fixed-rank factorisation
 constexpr size_t kMaxLds = 160 * 1024;
 
+// LDS of the panel factorisation: the rows' panel values, two pivot rows of
+// up to 128 values, and a flag per row.
+size_t panel_lds(int64_t rows, int64_t w, size_t es) {
+  return (size_t)rows * (size_t)panel_pitch((int)w, (int)es) * es + 256 * es + (size_t)rows * 4;
+}
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -164,11 +170,11 @@ struct Plan {
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
   size_t lupp_lds = 0;
-  int nbars = 0;
   size_t part_bytes = 0, fro_count = 0;
   int64_t schur_wgs = 0;
   // offsets
-  size_t o_ctrl, o_bars, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
+  size_t xwords_end = 0;  // end of the panel exchange words (zeroed per call)
+  size_t o_ctrl, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
       o_slotrows, o_nonfinite, o_linv, o_mtmp, o_yorig, o_tt, o_x, total;
 };
 
@@ -188,18 +194,19 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
   P.ldu = (int64_t)align_up((size_t)kcap, 16);
   P.ldl = (int64_t)align_up((size_t)kcap, 64);
-  // Panel factorisation: each workgroup keeps up to 256 candidate rows in LDS
-  // (fewer when wide FP64 panels would not fit).  Fewer, fuller workgroups
-  // mean fewer slots to publish and read at every pivot step.
+  // Panel factorisation: each workgroup keeps up to 192 candidate rows in
+  // LDS, one per thread of its three row waves (fewer when wide FP64 panels
+  // would not fit; more per thread only when n needs more than one
+  // workgroup per compute unit).
   {
-    const int64_t cap = (int64_t)((kMaxLds - 128 * es) / ((size_t)(wmax + 1) * es + 4));
-    const int64_t target = std::max<int64_t>(16, std::min<int64_t>(256, cap));
+    const int64_t cap =
+        (int64_t)((kMaxLds - 256 * es) / ((size_t)panel_pitch((int)wmax, (int)es) * es + 4));
+    const int64_t target = std::max<int64_t>(16, std::min<int64_t>(192, cap));
     P.lupp_g = (int)std::max<int64_t>(1, std::min<int64_t>(di.cu, ceil_div(n, target)));
   }
   P.lupp_rows = (int)ceil_div(n, P.lupp_g);
   P.lupp_g = (int)ceil_div(n, P.lupp_rows);
-  P.lupp_lds = (size_t)P.lupp_rows * (wmax + 1) * es + 128 * es + (size_t)P.lupp_rows * 4;
-  P.nbars = (int)(kcap + 8);
+  P.lupp_lds = panel_lds(P.lupp_rows, wmax, es);
   // sketch partials: every launch covers <= 64 vectors with the same split
   size_t pb = 0, fc = 0;
   if (low_precision(at)) {
@@ -221,7 +228,6 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
     return at;
   };
   P.o_ctrl = take(sizeof(Ctrl));
-  P.o_bars = take((size_t)P.nbars * 4);
   P.o_nonfinite = take(4);
   P.o_pos = take((size_t)n * 4);
   P.o_order = take((size_t)(kcap + 1) * 4);
@@ -231,8 +237,10 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.o_part = take(P.part_bytes);
   P.o_fro = take(P.fro_count * 8);
   P.o_norm = take((size_t)P.schur_wgs * 8);
-  P.o_slots = take((size_t)2 * P.lupp_g * sizeof(Slot));
-  P.o_slotrows = take((size_t)2 * P.lupp_g * wmax * es);
+  // panel exchange: tagged 64-bit words, es/4 per value, two buffers
+  P.o_slots = take((size_t)2 * P.lupp_g * (es / 4 + 1) * 8);
+  P.o_slotrows = take((size_t)2 * P.lupp_g * wmax * (es / 4) * 8);
+  P.xwords_end = o;
   P.o_linv = take((size_t)kcap * P.ldl * es);
   P.o_mtmp = take((size_t)wmax * P.ldl * es);
   // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
@@ -257,7 +265,6 @@ bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* c
 // Pointers into the caller's workspace.
 struct Ws {
   Ctrl* ctrl;
-  unsigned* bars;
   int* nonfinite;
   int* pos;
   int* order;
@@ -267,8 +274,8 @@ struct Ws {
   double* part;
   double* fro;
   double* norm;
-  Slot* slots;
-  void* slotrows;
+  xword* slots;
+  xword* slotrows;
   void* linv;
   void* mtmp;
   void* yorig;
@@ -280,7 +287,6 @@ Ws carve(const Plan& P, void* work) {
   char* b = static_cast<char*>(work);
   Ws w;
   w.ctrl = reinterpret_cast<Ctrl*>(b + P.o_ctrl);
-  w.bars = reinterpret_cast<unsigned*>(b + P.o_bars);
   w.nonfinite = reinterpret_cast<int*>(b + P.o_nonfinite);
   w.pos = reinterpret_cast<int*>(b + P.o_pos);
   w.order = reinterpret_cast<int*>(b + P.o_order);
@@ -290,8 +296,8 @@ Ws carve(const Plan& P, void* work) {
   w.part = reinterpret_cast<double*>(b + P.o_part);
   w.fro = reinterpret_cast<double*>(b + P.o_fro);
   w.norm = reinterpret_cast<double*>(b + P.o_norm);
-  w.slots = reinterpret_cast<Slot*>(b + P.o_slots);
-  w.slotrows = b + P.o_slotrows;
+  w.slots = reinterpret_cast<xword*>(b + P.o_slots);
+  w.slotrows = reinterpret_cast<xword*>(b + P.o_slotrows);
   w.linv = b + P.o_linv;
   w.mtmp = b + P.o_mtmp;
   w.yorig = P.refine ? b + P.o_yorig : nullptr;
@@ -488,11 +494,10 @@ int estimate(const Plan& P, const Ws& W, int w, double tol, int rel, int k, bool
 
 // ---- panel factorisation ---------------------------------------------------
 template <typename TF>
-int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
-            hipStream_t st) {
-  const size_t es = sizeof(TF);
-  const size_t lds = (size_t)P.lupp_rows * (w + 1) * es + 128 * es + (size_t)P.lupp_rows * 4;
-  if (lds > kMaxLds) return RID_ERR_ARG;
+int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, hipStream_t st) {
+  const size_t lds = panel_lds(P.lupp_rows, w, sizeof(TF));
+  // each of the 192 row threads keeps the flags of its rows in 32 bits
+  if (lds > kMaxLds || w > P.wmax || P.lupp_rows > 192 * 32) return RID_ERR_ARG;
   const void* fn = (const void*)k_panel_lupp<TF>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -502,13 +507,13 @@ int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, boo
   int* pos = W.pos;
   int* order = W.order;
   Ctrl* ctrl = W.ctrl;
-  Slot* slots = W.slots;
-  TF* slotrows = static_cast<TF*>(W.slotrows);
-  unsigned* bar = W.bars + bar_idx;
+  xword* xslot = W.slots;
+  xword* xrow = W.slotrows;
+  int wmax = (int)P.wmax;
   int rows = P.lupp_rows;
   int sf = stop_full ? 1 : 0;
   void* args[] = {&z, &ldz, &n, &zcol, &w, &f, &pos, &order, &ctrl,
-                  &slots, &slotrows, &bar, &rows, &mn, &sf};
+                  &xslot, &xrow, &wmax, &rows, &mn, &sf};
   const long pm = prof_begin(KC_LUPP, st);
   const hipError_t e =
       hipLaunchCooperativeKernel(fn, dim3(P.lupp_g), dim3(256), args, (unsigned)lds, st);
@@ -545,10 +550,10 @@ int linv_update_t(const Plan& P, const Ws& W, int k0, int f, hipStream_t st) {
   return RID_OK;
 }
 
-int panel(const Plan& P, const Ws& W, int zcol, int w, int f, int bar_idx, bool stop_full,
+int panel(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full,
           hipStream_t st) {
-  int rc = P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, bar_idx, stop_full, st)
-                           : panel_t<float>(P, W, zcol, w, f, bar_idx, stop_full, st);
+  int rc = P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, stop_full, st)
+                           : panel_t<float>(P, W, zcol, w, f, stop_full, st);
   if (rc != RID_OK) return rc;
   return P.dt == RID_F64 ? linv_update_t<double>(P, W, zcol, f, st)
                          : linv_update_t<float>(P, W, zcol, f, st);
@@ -609,13 +614,17 @@ int finish(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32_t
 }
 
 int init(const Plan& P, const Ws& W, hipStream_t st) {
-  const int64_t cnt = std::max<int64_t>(P.n, P.nbars);
-  hipLaunchKernelGGL(k_init, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, W.ctrl, W.pos,
-                     P.n, W.bars, P.nbars, W.nonfinite);
+  hipLaunchKernelGGL(k_init, dim3((unsigned)ceil_div(P.n, 256)), dim3(256), 0, st, W.ctrl, W.pos,
+                     P.n, W.nonfinite);
   RID_LAUNCH_CHECK();
   const int64_t words = P.kcap * P.ldl * (int64_t)esize(P.dt) / 4;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, ceil_div(words, 256))), dim3(256),
                      0, st, static_cast<unsigned int*>(W.linv), words);
+  RID_LAUNCH_CHECK();
+  // panel exchange words: tag 0 never matches a step
+  const int64_t xw = (int64_t)(P.xwords_end - P.o_slots) / 4;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, ceil_div(xw, 256))), dim3(256),
+                     0, st, reinterpret_cast<unsigned int*>(W.slots), xw);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }
@@ -711,11 +720,10 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
     const int w = (int)std::min<int64_t>(P.wmax, k + p - c);
     RID_TRY(sketch_block(P, W, A, lda, cfg->seed, c, w, W.z, P.ldz, (int)c, c == 0, true, stream));
   }
-  int bar = 0;
   for (int64_t k0 = 0; k0 < k; k0 += kPanel) {
     const int f = (int)std::min<int64_t>(kPanel, k - k0);
     if (k0 > 0) RID_TRY(block_update(P, W, (int)k0, (int)k0, f, false, stream));
-    RID_TRY(panel(P, W, (int)k0, f, f, bar++, false, stream));
+    RID_TRY(panel(P, W, (int)k0, f, f, false, stream));
   }
   if (p > 0) {
     RID_TRY(block_update(P, W, (int)k, (int)k, (int)p, true, stream));
@@ -744,8 +752,7 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
   RID_TRY(init(P, W, stream));
   const int w0 = (int)std::min<int64_t>(b, kcap);
   RID_TRY(sketch_block(P, W, A, lda, cfg->seed, 0, w0, W.z, P.ldz, 0, true, true, stream));
-  int bar = 0;
-  RID_TRY(panel(P, W, 0, w0, w0, bar++, true, stream));
+  RID_TRY(panel(P, W, 0, w0, w0, true, stream));
   int64_t k = w0, cnext = w0;
   while (k < mn) {
     RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false, true,
@@ -755,7 +762,7 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     RID_TRY(estimate(P, W, (int)b, tol, cfg->tol_relative, (int)k, false, stream));
     if (k >= kcap) break;
     const int f = (int)std::min<int64_t>(b, kcap - k);
-    RID_TRY(panel(P, W, (int)k, (int)b, f, bar++, true, stream));
+    RID_TRY(panel(P, W, (int)k, (int)b, f, true, stream));
     k += f;
   }
   return finish(P, W, T, ldt, J, k_out, err_est, status, stream);

@@ -40,16 +40,10 @@ enum : int32_t {
   ST_ERR_HIP = -3
 };
 
-struct Slot {
-  double v;       // |candidate| of one workgroup at one pivot step
-  long long row;  // its candidate index, -1 if the workgroup has none left
-};
-
 // ---------------------------------------------------------------------------
-// Initialisation of the control block, the pivot map and barrier counters.
+// Initialisation of the control block and the pivot map.
 // ---------------------------------------------------------------------------
-__global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, unsigned* bars, int nbars,
-                       int* nonfinite) {
+__global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, int* nonfinite) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     *nonfinite = 0;
@@ -61,7 +55,6 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, unsigned* bars, int nbar
     ctrl->frob2 = 0.0;
   }
   if (t < n) pos[t] = -1;
-  if (t < nbars) bars[t] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -494,37 +487,32 @@ __global__ __launch_bounds__(256) void k_estimate(Ctrl* ctrl, const double* __re
 
 // ---------------------------------------------------------------------------
 // Panel LUPP (cooperative launch, all workgroups resident).  Workgroup g owns
-// candidate rows [g*R, (g+1)*R) and keeps their w panel values in LDS (row
-// pitch w+1, so column reads across rows are free of bank conflicts).  Per
-// pivot step, wave 0 alone carries the critical path:
-//   local arg-max of |value| over active rows (ties -> lower candidate index)
-//   -> publish (value, candidate) and the candidate's row to a
-//      double-buffered slot -> grid barrier (one counter per launch)
-//   -> reduce all slots to the winner (every workgroup reaches the same one)
-//   -> fetch the winner's row;
-// then every thread updates the rows it owns (scale by the pivot, rank-1
-// update).  Rows are never swapped: pos/order record the permutation.  An
-// exactly zero winner stops the factorisation (rank of the sketch reached).
-// Cross-workgroup data goes through agent-scope relaxed atomics (coherent
-// across XCDs without cache write-back or invalidation); a writer waits for
-// its stores to complete before the barrier counter is incremented.
+// candidate rows [g*R, (g+1)*R) and keeps their w panel values in LDS.
+//
+// Exchange.  At every pivot step each workgroup publishes its local arg-max
+// of |value| over its active rows (ties -> lower candidate index) and that
+// row, as 64-bit words whose upper half is a tag: the global pivot index of
+// the step plus one.  A reader accepts a word only when it carries the tag of
+// the step it waits for, so neither a barrier counter nor a wait for store
+// completion is needed; every workgroup reduces the same words to the same
+// winner.  The words are zeroed when a decomposition starts and each global
+// pivot index occurs once, so stale words never match.  Two buffers
+// alternate by step parity: a workgroup writes the buffer of step s+1 only
+// after it has seen every workgroup's step-s words, and each of those was
+// written after its writer had read everything of step s-1.
+//
+// Look-ahead.  After the winner of step s is known, every thread first
+// updates columns s and s+1 of its rows, the workgroup finds its candidate
+// for step s+1 on column s+1, wave 0 finishes that one row and publishes it,
+// and only then do all threads update the remaining columns; the exchange of
+// step s+1 travels while that update runs.  The arithmetic per element is
+// the same as a plain right-looking step: l = x_s / d, x_q -= l * p_q.
+// Rows are never swapped: pos/order record the permutation.  An exactly zero
+// winner stops the factorisation (rank of the sketch reached).  Words go
+// through agent-scope relaxed atomics (coherent across XCDs without cache
+// write-back or invalidation).
 // ---------------------------------------------------------------------------
-constexpr long long kSpinLimit = 1ll << 26;
-
-template <typename TF>
-struct Bits;
-template <>
-struct Bits<float> {
-  using U = uint32_t;
-  __device__ static U to(float v) { return __float_as_uint(v); }
-  __device__ static float from(U u) { return __uint_as_float(u); }
-};
-template <>
-struct Bits<double> {
-  using U = unsigned long long;
-  __device__ static U to(double v) { return (U)__double_as_longlong(v); }
-  __device__ static double from(U u) { return __longlong_as_double((long long)u); }
-};
+constexpr long long kSpinLimit = 1ll << 22;  // polls (each a memory round trip) before giving up
 
 template <typename T>
 __device__ __forceinline__ void st_agent(T* p, T v) {
@@ -535,29 +523,209 @@ __device__ __forceinline__ T ld_agent(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+using xword = unsigned long long;
+
+// Values as tagged words: one word per FP32 value, two per FP64 value.
+template <typename TF>
+struct Tagged;
+template <>
+struct Tagged<float> {
+  static constexpr int VW = 1;
+  __device__ static void put(xword* p, float v, uint32_t tag) {
+    st_agent(p, ((xword)tag << 32) | (xword)__float_as_uint(v));
+  }
+  __device__ static bool get(const xword* p, uint32_t tag, float& v) {
+    const xword x = ld_agent(p);
+    v = __uint_as_float((uint32_t)x);
+    return (uint32_t)(x >> 32) == tag;
+  }
+};
+template <>
+struct Tagged<double> {
+  static constexpr int VW = 2;
+  __device__ static void put(xword* p, double v, uint32_t tag) {
+    const xword u = (xword)__double_as_longlong(v);
+    st_agent(p, ((xword)tag << 32) | (u & 0xffffffffull));
+    st_agent(p + 1, ((xword)tag << 32) | (u >> 32));
+  }
+  __device__ static bool get(const xword* p, uint32_t tag, double& v) {
+    const xword lo = ld_agent(p), hi = ld_agent(p + 1);
+    v = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+    return (uint32_t)(lo >> 32) == tag && (uint32_t)(hi >> 32) == tag;
+  }
+};
+
+// Words of the exchange: per buffer, G slots of (value, index) words, then G
+// rows of w values (row stride wmax values).
+template <typename TF>
+__host__ __device__ constexpr int64_t panel_slot_words() {
+  return Tagged<TF>::VW + 1;
+}
+
+template <typename TF>
+__device__ __forceinline__ TF panel_upd(TF x, TF l, TF p) {
+  return fma(-l, p, x);
+}
+
+// LDS row pitch of the panel (values): a multiple of one 16-byte vector
+// whose vector count is odd, so that 16-byte accesses of consecutive rows by
+// consecutive lanes fall in distinct banks.
+__host__ __device__ constexpr int panel_pitch(int w, int es) {
+  const int e = 16 / es;
+  int m = (w + e - 1) / e;
+  if ((m & 1) == 0) ++m;
+  return m * e;
+}
+
+typedef float panel_f32x4 __attribute__((ext_vector_type(4)));
+typedef double panel_f64x2 __attribute__((ext_vector_type(2)));
+
+// row[q] -= l * prow[q] for q in [qa, w) with 16-byte LDS accesses; the
+// vector holding column qa keeps its columns below qa.  row and prow are
+// 16-byte aligned.
+template <typename TF>
+__device__ __forceinline__ void panel_row_update(TF* row, const TF* prow, TF l, int qa, int w) {
+  constexpr int E = 16 / (int)sizeof(TF);
+  using V = typename std::conditional<sizeof(TF) == 4, panel_f32x4, panel_f64x2>::type;
+  const int qv = qa / E * E;
+  for (int q0 = qv; q0 < w; q0 += 4 * E) {
+    V x[4], p[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (q0 + j * E < w) {
+        x[j] = *reinterpret_cast<const V*>(row + q0 + j * E);
+        p[j] = *reinterpret_cast<const V*>(prow + q0 + j * E);
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (q0 + j * E < w) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (q0 + j * E + e >= qa) x[j][e] = panel_upd((TF)x[j][e], l, (TF)p[j][e]);
+        *reinterpret_cast<V*>(row + q0 + j * E) = x[j];
+      }
+  }
+}
+
+// Pivot search keys.  A candidate (|v|, index i) maps to the pair
+// (vkey, ikey) = (bits(|v|) + 1, ~i): larger vkey is larger |v| (IEEE bits of
+// non-negative values are ordered like the values), and among equal vkey the
+// larger ikey is the lower index.  No candidate is (0, 0); NaN ranks as
+// zero.  Wave-wide maxima use DPP lane moves (row shifts within 16 lanes,
+// then row broadcasts 15 and 31) and a read of lane 63: no LDS traffic.
+template <int CTRL, int ROWM>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWM, 0xf, true);
+}
+template <int CTRL, int ROWM>
+__device__ __forceinline__ void dpp_max_step64(unsigned long long& k) {
+  const uint32_t lo = dpp_u32<CTRL, ROWM>((uint32_t)k);
+  const uint32_t hi = dpp_u32<CTRL, ROWM>((uint32_t)(k >> 32));
+  const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+  k = o > k ? o : k;
+}
+template <int CTRL, int ROWM>
+__device__ __forceinline__ void dpp_max_step32(uint32_t& k) {
+  const uint32_t o = dpp_u32<CTRL, ROWM>(k);
+  k = o > k ? o : k;
+}
+// maximum over the wave, returned in every lane
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  dpp_max_step64<0x111, 0xf>(k);  // row_shr:1
+  dpp_max_step64<0x112, 0xf>(k);  // row_shr:2
+  dpp_max_step64<0x114, 0xf>(k);  // row_shr:4
+  dpp_max_step64<0x118, 0xf>(k);  // row_shr:8 -> lane 15 of each row holds the row's maximum
+  dpp_max_step64<0x142, 0xa>(k);  // row_bcast:15 into rows 1 and 3
+  dpp_max_step64<0x143, 0xc>(k);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the maximum
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t k) {
+  dpp_max_step32<0x111, 0xf>(k);
+  dpp_max_step32<0x112, 0xf>(k);
+  dpp_max_step32<0x114, 0xf>(k);
+  dpp_max_step32<0x118, 0xf>(k);
+  dpp_max_step32<0x142, 0xa>(k);
+  dpp_max_step32<0x143, 0xc>(k);
+  return (uint32_t)__builtin_amdgcn_readlane((int)k, 63);
+}
+
+template <typename TF>
+struct PivKey {
+  unsigned long long v = 0;  // bits(|value|) + 1, 0 = no candidate
+  uint32_t i = 0;            // ~index
+  __device__ void put(TF a, int64_t idx) {
+    unsigned long long b;
+    if constexpr (sizeof(TF) == 4)
+      b = (unsigned long long)__float_as_uint(fabsf((float)a));
+    else
+      b = (unsigned long long)__double_as_longlong(fabs((double)a));
+    if (a != a) b = 0;
+    const unsigned long long vk = b + 1;
+    const uint32_t ik = ~(uint32_t)idx;
+    if (vk > v || (vk == v && ik > i)) {
+      v = vk;
+      i = ik;
+    }
+  }
+  __device__ void merge(const PivKey& o) {
+    if (o.v > v || (o.v == v && o.i > i)) {
+      v = o.v;
+      i = o.i;
+    }
+  }
+  __device__ void wave_reduce() {
+    if constexpr (sizeof(TF) == 4) {
+      // bits(|v|) + 1 < 2^32: one reduction of the packed pair
+      const unsigned long long k = wave_max_u64((v << 32) | i);
+      v = k >> 32;
+      i = (uint32_t)k;
+    } else {
+      const unsigned long long vm = wave_max_u64(v);
+      i = wave_max_u32(v == vm ? i : 0u);
+      v = vm;
+    }
+  }
+  __device__ bool none() const { return v == 0; }
+  __device__ int64_t index() const { return v == 0 ? -1 : (int64_t)(~i); }
+  __device__ TF value() const {
+    const unsigned long long b = v - 1;
+    if constexpr (sizeof(TF) == 4)
+      return __uint_as_float((uint32_t)b);
+    else
+      return __longlong_as_double((long long)b);
+  }
+};
+
 template <typename TF>
 __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t ldz, int64_t n,
                                                     int zcol, int w, int f, int* __restrict__ pos,
                                                     int* __restrict__ order, Ctrl* ctrl,
-                                                    Slot* slots, TF* slotrows, unsigned* bar,
+                                                    xword* xslot, xword* xrow, int wmax,
                                                     int rows_per_wg, int64_t mn, int stop_full) {
   if (ctrl->done) return;
-  using B = Bits<TF>;
-  using U = typename B::U;
-  extern __shared__ unsigned char smem_raw[];
-  const int pitch = w + 1;
+  using X = Tagged<TF>;
+  using K = PivKey<TF>;
+  constexpr int VW = X::VW;
+  constexpr int SW = (int)panel_slot_words<TF>();
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int pitch = panel_pitch(w, (int)sizeof(TF));
   TF* P = reinterpret_cast<TF*>(smem_raw);       // [rows_per_wg][pitch]
-  TF* prow = P + (size_t)rows_per_wg * pitch;     // [128]
-  int* act = reinterpret_cast<int*>(prow + 128);  // [rows_per_wg]
-  __shared__ double s_val;
-  __shared__ long long s_row;
+  TF* prow2 = P + (size_t)rows_per_wg * pitch;    // [2][128], by step parity
+  int* act = reinterpret_cast<int*>(prow2 + 256); // [rows_per_wg]: 1 candidate at launch, else 0
+  __shared__ unsigned long long red_v[4];
+  __shared__ uint32_t red_i[4];
   __shared__ int s_stop;  // 0 run, 1 deficient, 2 timeout
+  __shared__ int s_win;   // this step's pivot row if this workgroup owns it, else -1
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = (int64_t)g * rows_per_wg;
   int64_t r1 = r0 + rows_per_wg;
   if (r1 > n) r1 = n;
   const int R = r1 > r0 ? (int)(r1 - r0) : 0;
+  // wave 0 carries the exchange; waves 1-3 own rows tid-64, tid-64+192, ...
+  const int rt = tid - 64;
 
   for (int i = tid; i < R * w; i += 256) {
     const int rr = i / w, q = i % w;
@@ -566,64 +734,129 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
   for (int rr = tid; rr < R; rr += 256) act[rr] = (pos[r0 + rr] < 0) ? 1 : 0;
   if (tid == 0) s_stop = 0;
   __syncthreads();
+  // active flags of the own rows (bit j: row rt + 192 j), kept in a register
+  unsigned actm = 0;
+  if (rt >= 0)
+    for (int rr = rt, j = 0; rr < R; rr += 192, ++j)
+      if (act[rr]) actm |= 1u << j;
+
+  // Workgroup maximum of the per-thread keys (one __syncthreads).
+  auto block_reduce = [&](K& key) {
+    key.wave_reduce();
+    if (lane == 0) {
+      red_v[wave] = key.v;
+      red_i[wave] = key.i;
+    }
+    __syncthreads();
+    key = K();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      K o;
+      o.v = red_v[q];
+      o.i = red_i[q];
+      key.merge(o);
+    }
+  };
+  // Wave 0: publish the candidate for step t.  Its row is final for step t
+  // except columns >= qa, which get the pending update x -= l * pr[q] first
+  // (each lane updates and stores the same q).
+  auto publish = [&](int t, const K& key, int qa, TF l, const TF* pr) {
+    const uint32_t tag = (uint32_t)(zcol + t + 1);
+    xword* sl = xslot + ((size_t)(t & 1) * G + g) * SW;
+    const int64_t bi = key.index();
+    if (bi >= 0) {
+      xword* rw = xrow + ((size_t)(t & 1) * G + g) * (size_t)wmax * VW;
+      TF* row = P + (bi - r0) * pitch;
+      for (int q = lane; q < w; q += 64) {
+        TF x = row[q];
+        if (q >= qa) {
+          x = panel_upd(x, l, pr[q]);
+          row[q] = x;
+        }
+        X::put(rw + (size_t)q * VW, x, tag);
+      }
+    }
+    if (lane == 0) {
+      X::put(sl, bi >= 0 ? key.value() : (TF)-1, tag);
+      st_agent(sl + VW, ((xword)tag << 32) | (xword)(uint32_t)(int32_t)bi);
+    }
+  };
+
+  // candidate for step 0: column 0 as loaded
+  {
+    K key;
+    if (rt >= 0)
+      for (int rr = rt, j = 0; rr < R; rr += 192, ++j)
+        if (actm >> j & 1) key.put(P[rr * pitch], r0 + rr);
+    block_reduce(key);
+    if (wave == 0 && f > 0) publish(0, key, w, (TF)0, prow2);
+  }
 
   int steps = f;
+  int cand = -1;  // local row published for the next step, skipped by the bulk update
   for (int s = 0; s < f; ++s) {
+    TF* prow = prow2 + (s & 1) * 128;
     if (wave == 0) {
-      double bv = -1.0;
-      long long bi = -1;
-      for (int rr = lane; rr < R; rr += 64)
-        if (act[rr] == 1) argmax_merge(bv, bi, fabs((double)P[rr * pitch + s]), r0 + rr);
-      wave_argmax(bv, bi);
-      const int buf = s & 1;
-      Slot* sl = slots + (size_t)buf * G;
-      U* srow = reinterpret_cast<U*>(slotrows) + (size_t)buf * G * w;
-      if (lane == 0) {
-        st_agent(reinterpret_cast<unsigned long long*>(&sl[g].v),
-                 (unsigned long long)__double_as_longlong(bv));
-        st_agent(&sl[g].row, bi);
-      }
-      if (bi >= 0)
-        for (int q = lane; q < w; q += 64) st_agent(&srow[(size_t)g * w + q], B::to(P[(bi - r0) * pitch + q]));
-      __builtin_amdgcn_s_waitcnt(0);  // slot stores performed before the counter moves
+      // all slots of step s, then the winner's row
+      const uint32_t tag = (uint32_t)(zcol + s + 1);
+      const xword* sl = xslot + (size_t)(s & 1) * G * SW;
+      TF v[4];
+      int idx[4];
+      long long spins = 0;
       int timeout = 0;
-      if (lane == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = (unsigned)(s + 1) * (unsigned)G;
-        long long spins = 0;
-        while (ld_agent(bar) < target) {
+      while (true) {
+        int ok = 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int t = lane + 64 * i;
+          if (t < G) {
+            ok &= X::get(sl + (size_t)t * SW, tag, v[i]) ? 1 : 0;
+            const xword x = ld_agent(sl + (size_t)t * SW + VW);
+            idx[i] = (int)(uint32_t)x;
+            ok &= ((uint32_t)(x >> 32) == tag) ? 1 : 0;
+          }
+        }
+        if (__all(ok)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          timeout = 1;
+          break;
+        }
+      }
+      K key;
+      if (!timeout) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (lane + 64 * i < G && idx[i] >= 0) key.put(v[i], idx[i]);
+        key.wave_reduce();
+      }
+      const int64_t bi = key.index();
+      if (timeout) {
+        if (lane == 0) s_stop = 2;
+      } else if (bi < 0 || key.value() == (TF)0) {
+        if (lane == 0) s_stop = 1;
+      } else {
+        const int owner = (int)(bi / rows_per_wg);
+        const xword* rw = xrow + ((size_t)(s & 1) * G + owner) * (size_t)wmax * VW;
+        while (true) {
+          int ok = 1;
+          for (int q = lane; q < w; q += 64) {
+            TF val;
+            ok &= X::get(rw + (size_t)q * VW, tag, val) ? 1 : 0;
+            prow[q] = val;
+          }
+          if (__all(ok)) break;
           __builtin_amdgcn_s_sleep(1);
           if (++spins > kSpinLimit) {
             timeout = 1;
             break;
           }
         }
-      }
-      timeout = __shfl(timeout, 0, 64);
-      bv = -1.0;
-      bi = -1;
-      if (!timeout) {
-        for (int t = lane; t < G; t += 64) {
-          const double v = __longlong_as_double(
-              (long long)ld_agent(reinterpret_cast<const unsigned long long*>(&sl[t].v)));
-          argmax_merge(bv, bi, v, ld_agent(&sl[t].row));
-        }
-        wave_argmax(bv, bi);
-      }
-      if (timeout) {
-        if (lane == 0) s_stop = 2;
-      } else if (bi < 0 || bv == 0.0) {
-        if (lane == 0) s_stop = 1;
-      } else {
-        const int owner = (int)(bi / rows_per_wg);
-        for (int q = lane; q < w; q += 64) prow[q] = B::from(ld_agent(&srow[(size_t)owner * w + q]));
-        if (lane == 0) {
-          s_val = bv;
-          s_row = bi;
-          if (owner == g) {
-            act[bi - r0] = 2;
-            pos[bi] = zcol + s;
-          }
+        if (timeout) {
+          if (lane == 0) s_stop = 2;
+        } else if (lane == 0) {
+          s_win = owner == g ? (int)(bi - r0) : -1;
+          if (owner == g) pos[bi] = zcol + s;
           if (g == 0) order[zcol + s] = (int)bi;
         }
       }
@@ -640,19 +873,49 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
       steps = s;
       break;
     }
+    // columns s (multipliers) and s+1 of the own rows, and the candidate for
+    // step s+1
     const TF d = prow[s];
-    for (int rr = tid; rr < R; rr += 256) {
-      if (act[rr] != 1) continue;
-      TF* row = P + rr * pitch;
-      const TF l = row[s] / d;
-      row[s] = l;
-      for (int q = s + 1; q < w; ++q) row[q] -= l * prow[q];
+    const bool next = s + 1 < f;
+    K key;
+    if (rt >= 0) {
+      const int win = s_win;
+      for (int rr = rt, j = 0; rr < R; rr += 192, ++j) {
+        if (rr == win) actm &= ~(1u << j);
+        if (!(actm >> j & 1)) continue;
+        TF* row = P + rr * pitch;
+        const TF l = row[s] / d;
+        row[s] = l;
+        if (s + 1 < w) {
+          const TF x = panel_upd(row[s + 1], l, prow[s + 1]);
+          row[s + 1] = x;
+          if (next) key.put(x, r0 + rr);
+        }
+      }
     }
-    __syncthreads();
+    if (next) {
+      block_reduce(key);
+      const int64_t bi = key.index();
+      cand = bi >= 0 ? (int)(bi - r0) : -1;
+      if (wave == 0) publish(s + 1, key, s + 2, cand >= 0 ? P[cand * pitch + s] : (TF)0, prow);
+    } else {
+      cand = -1;
+    }
+    // remaining columns of the other own rows, while wave 0 goes on to the
+    // next step's exchange (which writes the other prow buffer; its winner
+    // can only be this step's candidate, which is skipped here)
+    if (rt >= 0) {
+      for (int rr = rt, j = 0; rr < R; rr += 192, ++j) {
+        if (rr == cand || !(actm >> j & 1)) continue;
+        TF* row = P + rr * pitch;
+        panel_row_update(row, prow, row[s], s + 2, w);
+      }
+    }
   }
+  __syncthreads();
   for (int i = tid; i < R * w; i += 256) {
     const int rr = i / w, q = i % w;
-    if (act[rr] != 0) Z[(r0 + rr) * ldz + zcol + q] = P[rr * pitch + q];
+    if (act[rr]) Z[(r0 + rr) * ldz + zcol + q] = P[rr * pitch + q];
   }
   if (g == 0 && tid == 0) {
     if (steps < f) {
