@@ -534,10 +534,10 @@ struct Tagged<float> {
   __device__ static void put(xword* p, float v, uint32_t tag) {
     st_agent(p, ((xword)tag << 32) | (xword)__float_as_uint(v));
   }
-  __device__ static bool get(const xword* p, uint32_t tag, float& v) {
-    const xword x = ld_agent(p);
-    v = __uint_as_float((uint32_t)x);
-    return (uint32_t)(x >> 32) == tag;
+  // value from words already loaded; true when they carry the tag
+  __device__ static bool decode(const xword* x, uint32_t tag, float& v) {
+    v = __uint_as_float((uint32_t)x[0]);
+    return (uint32_t)(x[0] >> 32) == tag;
   }
 };
 template <>
@@ -548,10 +548,9 @@ struct Tagged<double> {
     st_agent(p, ((xword)tag << 32) | (u & 0xffffffffull));
     st_agent(p + 1, ((xword)tag << 32) | (u >> 32));
   }
-  __device__ static bool get(const xword* p, uint32_t tag, double& v) {
-    const xword lo = ld_agent(p), hi = ld_agent(p + 1);
-    v = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
-    return (uint32_t)(lo >> 32) == tag && (uint32_t)(hi >> 32) == tag;
+  __device__ static bool decode(const xword* x, uint32_t tag, double& v) {
+    v = __longlong_as_double((long long)((x[1] << 32) | (x[0] & 0xffffffffull)));
+    return (uint32_t)(x[0] >> 32) == tag && (uint32_t)(x[1] >> 32) == tag;
   }
 };
 
@@ -800,20 +799,30 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
       // all slots of step s, then the winner's row
       const uint32_t tag = (uint32_t)(zcol + s + 1);
       const xword* sl = xslot + (size_t)(s & 1) * G * SW;
-      TF v[4];
-      int idx[4];
+      K key;
       long long spins = 0;
       int timeout = 0;
       while (true) {
+        // all loads first, then the checks: one round trip per attempt
+        xword wd[4][SW];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int t = lane + 64 * i;
+          if (t < G)
+#pragma unroll
+            for (int e = 0; e < SW; ++e) wd[i][e] = ld_agent(sl + (size_t)t * SW + e);
+        }
         int ok = 1;
+        key = K();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int t = lane + 64 * i;
           if (t < G) {
-            ok &= X::get(sl + (size_t)t * SW, tag, v[i]) ? 1 : 0;
-            const xword x = ld_agent(sl + (size_t)t * SW + VW);
-            idx[i] = (int)(uint32_t)x;
-            ok &= ((uint32_t)(x >> 32) == tag) ? 1 : 0;
+            TF v;
+            ok &= X::decode(wd[i], tag, v) ? 1 : 0;
+            ok &= ((uint32_t)(wd[i][VW] >> 32) == tag) ? 1 : 0;
+            const int idx = (int)(uint32_t)wd[i][VW];
+            if (idx >= 0) key.put(v, idx);
           }
         }
         if (__all(ok)) break;
@@ -823,13 +832,7 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
           break;
         }
       }
-      K key;
-      if (!timeout) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (lane + 64 * i < G && idx[i] >= 0) key.put(v[i], idx[i]);
-        key.wave_reduce();
-      }
+      if (!timeout) key.wave_reduce();
       const int64_t bi = key.index();
       if (timeout) {
         if (lane == 0) s_stop = 2;
@@ -839,11 +842,23 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
         const int owner = (int)(bi / rows_per_wg);
         const xword* rw = xrow + ((size_t)(s & 1) * G + owner) * (size_t)wmax * VW;
         while (true) {
+          xword wd[2][VW];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int q = lane + 64 * i;
+            if (q < w)
+#pragma unroll
+              for (int e = 0; e < VW; ++e) wd[i][e] = ld_agent(rw + (size_t)q * VW + e);
+          }
           int ok = 1;
-          for (int q = lane; q < w; q += 64) {
-            TF val;
-            ok &= X::get(rw + (size_t)q * VW, tag, val) ? 1 : 0;
-            prow[q] = val;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int q = lane + 64 * i;
+            if (q < w) {
+              TF val;
+              ok &= X::decode(wd[i], tag, val) ? 1 : 0;
+              prow[q] = val;
+            }
           }
           if (__all(ok)) break;
           __builtin_amdgcn_s_sleep(1);
@@ -862,8 +877,19 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
       }
     }
     __syncthreads();
-    if (s_stop) {
-      if (s_stop == 2) {
+    // everything pass 1 needs, read before any branch
+    const int stop = s_stop;
+    const int win = s_win;
+    const bool has1 = s + 1 < w;
+    const TF d = prow[s];
+    const TF p1 = has1 ? prow[s + 1] : (TF)0;
+    TF x0 = (TF)0, x1 = (TF)0;
+    if (rt >= 0 && rt < R) {
+      x0 = P[rt * pitch + s];
+      if (has1) x1 = P[rt * pitch + s + 1];
+    }
+    if (stop) {
+      if (stop == 2) {
         if (tid == 0) {
           ctrl->status = ST_ERR_HIP;
           ctrl->done = 1;
@@ -875,19 +901,19 @@ __global__ __launch_bounds__(256) void k_panel_lupp(TF* __restrict__ Z, int64_t 
     }
     // columns s (multipliers) and s+1 of the own rows, and the candidate for
     // step s+1
-    const TF d = prow[s];
     const bool next = s + 1 < f;
     K key;
     if (rt >= 0) {
-      const int win = s_win;
       for (int rr = rt, j = 0; rr < R; rr += 192, ++j) {
         if (rr == win) actm &= ~(1u << j);
         if (!(actm >> j & 1)) continue;
         TF* row = P + rr * pitch;
-        const TF l = row[s] / d;
+        const TF a0 = j == 0 ? x0 : row[s];
+        const TF a1 = j == 0 ? x1 : (has1 ? row[s + 1] : (TF)0);
+        const TF l = a0 / d;
         row[s] = l;
-        if (s + 1 < w) {
-          const TF x = panel_upd(row[s + 1], l, prow[s + 1]);
+        if (has1) {
+          const TF x = panel_upd(a1, l, p1);
           row[s + 1] = x;
           if (next) key.put(x, r0 + rr);
         }
