@@ -252,7 +252,8 @@ int rid_debug_mfma_probe(int kind, const void* A, const void* B, float* D, hipSt
  * elapsed milliseconds and the number of launches; it also ends recording.
  * Classes: 0 sketch, 1 sketch reduction, 2 U2 = L1^{-1} (P Y)(top),
  * 3 Schur update, 4 panel LUPP, 5 interpolation matrix, 6 update of L1^{-1},
- * 7 batched persistent kernel.  Process-wide state:
+ * 7 batched persistent kernel, 8 generation of the sketch vectors' Gaussian
+ * entries.  Process-wide state:
  * not for concurrent use from several host threads.
  */
 int rid_profile_start(void);

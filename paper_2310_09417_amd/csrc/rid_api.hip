@@ -59,7 +59,9 @@ DeviceInfo device_info() {
 inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
 
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
-enum KClass { KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_N };
+enum KClass {
+  KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA, KC_N
+};
 
 struct Profiler {
   bool on = false;
@@ -175,7 +177,7 @@ struct Plan {
   // offsets
   size_t xwords_end = 0;  // end of the panel exchange words (zeroed per call)
   size_t o_ctrl, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
-      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_yorig, o_tt, o_x, total;
+      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, total;
 };
 
 bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, rid_dtype at,
@@ -243,6 +245,8 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.xwords_end = o;
   P.o_linv = take((size_t)kcap * P.ldl * es);
   P.o_mtmp = take((size_t)wmax * P.ldl * es);
+  // Omega of one sketch launch (at most 64 vectors), rows padded to 64
+  P.o_omega = take(low_precision(at) ? 0 : (size_t)align_up((size_t)m, 64) * 64 * es);
   // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
@@ -278,6 +282,7 @@ struct Ws {
   xword* slotrows;
   void* linv;
   void* mtmp;
+  void* omega;
   void* yorig;
   void* tt;
   void* xr;
@@ -300,6 +305,7 @@ Ws carve(const Plan& P, void* work) {
   w.slotrows = reinterpret_cast<xword*>(b + P.o_slotrows);
   w.linv = b + P.o_linv;
   w.mtmp = b + P.o_mtmp;
+  w.omega = b + P.o_omega;
   w.yorig = P.refine ? b + P.o_yorig : nullptr;
   w.tt = P.refine ? b + P.o_tt : nullptr;
   w.xr = P.refine ? b + P.o_x : nullptr;
@@ -319,15 +325,22 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
-  const long pm = prof_begin(KC_SKETCH, st);
+  TC* om = static_cast<TC*>(W.omega);
+  const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
+  long pm = prof_begin(KC_OMEGA, st);
+  hipLaunchKernelGGL(k_omega<TC>, dim3((unsigned)ceil_div(mpad / 4 * g.wp, 256)), dim3(256), 0, st,
+                     k0, k1, (uint32_t)c0, w, g.wp, P.m, mpad, om, ctrl);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  pm = prof_begin(KC_SKETCH, st);
   if (norm)
     hipLaunchKernelGGL((k_sketch<TC, MT, KC, true, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
-                       static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
-                       g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
+                       static_cast<const TC*>(A), P.m, P.n, lda, om, w, g.rows_per_split, W.part,
+                       W.fro, W.nonfinite, ctrl);
   else
     hipLaunchKernelGGL((k_sketch<TC, MT, KC, false, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
-                       static_cast<const TC*>(A), P.m, P.n, lda, k0, k1, (uint32_t)c0, w,
-                       g.rows_per_split, W.part, W.fro, W.nonfinite, ctrl);
+                       static_cast<const TC*>(A), P.m, P.n, lda, om, w, g.rows_per_split, W.part,
+                       W.fro, W.nonfinite, ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;

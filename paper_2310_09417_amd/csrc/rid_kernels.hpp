@@ -66,9 +66,11 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, int* nonfinite) {
 //     q, output column j covers matrix column NQ j + q of the wave's strip.
 //   * The A operands of the next KC-row chunk are loaded into registers while
 //     the current chunk is multiplied (register double buffering).
-//   * Omega is generated into LDS, double buffered: the next chunk's entries
-//     are produced between the current chunk's MFMAs.  It is never stored in
-//     HBM and each entry is generated once per 256-column strip.
+//   * Omega comes from a row-major (rows x WP) buffer that k_omega fills once
+//     per launch (generating it inside the MFMA loop cost as many VALU
+//     cycles as a third of the MFMA work, once per 256-column strip).  Its
+//     next chunk is loaded while the current one is multiplied and staged in
+//     LDS, double buffered.
 //   * FP32: each chunk is accumulated by MFMA in FP32 and folded into FP64
 //     registers, so rounding grows with KC, not with m.
 //   * Partials part[split][j][c] (FP64) are summed in split order by
@@ -137,10 +139,28 @@ struct SketchShape {
   static constexpr int NT = 64 * 256 / (16 * NQ);     // 256 columns per workgroup
 };
 
+// Omega rows [0, mpad) for sketch vectors c0 .. c0 + WP - 1, row-major with
+// pitch WP: entry (i, c) is the Gaussian of row i, vector c0 + c; zero for
+// c >= w or i >= m.  One thread per (row quad, vector).
+template <typename TC>
+__global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uint32_t c0, int w,
+                                               int WP, int64_t m, int64_t mpad,
+                                               TC* __restrict__ om, const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (mpad / 4) * WP) return;
+  const int c = (int)(t % WP);
+  const int64_t q = t / WP;
+  TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
+  if (c < w && 4 * q < m) gauss4<TC>(key0, key1, (uint32_t)q, c0 + (uint32_t)c, v);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) om[(4 * q + a) * WP + c] = (4 * q + a < m) ? v[a] : TC(0);
+}
+
 template <typename TC, int MT, int KC, bool NORM, bool VEC>
 __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
-    const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, uint32_t key0, uint32_t key1,
-    uint32_t c0, int w, int64_t rows_per_split, double* __restrict__ part,
+    const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, const TC* __restrict__ omg,
+    int w, int64_t rows_per_split, double* __restrict__ part,
     double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
   if (ctrl && ctrl->done) return;
   constexpr int NQ = SketchShape<TC>::NQ;
@@ -149,9 +169,11 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
   constexpr int WP = MT * 16;            // padded number of sketch vectors
   constexpr int LDO = WP + 16;           // LDS row pitch of Omega
   constexpr int KS = KC / 4;             // MFMA k-steps (and row quads) per chunk
-  constexpr int NGEN = (KS * WP + NT - 1) / NT;  // gauss4 calls per thread per chunk
-  constexpr int GSTEP = KS / NGEN;               // k-steps between two of them
-  static_assert(NGEN >= 1 && KS % NGEN == 0, "chunk geometry");
+  // Omega tile of a chunk (KC x WP) per thread: NV loads of VE entries
+  constexpr int NE = KC * WP / NT;
+  constexpr int VE = (NE % (16 / (int)sizeof(TC)) == 0) ? 16 / (int)sizeof(TC) : 1;
+  constexpr int NV = NE / VE;
+  static_assert(NE >= 1 && (KC * WP) % NT == 0, "chunk geometry");
   using M = Mfma<TC>;
   using acc_t = typename M::acc_t;
   __shared__ TC om[2][KC * LDO];
@@ -166,8 +188,7 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
   // Interior workgroups (all 256 columns, all WP vectors, whole chunks, and
   // one more chunk of rows after the range so that prefetching it stays
   // inside A) run a loop without bounds tests.
-  const bool fast = VEC && (KS * WP) % NT == 0 && w == WP &&
-                    (int64_t)blockIdx.x * 256 + 256 <= n &&
+  const bool fast = VEC && w == WP && (int64_t)blockIdx.x * 256 + 256 <= n &&
                     (r_end - r_begin) % KC == 0 && r_end + KC <= m;
 
   acc_t acc[MT][NQ];
@@ -185,18 +206,24 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
 
   auto body = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
-    // Omega entries for row quads of chunk starting at r0, call index g
-    auto gen = [&](TC* omb, int64_t r0, int g) {
-      const int it = tid + g * NT;
-      if (!FAST && it >= KS * WP) return;
-      const int c = it % WP, qd = it / WP;
-      const int64_t row4 = r0 + 4 * qd;
-      TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
-      if (FAST || (c < w && row4 < r_end))
-        gauss4<TC>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
+    // Omega tile of the chunk starting at row r0: global -> registers, and
+    // registers -> LDS (entries e = (v NT + tid) VE .. + VE - 1, row e / WP)
+    using OV = typename std::conditional<VE == 4, floatx4,
+               typename std::conditional<VE == 2, doublex2, TC>::type>::type;
+    // pieces [v0, v1) of it, so that a part of the tile is in flight at once
+    auto om_load = [&](OV* r, int64_t r0, int v0, int v1) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        omb[(4 * qd + a) * LDO + c] = (FAST || row4 + a < r_end) ? v[a] : TC(0);
+      for (int v = v0; v < v1; ++v) {
+        const int e = (v * NT + tid) * VE;
+        r[v - v0] = *reinterpret_cast<const OV*>(omg + (r0 + e / WP) * WP + e % WP);
+      }
+    };
+    auto om_store = [&](TC* omb, const OV* r, int v0, int v1) {
+#pragma unroll
+      for (int v = v0; v < v1; ++v) {
+        const int e = (v * NT + tid) * VE;
+        *reinterpret_cast<OV*>(omb + (e / WP) * LDO + e % WP) = r[v - v0];
+      }
     };
     auto loadB = [&](TC (&buf)[KS][NQ], int64_t r0) {
 #pragma unroll
@@ -232,12 +259,22 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
         }
       }
     };
-    // multiply one chunk (Omega in omc, A operands in buf) while generating
-    // the next chunk's Omega into omn
+    // multiply one chunk (Omega in omc, A operands in buf) while loading the
+    // next chunk's Omega, which goes to omn at the end
+    // the next tile moves in OS pieces, piece p loaded at k-step p KS / OS and
+    // stored one segment later
+    constexpr int OS = NV >= 2 ? 2 : 1;
+    constexpr int PV = NV / OS;
+    static_assert(NV % OS == 0 && KS % OS == 0, "Omega pieces");
     auto compute = [&](const TC* omc, TC (&buf)[KS][NQ], TC* omn, int64_t rnext, bool has_next) {
+      OV onext[PV];
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
-        if ((FAST || has_next) && (j % GSTEP) == 0) gen(omn, rnext, j / GSTEP);
+        if ((FAST || has_next) && j % (KS / OS) == 0) {
+          const int p = j / (KS / OS);
+          if (p > 0) om_store(omn, onext, (p - 1) * PV, p * PV);
+          om_load(onext, rnext, p * PV, (p + 1) * PV);
+        }
         TC av[MT];
 #pragma unroll
         for (int a = 0; a < MT; ++a)
@@ -254,6 +291,7 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
 #pragma unroll
           for (int q = 0; q < NQ; ++q) acc[a][q] = M::op(av[a], buf[j][q], acc[a][q]);
       }
+      if (FAST || has_next) om_store(omn, onext, (OS - 1) * PV, OS * PV);
       if (sizeof(TC) == 4) {
 #pragma unroll
         for (int a = 0; a < MT; ++a)
@@ -268,8 +306,9 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
 
     TC bA[KS][NQ], bB[KS][NQ];
     if (nch > 0) {
-#pragma unroll
-      for (int g = 0; g < NGEN; ++g) gen(om[0], r_begin, g);
+      OV o0[NV];
+      om_load(o0, r_begin, 0, NV);
+      om_store(om[0], o0, 0, NV);
       loadB(bA, r_begin);
     }
     __syncthreads();
@@ -576,16 +615,13 @@ __host__ __device__ constexpr int panel_pitch(int w, int es) {
   return m * e;
 }
 
-typedef float panel_f32x4 __attribute__((ext_vector_type(4)));
-typedef double panel_f64x2 __attribute__((ext_vector_type(2)));
-
 // row[q] -= l * prow[q] for q in [qa, w) with 16-byte LDS accesses; the
 // vector holding column qa keeps its columns below qa.  row and prow are
 // 16-byte aligned.
 template <typename TF>
 __device__ __forceinline__ void panel_row_update(TF* row, const TF* prow, TF l, int qa, int w) {
   constexpr int E = 16 / (int)sizeof(TF);
-  using V = typename std::conditional<sizeof(TF) == 4, panel_f32x4, panel_f64x2>::type;
+  using V = typename std::conditional<sizeof(TF) == 4, floatx4, doublex2>::type;
   const int qv = qa / E * E;
   for (int q0 = qv; q0 < w; q0 += 4 * E) {
     V x[4], p[4];
