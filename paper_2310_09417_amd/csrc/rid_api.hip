@@ -104,7 +104,7 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   SketchGeom g;
   g.mt = w <= 16 ? 1 : w <= 32 ? 2 : 4;
   g.wp = g.mt * 16;
-  g.kc = dt == RID_F64 ? 32 : 64;
+  g.kc = 32;
   g.ncolg = ceil_div(n, 256);
   // One resident workgroup per CU (FP32: 4 waves of ~440 registers; FP64:
   // 8 waves of ~250): pick the number of row splits whose workgroup count
@@ -433,7 +433,7 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
     SketchGeom g = sketch_geom(P.m, P.n, wc, P.dt, P.cu);
     int rc = (P.dt == RID_F64)
                  ? launch_sketch<double, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st)
-                 : launch_sketch<float, 64>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st);
+                 : launch_sketch<float, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st);
     if (rc != RID_OK) return rc;
     const long pm = prof_begin(KC_REDUCE, st);
     if (P.dt == RID_F64)

@@ -128,15 +128,14 @@ __device__ __forceinline__ void load_row2(const TC* __restrict__ A, int64_t row,
   }
 }
 
-// Threads per sketch workgroup: FP32 uses 4 columns per lane and one wave
-// per SIMD (256 threads); FP64 uses 2 columns per lane and two waves per SIMD
-// (512 threads), which lets one wave's Gaussian generation overlap the other's
-// MFMAs (measured 153 -> 141 ms per FP64 decomposition of the 50000 x 20000
-// matrix, while the FP32 variant was slower that way: 1.65 -> 1.93 ms/pass).
+// Threads per sketch workgroup: 2 columns per lane and two waves per SIMD
+// (512 threads), so that one wave's loads are in flight while the other
+// multiplies (FP32 with 32-row chunks: 1.46 -> 1.41 ms per pass over the
+// 50000 x 20000 matrix against 4 columns per lane and one wave per SIMD).
 template <typename TC>
 struct SketchShape {
-  static constexpr int NQ = sizeof(TC) == 4 ? 4 : 2;  // columns per lane
-  static constexpr int NT = 64 * 256 / (16 * NQ);     // 256 columns per workgroup
+  static constexpr int NQ = 2;                     // columns per lane
+  static constexpr int NT = 64 * 256 / (16 * NQ);  // 256 columns per workgroup
 };
 
 // Omega rows [0, mpad) for sketch vectors c0 .. c0 + WP - 1, row-major with
