@@ -138,6 +138,66 @@ struct SketchShape {
   static constexpr int NT = 64 * 256 / (16 * NQ);  // 256 columns per workgroup
 };
 
+// Direct copies from global memory into LDS: lane l's 16 (or 4) bytes land
+// at LDS byte address lds + 16 l (or 4 l); each counts once in vmcnt.  Issued
+// as asm so that the compiler neither reorders them nor adds waits of its own
+// for them; the caller waits explicitly.  M0 is restored afterwards.
+__device__ __forceinline__ void copy16_to_lds(const void* src, uint32_t lds) {
+  uint32_t keep;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(keep)
+      : "s"(lds), "v"(src)
+      : "memory");
+}
+__device__ __forceinline__ void copy4_to_lds(const void* src, uint32_t lds) {
+  uint32_t keep;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dword %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(keep)
+      : "s"(lds), "v"(src)
+      : "memory");
+}
+template <typename T>
+__device__ __forceinline__ uint32_t lds_addr(T* p) {
+  return (uint32_t)reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) T*)p);
+}
+
+// Eight 8-byte LDS reads at byte offsets addr + 512 j, complete on return.
+// Written as one asm block so that the compiler adds no wait of its own for
+// the asynchronous copies into that memory (the caller has ordered them).
+__device__ __forceinline__ void lds_read8x8(uint32_t addr, floatx2 (&r)[8]) {
+  asm volatile(
+      "ds_read_b64 %0, %8 offset:0\n\t"
+      "ds_read_b64 %1, %8 offset:512\n\t"
+      "ds_read_b64 %2, %8 offset:1024\n\t"
+      "ds_read_b64 %3, %8 offset:1536\n\t"
+      "ds_read_b64 %4, %8 offset:2048\n\t"
+      "ds_read_b64 %5, %8 offset:2560\n\t"
+      "ds_read_b64 %6, %8 offset:3072\n\t"
+      "ds_read_b64 %7, %8 offset:3584\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+        "=&v"(r[6]), "=&v"(r[7])
+      : "v"(addr));
+}
+
+// Wait until at most 8 vector-memory operations of this wave are
+// outstanding, then a workgroup barrier that does not wait for the rest.
+__device__ __forceinline__ void vm8_barrier() {
+  asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Omega rows [0, mpad) for sketch vectors c0 .. c0 + WP - 1, row-major with
 // pitch WP: entry (i, c) is the Gaussian of row i, vector c0 + c; zero for
 // c >= w or i >= m.  One thread per (row quad, vector).
@@ -177,6 +237,12 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
   using acc_t = typename M::acc_t;
   __shared__ TC om[2][KC * LDO];
   __shared__ double red[NW];
+  // FP32 interior workgroups: A and Omega staged through LDS by direct
+  // copies, three chunks deep; A in one region per wave ([stage][wave][KC
+  // rows][32 columns]), Omega shared ([stage][KC rows][LDO])
+  constexpr bool DMA = sizeof(TC) == 4 && NQ == 2 && KC == 32;
+  __shared__ __attribute__((aligned(16))) TC sA[DMA ? 3 * NW * KC * 32 : 1];
+  __shared__ __attribute__((aligned(16))) TC sO[DMA ? 3 * KC * LDO : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // a wave owns 16 NQ columns; lane l loads NQ consecutive columns from NQ (l % 16)
@@ -224,6 +290,76 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
         *reinterpret_cast<OV*>(omb + (e / WP) * LDO + e % WP) = r[v - v0];
       }
     };
+    if constexpr (FAST && DMA) {
+      // Per chunk and wave: 4 copies of A (8 rows x 32 columns each, this
+      // wave's columns) and 4 of Omega (one row each, rows 4 wave .. +3),
+      // always 8 (chunks past the end re-read this chunk's rows into a stage
+      // no later chunk reads), so that vmcnt(8) at the top of chunk c means
+      // chunk c has landed while chunk c+1 is still in flight.
+      static_assert(KC == 4 * NW && KS == 8, "copy geometry");
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
+      const int64_t cw = (int64_t)blockIdx.x * 256 + wv * 32;
+      const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
+      // per-lane sources at the first chunk; a chunk adds a uniform offset
+      const TC* pa[KC / 8];
+      const TC* po[4];
+#pragma unroll
+      for (int i = 0; i < KC / 8; ++i)
+        pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + cw + 4 * (lane & 7);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) po[i] = omg + (r_begin + 4 * wv + i) * WP + lane;
+      auto copy_chunk = [&](int chunk, int st) {
+        const int64_t roff = (int64_t)chunk * KC;
+        const int64_t da = roff * lda, dO = roff * WP;
+#pragma unroll
+        for (int i = 0; i < KC / 8; ++i)
+          copy16_to_lds(pa[i] + da, sa + (uint32_t)(((st * NW + wv) * KC + 8 * i) * 32 * 4));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (lane < WP) copy4_to_lds(po[i] + dO, so + (uint32_t)((st * KC + 4 * wv + i) * LDO * 4));
+      };
+      const uint32_t lane_off = (uint32_t)(((lane >> 4) * 32 + 2 * (lane & 15)) * 4);
+      copy_chunk(0, 0);
+      copy_chunk(nch > 1 ? 1 : 0, 1);
+      for (int c = 0; c < nch; ++c) {
+        const int st = c % 3;
+        vm8_barrier();  // chunk c complete in every wave; chunk c-1's stage free
+        copy_chunk(c + 2 < nch ? c + 2 : c, (c + 2) % 3);
+        floatx2 a2[8];
+        lds_read8x8(sa + (uint32_t)(((st * NW + wv) * KC * 32) * 4) + lane_off, a2);
+        const TC* omc = sO + st * KC * LDO;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          TC av[MT];
+#pragma unroll
+          for (int a = 0; a < MT; ++a)
+            av[a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
+          if (NORM) {
+            fro += (double)a2[j].x * (double)a2[j].x + (double)a2[j].y * (double)a2[j].y;
+            bad |= !__builtin_isfinite((double)a2[j].x) || !__builtin_isfinite((double)a2[j].y);
+          }
+#pragma unroll
+          for (int a = 0; a < MT; ++a) {
+            acc[a][0] = M::op(av[a], a2[j].x, acc[a][0]);
+            acc[a][1] = M::op(av[a], a2[j].y, acc[a][1]);
+          }
+        }
+        // FP32 sums of 64 rows (two chunks) are folded into FP64
+        if ((c & 1) || c + 1 == nch) {
+#pragma unroll
+          for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
+              acc[a][q] = M::zero();
+            }
+        }
+      }
+      // every copy has landed before the workgroup's LDS is released
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      return;
+    }
     auto loadB = [&](TC (&buf)[KS][NQ], int64_t r0) {
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
