@@ -105,20 +105,22 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   g.mt = w <= 16 ? 1 : w <= 32 ? 2 : 4;
   g.wp = g.mt * 16;
   g.kc = 32;
-  g.ncolg = ceil_div(n, 256);
-  // One resident workgroup per CU (FP32: 4 waves of ~440 registers; FP64:
-  // 8 waves of ~250): pick the number of row splits whose workgroup count
-  // fills the last round best, between ~2 and ~8 rounds, preferring fewer.
+  g.ncolg = ceil_div(n, dt == RID_F64 ? SketchShape<double>::CPW : SketchShape<float>::CPW);
+  // Resident workgroups: two per CU in FP32 (4 waves, ~78 KB of LDS each),
+  // one in FP64 (8 waves).  Pick the number of row splits whose workgroup
+  // count fills the last round best, between ~2 and ~8 rounds, preferring
+  // fewer.
+  const int64_t slots = (int64_t)cu * (dt == RID_F64 ? 1 : 2);
   const int64_t maxsplit = ceil_div(m, g.kc);
-  const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(2 * cu, g.ncolg)));
-  const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(maxsplit, ceil_div(8 * cu, g.ncolg)));
+  const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(2 * slots, g.ncolg)));
+  const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(maxsplit, ceil_div(8 * slots, g.ncolg)));
   double best = -1.0;
   int64_t best_ns = lo;
   for (int64_t ns = lo; ns <= hi; ++ns) {
     const int64_t rps = ceil_div(ceil_div(m, ns), g.kc) * g.kc;
     const int64_t real_ns = ceil_div(m, rps);
     const int64_t items = g.ncolg * real_ns;
-    const double eff = (double)items / (double)(ceil_div(items, cu) * cu);
+    const double eff = (double)items / (double)(ceil_div(items, slots) * slots);
     if (eff > best + 1e-3) {
       best = eff;
       best_ns = ns;

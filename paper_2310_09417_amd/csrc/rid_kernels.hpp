@@ -59,8 +59,9 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, int* nonfinite) {
 
 // ---------------------------------------------------------------------------
 // Sketch: partial sums of Y(c, j) = sum_i omega(c0 + c, i) A(i, j) over one
-// row range ("split") per grid row, for a strip of 256 columns per grid
-// column (FP32: 4 waves x 64 columns; FP64: 8 waves x 32 columns).
+// row range ("split") per grid row, for a strip of columns per grid column
+// (FP32: 4 waves x 32 columns, two workgroups per CU; FP64: 8 waves x 32
+// columns).
 //   * A is streamed once.  Each lane loads NQ consecutive columns of one row
 //     (one 16- or 32-byte load) and feeds them to NQ different MFMAs, so MFMA
 //     q, output column j covers matrix column NQ j + q of the wave's strip.
@@ -128,14 +129,15 @@ __device__ __forceinline__ void load_row2(const TC* __restrict__ A, int64_t row,
   }
 }
 
-// Threads per sketch workgroup: 2 columns per lane and two waves per SIMD
-// (512 threads), so that one wave's loads are in flight while the other
-// multiplies (FP32 with 32-row chunks: 1.46 -> 1.41 ms per pass over the
-// 50000 x 20000 matrix against 4 columns per lane and one wave per SIMD).
+// Workgroup shape: 2 columns per lane and two waves per SIMD, so that one
+// wave's loads and LDS traffic overlap the other's MFMAs.  FP32: two
+// independent 256-thread workgroups per CU (they synchronise separately and
+// drift out of phase); FP64: one 512-thread workgroup.
 template <typename TC>
 struct SketchShape {
-  static constexpr int NQ = 2;                     // columns per lane
-  static constexpr int NT = 64 * 256 / (16 * NQ);  // 256 columns per workgroup
+  static constexpr int NQ = 2;                              // columns per lane
+  static constexpr int NT = sizeof(TC) == 4 ? 256 : 512;    // threads
+  static constexpr int CPW = NT / 64 * 16 * NQ;             // columns per workgroup
 };
 
 // Direct copies from global memory into LDS: lane l's 16 (or 4) bytes land
@@ -190,10 +192,11 @@ __device__ __forceinline__ void lds_read8x8(uint32_t addr, floatx2 (&r)[8]) {
       : "v"(addr));
 }
 
-// Wait until at most 8 vector-memory operations of this wave are
+// Wait until at most N vector-memory operations of this wave are
 // outstanding, then a workgroup barrier that does not wait for the rest.
-__device__ __forceinline__ void vm8_barrier() {
-  asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+template <int N>
+__device__ __forceinline__ void vm_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
 }
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uin
 }
 
 template <typename TC, int MT, int KC, bool NORM, bool VEC>
-__global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
+__global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
     const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, const TC* __restrict__ omg,
     int w, int64_t rows_per_split, double* __restrict__ part,
     double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
@@ -235,25 +238,27 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
   static_assert(NE >= 1 && (KC * WP) % NT == 0, "chunk geometry");
   using M = Mfma<TC>;
   using acc_t = typename M::acc_t;
-  __shared__ TC om[2][KC * LDO];
   __shared__ double red[NW];
   // FP32 interior workgroups: A and Omega staged through LDS by direct
   // copies, three chunks deep; A in one region per wave ([stage][wave][KC
-  // rows][32 columns]), Omega shared ([stage][KC rows][LDO])
+  // rows][32 columns]), Omega shared ([stage][KC rows][LDO]).  The other
+  // workgroups use the first two Omega stages as a double buffer.
   constexpr bool DMA = sizeof(TC) == 4 && NQ == 2 && KC == 32;
   __shared__ __attribute__((aligned(16))) TC sA[DMA ? 3 * NW * KC * 32 : 1];
-  __shared__ __attribute__((aligned(16))) TC sO[DMA ? 3 * KC * LDO : 1];
+  __shared__ __attribute__((aligned(16))) TC sO[3 * KC * LDO];
+  TC* const om[2] = {sO, sO + KC * LDO};
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // a wave owns 16 NQ columns; lane l loads NQ consecutive columns from NQ (l % 16)
-  const int64_t colq = (int64_t)blockIdx.x * 256 + wave * 16 * NQ + NQ * (lane & 15);
+  constexpr int CPW = SketchShape<TC>::CPW;
+  const int64_t colq = (int64_t)blockIdx.x * CPW + wave * 16 * NQ + NQ * (lane & 15);
   const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
   const int nch = (int)((r_end - r_begin + KC - 1) / KC);
-  // Interior workgroups (all 256 columns, all WP vectors, whole chunks, and
+  // Interior workgroups (all CPW columns, all WP vectors, whole chunks, and
   // one more chunk of rows after the range so that prefetching it stays
   // inside A) run a loop without bounds tests.
-  const bool fast = VEC && w == WP && (int64_t)blockIdx.x * 256 + 256 <= n &&
+  const bool fast = VEC && w == WP && (int64_t)blockIdx.x * CPW + CPW <= n &&
                     (r_end - r_begin) % KC == 0 && r_end + KC <= m;
 
   acc_t acc[MT][NQ];
@@ -291,23 +296,25 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
       }
     };
     if constexpr (FAST && DMA) {
-      // Per chunk and wave: 4 copies of A (8 rows x 32 columns each, this
-      // wave's columns) and 4 of Omega (one row each, rows 4 wave .. +3),
-      // always 8 (chunks past the end re-read this chunk's rows into a stage
-      // no later chunk reads), so that vmcnt(8) at the top of chunk c means
-      // chunk c has landed while chunk c+1 is still in flight.
-      static_assert(KC == 4 * NW && KS == 8, "copy geometry");
+      // Per chunk and wave: KC/8 copies of A (8 rows x 32 columns each, this
+      // wave's columns) and KC/NW of Omega (one row each), always the same
+      // number NCP (chunks past the end re-read this chunk's rows into a
+      // stage no later chunk reads), so that vmcnt(NCP) at the top of chunk
+      // c means chunk c has landed while chunk c+1 is still in flight.
+      constexpr int ORW = KC / NW;   // Omega rows copied per wave
+      constexpr int NCP = KC / 8 + ORW;  // copies per wave and chunk
+      static_assert(KC % NW == 0 && KS == 8, "copy geometry");
       const int wv = __builtin_amdgcn_readfirstlane(wave);
-      const int64_t cw = (int64_t)blockIdx.x * 256 + wv * 32;
+      const int64_t cw = (int64_t)blockIdx.x * CPW + wv * 32;
       const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
       // per-lane sources at the first chunk; a chunk adds a uniform offset
       const TC* pa[KC / 8];
-      const TC* po[4];
+      const TC* po[ORW];
 #pragma unroll
       for (int i = 0; i < KC / 8; ++i)
         pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + cw + 4 * (lane & 7);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) po[i] = omg + (r_begin + 4 * wv + i) * WP + lane;
+      for (int i = 0; i < ORW; ++i) po[i] = omg + (r_begin + ORW * wv + i) * WP + lane;
       auto copy_chunk = [&](int chunk, int st) {
         const int64_t roff = (int64_t)chunk * KC;
         const int64_t da = roff * lda, dO = roff * WP;
@@ -315,15 +322,15 @@ __global__ __launch_bounds__(SketchShape<TC>::NT) void k_sketch(
         for (int i = 0; i < KC / 8; ++i)
           copy16_to_lds(pa[i] + da, sa + (uint32_t)(((st * NW + wv) * KC + 8 * i) * 32 * 4));
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (lane < WP) copy4_to_lds(po[i] + dO, so + (uint32_t)((st * KC + 4 * wv + i) * LDO * 4));
+        for (int i = 0; i < ORW; ++i)
+          if (lane < WP) copy4_to_lds(po[i] + dO, so + (uint32_t)((st * KC + ORW * wv + i) * LDO * 4));
       };
       const uint32_t lane_off = (uint32_t)(((lane >> 4) * 32 + 2 * (lane & 15)) * 4);
       copy_chunk(0, 0);
       copy_chunk(nch > 1 ? 1 : 0, 1);
       for (int c = 0; c < nch; ++c) {
         const int st = c % 3;
-        vm8_barrier();  // chunk c complete in every wave; chunk c-1's stage free
+        vm_barrier<NCP>();  // chunk c complete in every wave; chunk c-1's stage free
         copy_chunk(c + 2 < nch ? c + 2 : c, (c + 2) % 3);
         floatx2 a2[8];
         lds_read8x8(sa + (uint32_t)(((st * NW + wv) * KC * 32) * 4) + lane_off, a2);
