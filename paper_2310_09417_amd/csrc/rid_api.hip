@@ -548,7 +548,7 @@ int linv_update_t(const Plan& P, const Ws& W, int k0, int f, hipStream_t st) {
       hipFuncSetAttribute((const void*)k_linv_diag<TF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds) != hipSuccess)
     return RID_ERR_HIP;
-  hipLaunchKernelGGL(k_linv_diag<TF>, dim3(1), dim3(128), lds, st, static_cast<const TF*>(W.z),
+  hipLaunchKernelGGL(k_linv_diag<TF>, dim3(1), dim3(256), lds, st, static_cast<const TF*>(W.z),
                      P.ldz, W.order, k0, static_cast<TF*>(W.linv), P.ldl, W.ctrl, x_in_lds);
   RID_LAUNCH_CHECK();
   if (k0 > 0) {

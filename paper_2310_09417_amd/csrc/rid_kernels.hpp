@@ -1306,11 +1306,15 @@ __global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ Z, int64_t ld
 }
 
 // Diagonal block of Linv for the f_act pivots of the panel at k0:
-// Linv[k0:k0+f, k0:k0+f] = L22^{-1} (one workgroup; column j solved by thread
-// j, with L22 and, when it fits, the result kept in LDS).  f_act = ctrl->k -
-// k0 (0 when the panel did not run).
+// Linv[k0:k0+f, k0:k0+f] = L22^{-1} (one workgroup of 256).  Right-looking
+// substitution on all columns at once: X starts as the identity; L22 has a
+// unit diagonal, so after step p row p of X is final, and every row i > p then
+// takes x_ij -= l_ip x_pj for j <= p (each entry accumulates in the order of a
+// column-by-column forward substitution).  L22 and, when it fits, X live in
+// LDS; otherwise X is updated in place in Linv.  f_act = ctrl->k - k0 (0 when
+// the panel did not run).
 template <typename TF>
-__global__ __launch_bounds__(128) void k_linv_diag(const TF* __restrict__ Z, int64_t ldz,
+__global__ __launch_bounds__(256) void k_linv_diag(const TF* __restrict__ Z, int64_t ldz,
                                                    const int* __restrict__ order, int k0,
                                                    TF* __restrict__ Linv, int64_t ldl,
                                                    const Ctrl* ctrl, int x_in_lds) {
@@ -1320,33 +1324,31 @@ __global__ __launch_bounds__(128) void k_linv_diag(const TF* __restrict__ Z, int
   extern __shared__ unsigned char smem_raw[];
   const int pitch = f + 1;
   TF* L = reinterpret_cast<TF*>(smem_raw);  // f x pitch
-  TF* X = L + (size_t)f * pitch;              // f x pitch when x_in_lds
+  TF* out = Linv + (int64_t)k0 * ldl + k0;
+  TF* X = x_in_lds ? L + (size_t)f * pitch : out;
+  const int64_t ldx = x_in_lds ? pitch : ldl;
   for (int t = threadIdx.x; t < f * f; t += blockDim.x) {
     const int a = t / f, b = t % f;
     L[a * pitch + b] = (b < a) ? Z[(int64_t)order[k0 + a] * ldz + k0 + b] : TF(0);
+    X[a * ldx + b] = (a == b) ? TF(1) : TF(0);
   }
   __syncthreads();
-  const int j = threadIdx.x;
-  TF* out = Linv + (int64_t)k0 * ldl + k0;
-  if (j < f) {
-    // column j of L22^{-1}: X[j][j] = 1, X[i][j] = -sum_{j<=p<i} L[i][p] X[p][j]
-    if (x_in_lds) {
-      X[j * pitch + j] = TF(1);
-      for (int i = j + 1; i < f; ++i) {
-        TF acc = L[i * pitch + j];
-        for (int p = j + 1; p < i; ++p) acc += L[i * pitch + p] * X[p * pitch + j];
-        X[i * pitch + j] = -acc;
-      }
-      for (int i = j; i < f; ++i) out[(int64_t)i * ldl + j] = X[i * pitch + j];
-    } else {
-      out[(int64_t)j * ldl + j] = TF(1);
-      for (int i = j + 1; i < f; ++i) {
-        TF acc = L[i * pitch + j];
-        for (int p = j + 1; p < i; ++p) acc += L[i * pitch + p] * out[(int64_t)p * ldl + j];
-        out[(int64_t)i * ldl + j] = -acc;
-      }
+  // thread (ri, cj): rows p+1+ri+16u, columns cj+16v
+  const int ri = threadIdx.x >> 4, cj = threadIdx.x & 15;
+  for (int p = 0; p + 1 < f; ++p) {
+    const TF* xp = X + (int64_t)p * ldx;
+    for (int i = p + 1 + ri; i < f; i += 16) {
+      const TF lip = L[i * pitch + p];
+      TF* xi = X + (int64_t)i * ldx;
+      for (int j = cj; j <= p; j += 16) xi[j] = fma(-lip, xp[j], xi[j]);
     }
+    __syncthreads();
   }
+  if (x_in_lds)
+    for (int t = threadIdx.x; t < f * f; t += blockDim.x) {
+      const int a = t / f, b = t % f;
+      if (b <= a) out[(int64_t)a * ldl + b] = X[a * ldx + b];
+    }
 }
 
 // Mtmp = L21 L1^{-1}_old: rows i < f_act (new pivots), columns s < k0.
