@@ -585,19 +585,27 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
   }
-  for (int s0 = 0; s0 < k; s0 += 16) {
-    const int kidx = s0 + 4 * (lane >> 4);
+  // K chunks of 16; the operands of chunk c+1 are loaded while chunk c is
+  // multiplied (two register buffers, unrolled by two)
+  struct Ops {
     TF a4[4];
-    load4(Z, arow * ldz, kidx, k, arow_ok, a4);
+    TF b4[NT][4];
+  };
+  auto load_ops = [&](Ops& o, int s0) {
+    const int kidx = s0 + 4 * (lane >> 4);
+    load4(Z, arow * ldz, kidx, k, arow_ok, o.a4);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = t * 16 + (lane & 15);
-      TF b4[4];
-      load4(U2T, (int64_t)col * ldu, kidx, k, col < w, b4);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[t] = M::op(a4[j], b4[j], acc[t]);
+      load4(U2T, (int64_t)col * ldu, kidx, k, col < w, o.b4[t]);
     }
-    if (sizeof(TF) == 4 && ((s0 >> 4) & 3) == 3) {
+  };
+  auto mma_ops = [&](const Ops& o, int ci) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[t] = M::op(o.a4[j], o.b4[t][j], acc[t]);
+    if (sizeof(TF) == 4 && (ci & 3) == 3) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -605,6 +613,16 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
         acc[t] = M::zero();
       }
     }
+  };
+  const int nchk = (k + 15) / 16;
+  Ops o0, o1;
+  if (nchk > 0) load_ops(o0, 0);
+  for (int ci = 0; ci < nchk; ci += 2) {
+    if (ci + 1 < nchk) load_ops(o1, 16 * (ci + 1));
+    mma_ops(o0, ci);
+    if (ci + 1 >= nchk) break;
+    if (ci + 2 < nchk) load_ops(o0, 16 * (ci + 2));
+    mma_ops(o1, ci + 1);
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -1195,40 +1213,93 @@ __device__ __forceinline__ void ld4_masked(const TF* p, int e0, int lim, TF out[
   for (int e = 0; e < 4; ++e) out[e] = (e0 + e < lim) ? p[e] : TF(0);
 }
 
-template <typename TF, typename BRow>
+template <typename TF, bool PREFETCH = true, typename BRow>
 __device__ __forceinline__ void wave_tile(const TF* arow, BRow brow, int kb, int ke, int bcols,
                                           typename Mfma<TF>::acc_t acc[4],
                                           double acc64[4][4]) {
   using M = Mfma<TF>;
   const int lane = threadIdx.x & 63;
   const int bc = 4 * (lane & 15);
-  int chunk = 0;
-  for (int p0 = kb & ~15; p0 < ke; p0 += 16, ++chunk) {
-    const int pa = p0 + 4 * (lane >> 4);
+  // chunks of 16 K values starting at kb & ~15; with PREFETCH the operands
+  // of chunk c+1 are loaded while chunk c is multiplied (two register
+  // buffers: for small grids; large grids hide latency by occupancy)
+  struct Ops {
     TF a4[4];
+    TF b4[4][4];
+  };
+  auto load_ops = [&](Ops& o, int p0) {
+    const int pa = p0 + 4 * (lane >> 4);
     if (arow && pa >= kb && pa + 3 < ke) {
-      ld4_masked(arow + pa, 0, 4, a4);
+      ld4_masked(arow + pa, 0, 4, o.a4);
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a4[e] = (arow && pa + e >= kb && pa + e < ke) ? arow[pa + e] : TF(0);
+      for (int e = 0; e < 4; ++e) o.a4[e] = (arow && pa + e >= kb && pa + e < ke) ? arow[pa + e] : TF(0);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int pp = pa + j;
-      TF b4[4] = {TF(0), TF(0), TF(0), TF(0)};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o.b4[j][q] = TF(0);
       if (pp >= kb && pp < ke) {
         const TF* br = brow(pp);
-        if (br) ld4_masked(br + bc, bc, bcols, b4);
+        if (br) ld4_masked(br + bc, bc, bcols, o.b4[j]);
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = M::op(a4[j], b4[q], acc[q]);
     }
+  };
+  auto mma_ops = [&](const Ops& o, int chunk) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = M::op(o.a4[j], o.b4[j][q], acc[q]);
     if (sizeof(TF) == 4 && (chunk & 3) == 3) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc64[q][r] += (double)acc[q][r];
         acc[q] = M::zero();
+      }
+    }
+  };
+  const int pbeg = kb & ~15;
+  const int nchk = ke > pbeg ? (ke - pbeg + 15) / 16 : 0;
+  if constexpr (PREFETCH) {
+    Ops o0, o1;
+    if (nchk > 0) load_ops(o0, pbeg);
+    for (int c = 0; c < nchk; c += 2) {
+      if (c + 1 < nchk) load_ops(o1, pbeg + 16 * (c + 1));
+      mma_ops(o0, c);
+      if (c + 1 >= nchk) break;
+      if (c + 2 < nchk) load_ops(o0, pbeg + 16 * (c + 2));
+      mma_ops(o1, c + 1);
+    }
+  } else {
+    for (int c = 0; c < nchk; ++c) {
+      const int pa = pbeg + 16 * c + 4 * (lane >> 4);
+      TF a4[4];
+      if (arow && pa >= kb && pa + 3 < ke) {
+        ld4_masked(arow + pa, 0, 4, a4);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a4[e] = (arow && pa + e >= kb && pa + e < ke) ? arow[pa + e] : TF(0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int pp = pa + j;
+        TF b4[4] = {TF(0), TF(0), TF(0), TF(0)};
+        if (pp >= kb && pp < ke) {
+          const TF* br = brow(pp);
+          if (br) ld4_masked(br + bc, bc, bcols, b4);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = M::op(a4[j], b4[q], acc[q]);
+      }
+      if (sizeof(TF) == 4 && (c & 3) == 3) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[q][r] += (double)acc[q][r];
+          acc[q] = M::zero();
+        }
       }
     }
   }
@@ -1435,7 +1506,7 @@ __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t
     for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
   }
   // Linv[p][s] = 0 for p < s: p runs over [j0, k)
-  wave_tile<TF>(arow, brow, j0, k, bcols, acc, acc64);
+  wave_tile<TF, false>(arow, brow, j0, k, bcols, acc, acc64);
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
