@@ -335,12 +335,16 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
         floatx2 a2[8];
         lds_read8x8(sa + (uint32_t)(((st * NW + wv) * KC * 32) * 4) + lane_off, a2);
         const TC* omc = sO + st * KC * LDO;
+        // all Omega operands of the chunk first, then 8 k-steps of MFMAs
+        TC avs[KS][MT];
 #pragma unroll
-        for (int j = 0; j < KS; ++j) {
-          TC av[MT];
+        for (int j = 0; j < KS; ++j)
 #pragma unroll
           for (int a = 0; a < MT; ++a)
-            av[a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
+            avs[j][a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          const TC* av = avs[j];
           if (NORM) {
             fro += (double)a2[j].x * (double)a2[j].x + (double)a2[j].y * (double)a2[j].y;
             bad |= !__builtin_isfinite((double)a2[j].x) || !__builtin_isfinite((double)a2[j].y);
@@ -351,6 +355,9 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
             acc[a][1] = M::op(av[a], a2[j].y, acc[a][1]);
           }
         }
+        // schedule: the chunk's Omega reads, then its MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x100, KS * MT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, KS * MT * 2, 0);
         // FP32 sums of 64 rows (two chunks) are folded into FP64
         if ((c & 1) || c + 1 == nch) {
 #pragma unroll
