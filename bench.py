@@ -184,7 +184,7 @@ def main():
     sk_avg_s = sk_ms * 1e-3 / max(sk_cnt, 1)
     sk_flops = 2.0 * b * m * n  # per launch: one block of b sketch vectors over all of A
     roof = {
-        "kernel": "k_sketch (fp32 MFMA 16x16x4, on-the-fly Philox Gaussian)",
+        "kernel": "k_sketch (FP32 MFMA 16x16x4; A and Gaussian tiles staged into LDS by direct copies)",
         "dominant": dom == "sketch",
         "bound": "mfma",
         "achieved": sk_flops / sk_avg_s / 1e12,

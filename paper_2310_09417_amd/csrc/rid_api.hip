@@ -13,6 +13,7 @@
 
 #include "../../include/rid.h"
 #include "rid_kernels.hpp"
+#include "rid_sketch.hpp"
 #include "rid_batched.hpp"
 #include "rid_sketch_lp.hpp"
 #include "rid_refine.hpp"

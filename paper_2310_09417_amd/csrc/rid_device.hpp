@@ -182,4 +182,55 @@ __device__ __forceinline__ void fence_acquire_agent() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// One row's NQ consecutive entries of A from column col (zeros outside the
+// row range [.., r_end) or past column n); VEC: 16-byte aligned vector loads.
+template <typename TC, bool VEC>
+__device__ __forceinline__ void load_row4(const TC* __restrict__ A, int64_t row, int64_t r_end,
+                                          int64_t col, int64_t n, int64_t lda, TC out[4]) {
+  if (row < r_end && col + 3 < n) {
+    const TC* p = A + row * lda + col;
+    if (VEC) {
+      if (sizeof(TC) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2*>(p);
+        const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+        out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[e] = p[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      out[e] = (row < r_end && col + e < n) ? A[row * lda + col + e] : TC(0);
+  }
+}
+
+template <typename TC, bool VEC>
+__device__ __forceinline__ void load_row2(const TC* __restrict__ A, int64_t row, int64_t r_end,
+                                          int64_t col, int64_t n, int64_t lda, TC out[2]) {
+  if (row < r_end && col + 1 < n) {
+    const TC* p = A + row * lda + col;
+    if (VEC) {
+      if (sizeof(TC) == 4) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        out[0] = v.x; out[1] = v.y;
+      } else {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        out[0] = v.x; out[1] = v.y;
+      }
+    } else {
+      out[0] = p[0];
+      out[1] = p[1];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      out[e] = (row < r_end && col + e < n) ? A[row * lda + col + e] : TC(0);
+  }
+}
+
 }  // namespace rid

@@ -58,491 +58,6 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, int* nonfinite) {
 }
 
 // ---------------------------------------------------------------------------
-// Sketch: partial sums of Y(c, j) = sum_i omega(c0 + c, i) A(i, j) over one
-// row range ("split") per grid row, for a strip of columns per grid column
-// (FP32: 4 waves x 32 columns, two workgroups per CU; FP64: 8 waves x 32
-// columns).
-//   * A is streamed once.  Each lane loads NQ consecutive columns of one row
-//     (one 16- or 32-byte load) and feeds them to NQ different MFMAs, so MFMA
-//     q, output column j covers matrix column NQ j + q of the wave's strip.
-//   * The A operands of the next KC-row chunk are loaded into registers while
-//     the current chunk is multiplied (register double buffering).
-//   * Omega comes from a row-major (rows x WP) buffer that k_omega fills once
-//     per launch (generating it inside the MFMA loop cost as many VALU
-//     cycles as a third of the MFMA work, once per 256-column strip).  Its
-//     next chunk is loaded while the current one is multiplied and staged in
-//     LDS, double buffered.
-//   * FP32: each chunk is accumulated by MFMA in FP32 and folded into FP64
-//     registers, so rounding grows with KC, not with m.
-//   * Partials part[split][j][c] (FP64) are summed in split order by
-//     k_sketch_reduce, so the result does not depend on scheduling.
-//   * NORM: also accumulates sum A^2 (FP64) and flags non-finite entries.
-//   * Workgroups away from the matrix edges run the same loop without any
-//     bounds test (see `fast` below).
-// ---------------------------------------------------------------------------
-template <typename TC, bool VEC>
-__device__ __forceinline__ void load_row4(const TC* __restrict__ A, int64_t row, int64_t r_end,
-                                          int64_t col, int64_t n, int64_t lda, TC out[4]) {
-  if (row < r_end && col + 3 < n) {
-    const TC* p = A + row * lda + col;
-    if (VEC) {
-      if (sizeof(TC) == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
-      } else {
-        const double2 v0 = *reinterpret_cast<const double2*>(p);
-        const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
-        out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) out[e] = p[e];
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      out[e] = (row < r_end && col + e < n) ? A[row * lda + col + e] : TC(0);
-  }
-}
-
-template <typename TC, bool VEC>
-__device__ __forceinline__ void load_row2(const TC* __restrict__ A, int64_t row, int64_t r_end,
-                                          int64_t col, int64_t n, int64_t lda, TC out[2]) {
-  if (row < r_end && col + 1 < n) {
-    const TC* p = A + row * lda + col;
-    if (VEC) {
-      if (sizeof(TC) == 4) {
-        const float2 v = *reinterpret_cast<const float2*>(p);
-        out[0] = v.x; out[1] = v.y;
-      } else {
-        const double2 v = *reinterpret_cast<const double2*>(p);
-        out[0] = v.x; out[1] = v.y;
-      }
-    } else {
-      out[0] = p[0];
-      out[1] = p[1];
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-      out[e] = (row < r_end && col + e < n) ? A[row * lda + col + e] : TC(0);
-  }
-}
-
-// Workgroup shape: 2 columns per lane and two waves per SIMD, so that one
-// wave's loads and LDS traffic overlap the other's MFMAs.  FP32: two
-// independent 256-thread workgroups per CU (they synchronise separately and
-// drift out of phase); FP64: one 512-thread workgroup.
-template <typename TC>
-struct SketchShape {
-  static constexpr int NQ = 2;                              // columns per lane
-  static constexpr int NT = sizeof(TC) == 4 ? 256 : 512;    // threads
-  static constexpr int CPW = NT / 64 * 16 * NQ;             // columns per workgroup
-};
-
-// Direct copies from global memory into LDS: lane l's 16 (or 4) bytes land
-// at LDS byte address lds + 16 l (or 4 l); each counts once in vmcnt.  Issued
-// as asm so that the compiler neither reorders them nor adds waits of its own
-// for them; the caller waits explicitly.  M0 is restored afterwards.
-__device__ __forceinline__ void copy16_to_lds(const void* src, uint32_t lds) {
-  uint32_t keep;
-  asm volatile(
-      "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %1\n\t"
-      "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %2, off\n\t"
-      "s_mov_b32 m0, %0"
-      : "=&s"(keep)
-      : "s"(lds), "v"(src)
-      : "memory");
-}
-__device__ __forceinline__ void copy4_to_lds(const void* src, uint32_t lds) {
-  uint32_t keep;
-  asm volatile(
-      "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %1\n\t"
-      "s_nop 0\n\t"
-      "global_load_lds_dword %2, off\n\t"
-      "s_mov_b32 m0, %0"
-      : "=&s"(keep)
-      : "s"(lds), "v"(src)
-      : "memory");
-}
-template <typename T>
-__device__ __forceinline__ uint32_t lds_addr(T* p) {
-  return (uint32_t)reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) T*)p);
-}
-
-// Eight 8-byte LDS reads at byte offsets addr + 512 j, complete on return.
-// Written as one asm block so that the compiler adds no wait of its own for
-// the asynchronous copies into that memory (the caller has ordered them).
-__device__ __forceinline__ void lds_read8x8(uint32_t addr, floatx2 (&r)[8]) {
-  asm volatile(
-      "ds_read_b64 %0, %8 offset:0\n\t"
-      "ds_read_b64 %1, %8 offset:512\n\t"
-      "ds_read_b64 %2, %8 offset:1024\n\t"
-      "ds_read_b64 %3, %8 offset:1536\n\t"
-      "ds_read_b64 %4, %8 offset:2048\n\t"
-      "ds_read_b64 %5, %8 offset:2560\n\t"
-      "ds_read_b64 %6, %8 offset:3072\n\t"
-      "ds_read_b64 %7, %8 offset:3584\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
-        "=&v"(r[6]), "=&v"(r[7])
-      : "v"(addr));
-}
-
-// Wait until at most N vector-memory operations of this wave are
-// outstanding, then a workgroup barrier that does not wait for the rest.
-template <int N>
-__device__ __forceinline__ void vm_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// Omega rows [0, mpad) for sketch vectors c0 .. c0 + WP - 1, row-major with
-// pitch WP: entry (i, c) is the Gaussian of row i, vector c0 + c; zero for
-// c >= w or i >= m.  One thread per (row quad, vector).
-template <typename TC>
-__global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uint32_t c0, int w,
-                                               int WP, int64_t m, int64_t mpad,
-                                               TC* __restrict__ om, const Ctrl* __restrict__ ctrl) {
-  if (ctrl && ctrl->done) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (mpad / 4) * WP) return;
-  const int c = (int)(t % WP);
-  const int64_t q = t / WP;
-  TC v[4] = {TC(0), TC(0), TC(0), TC(0)};
-  if (c < w && 4 * q < m) gauss4<TC>(key0, key1, (uint32_t)q, c0 + (uint32_t)c, v);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) om[(4 * q + a) * WP + c] = (4 * q + a < m) ? v[a] : TC(0);
-}
-
-template <typename TC, int MT, int KC, bool NORM, bool VEC>
-__global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
-    const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, const TC* __restrict__ omg,
-    int w, int64_t rows_per_split, double* __restrict__ part,
-    double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
-  if (ctrl && ctrl->done) return;
-  constexpr int NQ = SketchShape<TC>::NQ;
-  constexpr int NT = SketchShape<TC>::NT;
-  constexpr int NW = NT / 64;
-  constexpr int WP = MT * 16;            // padded number of sketch vectors
-  constexpr int LDO = WP + 16;           // LDS row pitch of Omega
-  constexpr int KS = KC / 4;             // MFMA k-steps (and row quads) per chunk
-  // Omega tile of a chunk (KC x WP) per thread: NV loads of VE entries
-  constexpr int NE = KC * WP / NT;
-  constexpr int VE = (NE % (16 / (int)sizeof(TC)) == 0) ? 16 / (int)sizeof(TC) : 1;
-  constexpr int NV = NE / VE;
-  static_assert(NE >= 1 && (KC * WP) % NT == 0, "chunk geometry");
-  using M = Mfma<TC>;
-  using acc_t = typename M::acc_t;
-  __shared__ double red[NW];
-  // FP32 interior workgroups: A and Omega staged through LDS by direct
-  // copies, three chunks deep; A in one region per wave ([stage][wave][KC
-  // rows][32 columns]), Omega shared ([stage][KC rows][LDO]).  The other
-  // workgroups use the first two Omega stages as a double buffer.
-  constexpr bool DMA = sizeof(TC) == 4 && NQ == 2 && KC == 32;
-  __shared__ __attribute__((aligned(16))) TC sA[DMA ? 3 * NW * KC * 32 : 1];
-  __shared__ __attribute__((aligned(16))) TC sO[3 * KC * LDO];
-  TC* const om[2] = {sO, sO + KC * LDO};
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // a wave owns 16 NQ columns; lane l loads NQ consecutive columns from NQ (l % 16)
-  constexpr int CPW = SketchShape<TC>::CPW;
-  const int64_t colq = (int64_t)blockIdx.x * CPW + wave * 16 * NQ + NQ * (lane & 15);
-  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
-  const int nch = (int)((r_end - r_begin + KC - 1) / KC);
-  // Interior workgroups (all CPW columns, all WP vectors, whole chunks, and
-  // one more chunk of rows after the range so that prefetching it stays
-  // inside A) run a loop without bounds tests.
-  const bool fast = VEC && w == WP && (int64_t)blockIdx.x * CPW + CPW <= n &&
-                    (r_end - r_begin) % KC == 0 && r_end + KC <= m;
-
-  acc_t acc[MT][NQ];
-  double acc64[MT][NQ][4];
-#pragma unroll
-  for (int a = 0; a < MT; ++a)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      acc[a][q] = M::zero();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
-    }
-  double fro = 0.0;
-  bool bad = false;
-
-  auto body = [&](auto fast_tag) {
-    constexpr bool FAST = decltype(fast_tag)::value;
-    // Omega tile of the chunk starting at row r0: global -> registers, and
-    // registers -> LDS (entries e = (v NT + tid) VE .. + VE - 1, row e / WP)
-    using OV = typename std::conditional<VE == 4, floatx4,
-               typename std::conditional<VE == 2, doublex2, TC>::type>::type;
-    // pieces [v0, v1) of it, so that a part of the tile is in flight at once
-    auto om_load = [&](OV* r, int64_t r0, int v0, int v1) {
-#pragma unroll
-      for (int v = v0; v < v1; ++v) {
-        const int e = (v * NT + tid) * VE;
-        r[v - v0] = *reinterpret_cast<const OV*>(omg + (r0 + e / WP) * WP + e % WP);
-      }
-    };
-    auto om_store = [&](TC* omb, const OV* r, int v0, int v1) {
-#pragma unroll
-      for (int v = v0; v < v1; ++v) {
-        const int e = (v * NT + tid) * VE;
-        *reinterpret_cast<OV*>(omb + (e / WP) * LDO + e % WP) = r[v - v0];
-      }
-    };
-    if constexpr (FAST && DMA) {
-      // Per chunk and wave: KC/8 copies of A (8 rows x 32 columns each, this
-      // wave's columns) and KC/NW of Omega (one row each), always the same
-      // number NCP (chunks past the end re-read this chunk's rows into a
-      // stage no later chunk reads), so that vmcnt(NCP) at the top of chunk
-      // c means chunk c has landed while chunk c+1 is still in flight.
-      constexpr int ORW = KC / NW;   // Omega rows copied per wave
-      constexpr int NCP = KC / 8 + ORW;  // copies per wave and chunk
-      static_assert(KC % NW == 0 && KS == 8, "copy geometry");
-      const int wv = __builtin_amdgcn_readfirstlane(wave);
-      const int64_t cw = (int64_t)blockIdx.x * CPW + wv * 32;
-      const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
-      // per-lane sources at the first chunk; a chunk adds a uniform offset
-      const TC* pa[KC / 8];
-      const TC* po[ORW];
-#pragma unroll
-      for (int i = 0; i < KC / 8; ++i)
-        pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + cw + 4 * (lane & 7);
-#pragma unroll
-      for (int i = 0; i < ORW; ++i) po[i] = omg + (r_begin + ORW * wv + i) * WP + lane;
-      auto copy_chunk = [&](int chunk, int st) {
-        const int64_t roff = (int64_t)chunk * KC;
-        const int64_t da = roff * lda, dO = roff * WP;
-#pragma unroll
-        for (int i = 0; i < KC / 8; ++i)
-          copy16_to_lds(pa[i] + da, sa + (uint32_t)(((st * NW + wv) * KC + 8 * i) * 32 * 4));
-#pragma unroll
-        for (int i = 0; i < ORW; ++i)
-          if (lane < WP) copy4_to_lds(po[i] + dO, so + (uint32_t)((st * KC + ORW * wv + i) * LDO * 4));
-      };
-      const uint32_t lane_off = (uint32_t)(((lane >> 4) * 32 + 2 * (lane & 15)) * 4);
-      copy_chunk(0, 0);
-      copy_chunk(nch > 1 ? 1 : 0, 1);
-      for (int c = 0; c < nch; ++c) {
-        const int st = c % 3;
-        vm_barrier<NCP>();  // chunk c complete in every wave; chunk c-1's stage free
-        copy_chunk(c + 2 < nch ? c + 2 : c, (c + 2) % 3);
-        floatx2 a2[8];
-        lds_read8x8(sa + (uint32_t)(((st * NW + wv) * KC * 32) * 4) + lane_off, a2);
-        const TC* omc = sO + st * KC * LDO;
-        // all Omega operands of the chunk first, then 8 k-steps of MFMAs
-        TC avs[KS][MT];
-#pragma unroll
-        for (int j = 0; j < KS; ++j)
-#pragma unroll
-          for (int a = 0; a < MT; ++a)
-            avs[j][a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < KS; ++j) {
-          const TC* av = avs[j];
-          if (NORM) {
-            fro += (double)a2[j].x * (double)a2[j].x + (double)a2[j].y * (double)a2[j].y;
-            bad |= !__builtin_isfinite((double)a2[j].x) || !__builtin_isfinite((double)a2[j].y);
-          }
-#pragma unroll
-          for (int a = 0; a < MT; ++a) {
-            acc[a][0] = M::op(av[a], a2[j].x, acc[a][0]);
-            acc[a][1] = M::op(av[a], a2[j].y, acc[a][1]);
-          }
-        }
-        // schedule: the chunk's Omega reads, then its MFMAs
-        __builtin_amdgcn_sched_group_barrier(0x100, KS * MT, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, KS * MT * 2, 0);
-        // FP32 sums of 64 rows (two chunks) are folded into FP64
-        if ((c & 1) || c + 1 == nch) {
-#pragma unroll
-          for (int a = 0; a < MT; ++a)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-              for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
-              acc[a][q] = M::zero();
-            }
-        }
-      }
-      // every copy has landed before the workgroup's LDS is released
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      return;
-    }
-    auto loadB = [&](TC (&buf)[KS][NQ], int64_t r0) {
-#pragma unroll
-      for (int j = 0; j < KS; ++j) {
-        const int64_t row = r0 + 4 * j + (lane >> 4);
-        if constexpr (NQ == 4) {
-          if (FAST) {
-            const TC* p = A + row * lda + colq;
-            if (sizeof(TC) == 4) {
-              const float4 v = *reinterpret_cast<const float4*>(p);
-              buf[j][0] = v.x; buf[j][1] = v.y; buf[j][2] = v.z; buf[j][3] = v.w;
-            } else {
-              const double2 v0 = *reinterpret_cast<const double2*>(p);
-              const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
-              buf[j][0] = v0.x; buf[j][1] = v0.y; buf[j][2] = v1.x; buf[j][3] = v1.y;
-            }
-          } else {
-            load_row4<TC, VEC>(A, row, r_end, colq, n, lda, buf[j]);
-          }
-        } else {
-          if (FAST) {
-            const TC* p = A + row * lda + colq;
-            if (sizeof(TC) == 4) {
-              const float2 v = *reinterpret_cast<const float2*>(p);
-              buf[j][0] = v.x; buf[j][1] = v.y;
-            } else {
-              const double2 v = *reinterpret_cast<const double2*>(p);
-              buf[j][0] = v.x; buf[j][1] = v.y;
-            }
-          } else {
-            load_row2<TC, VEC>(A, row, r_end, colq, n, lda, buf[j]);
-          }
-        }
-      }
-    };
-    // multiply one chunk (Omega in omc, A operands in buf) while loading the
-    // next chunk's Omega, which goes to omn at the end
-    // the next tile moves in OS pieces, piece p loaded at k-step p KS / OS and
-    // stored one segment later
-    constexpr int OS = NV >= 2 ? 2 : 1;
-    constexpr int PV = NV / OS;
-    static_assert(NV % OS == 0 && KS % OS == 0, "Omega pieces");
-    auto compute = [&](const TC* omc, TC (&buf)[KS][NQ], TC* omn, int64_t rnext, bool has_next) {
-      OV onext[PV];
-#pragma unroll
-      for (int j = 0; j < KS; ++j) {
-        if ((FAST || has_next) && j % (KS / OS) == 0) {
-          const int p = j / (KS / OS);
-          if (p > 0) om_store(omn, onext, (p - 1) * PV, p * PV);
-          om_load(onext, rnext, p * PV, (p + 1) * PV);
-        }
-        TC av[MT];
-#pragma unroll
-        for (int a = 0; a < MT; ++a)
-          av[a] = omc[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
-        if (NORM) {
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            fro += (double)buf[j][q] * (double)buf[j][q];
-            bad |= !__builtin_isfinite((double)buf[j][q]);
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < MT; ++a)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) acc[a][q] = M::op(av[a], buf[j][q], acc[a][q]);
-      }
-      if (FAST || has_next) om_store(omn, onext, (OS - 1) * PV, OS * PV);
-      if (sizeof(TC) == 4) {
-#pragma unroll
-        for (int a = 0; a < MT; ++a)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
-            acc[a][q] = M::zero();
-          }
-      }
-    };
-
-    TC bA[KS][NQ], bB[KS][NQ];
-    if (nch > 0) {
-      OV o0[NV];
-      om_load(o0, r_begin, 0, NV);
-      om_store(om[0], o0, 0, NV);
-      loadB(bA, r_begin);
-    }
-    __syncthreads();
-    for (int ci = 0; ci < nch; ci += 2) {
-      const int64_t r0 = r_begin + (int64_t)ci * KC;
-      const bool n1 = ci + 1 < nch, n2 = ci + 2 < nch;
-      if (n1) loadB(bB, r0 + KC);
-      compute(om[0], bA, om[1], r0 + KC, n1);
-      __syncthreads();
-      if (!n1) break;
-      if (n2) loadB(bA, r0 + 2 * KC);
-      compute(om[1], bB, om[0], r0 + 2 * KC, n2);
-      __syncthreads();
-    }
-  };
-  if (fast)
-    body(std::true_type{});
-  else
-    body(std::false_type{});
-
-  if (sizeof(TC) == 8) {
-#pragma unroll
-    for (int a = 0; a < MT; ++a)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc64[a][q][r] = (double)acc[a][q][r];
-  }
-  const int64_t split = blockIdx.y;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int64_t col = colq + q;
-    if (col < n) {
-      double* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP;
-#pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = acc64[a][q][r];
-    }
-  }
-  if (NORM) {
-    fro = wave_sum(fro);
-    if (lane == 0) red[wave] = fro;
-    if (bad) atomicOr(nonfinite, 1);
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int wv = 0; wv < NW; ++wv) t += red[wv];
-      fro_part[blockIdx.y * gridDim.x + blockIdx.x] = t;
-    }
-  }
-}
-
-// Sum of the split partials in split order; writes Y^T into Z columns
-// [zcol, zcol + w) in the factor type.  With `first`, also finishes ||A||_F^2
-// and the non-finite check.
-template <typename TF>
-__global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int64_t n, int WP,
-                                int w, TF* __restrict__ Z, int64_t ldz, int zcol,
-                                TF* __restrict__ Z2, const double* __restrict__ fro_part,
-                                int nfro, const int* __restrict__ nonfinite, Ctrl* ctrl,
-                                int first) {
-  if (ctrl && ctrl->done) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n * w) {
-    const int64_t j = t / w;
-    const int c = (int)(t % w);
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[((size_t)sp * (size_t)n + (size_t)j) * WP + c];
-    Z[j * ldz + zcol + c] = (TF)s;
-    if (Z2) Z2[j * ldz + zcol + c] = (TF)s;  // kept copy of the sketch (refinement)
-  }
-  if (first && t == 0 && ctrl) {
-    double f = 0.0;
-    for (int i = 0; i < nfro; ++i) f += fro_part[i];
-    ctrl->frob2 = f;
-    if (*nonfinite) {
-      ctrl->status = ST_ERR_NONFINITE;
-      ctrl->done = 1;
-      ctrl->k = 0;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Schur block S = (P Y)(non-pivots, block) - L2 U2 (MFMA, K = k), written in
 // place for every non-pivot row; with `want_norm` each workgroup also leaves
 // its FP64 sum of S^2 in normpart[blockIdx.x].  Each wave owns 16 rows and
