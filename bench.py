@@ -90,6 +90,11 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--learned-blocks", type=int, default=1536,
                     help="training blocks of the learned-rank section (0 skips it)")
+    ap.add_argument("--paper-sizes", type=str, default="2048,4096,8192,16384",
+                    help="n of the paper's n x n Fast Decay timing workload (empty: skip)")
+    ap.add_argument("--paper-steps", type=int, default=2)
+    ap.add_argument("--paper-bsweep-n", type=int, default=8192,
+                    help="n at which the paper workload also runs b = 32 and 64")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -330,6 +335,9 @@ def main():
     learned = None
     if args.learned_blocks > 0:
         learned = bench_learned(args, torch, rid, workloads)
+    paper = None
+    if args.paper_sizes:
+        paper = bench_paper(args, torch, rid, workloads)
 
     rec = {
         "metric": "ID GFLOP/s + blocks/s at tol 1e-6; speedup vs plain FP64 GPU path",
@@ -363,9 +371,94 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "learned_rank": learned,
+        "paper_workload": paper,
         "source_hash": source_hash(),
     }
     print(json.dumps(rec), flush=True)
+
+
+def bench_paper(args, torch, rid, workloads):
+    """The paper's own timing workload (Sec. 5.2, timing figures): n x n Fast
+    Decay (sigma_i = 1e-16^((i-1)/(n-1)), Haar factors), FP64, absolute
+    tolerances 1e-8 and 1e-4 (numerical rank about n/2 and n/4), block size
+    128; plus block sizes 32 and 64 at n = 8192 and tolerance 1e-8.  Each
+    configuration: one untimed run, then paper_steps timed runs (HIP events
+    around the library call, workspace allocated beforehand)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    sizes = [int(x) for x in args.paper_sizes.split(",") if x]
+    runs, gemms = [], []
+    for n in sizes:
+        t0 = time.time()
+        sig = workloads.sigma_geometric(n, 16.0)
+        A = workloads.svd_matrix_device(n, n, sig, seed=args.seed + n, device=dev)
+        torch.cuda.synchronize()
+        log(f"[bench] paper workload: generated {n}x{n} Fast Decay in {time.time() - t0:.1f}s")
+        cases = [(128, 1e-8), (128, 1e-4)]
+        if n == args.paper_bsweep_n:
+            cases += [(32, 1e-8), (64, 1e-8)]
+        for b, tol in cases:
+            cfg = rid.binding._cfg(rid.RID_F64, args.seed, False)
+            wb = rid.rid_workspace_bytes(n, n, n, b, cfg)
+            work = torch.empty(wb, dtype=torch.uint8, device=dev)
+            J = torch.zeros(n, dtype=torch.int64, device=dev)
+            T = torch.zeros((n, n), dtype=torch.float64, device=dev)
+            ko = torch.zeros(1, dtype=torch.int32, device=dev)
+            eo = torch.zeros(1, dtype=torch.float64, device=dev)
+            so = torch.zeros(1, dtype=torch.int32, device=dev)
+
+            def run():
+                rc = rid.rid_lupp_adaptive(A.data_ptr(), n, n, n, b, tol, n, cfg, J.data_ptr(),
+                                           T.data_ptr(), n, ko.data_ptr(), eo.data_ptr(),
+                                           so.data_ptr(), work.data_ptr(), wb, stream)
+                if rc != 0:
+                    raise RuntimeError(f"rid_lupp_adaptive -> {rc}")
+
+            run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.paper_steps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.paper_steps
+            k, E, st = int(ko.item()), float(eo.item()), int(so.item())
+            F = rid.flops_id(n, n, k, k + b if k < n else k)
+            r = {"n": n, "b": b, "tol": tol, "ms": ms, "k": k, "status": rid.status_string(st),
+                 "err_est": E, "gflops": F / (ms * 1e-3) / 1e9}
+            log(f"[bench] paper workload n={n} b={b} tol={tol:g}: {ms:.2f} ms, k={k}, "
+                f"{r['status']}, E={E:.2e}, {r['gflops']:.0f} GFLOP/s")
+            if b == 128:
+                # time split over kernel classes, from one more (untimed) call
+                rid.rid_profile_start()
+                run()
+                torch.cuda.synchronize()
+                prof = rid.rid_profile_stop()
+                tot = sum(v[0] for v in prof.values()) or 1.0
+                r["split_ms"] = {c: round(v[0], 4) for c, v in prof.items() if v[1]}
+                log("[bench]   split: " + ", ".join(
+                    f"{c} {100 * v[0] / tot:.0f}%" for c, v in
+                    sorted(prof.items(), key=lambda kv: -kv[1][0]) if v[0] > 0.01 * tot))
+            runs.append(r)
+            del work, J, T
+        # context line of the paper's timing figure: one n x n FP64 GEMM (library)
+        B = torch.empty_like(A)
+        torch.matmul(A, A, out=B)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.paper_steps):
+            torch.matmul(A, A, out=B)
+        e1.record()
+        torch.cuda.synchronize()
+        gemm_ms = e0.elapsed_time(e1) / args.paper_steps
+        gemms.append({"n": n, "ms": gemm_ms, "tflops": 2.0 * n ** 3 / (gemm_ms * 1e-3) / 1e12})
+        log(f"[bench] paper workload n={n}: n x n FP64 GEMM (library) {gemm_ms:.2f} ms")
+        del A, B
+        torch.cuda.empty_cache()
+    return {"workload": "n x n Fast Decay (16 decades), FP64, absolute tolerance, the paper's "
+                        "timing experiment", "runs": runs, "gemm_fp64": gemms}
 
 
 def bench_learned(args, torch, rid, workloads):

@@ -234,3 +234,42 @@ def test_deterministic(torch, rid):
     g2 = rid.adaptive(Ad, 32, 1e-7, 900, seed=4)
     assert g1.k == g2.k and g1.err_est == g2.err_est
     assert torch.equal(g1.J, g2.J) and torch.equal(g1.T, g2.T)
+
+
+# -- the paper's timing workload ----------------------------------------------------
+
+@pytest.mark.parametrize("n,tol", [(1200, 1e-8), (1024, 1e-4)])
+def test_adaptive_fp64_paper_timing_workload(torch, rid, orc, n, tol):
+    """The paper's timing workload at a size the oracle finishes in seconds:
+    n x n Fast Decay (16 decades), absolute tolerance (rank about n/2 at 1e-8,
+    n/4 at 1e-4), b = 128, the widest block (128-column panels, eight 16-column
+    Schur tiles)."""
+    _say("paper64", n, n, 128, tol, n)
+    A, _ = workloads.fast_decay(n, n, decades=16.0, seed=11 + n)
+    o = orc.rid_adaptive(A, 128, tol, n, seed=13, relative=False)
+    g = rid.adaptive(_dev(torch, A, torch.float64), 128, tol, n, seed=13, relative=False)
+    check_fp64(A, g.J.cpu().numpy(), g.T.cpu().numpy(), g.k, g.status, g.err_est, o, 128)
+
+
+def test_adaptive_fp32_paper_timing_workload_b128(torch, rid, orc):
+    """FP32 with 128-wide blocks on the paper's matrix family (tolerance 1e-4,
+    absolute): same status, rank within one block, and a residual that meets
+    the tolerance and exceeds the oracle's (FP64 on the same FP32-rounded
+    input) by no more than the FP32 floor of the interpolation step. The
+    computed T solves the sketched system with a backward error of a few units
+    of u = 2^-24 relative to |Y|, which puts A(:,J) dT at about
+    u * ||A||_F * ||T||_F (3.8e-5 here, where the oracle's own residual is
+    2.4e-6); the bound allows four times that."""
+    n = 1024
+    A, _ = workloads.fast_decay(n, n, decades=16.0, seed=5)
+    A32 = A.astype(np.float32).astype(np.float64)
+    o = orc.rid_adaptive(A32, 128, 1e-4, n, seed=3, relative=False)
+    g = rid.adaptive(_dev(torch, A32, torch.float32), 128, 1e-4, n, seed=3, relative=False)
+    assert g.status == o.status
+    assert abs(g.k - o.k) <= 128
+    res_g = orc.true_residual(A32, g.J.cpu().numpy(), g.T.cpu().numpy().astype(np.float64))
+    res_o = orc.true_residual(A32, o.J, o.T)
+    T_g = g.T.cpu().numpy().astype(np.float64)
+    floor32 = 4.0 * 2.0**-24 * np.linalg.norm(A32) * np.linalg.norm(T_g)
+    assert res_g <= 1.25 * res_o + floor32
+    assert g.status != rid.RID_OK or (res_g <= 1e-4 and g.err_est <= 1e-4)
