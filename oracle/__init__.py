@@ -12,6 +12,8 @@ Method: Pearce, Chen, Dong, Martinsson, arXiv 2310.09417.
   * E_Schur estimate       -- Sec. 3.2, eq. (errSch)
   * interpolation matrix   -- Sec. 3.2, eq. (inty); Alg. 1, final step
   * adaptive blocked loop  -- Sec. 4.2 and Alg. 1 (randLUPPadap)
+  * residual triangle      -- Sec. 3.2, Remark 1 (eqs. normUest, maxUest) and
+                              the a-posteriori certificate it closes with
 """
 from __future__ import annotations
 
@@ -80,6 +82,15 @@ def _load():
         lib.orc_rid_adaptive_first.argtypes = [P, i64, i64, i64, i64, i64, dbl, cint, i64, u64,
                                                P, P, i64, P, i64, ctypes.POINTER(_Result)]
         lib.orc_rid_adaptive_first.restype = cint
+        lib.orc_rid_lupp_est.argtypes = [P, i64, i64, i64, cint, i64, i64, cint, i64, dbl, cint,
+                                         i64, u64, P, P, i64, P, P, i64, ctypes.POINTER(_Result)]
+        lib.orc_rid_lupp_est.restype = cint
+        lib.orc_resid_triangle.argtypes = [P, i64, i64, i64, i64, i64, u64, i64, i64, P, P, P]
+        lib.orc_resid_triangle.restype = cint
+        lib.orc_certificate.argtypes = [P, i64, i64, i64, P, i64, P, i64, u64, i64, i64, P]
+        lib.orc_certificate.restype = cint
+        lib.orc_growth_scale.argtypes = [i64]
+        lib.orc_growth_scale.restype = dbl
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = cint
         _lib = lib
@@ -152,6 +163,14 @@ class IDResult:
     min_gap_step: int = -1
     fro_a: float = 0.0
     robust_k: int = 0       # leading pivots decided above the FP64 rounding floor
+    est_hist: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    # residual-triangle estimates per step (Remark 1): columns = Schur estimate
+    # on the set-aside sample, eq. normUest, eq. maxUest
+
+    @property
+    def est3(self) -> np.ndarray:
+        """The three estimates of the last step, or [-1, -1, -1] if none."""
+        return self.est_hist[-1].copy() if len(self.est_hist) else -np.ones(3)
 
     def X(self, n: int) -> np.ndarray:
         """Column interpolation matrix (k x n) with X[:, J] = I."""
@@ -163,7 +182,8 @@ class IDResult:
         return X
 
 
-def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0) -> IDResult:
+def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, estimator=0,
+         resid_p=0) -> IDResult:
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
@@ -171,8 +191,13 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0) -> 
     J = np.zeros(cap, dtype=np.int64)
     T = np.zeros((cap, n), dtype=np.float64)
     hist = np.zeros(hist_cap, dtype=np.float64)
+    est = np.zeros((hist_cap, 3), dtype=np.float64)
     res = _Result()
-    if first_w > 0:
+    if estimator:
+        lib.orc_rid_lupp_est(_ptr(A), m, n, n, mode, k_or_b, p, estimator, resid_p, tol,
+                             1 if rel else 0, kmax, seed, _ptr(J), _ptr(T), n, _ptr(hist),
+                             _ptr(est), hist_cap, ctypes.byref(res))
+    elif first_w > 0:
         lib.orc_rid_adaptive_first(_ptr(A), m, n, n, k_or_b, first_w, tol, 1 if rel else 0, kmax,
                                    seed, _ptr(J), _ptr(T), n, _ptr(hist), hist_cap,
                                    ctypes.byref(res))
@@ -183,7 +208,8 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0) -> 
     return IDResult(J=J[:k].copy(), T=T[:k, : n - k].copy(), k=k, err_est=float(res.err_est),
                     status=int(res.status), E_hist=hist[: res.nsteps].copy(),
                     min_gap=float(res.min_gap), min_gap_step=int(res.min_gap_step),
-                    fro_a=float(res.fro_a), robust_k=int(res.robust_k))
+                    fro_a=float(res.fro_a), robust_k=int(res.robust_k),
+                    est_hist=est[: res.nsteps].copy() if estimator else np.zeros((0, 3)))
 
 
 def rid_fixed_rank(A, k: int, p: int, seed: int) -> IDResult:
@@ -197,6 +223,64 @@ def rid_adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = T
     first_width > 0 makes the first factored block that wide (a rank known
     or predicted beforehand); the rest of the method is unchanged."""
     return _run(A, 1, b, 0, tol, relative, kmax, seed, first_w=first_width)
+
+
+# Estimators of Remark 1 (Sec. 3.2): 0 = Schur estimate on the next block
+# (eq. errSch), 1 = Schur estimate on the set-aside sample, 2 = eq. normUest,
+# 3 = eq. maxUest.
+EST_SCHUR, EST_SAMPLE, EST_UR_FRO, EST_UR_MAX = 0, 1, 2, 3
+RESID_C0 = 1 << 31   # stream index of the first set-aside vector
+
+
+def rid_adaptive_est(A, b: int, tol: float, kmax: int, seed: int, estimator: int, resid_p: int,
+                     relative: bool = True) -> IDResult:
+    """randLUPPadap stopped by a residual-triangle estimate (Remark 1): the
+    resid_p sample vectors are drawn once and the estimate of the rank-k ID
+    is taken after every factored block."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed, estimator=estimator, resid_p=resid_p)
+
+
+def rid_fixed_rank_est(A, k: int, p: int, seed: int, estimator: int) -> IDResult:
+    """randLUPP at rank k whose p oversampling vectors give the Remark-1
+    estimates."""
+    return _run(A, 0, k, p, 0.0, False, k, seed, estimator=estimator, resid_p=p)
+
+
+def growth_scale(k: int) -> float:
+    """gamma(k) = 1 / max(1, k / (4 ln k)), 1 for k < 2 (Remark 1)."""
+    return float(_load().orc_growth_scale(k))
+
+
+def resid_triangle(A, l: int, k: int, seed: int, c_r: int, p: int):
+    """k LUPP steps on the first l sketch vectors, then the residual triangle
+    of the p vectors c_r.. : returns (status, est[3], U_r p x p, perm)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    est = np.zeros(3)
+    Ur = np.zeros((p, p))
+    perm = np.zeros(n, dtype=np.int64)
+    st = lib.orc_resid_triangle(_ptr(A), m, n, n, l, k, seed, c_r, p, _ptr(est), _ptr(Ur),
+                                _ptr(perm))
+    return int(st), est, Ur, perm
+
+
+def certificate(A, J, T, seed: int, c0: int, p: int) -> float:
+    """A-posteriori certificate ||Yc(:,J^c) - Yc(:,J) T||_F / sqrt(p) with
+    Yc = the p sketch vectors c0.. of the stream (Remark 1's closing note)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    k = len(J)
+    T = np.ascontiguousarray(T, dtype=np.float64).reshape(k, n - k) if k else np.zeros((0, n))
+    Tp = T if k else np.zeros((1, max(n, 1)))
+    out = np.zeros(1)
+    st = lib.orc_certificate(_ptr(A), m, n, n, _ptr(J), k, _ptr(Tp), max(n - k, 1), seed, c0, p,
+                             _ptr(out))
+    if st != OK:
+        raise ValueError("certificate: J out of range or repeated")
+    return float(out[0])
 
 
 def lupp_factors(A, l: int, k: int, seed: int):

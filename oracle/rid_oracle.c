@@ -242,15 +242,33 @@ typedef struct {
  */
 static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
-                         int64_t first_width, uint64_t seed, int64_t* J, double* T, int64_t ldt,
-                         double* E_hist, int64_t hist_cap, orc_result* res);
+                         int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
+                         int64_t* J, double* T, int64_t ldt, double* E_hist, double* est_hist,
+                         int64_t hist_cap, orc_result* res);
 
 int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                  int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                  uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                  int64_t hist_cap, orc_result* res) {
-  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, J, T, ldt,
-                       E_hist, hist_cap, res);
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, J,
+                       T, ldt, E_hist, NULL, hist_cap, res);
+}
+
+/* Same as orc_rid_lupp with the stopping estimate taken from the residual
+ * triangle of Remark 1 (estimator 1: Schur estimate on the set-aside sample,
+ * 2: eq. normUest, 3: eq. maxUest; see resid_triangle below).  Adaptive mode:
+ * resid_p vectors are set aside once (stream indices ORC_RESID_C0 + j) and the
+ * estimate of the current rank is taken after every factored block, so no
+ * block is drawn only to be measured.  Fixed-rank mode: the p oversampling
+ * vectors are the sample.  est_hist receives the three estimates of every
+ * step (3 entries per step). */
+int orc_rid_lupp_est(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                     int64_t k_or_b, int64_t p, int estimator, int64_t resid_p, double tol,
+                     int tol_relative, int64_t kmax, uint64_t seed, int64_t* J, double* T,
+                     int64_t ldt, double* E_hist, double* est_hist, int64_t hist_cap,
+                     orc_result* res) {
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, estimator,
+                       resid_p, J, T, ldt, E_hist, est_hist, hist_cap, res);
 }
 
 /* Adaptive variant whose first factored block has first_width vectors
@@ -260,19 +278,218 @@ int orc_rid_adaptive_first(const double* A, int64_t m, int64_t n, int64_t lda, i
                            int64_t first_width, double tol, int tol_relative, int64_t kmax,
                            uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                            int64_t hist_cap, orc_result* res) {
-  return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, J, T,
-                       ldt, E_hist, hist_cap, res);
+  return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, 0, 0, J,
+                       T, ldt, E_hist, NULL, hist_cap, res);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual triangle (paper Sec. 3.2, Remark 1), column form.                */
+/* Z (n x zc) holds the LU factors of the permuted sketch in its first k    */
+/* columns (rows in the order perm); Yr (p x n, row c = sample vector c) is  */
+/* an independent Gaussian sample.  With P the current row permutation,     */
+/*   U2_r = L1^{-1} (P Yr^T)(0:k)      (forward substitution, ascending)     */
+/*   S_r  = (P Yr^T)(k:n) - L2 U2_r    (ascending s)                         */
+/* and S_r is factored by LU with partial pivoting (ties to the lowest       */
+/* original column index; an exactly zero pivot column ends it, the rows of  */
+/* U_r not reached stay zero), so that P[Y Yr]^T = [L1 0; L2 L_r] [U1 U2;   */
+/* 0 U_r].  Estimates (nr = n - k candidates left):                          */
+/*   est[0] = ||S_r||_F / sqrt(p)            (Schur estimate on the sample)  */
+/*   est[1] = gamma(k) sqrt(nr) ||U_r||_F     (eq. normUest)                 */
+/*   est[2] = gamma(k) sqrt(nr) max |U_r|     (eq. maxUest)                  */
+/* gamma(k) = 1 / max(1, k / (4 ln k)), gamma(1) = 1: the reciprocal of the  */
+/* asymptotic growth-factor bound k / (4 log k) of LU on Haar matrices,     */
+/* never above one because a growth factor is at least one.                 */
+/* Ur (p x p, row-major, may be NULL) receives U_r.                          */
+/* ------------------------------------------------------------------------ */
+#define ORC_RESID_C0 2147483648LL /* stream index of the first set-aside vector */
+
+double orc_growth_scale(int64_t k) {
+  if (k < 2) return 1.0;
+  const double g = (double)k / (4.0 * log((double)k));
+  return g > 1.0 ? 1.0 / g : 1.0;
+}
+
+static void resid_triangle(const double* Z, int64_t zc, const int64_t* perm, int64_t n, int64_t k,
+                           const double* Yr, int64_t p, double est[3], double* Ur) {
+  const int64_t nr = n - k;
+  double* W = (double*)malloc(sizeof(double) * (size_t)n * (size_t)p);
+  int64_t* oi = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nr > 0 ? nr : 1));
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t q = 0; q < p; ++q) W[r * p + q] = Yr[q * n + perm[r]];
+  for (int64_t r = 0; r < k; ++r)
+    for (int64_t q = 0; q < p; ++q) {
+      double acc = W[r * p + q];
+      for (int64_t s = 0; s < r; ++s) acc = acc - Z[r * zc + s] * W[s * p + q];
+      W[r * p + q] = acc;
+    }
+  for (int64_t r = k; r < n; ++r)
+    for (int64_t q = 0; q < p; ++q) {
+      double acc = W[r * p + q];
+      for (int64_t s = 0; s < k; ++s) acc = acc - Z[r * zc + s] * W[s * p + q];
+      W[r * p + q] = acc;
+    }
+  double s2 = 0.0;
+  for (int64_t r = k; r < n; ++r)
+    for (int64_t q = 0; q < p; ++q) s2 = s2 + W[r * p + q] * W[r * p + q];
+  est[0] = sqrt(s2) / sqrt((double)p);
+  /* LU with partial pivoting on S_r = W(k:n, :) */
+  double* S = W + k * p;
+  for (int64_t r = 0; r < nr; ++r) oi[r] = perm[k + r];
+  if (Ur)
+    for (int64_t t = 0; t < p * p; ++t) Ur[t] = 0.0;
+  double fro2 = 0.0, mx = 0.0;
+  const int64_t steps = p < nr ? p : nr;
+  for (int64_t j = 0; j < steps; ++j) {
+    int64_t piv = j;
+    double best = fabs(S[j * p + j]);
+    for (int64_t r = j + 1; r < nr; ++r) {
+      const double v = fabs(S[r * p + j]);
+      if (v > best || (v == best && oi[r] < oi[piv])) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (best == 0.0) break;
+    if (piv != j) {
+      for (int64_t q = 0; q < p; ++q) {
+        const double t = S[j * p + q];
+        S[j * p + q] = S[piv * p + q];
+        S[piv * p + q] = t;
+      }
+      const int64_t t = oi[j];
+      oi[j] = oi[piv];
+      oi[piv] = t;
+    }
+    for (int64_t q = j; q < p; ++q) {
+      const double u = S[j * p + q];
+      fro2 = fro2 + u * u;
+      if (fabs(u) > mx) mx = fabs(u);
+      if (Ur) Ur[j * p + q] = u;
+    }
+    for (int64_t r = j + 1; r < nr; ++r) {
+      const double l = S[r * p + j] / S[j * p + j];
+      S[r * p + j] = l;
+      for (int64_t q = j + 1; q < p; ++q) S[r * p + q] = S[r * p + q] - l * S[j * p + q];
+    }
+  }
+  const double g = orc_growth_scale(k) * sqrt((double)nr);
+  est[1] = g * sqrt(fro2);
+  est[2] = g * mx;
+  free(W);
+  free(oi);
+}
+
+/* Residual triangle after k LUPP steps on the first l sketch vectors (for
+ * tests): Yr = the p vectors c_r .. c_r + p - 1 of the same stream.  Returns
+ * ORC_RANK_DEFICIENT when the k steps meet a zero pivot. */
+int orc_resid_triangle(const double* A, int64_t m, int64_t n, int64_t lda, int64_t l, int64_t k,
+                       uint64_t seed, int64_t c_r, int64_t p, double est[3], double* Ur,
+                       int64_t* perm_out) {
+  if (k > l || k > n || p < 1) return ORC_ERR_ARG;
+  double* Y = (double*)malloc(sizeof(double) * (size_t)l * (size_t)n);
+  double* Yr = (double*)malloc(sizeof(double) * (size_t)p * (size_t)n);
+  orc_sketch(A, m, n, lda, seed, 0, l, Y, n);
+  orc_sketch(A, m, n, lda, seed, c_r, p, Yr, n);
+  double* Z = (double*)malloc(sizeof(double) * (size_t)n * (size_t)l);
+  int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int st = ORC_OK;
+  for (int64_t r = 0; r < n; ++r) {
+    perm[r] = r;
+    for (int64_t q = 0; q < l; ++q) Z[r * l + q] = Y[q * n + r];
+  }
+  for (int64_t s = 0; s < k && st == ORC_OK; ++s) {
+    int64_t piv = s;
+    double best = fabs(Z[s * l + s]);
+    for (int64_t r = s + 1; r < n; ++r) {
+      const double v = fabs(Z[r * l + s]);
+      if (v > best || (v == best && perm[r] < perm[piv])) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (best == 0.0) {
+      st = ORC_RANK_DEFICIENT;
+      break;
+    }
+    if (piv != s) {
+      for (int64_t q = 0; q < l; ++q) {
+        const double t = Z[s * l + q];
+        Z[s * l + q] = Z[piv * l + q];
+        Z[piv * l + q] = t;
+      }
+      const int64_t t = perm[s];
+      perm[s] = perm[piv];
+      perm[piv] = t;
+    }
+    for (int64_t r = s + 1; r < n; ++r) {
+      const double lv = Z[r * l + s] / Z[s * l + s];
+      Z[r * l + s] = lv;
+      for (int64_t q = s + 1; q < l; ++q) Z[r * l + q] = Z[r * l + q] - lv * Z[s * l + q];
+    }
+  }
+  if (st == ORC_OK) resid_triangle(Z, l, perm, n, k, Yr, p, est, Ur);
+  if (perm_out)
+    for (int64_t r = 0; r < n; ++r) perm_out[r] = perm[r];
+  free(Y);
+  free(Yr);
+  free(Z);
+  free(perm);
+  return st;
+}
+
+/* A-posteriori certificate of an ID (the sketched residual of the returned
+ * factorization, after Martinsson and Tropp 2020, cited in Remark 1): with
+ * Yc = Omega_c A for the p vectors c0 .. c0 + p - 1 of the stream,
+ *   cert = ||Yc(:, J^c) - Yc(:, J) T||_F / sqrt(p),
+ * J in any order with T (k x (n-k), row-major, ldt) in that order, column q of
+ * T for the q-th non-skeleton column in ascending index.  cert^2 is an
+ * unbiased estimate of ||A(:, J^c) - A(:, J) T||_F^2.  Sums: s ascending for
+ * each entry, then q ascending within c ascending.  Returns ORC_ERR_ARG when J
+ * holds an index out of range or twice. */
+int orc_certificate(const double* A, int64_t m, int64_t n, int64_t lda, const int64_t* J,
+                    int64_t k, const double* T, int64_t ldt, uint64_t seed, int64_t c0, int64_t p,
+                    double* cert) {
+  if (k < 0 || k > n || p < 1) return ORC_ERR_ARG;
+  char* is_skel = (char*)calloc((size_t)n, 1);
+  for (int64_t s = 0; s < k; ++s) {
+    if (J[s] < 0 || J[s] >= n || is_skel[J[s]]) {
+      free(is_skel);
+      return ORC_ERR_ARG;
+    }
+    is_skel[J[s]] = 1;
+  }
+  int64_t* rest = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n - k > 0 ? n - k : 1));
+  int64_t nr = 0;
+  for (int64_t j = 0; j < n; ++j)
+    if (!is_skel[j]) rest[nr++] = j;
+  double* Yc = (double*)malloc(sizeof(double) * (size_t)p * (size_t)n);
+  orc_sketch(A, m, n, lda, seed, c0, p, Yc, n);
+  double ss = 0.0;
+  for (int64_t c = 0; c < p; ++c)
+    for (int64_t q = 0; q < nr; ++q) {
+      double acc = 0.0;
+      for (int64_t s = 0; s < k; ++s) acc = acc + Yc[c * n + J[s]] * T[s * ldt + q];
+      const double r = Yc[c * n + rest[q]] - acc;
+      ss = ss + r * r;
+    }
+  *cert = sqrt(ss / (double)p);
+  free(is_skel);
+  free(rest);
+  free(Yc);
+  return ORC_OK;
 }
 
 static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
-                         int64_t first_width, uint64_t seed, int64_t* J, double* T, int64_t ldt,
-                         double* E_hist, int64_t hist_cap, orc_result* res) {
+                         int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
+                         int64_t* J, double* T, int64_t ldt, double* E_hist, double* est_hist,
+                         int64_t hist_cap, orc_result* res) {
   memset(res, 0, sizeof(*res));
   res->err_est = -1.0;
   res->min_gap = INFINITY;
   res->min_gap_step = -1;
-  if (m < 1 || n < 1 || lda < n || k_or_b < 1 || p < 0 || (mode != 0 && mode != 1)) {
+  if (m < 1 || n < 1 || lda < n || k_or_b < 1 || p < 0 || (mode != 0 && mode != 1) ||
+      estimator < 0 || estimator > 3 || (estimator > 0 && mode == 1 && resid_p < 1)) {
     res->status = ORC_ERR_ARG;
     return ORC_ERR_ARG;
   }
@@ -311,6 +528,13 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
   int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
   double* Ynew = (double*)malloc(sizeof(double) * (size_t)n * (size_t)(zc));
   for (int64_t r = 0; r < n; ++r) perm[r] = r;
+  /* Remark 1: the sample set aside for the estimate (adaptive mode) */
+  double* Yr = NULL;
+  if (estimator > 0 && mode == 1) {
+    Yr = (double*)malloc(sizeof(double) * (size_t)resid_p * (size_t)n);
+    orc_sketch(A, m, n, lda, seed, ORC_RESID_C0, resid_p, Yr, n);
+  }
+  double est[3];
 
   int64_t k = 0;        /* pivots taken so far */
   int64_t cnext = 0;    /* next unused sketch vector */
@@ -349,7 +573,19 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
         }
     }
 
-    if (!first) {
+    if (!first && estimator > 0 && mode == 0) {
+      /* fixed rank: the p oversampling vectors are the sample of Remark 1 */
+      resid_triangle(Z, zc, perm, n, k, Ynew, w, est, NULL);
+      E = est[estimator - 1];
+      if (res->nsteps < hist_cap) {
+        if (E_hist) E_hist[res->nsteps] = E;
+        if (est_hist)
+          for (int e = 0; e < 3; ++e) est_hist[3 * res->nsteps + e] = est[e];
+      }
+      res->nsteps++;
+      break;
+    }
+    if (!first && estimator == 0) {
       /* E = ||S||_F / sqrt(w), rows k..n-1 in order, columns in order. */
       double s2 = 0.0;
       for (int64_t r = k; r < n; ++r)
@@ -433,6 +669,23 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
       break;
     }
     if (mode == 0 && p == 0) break;
+    if (mode == 1 && estimator > 0) {
+      /* Remark 1: estimate the error of the rank-k ID from the residual
+       * triangle of the set-aside sample; stop as soon as it passes */
+      resid_triangle(Z, zc, perm, n, k, Yr, resid_p, est, NULL);
+      E = est[estimator - 1];
+      if (res->nsteps < hist_cap) {
+        if (E_hist) E_hist[res->nsteps] = E;
+        if (est_hist)
+          for (int e = 0; e < 3; ++e) est_hist[3 * res->nsteps + e] = est[e];
+      }
+      res->nsteps++;
+      if (E <= thr) break;
+      if (k >= kcap) {
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+    }
   }
 
   /* Outputs: skeletons in pivot order and T = L1^{-T} L2^T (paper eq. for the
@@ -471,6 +724,7 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
   free(Z);
   free(perm);
   free(Ynew);
+  free(Yr);
   res->k = k;
   res->err_est = E;
   res->status = status;
