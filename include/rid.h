@@ -77,7 +77,47 @@ typedef struct {
   int refine;           /* 0, or 1 (dtype RID_F32 only): one iterative-refinement
                            step on T whose residual Y(:,J) T - Y(:,J^c) is
                            formed in FP64 from the FP32 sketch                  */
+  int estimator;        /* stopping estimate, one of rid_estimator.  0 (the
+                           default) is the Schur estimate of eq. (errSch) on the
+                           next block; 1-3 are the residual-triangle estimates
+                           of Sec. 3.2, Remark 1 (see below)                    */
+  int resid_p;          /* adaptive calls with estimator > 0: number p of
+                           vectors set aside for the estimate, 1..16            */
+  double* est_out;      /* (device, nullable) with estimator > 0: the three
+                           Remark-1 estimates (sample, normUest, maxUest) last
+                           taken: those of the returned rank when the call
+                           stopped on the estimate or at kmax, of an earlier
+                           rank when the ID then became exact (k = min(m, n))
+                           or the sketch rank-deficient; -1 each when none was
+                           taken.  Pass the same cfg to rid_workspace_bytes.  */
 } rid_config;
+
+/*
+ * Stopping estimates (Sec. 3.2, Remark 1).  With P the row permutation of the
+ * factorisation and Yr = Omega_r A an independent Gaussian sample of p
+ * vectors, the LU factors of P [Y Yr]^T end in a p x p upper triangle U_r
+ * ("residual triangle"): U_r is the U factor of LU with partial pivoting on
+ * the Schur complement S_r = (P Yr^T)(rest) - L2 L1^{-1} (P Yr^T)(pivots).
+ * With nr = n - k candidates left and gamma(k) = 1 / max(1, k / (4 ln k))
+ * (gamma(1) = 1; the reciprocal of the asymptotic LU growth bound k/(4 log k)):
+ *   RID_EST_SAMPLE  ||S_r||_F / sqrt(p)
+ *   RID_EST_UR_FRO  gamma(k) sqrt(nr) ||U_r||_F          (eq. normUest)
+ *   RID_EST_UR_MAX  gamma(k) sqrt(nr) max |U_r(i, j)|    (eq. maxUest; may
+ *                   under-estimate, as the remark notes)
+ * Adaptive calls draw the p sample vectors once (stream indices 2^31 + j of
+ * the seed's Gaussian stream) and take the estimate of the current rank after
+ * every factored block, so no block is drawn only to be measured; the rank
+ * returned is the first block edge whose estimate meets the tolerance.
+ * Fixed-rank calls use their p oversampling vectors as the sample.  The LU of
+ * S_r stops at an exactly zero pivot column; the rows of U_r not reached are
+ * zero.
+ */
+typedef enum {
+  RID_EST_SCHUR = 0,
+  RID_EST_SAMPLE = 1,
+  RID_EST_UR_FRO = 2,
+  RID_EST_UR_MAX = 3
+} rid_estimator;
 
 /*
  * Workspace size in bytes for a call with these sizes.  kmax is the rank
@@ -91,12 +131,13 @@ const char* rid_status_string(int status);
 
 /*
  * Fixed-rank randomized LUPP ID (randLUPP; Sec. 3.1 and Sec. 3.2).
- *   Y = Omega A with Omega (k+p) x m Gaussian, generated on the fly and never
- *   stored.  LU with partial pivoting on the first k columns of Y^T selects J
+ *   Y = Omega A with Omega (k+p) x m Gaussian, generated on the device from
+ *   (seed, vector, row) for each sketch launch.  LU with partial pivoting on the first k columns of Y^T selects J
  *   (|J| = k, ties to the lowest column index); T = L1^{-T} L2^T
  *   (eq. (inty)).  The p remaining sketch vectors form an independent sample:
  *   err_est = ||S||_F / sqrt(p) for the Schur block S of eq. (errSch), the
- *   unbiased estimate of ||A - A(:,J) X||_F (0 <= p; p = 0 gives -1).
+ *   unbiased estimate of ||A - A(:,J) X||_F (0 <= p; p = 0 gives -1).  With
+ *   cfg->estimator > 0 err_est is that Remark-1 estimate instead (p >= 1).
  * Arguments: 1 <= k <= min(m, n); J (device, int64[k]); T (device, dtype,
  *   k rows of ldt); k_out, status (device int32), err_est (device double).
  * Errors: RID_ERR_ARG for bad sizes or null pointers, RID_ERR_WORKSPACE when
@@ -116,6 +157,8 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
  *   status RID_OK; otherwise S is factored with partial pivoting and appended.
  *   At k = kmax (capped by min(m, n)) with E above tolerance the status is
  *   RID_NOT_CONVERGED; at k = min(m, n) the ID is exact (E = 0, RID_OK).
+ *   With cfg->estimator > 0 the stopping estimate is a Remark-1 estimate of
+ *   the rank just factored (see rid_estimator) and err_est holds it.
  * Arguments: 1 <= b <= 128; kmax >= 1; J (device, int64, capacity
  *   min(kmax, m, n)); T (device, capacity min(kmax,m,n) rows of ldt).
  * Errors: as rid_lupp_fixed_rank.
@@ -124,6 +167,27 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
                       int64_t kmax, const rid_config* cfg, int64_t* J, void* T, int64_t ldt,
                       int32_t* k_out, double* err_est, int32_t* status, void* work,
                       size_t work_bytes, hipStream_t stream);
+
+/*
+ * A-posteriori certificate of an ID (the check Remark 1 ends with, after
+ * Martinsson and Tropp, 2020): with Yc = Omega_c A for the p Gaussian vectors
+ * c0 .. c0+p-1 of cfg->seed's stream,
+ *     *cert = ||Yc(:, J^c) - Yc(:, J) T||_F / sqrt(p),
+ * whose square is an unbiased estimate of ||A(:, J^c) - A(:, J) T||_F^2.
+ * Use vectors the decomposition did not draw (e.g. c0 = 2^30).
+ * Arguments: A as for rid_lupp_adaptive, stored in cfg->a_type; J (device,
+ *   int64[k], any order, 0 <= k <= n), T (device, cfg->dtype, k rows of ldt;
+ *   unused and may be NULL when k = 0 or k = n;
+ *   rows in the order of J, column q for the q-th non-skeleton column in
+ *   ascending index), 1 <= p <= 32, cert (device double).  Sums in FP64.
+ * Errors: RID_ERR_ARG / RID_ERR_WORKSPACE / RID_ERR_HIP as above (workspace:
+ *   rid_certificate_workspace_bytes).  A J entry out of range or repeated is
+ *   found on the device and gives *cert = -1.
+ */
+size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const rid_config* cfg);
+int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
+                    const void* T, int64_t ldt, int64_t p, int64_t c0, const rid_config* cfg,
+                    double* cert, void* work, size_t work_bytes, hipStream_t stream);
 
 /*
  * Batched adaptive LUPP IDs of many independent blocks in one persistent

@@ -14,5 +14,7 @@ from .binding import (  # noqa: F401
     rid_lupp_fixed_rank, rid_lupp_adaptive, rid_workspace_bytes, rid_debug_gaussian,
     rid_debug_sketch, rid_status_string, rid_profile_start, rid_profile_stop, KERNEL_CLASSES,
     rid_batched_workspace_bytes, rid_lupp_batched, BatchPlan, BatchOutput, batched,
-    rank_features, mlp_param_count, mlp_forward, mlp_backward, mlp_adamw, rank_hint, N_FEATURES)
+    rank_features, mlp_param_count, mlp_forward, mlp_backward, mlp_adamw, rank_hint, N_FEATURES,
+    RID_EST_SCHUR, RID_EST_SAMPLE, RID_EST_UR_FRO, RID_EST_UR_MAX, certificate, rid_certificate,
+    rid_certificate_workspace_bytes)
 from .flops import flops_id  # noqa: F401

@@ -28,7 +28,9 @@ class RidError(RuntimeError):
 class RidConfig(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("tol_relative", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("a_type", ctypes.c_int),
-                ("a_col_scale", ctypes.c_void_p), ("refine", ctypes.c_int)]
+                ("a_col_scale", ctypes.c_void_p), ("refine", ctypes.c_int),
+                ("estimator", ctypes.c_int), ("resid_p", ctypes.c_int),
+                ("est_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -55,6 +57,11 @@ def library() -> ctypes.CDLL:
         lib.rid_lupp_adaptive.argtypes = [P, i64, i64, i64, i64, dbl, i64, cfgp, P, P, i64, P, P,
                                           P, P, sz, P]
         lib.rid_lupp_adaptive.restype = i32
+        lib.rid_certificate_workspace_bytes.argtypes = [i64, i64, i64, cfgp]
+        lib.rid_certificate_workspace_bytes.restype = sz
+        lib.rid_certificate.argtypes = [P, i64, i64, i64, P, i64, P, i64, i64, i64, cfgp, P, P,
+                                        sz, P]
+        lib.rid_certificate.restype = i32
         lib.rid_debug_gaussian.argtypes = [ctypes.c_uint64, i64, i64, i64, i32, P, P]
         lib.rid_debug_gaussian.restype = i32
         lib.rid_debug_sketch.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, i64, P, sz, P]
@@ -89,11 +96,18 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
+# Stopping estimates (rid_estimator): Schur estimate on the next block, and the
+# residual-triangle estimates of Remark 1 (sample Schur, normUest, maxUest).
+RID_EST_SCHUR, RID_EST_SAMPLE, RID_EST_UR_FRO, RID_EST_UR_MAX = 0, 1, 2, 3
+
+
 def _cfg(dtype: int, seed: int, tol_relative: bool = True, a_type: int | None = None,
-         col_scale: int = 0, refine: bool = False) -> RidConfig:
+         col_scale: int = 0, refine: bool = False, estimator: int = 0, resid_p: int = 0,
+         est_out: int = 0) -> RidConfig:
     return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed,
                      a_type=dtype if a_type is None else a_type, a_col_scale=col_scale or None,
-                     refine=1 if refine else 0)
+                     refine=1 if refine else 0, estimator=estimator, resid_p=resid_p,
+                     est_out=est_out or None)
 
 
 # ---- raw C-ABI mirrors (pointers as ints) ----------------------------------
@@ -104,6 +118,16 @@ def rid_workspace_bytes(m, n, kmax, b, cfg: RidConfig) -> int:
 
 def rid_status_string(status: int) -> str:
     return library().rid_status_string(status).decode()
+
+
+def rid_certificate_workspace_bytes(m, n, p, cfg: RidConfig) -> int:
+    return int(library().rid_certificate_workspace_bytes(m, n, p, ctypes.byref(cfg)))
+
+
+def rid_certificate(A, m, n, lda, J, k, T, ldt, p, c0, cfg: RidConfig, cert, work, work_bytes,
+                    stream) -> int:
+    return int(library().rid_certificate(A, m, n, lda, J or None, k, T or None, ldt, p, c0,
+                                         ctypes.byref(cfg), cert, work, work_bytes, stream))
 
 
 def rid_lupp_fixed_rank(A, m, n, lda, k, p, cfg, J, T, ldt, k_out, err_est, status, work,
@@ -140,7 +164,7 @@ def rid_lupp_batched(nblk, A, lda, m, n, b, tol, kmax, k_hint, cfg, J, T, ldt, k
 
 
 KERNEL_CLASSES = ("sketch", "sketch_reduce", "u2", "schur", "panel_lupp", "tgemm", "linv_update",
-                  "batched", "omega")
+                  "batched", "omega", "resid_est")
 
 
 def rid_profile_start() -> int:
@@ -175,28 +199,30 @@ def _dtype_code(t) -> int:
     raise RidError(f"unsupported dtype {t.dtype}")
 
 
-def _config_for(A, seed: int, relative: bool = True, col_scale=None, refine: bool = False):
+def _config_for(A, seed: int, relative: bool = True, col_scale=None, refine: bool = False,
+                estimator: int = 0, resid_p: int = 0, est_out: int = 0):
     """Config for A's storage: float64 / float32 run the whole path in that
     type; bfloat16 A, or float8_e4m3fn (or uint8 codes) A with col_scale
     (float32 device tensor, ceil(n/128) powers of two), run the sketch in that
     format and the factorisation in FP32.  Returns (cfg, dtype of T)."""
     torch = _torch()
+    ex = dict(refine=refine, estimator=estimator, resid_p=resid_p, est_out=est_out)
     if A.dtype in (torch.float64, torch.float32):
         if col_scale is not None:
             raise RidError("col_scale applies to FP8 storage only")
         dt = _dtype_code(A)
-        return _cfg(dt, seed, relative, refine=refine), A.dtype
+        return _cfg(dt, seed, relative, **ex), A.dtype
     if A.dtype == torch.bfloat16:
         if col_scale is not None:
             raise RidError("col_scale applies to FP8 storage only")
-        return _cfg(RID_F32, seed, relative, a_type=RID_BF16, refine=refine), torch.float32
+        return _cfg(RID_F32, seed, relative, a_type=RID_BF16, **ex), torch.float32
     if A.dtype in (torch.float8_e4m3fn, torch.uint8):
         n = A.shape[1]
         if (col_scale is None or col_scale.dtype != torch.float32 or not col_scale.is_contiguous()
                 or col_scale.numel() < (n + 127) // 128 or col_scale.device != A.device):
             raise RidError("FP8 storage needs col_scale: float32 device tensor of ceil(n/128)")
         return (_cfg(RID_F32, seed, relative, a_type=RID_FP8_E4M3, col_scale=col_scale.data_ptr(),
-                     refine=refine), torch.float32)
+                     **ex), torch.float32)
     raise RidError(f"unsupported dtype {A.dtype}")
 
 
@@ -220,6 +246,7 @@ class IDOutput:
     k: int
     err_est: float
     status: int
+    est3: "object" = None  # Remark-1 estimates (sample, normUest, maxUest) or None
 
 
 class _Outputs:
@@ -231,12 +258,15 @@ class _Outputs:
         self.E = torch.zeros(1, dtype=torch.float64, device=device)
         self.st = torch.zeros(1, dtype=torch.int32, device=device)
 
-    def result(self, n) -> IDOutput:
+        self.est = torch.zeros(3, dtype=torch.float64, device=device)
+
+    def result(self, n, with_est: bool = False) -> IDOutput:
         torch = _torch()
         torch.cuda.current_stream().synchronize()
         k = int(self.k.item())
         return IDOutput(J=self.J[:k], T=self.T[:k, : n - k], k=k, err_est=float(self.E.item()),
-                        status=int(self.st.item()))
+                        status=int(self.st.item()),
+                        est3=self.est.cpu().numpy() if with_est else None)
 
 
 def _stream_ptr():
@@ -249,46 +279,81 @@ def _work(nbytes, device):
 
 
 def fixed_rank(A, k: int, p: int, seed: int, work=None, col_scale=None,
-               refine: bool = False) -> IDOutput:
+               refine: bool = False, estimator: int = 0) -> IDOutput:
     """randLUPP at rank k with p estimation vectors (A: m x n device tensor;
-    BF16 / FP8 storage as described in _config_for)."""
+    BF16 / FP8 storage as described in _config_for).  estimator > 0: the p
+    vectors give the Remark-1 estimates (returned in est3)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
     cfg, tdt = _config_for(A, seed, True, col_scale, refine)
+    out = _Outputs(k, n, tdt, A.device)
+    if estimator:
+        cfg, tdt = _config_for(A, seed, True, col_scale, refine, estimator, 0, out.est.data_ptr())
     wb = rid_workspace_bytes(m, n, k + p, p, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
     if work is None:
         work = _work(wb, A.device)
-    out = _Outputs(k, n, tdt, A.device)
     rc = rid_lupp_fixed_rank(A.data_ptr(), m, n, lda, k, p, cfg, out.J.data_ptr(),
                              out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
                              out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
     _check(rc, "rid_lupp_fixed_rank")
-    return out.result(n)
+    return out.result(n, with_est=bool(estimator))
 
 
 def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
-             work=None, col_scale=None, refine: bool = False) -> IDOutput:
+             work=None, col_scale=None, refine: bool = False, estimator: int = 0,
+             resid_p: int = 8) -> IDOutput:
     """randLUPPadap with block size b, tolerance tol, rank cap kmax (BF16 /
-    FP8 storage as described in _config_for)."""
+    FP8 storage as described in _config_for).  estimator > 0 stops on a
+    Remark-1 estimate from resid_p set-aside vectors (estimates in est3)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
+    cap = min(kmax, m, n)
     cfg, tdt = _config_for(A, seed, relative, col_scale, refine)
+    out = _Outputs(cap, n, tdt, A.device)
+    if estimator:
+        cfg, tdt = _config_for(A, seed, relative, col_scale, refine, estimator, resid_p,
+                               out.est.data_ptr())
     wb = rid_workspace_bytes(m, n, kmax, b, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
     if work is None:
         work = _work(wb, A.device)
-    cap = min(kmax, m, n)
-    out = _Outputs(cap, n, tdt, A.device)
     rc = rid_lupp_adaptive(A.data_ptr(), m, n, lda, b, tol, kmax, cfg, out.J.data_ptr(),
                            out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
                            out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
     _check(rc, "rid_lupp_adaptive")
-    return out.result(n)
+    return out.result(n, with_est=bool(estimator))
+
+
+def certificate(A, J, T, p: int, seed: int, c0: int = 1 << 30, col_scale=None,
+                work=None) -> float:
+    """A-posteriori certificate ||Yc(:,J^c) - Yc(:,J) T||_F / sqrt(p) with the
+    p Gaussian vectors c0.. of seed's stream (J: int64 device tensor, T: k x
+    (n-k) device tensor in the factor type; -1 when J is invalid)."""
+    torch = _torch()
+    m, n = A.shape
+    assert A.stride(1) == 1
+    cfg, tdt = _config_for(A, seed, True, col_scale)
+    k = int(J.numel())
+    if k and (T.dtype != tdt or T.shape[0] != k or T.stride(1) != 1):
+        raise RidError("T must be k x (n-k), row-major, in the factor type")
+    wb = rid_certificate_workspace_bytes(m, n, p, cfg)
+    if wb == 0:
+        raise RidError("invalid sizes")
+    if work is None:
+        work = _work(wb, A.device)
+    out = torch.zeros(1, dtype=torch.float64, device=A.device)
+    Jc = J.contiguous() if k else None
+    rc = rid_certificate(A.data_ptr(), m, n, A.stride(0), Jc.data_ptr() if k else 0, k,
+                         T.data_ptr() if k else 0, T.stride(0) if k else max(n - k, 1), p, c0,
+                         cfg, out.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
+    _check(rc, "rid_certificate")
+    torch.cuda.current_stream().synchronize()
+    return float(out.item())
 
 
 def debug_gaussian(seed: int, c0: int, w: int, m: int, dtype, device="cuda"):

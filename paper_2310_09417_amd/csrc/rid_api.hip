@@ -18,6 +18,7 @@
 #include "rid_sketch_lp.hpp"
 #include "rid_refine.hpp"
 #include "rid_mlp.hpp"
+#include "rid_resid.hpp"
 
 using namespace rid;
 
@@ -61,11 +62,13 @@ inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
 
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
 enum KClass {
-  KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA, KC_N
+  KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA,
+  KC_RESID, KC_N
 };
 
 struct Profiler {
   bool on = false;
+  int override_class = -1;  // >= 0: every launch is counted in this class
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
@@ -84,6 +87,7 @@ inline long prof_begin(int c, hipStream_t st) {
     if (hipEventCreate(&e) != hipSuccess) return -1;
     p.pool.push_back(e);
   }
+  if (p.override_class >= 0) c = p.override_class;
   const size_t at = p.used;
   p.used += 2;
   if (hipEventRecord(p.pool[at], st) != hipSuccess) return -1;
@@ -171,6 +175,9 @@ struct Plan {
   rid_dtype at = RID_F64;   // storage type of A
   const float* scale = nullptr;  // FP8 column-tile scales (device)
   bool refine = false;           // FP64-residual refinement step on T
+  int est = 0;                   // rid_estimator of the stopping test
+  int resid_p = 0;               // set-aside sample width (adaptive, est > 0)
+  int64_t zr = 0;                // first Z column of the sample (adaptive, est > 0)
   int64_t ldz = 0, ldu = 0, ldl = 0;
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
@@ -180,11 +187,14 @@ struct Plan {
   // offsets
   size_t xwords_end = 0;  // end of the panel exchange words (zeroed per call)
   size_t o_ctrl, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
-      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, total;
+      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, o_yr, o_posr,
+      o_orderr, o_ctrlr, total;
 };
 
+// est > 0: a Remark-1 stopping estimate; sample_cols > 0 (adaptive calls)
+// reserves that many Z columns after the decomposition's own for the sample.
 bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, rid_dtype at,
-               bool refine, Plan& P) {
+               bool refine, int est, int sample_cols, Plan& P) {
   DeviceInfo di = device_info();
   if (!di.ok) return false;
   P.m = m;
@@ -194,9 +204,13 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.dt = dt;
   P.at = at;
   P.refine = refine;
+  P.est = est;
+  P.resid_p = sample_cols;
   P.cu = di.cu;
   const size_t es = esize(dt);
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
+  P.zr = P.ldz;
+  if (sample_cols > 0) P.ldz = (int64_t)align_up((size_t)(P.zr + kResidPMax), 4);
   P.ldu = (int64_t)align_up((size_t)kcap, 16);
   P.ldl = (int64_t)align_up((size_t)kcap, 64);
   // Panel factorisation: each workgroup keeps up to 192 candidate rows in
@@ -254,17 +268,30 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
   P.o_x = take(refine ? (size_t)n * P.ldl * es : 0);
+  // Remark-1 estimate: the kept sample (n x 16) and the private pivot state
+  // of the sample's factorisation
+  P.o_yr = take(sample_cols > 0 ? (size_t)n * kResidPMax * es : 0);
+  P.o_posr = take(est > 0 ? (size_t)n * 4 : 0);
+  P.o_orderr = take(est > 0 ? (size_t)(P.ldz + 1) * 4 : 0);
+  P.o_ctrlr = take(est > 0 ? sizeof(Ctrl) : 0);
   P.total = o;
   return true;
 }
 
 // Plan of a call with rank cap kmax and block width b (fixed rank: kmax = k + p,
 // b = p): kcap = min(kmax, m, n), widest block min(128, max(b, min(kcap, 128))).
-bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg, Plan& P) {
+// sample: the call sets a Remark-1 sample aside (adaptive calls with an
+// estimator).
+bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg, Plan& P,
+              bool sample = false) {
   const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
-  const int64_t wmax =
+  int64_t wmax =
       std::min<int64_t>(kMaxW, std::max<int64_t>({b, std::min<int64_t>(kcap, kMaxW), 1}));
-  if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, cfg->refine != 0, P)) return false;
+  const int est = cfg->estimator;
+  if (sample && est > 0) wmax = std::max<int64_t>(wmax, cfg->resid_p);
+  if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, cfg->refine != 0, est,
+                 sample && est > 0 ? cfg->resid_p : 0, P))
+    return false;
   P.scale = cfg->a_col_scale;
   return true;
 }
@@ -289,6 +316,10 @@ struct Ws {
   void* yorig;
   void* tt;
   void* xr;
+  void* yr;
+  int* pos_r;
+  int* order_r;
+  Ctrl* ctrl_r;
 };
 
 Ws carve(const Plan& P, void* work) {
@@ -312,12 +343,22 @@ Ws carve(const Plan& P, void* work) {
   w.yorig = P.refine ? b + P.o_yorig : nullptr;
   w.tt = P.refine ? b + P.o_tt : nullptr;
   w.xr = P.refine ? b + P.o_x : nullptr;
+  w.yr = P.resid_p > 0 ? b + P.o_yr : nullptr;
+  w.pos_r = P.est > 0 ? reinterpret_cast<int*>(b + P.o_posr) : nullptr;
+  w.order_r = P.est > 0 ? reinterpret_cast<int*>(b + P.o_orderr) : nullptr;
+  w.ctrl_r = P.est > 0 ? reinterpret_cast<Ctrl*>(b + P.o_ctrlr) : nullptr;
   return w;
 }
 
 #define RID_LAUNCH_CHECK()                          \
   do {                                              \
     if (hipGetLastError() != hipSuccess) return RID_ERR_HIP; \
+  } while (0)
+
+#define RID_TRY(expr)             \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != RID_OK) return rc_; \
   } while (0)
 
 // ---- sketch dispatch -------------------------------------------------------
@@ -510,7 +551,8 @@ int estimate(const Plan& P, const Ws& W, int w, double tol, int rel, int k, bool
 
 // ---- panel factorisation ---------------------------------------------------
 template <typename TF>
-int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, hipStream_t st) {
+int panel_state_t(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, int* pos,
+                  int* order, Ctrl* ctrl, hipStream_t st) {
   const size_t lds = panel_lds(P.lupp_rows, w, sizeof(TF));
   // each of the 192 row threads keeps the flags of its rows in 32 bits
   if (lds > kMaxLds || w > P.wmax || P.lupp_rows > 192 * 32) return RID_ERR_ARG;
@@ -520,9 +562,6 @@ int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, 
     return RID_ERR_HIP;
   TF* z = static_cast<TF*>(W.z);
   int64_t ldz = P.ldz, n = P.n, mn = std::min(P.m, P.n);
-  int* pos = W.pos;
-  int* order = W.order;
-  Ctrl* ctrl = W.ctrl;
   xword* xslot = W.slots;
   xword* xrow = W.slotrows;
   int wmax = (int)P.wmax;
@@ -535,6 +574,11 @@ int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, 
       hipLaunchCooperativeKernel(fn, dim3(P.lupp_g), dim3(256), args, (unsigned)lds, st);
   prof_end(pm, st);
   return e == hipSuccess ? RID_OK : RID_ERR_HIP;
+}
+
+template <typename TF>
+int panel_t(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, hipStream_t st) {
+  return panel_state_t<TF>(P, W, zcol, w, f, stop_full, W.pos, W.order, W.ctrl, st);
 }
 
 // Linv grows by the block row of the pivots just taken at k0 (at most f;
@@ -573,6 +617,56 @@ int panel(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full,
   if (rc != RID_OK) return rc;
   return P.dt == RID_F64 ? linv_update_t<double>(P, W, zcol, f, st)
                          : linv_update_t<float>(P, W, zcol, f, st);
+}
+
+// Panel exchange words: tag 0 never matches a step.
+int zero_xwords(const Plan& P, const Ws& W, hipStream_t st) {
+  const int64_t xw = (int64_t)(P.xwords_end - P.o_slots) / 4;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, ceil_div(xw, 256))), dim3(256),
+                     0, st, reinterpret_cast<unsigned int*>(W.slots), xw);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+// ---- Remark-1 estimate of the current rank k (Sec. 3.2) --------------------
+// Z columns [zcol, zcol+p) receive the sample's Schur complement: adaptive
+// calls copy the kept sample there and reduce it with the current factors
+// (U2, Schur kernels); fixed-rank calls pass the oversampling block, already
+// reduced by the caller.  The panel kernel then factors it with the private
+// pivot state (pos_r, order_r, ctrl_r; its words carry tags zcol + s + 1,
+// which repeat from one estimate to the next, hence the zeroing), and
+// k_resid_est applies the stopping test.  Counted as one profiler class.
+template <typename TF>
+int resid_estimate_body(const Plan& P, const Ws& W, int k, int zcol, int p, bool from_sample,
+                        double tol, int rel, bool fixed, double* est_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid_prep<TF>, dim3((unsigned)ceil_div(P.n, 256)), dim3(256), 0, st,
+                     from_sample ? static_cast<const TF*>(W.yr) : nullptr, (int64_t)kResidPMax,
+                     static_cast<TF*>(W.z), P.ldz, zcol, p, P.n, W.pos, W.pos_r, W.ctrl,
+                     W.ctrl_r);
+  RID_LAUNCH_CHECK();
+  if (from_sample) RID_TRY(block_update(P, W, k, zcol, p, true, st));
+  const int f = (int)std::min<int64_t>(p, P.n - k);
+  if (f < 1) return RID_OK;  // k = n: the decomposition is exact and done
+  RID_TRY(zero_xwords(P, W, st));
+  RID_TRY(panel_state_t<TF>(P, W, zcol, p, f, false, W.pos_r, W.order_r, W.ctrl_r, st));
+  hipLaunchKernelGGL(k_resid_est<TF>, dim3(1), dim3(256), 0, st, W.ctrl, W.ctrl_r, W.order_r,
+                     static_cast<const TF*>(W.z), P.ldz, zcol, p, W.norm, (int)P.schur_wgs, P.n,
+                     P.est, tol, rel, (int)P.kcap, fixed ? 1 : 0, est_out);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int resid_estimate(const Plan& P, const Ws& W, int k, int zcol, int p, bool from_sample,
+                   double tol, int rel, bool fixed, double* est_out, hipStream_t st) {
+  Profiler& pr = prof();
+  const int saved = pr.override_class;
+  pr.override_class = KC_RESID;
+  const int rc =
+      P.dt == RID_F64
+          ? resid_estimate_body<double>(P, W, k, zcol, p, from_sample, tol, rel, fixed, est_out, st)
+          : resid_estimate_body<float>(P, W, k, zcol, p, from_sample, tol, rel, fixed, est_out, st);
+  pr.override_class = saved;
+  return rc;
 }
 
 // ---- interpolation matrix and outputs --------------------------------------
@@ -637,16 +731,20 @@ int init(const Plan& P, const Ws& W, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, ceil_div(words, 256))), dim3(256),
                      0, st, static_cast<unsigned int*>(W.linv), words);
   RID_LAUNCH_CHECK();
-  // panel exchange words: tag 0 never matches a step
-  const int64_t xw = (int64_t)(P.xwords_end - P.o_slots) / 4;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, ceil_div(xw, 256))), dim3(256),
-                     0, st, reinterpret_cast<unsigned int*>(W.slots), xw);
+  return zero_xwords(P, W, st);
+}
+
+// est_out (nullable, device): -1 until an estimate is taken.
+int init_est_out(double* est_out, hipStream_t st) {
+  if (!est_out) return RID_OK;
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, est_out, 3, -1.0);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }
 
 bool valid_cfg(const rid_config* cfg) {
   if (!cfg || (cfg->dtype != RID_F64 && cfg->dtype != RID_F32)) return false;
+  if (cfg->estimator < RID_EST_SCHUR || cfg->estimator > RID_EST_UR_MAX) return false;
   if (cfg->a_type != cfg->dtype) {
     if (cfg->dtype != RID_F32 || !low_precision(cfg->a_type)) return false;
     if (cfg->a_type == RID_FP8_E4M3 && !cfg->a_col_scale) return false;
@@ -687,18 +785,16 @@ bool bplan(int32_t maxn, int32_t maxk, int32_t b, rid_dtype dt, BPlan& P) {
 
 }  // namespace
 
-#define RID_TRY(expr)             \
-  do {                            \
-    int rc_ = (expr);             \
-    if (rc_ != RID_OK) return rc_; \
-  } while (0)
 
 extern "C" {
 
 size_t rid_workspace_bytes(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg) {
   if (m < 1 || n < 1 || kmax < 1 || b < 0 || !valid_cfg(cfg)) return 0;
   Plan P;
-  if (!plan_for(m, n, kmax, b, cfg, P)) return 0;
+  // with a Remark-1 estimator and a sample width, the adaptive call's layout
+  // (a superset of the fixed-rank call's)
+  const bool sample = cfg->estimator > 0 && cfg->resid_p >= 1 && cfg->resid_p <= kResidPMax;
+  if (!plan_for(m, n, kmax, b, cfg, P, sample)) return 0;
   return P.total;
 }
 
@@ -725,12 +821,14 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
       p > kMaxW || m > INT32_MAX || n > INT32_MAX)
     return RID_ERR_ARG;
   if (k > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
+  if (cfg->estimator > 0 && p < 1) return RID_ERR_ARG;
   Plan P;
   if (!plan_for(m, n, k + p, p, cfg, P)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
   if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
   Ws W = carve(P, work);
   RID_TRY(init(P, W, stream));
+  RID_TRY(init_est_out(cfg->estimator > 0 ? cfg->est_out : nullptr, stream));
   // one pass per <= 128 sketch vectors: all k + p vectors up front
   for (int64_t c = 0; c < k + p; c += P.wmax) {
     const int w = (int)std::min<int64_t>(P.wmax, k + p - c);
@@ -743,7 +841,11 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
   }
   if (p > 0) {
     RID_TRY(block_update(P, W, (int)k, (int)k, (int)p, true, stream));
-    RID_TRY(estimate(P, W, (int)p, 0.0, 0, (int)k, true, stream));
+    if (cfg->estimator > 0)
+      RID_TRY(resid_estimate(P, W, (int)k, (int)k, (int)p, false, 0.0, 0, true, cfg->est_out,
+                             stream));
+    else
+      RID_TRY(estimate(P, W, (int)p, 0.0, 0, (int)k, true, stream));
   }
   return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
 }
@@ -760,8 +862,10 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
   const int64_t mn = std::min(m, n);
   const int64_t kcap = std::min(kmax, mn);
   if (kcap > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
+  const int est = cfg->estimator;
+  if (est > 0 && (cfg->resid_p < 1 || cfg->resid_p > kResidPMax)) return RID_ERR_ARG;
   Plan P;
-  if (!plan_for(m, n, kmax, b, cfg, P)) return RID_ERR_HIP;
+  if (!plan_for(m, n, kmax, b, cfg, P, true)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
   if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
   Ws W = carve(P, work);
@@ -770,6 +874,28 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
   RID_TRY(sketch_block(P, W, A, lda, cfg->seed, 0, w0, W.z, P.ldz, 0, true, true, stream));
   RID_TRY(panel(P, W, 0, w0, w0, true, stream));
   int64_t k = w0, cnext = w0;
+  if (est > 0) {
+    // Remark 1: the sample is drawn once; every factored block is followed
+    // by the estimate of its rank, and no block is drawn only to measure
+    const int p = cfg->resid_p;
+    RID_TRY(init_est_out(cfg->est_out, stream));
+    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, kResidC0, p, W.yr, kResidPMax, 0, false, true,
+                         stream));
+    RID_TRY(resid_estimate(P, W, (int)k, (int)P.zr, p, true, tol, cfg->tol_relative, false,
+                           cfg->est_out, stream));
+    while (k < kcap) {
+      RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false,
+                           true, stream));
+      cnext += b;
+      RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, false, stream));
+      const int f = (int)std::min<int64_t>(b, kcap - k);
+      RID_TRY(panel(P, W, (int)k, (int)b, f, true, stream));
+      k += f;
+      RID_TRY(resid_estimate(P, W, (int)k, (int)P.zr, p, true, tol, cfg->tol_relative, false,
+                             cfg->est_out, stream));
+    }
+    return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+  }
   while (k < mn) {
     RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false, true,
                          stream));
@@ -782,6 +908,66 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     k += f;
   }
   return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+}
+
+size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const rid_config* cfg) {
+  if (m < 1 || n < 1 || p < 1 || p > kCertPMax || !valid_cfg(cfg)) return 0;
+  rid_config c = *cfg;
+  c.estimator = 0;
+  Plan P;
+  if (!plan_for(m, n, p, p, &c, P)) return 0;
+  return P.total;
+}
+
+int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
+                    const void* T, int64_t ldt, int64_t p, int64_t c0, const rid_config* cfg,
+                    double* cert, void* work, size_t work_bytes, hipStream_t stream) {
+  if (!A || (k > 0 && !J) || (k > 0 && k < n && !T) || !cert || !work || !valid_cfg(cfg))
+    return RID_ERR_ARG;
+  if (m < 1 || n < 1 || lda < n || k < 0 || k > n || p < 1 || p > kCertPMax || c0 < 0 ||
+      c0 + p > (int64_t(1) << 32) || (k > 0 && ldt < n - k) || m > INT32_MAX || n > INT32_MAX)
+    return RID_ERR_ARG;
+  rid_config c = *cfg;
+  c.estimator = 0;
+  Plan P;
+  if (!plan_for(m, n, p, p, &c, P)) return RID_ERR_HIP;
+  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  Ws W = carve(P, work);
+  const unsigned gn = (unsigned)ceil_div(n, 256);
+  hipLaunchKernelGGL(k_cert_clear, dim3(gn), dim3(256), 0, stream, W.pos, n, W.ctrl);
+  RID_LAUNCH_CHECK();
+  // Yc^T in Z's first p columns
+  RID_TRY(sketch_block(P, W, A, lda, cfg->seed, c0, (int)p, W.z, P.ldz, 0, false, true, stream));
+  if (k > 0) {
+    hipLaunchKernelGGL(k_cert_mark, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, stream, J, k,
+                       W.pos, n, W.ctrl);
+    RID_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_nonpiv, dim3(1), dim3(1024), 0, stream, W.pos, n, W.nonpiv);
+  RID_LAUNCH_CHECK();
+  const int64_t nr = n - k;
+  // partials: one per 256 non-skeleton columns, in the Schur partials' buffer
+  // (ceil(n/64) entries)
+  const int nparts = (int)std::max<int64_t>(1, ceil_div(nr, 256));
+  const bool f64 = P.dt == RID_F64;
+  if (nr > 0) {
+    if (f64)
+      hipLaunchKernelGGL((k_cert<double, kCertPMax>), dim3((unsigned)nparts), dim3(256), 0, stream,
+                         static_cast<const double*>(W.z), P.ldz, (int)p, J, k, W.nonpiv, n,
+                         static_cast<const double*>(T), ldt, W.norm, W.ctrl);
+    else
+      hipLaunchKernelGGL((k_cert<float, kCertPMax>), dim3((unsigned)nparts), dim3(256), 0, stream,
+                         static_cast<const float*>(W.z), P.ldz, (int)p, J, k, W.nonpiv, n,
+                         static_cast<const float*>(T), ldt, W.norm, W.ctrl);
+    RID_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, stream, W.norm, 1, 0.0);
+    RID_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_cert_reduce, dim3(1), dim3(256), 0, stream, W.norm, nparts, (int)p, W.ctrl,
+                     cert);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
 }
 
 int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtype, void* out,

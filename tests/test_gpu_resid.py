@@ -1,0 +1,214 @@
+"""GPU parity of the residual-triangle estimates (Sec. 3.2, Remark 1) and of
+the a-posteriori certificate: the HIP path through the C ABI against the CPU
+oracle on the same seeded inputs."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from parity_util import check_fp64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def rid():
+    import paper_2310_09417_amd as r
+    r.library()
+    return r
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _dev(torch, A, dtype):
+    return torch.tensor(np.ascontiguousarray(A), dtype=dtype, device="cuda")
+
+
+def _close(a, b, rel, floor=0.0):
+    return abs(a - b) <= rel * abs(b) + floor
+
+
+@pytest.mark.parametrize("m,n,b,p,est,tol,dec", [
+    (300, 200, 8, 8, 1, 1e-6, 10.0),
+    (300, 200, 8, 8, 2, 1e-6, 10.0),
+    (300, 200, 8, 8, 3, 1e-6, 10.0),
+    (2000, 1500, 64, 16, 2, 1e-7, 12.0),   # several panel workgroups, 64-wide blocks
+    (700, 1100, 32, 5, 2, 1e-3, 8.0),      # wide, odd sample width
+])
+def test_adaptive_estimator_fp64(torch, rid, orc, m, n, b, p, est, tol, dec):
+    """FP64: same ID as the oracle's estimator mode (skeletons, T, rank,
+    status) and the three estimates of the returned rank within rounding."""
+    _say("resid64", m, n, b, p, est, tol)
+    A, _ = workloads.fast_decay(m, n, decades=dec, seed=m + n + est)
+    o = orc.rid_adaptive_est(A, b, tol, min(m, n), 5, est, p)
+    g = rid.adaptive(_dev(torch, A, torch.float64), b, tol, min(m, n), 5, estimator=est,
+                     resid_p=p)
+    check_fp64(A, g.J.cpu().numpy(), g.T.cpu().numpy(), g.k, g.status, g.err_est, o, b)
+    if g.k == o.k and np.array_equal(g.J.cpu().numpy(), o.J):
+        floor = 64 * 2.0 ** -53 * o.fro_a * math.sqrt(n)
+        for i in range(3):
+            assert _close(g.est3[i], o.est3[i], 1e-7, floor), (i, g.est3, o.est3)
+        assert g.err_est == g.est3[est - 1]
+
+
+def test_estimator_runs_its_own_kernels(torch, rid, orc):
+    """The sample estimate stops where the oracle's does, and its launches
+    (sample copy, Schur update, private LUPP, estimate) run only in that
+    mode (the profiler's resid_est class)."""
+    m, n, b = 1200, 800, 64
+    A, _ = workloads.fast_decay(m, n, decades=10.0, seed=3)
+    Ad = _dev(torch, A, torch.float64)
+    rid.rid_profile_start()
+    g0 = rid.adaptive(Ad, b, 1e-6, n, 9)
+    p0 = rid.rid_profile_stop()
+    rid.rid_profile_start()
+    g1 = rid.adaptive(Ad, b, 1e-6, n, 9, estimator=rid.RID_EST_SAMPLE, resid_p=8)
+    p1 = rid.rid_profile_stop()
+    assert g0.status == g1.status == rid.RID_OK
+    o0 = orc.rid_adaptive(A, b, 1e-6, n, 9)
+    o1 = orc.rid_adaptive_est(A, b, 1e-6, n, 9, 1, 8)
+    assert (g0.k, g1.k) == (o0.k, o1.k)
+    assert p1["resid_est"][1] > 0 and p0["resid_est"][1] == 0
+
+
+@pytest.mark.parametrize("tol,rel_s,rel_u", [(1e-3, 0.05, 0.25), (1e-4, 0.5, 0.5)])
+def test_adaptive_estimator_fp32(torch, rid, orc, tol, rel_s, rel_u):
+    """FP32: same status, rank within one block, and the estimates close to
+    the oracle's on the same FP32-rounded input.  S_r is formed by
+    cancellation: its entries (about E sqrt(p) / sqrt(p (n-k)), 2e-5 at
+    tol 1e-4 here) come from sketch entries near 0.17 minus k ~ 300 products,
+    so FP32 rounding (u = 6e-8, times sqrt(k) and the size of U2) puts a few
+    percent of error on them at 1e-4 and ten times less at 1e-3.  The error
+    spread over all (n-k) p entries adds to ||S_r||_F and reaches the later
+    elimination steps of U_r (measured at 1e-4: 7-25% on the sample estimate,
+    2-28% on the triangle estimates), so the strict bounds are checked at
+    1e-3 and only agreement within 50% at 1e-4, where the stopping decision
+    itself (status, rank) still matches."""
+    m, n, b, p = 1500, 1000, 32, 8
+    A, _ = workloads.fast_decay(m, n, decades=8.0, seed=31)
+    A32 = A.astype(np.float32).astype(np.float64)
+    for est in (1, 2):
+        _say("resid32", tol, est)
+        o = orc.rid_adaptive_est(A32, b, tol, n, 3, est, p)
+        g = rid.adaptive(_dev(torch, A32, torch.float32), b, tol, n, 3, estimator=est,
+                         resid_p=p)
+        assert g.status == o.status
+        assert abs(g.k - o.k) <= b
+        if g.k == o.k:
+            assert _close(g.est3[0], o.est3[0], rel_s), (g.est3, o.est3)
+            assert _close(g.est3[1], o.est3[1], rel_u), (g.est3, o.est3)
+            assert _close(g.est3[2], o.est3[2], rel_u), (g.est3, o.est3)
+
+
+@pytest.mark.parametrize("est", [1, 2, 3])
+def test_fixed_rank_estimator_fp64(torch, rid, orc, est):
+    """Fixed rank: the p oversampling vectors are the sample; the sample
+    estimate equals the plain Schur estimate and the others follow the
+    oracle."""
+    A, _ = workloads.fast_decay(900, 600, decades=9.0, seed=44)
+    k, p = 96, 12
+    o = orc.rid_fixed_rank_est(A, k, p, 7, est)
+    g = rid.fixed_rank(_dev(torch, A, torch.float64), k, p, 7, estimator=est)
+    assert g.k == k and g.status == rid.RID_OK
+    assert np.array_equal(g.J.cpu().numpy(), o.J)
+    floor = 64 * 2.0 ** -53 * o.fro_a * math.sqrt(600)
+    for i in range(3):
+        assert _close(g.est3[i], o.est3[i], 1e-7, floor), (i, g.est3, o.est3)
+    g0 = rid.fixed_rank(_dev(torch, A, torch.float64), k, p, 7)
+    assert _close(g.est3[0], g0.err_est, 1e-12)
+
+
+def test_estimator_exact_rank_and_edges(torch, rid, orc):
+    """Exact rank 37 with b = 16: the estimate at rank 48 is at rounding
+    level and the call stops there; a cap below the rank gives
+    NOT_CONVERGED at the cap with the estimate of that rank; full rank is
+    exact with no estimate."""
+    A = workloads.exact_rank(300, 200, 37, seed=13)
+    Ad = _dev(torch, A, torch.float64)
+    g = rid.adaptive(Ad, 16, 1e-10, 200, 2, estimator=rid.RID_EST_UR_FRO, resid_p=8)
+    assert (g.status, g.k) == (rid.RID_OK, 48)
+    assert max(g.est3) <= 1e-11 * np.linalg.norm(A)
+    g = rid.adaptive(Ad, 16, 1e-10, 20, 2, estimator=rid.RID_EST_UR_FRO, resid_p=8)
+    o = orc.rid_adaptive_est(A, 16, 1e-10, 20, 2, 2, 8)
+    assert (g.status, g.k) == (o.status, o.k) == (rid.RID_NOT_CONVERGED, 20)
+    assert _close(g.err_est, o.err_est, 1e-7)
+    # full rank: the ID becomes exact (E = 0) after estimates at ranks 16 and
+    # 32; est_out keeps the last of them, as the oracle's history does
+    B, _ = workloads.fast_decay(60, 40, decades=2.0, seed=1)
+    g = rid.adaptive(_dev(torch, B, torch.float64), 16, 0.0, 40, 2, estimator=2, resid_p=4)
+    o = orc.rid_adaptive_est(B, 16, 0.0, 40, 2, 2, 4)
+    assert (g.status, g.k) == (o.status, o.k) == (rid.RID_OK, 40)
+    assert g.err_est == 0.0 == o.err_est
+    assert len(o.est_hist) == 2
+    for i in range(3):
+        assert _close(g.est3[i], o.est3[i], 1e-7)
+    # a first block that is already exact: no estimate was taken
+    g = rid.adaptive(_dev(torch, B, torch.float64), 64, 0.0, 40, 2, estimator=2, resid_p=4)
+    assert (g.status, g.k, g.err_est) == (rid.RID_OK, 40, 0.0)
+    assert list(g.est3) == [-1.0, -1.0, -1.0]
+
+
+def test_estimator_argument_errors(torch, rid):
+    A = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    for p in (0, 17):
+        with pytest.raises(rid.RidError):
+            rid.adaptive(A, 8, 1e-6, 64, 1, estimator=2, resid_p=p)
+    with pytest.raises(rid.RidError):
+        rid.adaptive(A, 8, 1e-6, 64, 1, estimator=4, resid_p=8)
+    with pytest.raises(rid.RidError):
+        rid.fixed_rank(A, 8, 0, 1, estimator=2)
+
+
+@pytest.mark.parametrize("m,n,tol,p", [(400, 300, 1e-6, 8), (2500, 1800, 1e-5, 32)])
+def test_certificate_fp64(torch, rid, orc, m, n, tol, p):
+    """Certificate of the GPU's own ID against the oracle's certificate of
+    the same J and T (FP64, same vectors), within rounding; J in a shuffled
+    order with T's rows alike gives the same value."""
+    _say("cert64", m, n, p)
+    A, _ = workloads.fast_decay(m, n, decades=9.0, seed=m)
+    Ad = _dev(torch, A, torch.float64)
+    g = rid.adaptive(Ad, 32, tol, n, 4)
+    c_gpu = rid.certificate(Ad, g.J, g.T.contiguous(), p, 4)
+    c_orc = orc.certificate(A, g.J.cpu().numpy(), g.T.cpu().numpy(), 4, 1 << 30, p)
+    assert _close(c_gpu, c_orc, 1e-8)
+    perm = torch.randperm(g.k, device="cuda")
+    c2 = rid.certificate(Ad, g.J[perm].contiguous(), g.T[perm].contiguous(), p, 4)
+    assert _close(c2, c_gpu, 1e-8)
+
+
+def test_certificate_fp32_and_edges(torch, rid, orc):
+    A, _ = workloads.fast_decay(800, 500, decades=6.0, seed=2)
+    A32 = A.astype(np.float32).astype(np.float64)
+    Ad = _dev(torch, A32, torch.float32)
+    g = rid.adaptive(Ad, 32, 1e-4, 500, 6)
+    c_gpu = rid.certificate(Ad, g.J, g.T.contiguous(), 8, 6)
+    c_orc = orc.certificate(A32, g.J.cpu().numpy(), g.T.cpu().numpy().astype(np.float64), 6,
+                            1 << 30, 8)
+    assert _close(c_gpu, c_orc, 1e-3)
+    Ad64 = _dev(torch, A, torch.float64)
+    # k = n: nothing left to reproduce
+    Jall = torch.arange(500, dtype=torch.int64, device="cuda")
+    Tnone = torch.zeros((500, 0), dtype=torch.float64, device="cuda")
+    assert rid.certificate(Ad64, Jall, Tnone, 8, 6) == 0.0
+    # k = 0: ||Yc||_F / sqrt(p)
+    J0 = torch.zeros(0, dtype=torch.int64, device="cuda")
+    c0 = rid.certificate(Ad64, J0, None, 8, 6)
+    assert _close(c0, np.linalg.norm(orc.sketch(A, 6, 1 << 30, 8)) / math.sqrt(8), 1e-10)
+    # repeated or out-of-range skeletons are found on the device
+    Jbad = torch.tensor([3, 3], dtype=torch.int64, device="cuda")
+    T2 = torch.zeros((2, 498), dtype=torch.float64, device="cuda")
+    assert rid.certificate(Ad64, Jbad, T2, 8, 6) == -1.0
+    Jbad = torch.tensor([3, 500], dtype=torch.int64, device="cuda")
+    assert rid.certificate(Ad64, Jbad, T2, 8, 6) == -1.0
