@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--paper-steps", type=int, default=2)
     ap.add_argument("--paper-bsweep-n", type=int, default=8192,
                     help="n at which the paper workload also runs b = 32 and 64")
+    ap.add_argument("--cert-p", type=int, default=8,
+                    help="vectors of the a-posteriori certificate of the fp32 ID (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -237,6 +239,38 @@ def main():
         torch.linalg.vector_norm(A64).item())
     log(f"[bench] fp32 true residual / ||A|| = {resid32:.3e}")
 
+    # a-posteriori certificate of the FP32 result (the check Remark 1 ends
+    # with): one pass of p sketch vectors over A and the k x (n-k) product
+    cert = None
+    if args.cert_p > 0:
+        cfgc = rid.binding._cfg(rid.RID_F32, seed, True)
+        wbc = rid.rid_certificate_workspace_bytes(m, n, args.cert_p, cfgc)
+        workc = torch.empty(wbc, dtype=torch.uint8, device=dev)
+        Jc = out32[0][:k32].contiguous()
+        certo = torch.zeros(1, dtype=torch.float64, device=dev)
+
+        def runc():
+            rc = rid.rid_certificate(A32.data_ptr(), m, n, A32.stride(0), Jc.data_ptr(), k32,
+                                     out32[1].data_ptr(), n, args.cert_p, 1 << 30, cfgc,
+                                     certo.data_ptr(), workc.data_ptr(), wbc, stream)
+            if rc != 0:
+                raise RuntimeError(f"rid_certificate -> {rc}")
+
+        runc()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            runc()
+        e1.record()
+        torch.cuda.synchronize()
+        msc = e0.elapsed_time(e1) / 3
+        cert = {"p": args.cert_p, "ms": msc, "cert_rel": float(certo.item()) / fro,
+                "resid_rel_true": resid32, "err_est_rel": E / fro}
+        log(f"[bench] certificate (p={args.cert_p}) of the fp32 ID: {msc:.3f} ms, "
+            f"cert/||A|| = {cert['cert_rel']:.3e} (true {resid32:.3e})")
+        del workc
+
     # FP32 path with the FP64-residual refinement step on T
     refine = None
     if args.lp_steps > 0:
@@ -365,6 +399,7 @@ def main():
         "err_rel_vs_fp64_matrix": err32_orig,
         "precision_forms": precision,
         "refine": refine,
+        "certificate": cert,
         "fp64_path": fp64,
         "kernel_breakdown": breakdown,
         "roofline": roof,
@@ -394,11 +429,16 @@ def bench_paper(args, torch, rid, workloads):
         A = workloads.svd_matrix_device(n, n, sig, seed=args.seed + n, device=dev)
         torch.cuda.synchronize()
         log(f"[bench] paper workload: generated {n}x{n} Fast Decay in {time.time() - t0:.1f}s")
-        cases = [(128, 1e-8), (128, 1e-4)]
+        # (b, tol, stopping estimate): the Schur estimate of Alg. 1, and at
+        # the b-sweep size also the Remark-1 sample and normUest estimates
+        # (8 set-aside vectors)
+        cases = [(128, 1e-8, 0), (128, 1e-4, 0)]
         if n == args.paper_bsweep_n:
-            cases += [(32, 1e-8), (64, 1e-8)]
-        for b, tol in cases:
-            cfg = rid.binding._cfg(rid.RID_F64, args.seed, False)
+            cases += [(32, 1e-8, 0), (64, 1e-8, 0), (128, 1e-8, 1), (128, 1e-8, 2)]
+        for b, tol, est in cases:
+            est3 = torch.zeros(3, dtype=torch.float64, device=dev)
+            cfg = rid.binding._cfg(rid.RID_F64, args.seed, False, estimator=est,
+                                   resid_p=8 if est else 0, est_out=est3.data_ptr() if est else 0)
             wb = rid.rid_workspace_bytes(n, n, n, b, cfg)
             work = torch.empty(wb, dtype=torch.uint8, device=dev)
             J = torch.zeros(n, dtype=torch.int64, device=dev)
@@ -425,9 +465,18 @@ def bench_paper(args, torch, rid, workloads):
             ms = e0.elapsed_time(e1) / args.paper_steps
             k, E, st = int(ko.item()), float(eo.item()), int(so.item())
             F = rid.flops_id(n, n, k, k + b if k < n else k)
-            r = {"n": n, "b": b, "tol": tol, "ms": ms, "k": k, "status": rid.status_string(st),
-                 "err_est": E, "gflops": F / (ms * 1e-3) / 1e9}
-            log(f"[bench] paper workload n={n} b={b} tol={tol:g}: {ms:.2f} ms, k={k}, "
+            r = {"n": n, "b": b, "tol": tol, "estimator": est, "ms": ms, "k": k,
+                 "status": rid.status_string(st), "err_est": E, "gflops": F / (ms * 1e-3) / 1e9}
+            if est:
+                r["est3"] = [float(x) for x in est3.cpu()]
+            if n == args.paper_bsweep_n and 0 < k < n:
+                # true ID error (FP64 product on the GPU, outside the timing)
+                mask = torch.ones(n, dtype=torch.bool, device=dev)
+                mask[J[:k]] = False
+                R = A[:, mask] - A[:, J[:k]] @ T[:k, : n - k]
+                r["resid_true"] = float(torch.linalg.vector_norm(R).item())
+                del R, mask
+            log(f"[bench] paper workload n={n} b={b} tol={tol:g} est={est}: {ms:.2f} ms, k={k}, "
                 f"{r['status']}, E={E:.2e}, {r['gflops']:.0f} GFLOP/s")
             if b == 128:
                 # time split over kernel classes, from one more (untimed) call

@@ -178,6 +178,7 @@ struct Plan {
   int est = 0;                   // rid_estimator of the stopping test
   int resid_p = 0;               // set-aside sample width (adaptive, est > 0)
   int64_t zr = 0;                // first Z column of the sample (adaptive, est > 0)
+  int64_t zs = 0;                // first Z column of its copy that the private LU factors
   int64_t ldz = 0, ldu = 0, ldl = 0;
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
@@ -187,8 +188,8 @@ struct Plan {
   // offsets
   size_t xwords_end = 0;  // end of the panel exchange words (zeroed per call)
   size_t o_ctrl, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
-      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, o_yr, o_posr,
-      o_orderr, o_ctrlr, total;
+      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, o_posr, o_orderr,
+      o_ctrlr, total;
 };
 
 // est > 0: a Remark-1 stopping estimate; sample_cols > 0 (adaptive calls)
@@ -210,7 +211,8 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   const size_t es = esize(dt);
   P.ldz = (int64_t)align_up((size_t)(kcap + wmax), 4);
   P.zr = P.ldz;
-  if (sample_cols > 0) P.ldz = (int64_t)align_up((size_t)(P.zr + kResidPMax), 4);
+  P.zs = P.zr + kResidPMax;
+  if (sample_cols > 0) P.ldz = (int64_t)align_up((size_t)(P.zs + kResidPMax), 4);
   P.ldu = (int64_t)align_up((size_t)kcap, 16);
   P.ldl = (int64_t)align_up((size_t)kcap, 64);
   // Panel factorisation: each workgroup keeps up to 192 candidate rows in
@@ -268,9 +270,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
   P.o_x = take(refine ? (size_t)n * P.ldl * es : 0);
-  // Remark-1 estimate: the kept sample (n x 16) and the private pivot state
-  // of the sample's factorisation
-  P.o_yr = take(sample_cols > 0 ? (size_t)n * kResidPMax * es : 0);
+  // Remark-1 estimate: the private pivot state of the sample's factorisation
   P.o_posr = take(est > 0 ? (size_t)n * 4 : 0);
   P.o_orderr = take(est > 0 ? (size_t)(P.ldz + 1) * 4 : 0);
   P.o_ctrlr = take(est > 0 ? sizeof(Ctrl) : 0);
@@ -316,7 +316,6 @@ struct Ws {
   void* yorig;
   void* tt;
   void* xr;
-  void* yr;
   int* pos_r;
   int* order_r;
   Ctrl* ctrl_r;
@@ -343,7 +342,6 @@ Ws carve(const Plan& P, void* work) {
   w.yorig = P.refine ? b + P.o_yorig : nullptr;
   w.tt = P.refine ? b + P.o_tt : nullptr;
   w.xr = P.refine ? b + P.o_x : nullptr;
-  w.yr = P.resid_p > 0 ? b + P.o_yr : nullptr;
   w.pos_r = P.est > 0 ? reinterpret_cast<int*>(b + P.o_posr) : nullptr;
   w.order_r = P.est > 0 ? reinterpret_cast<int*>(b + P.o_orderr) : nullptr;
   w.ctrl_r = P.est > 0 ? reinterpret_cast<Ctrl*>(b + P.o_ctrlr) : nullptr;
@@ -497,15 +495,20 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
 }
 
 // ---- block update: U2 (triangular solve) then S (Schur GEMM) --------------
+// kb > 0 (the Remark-1 sample only): the columns already hold the Schur
+// complement for the first kb pivots and are reduced by pivots kb..k-1.
 template <typename TF>
-int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, hipStream_t st) {
+int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, bool norm,
+                   hipStream_t st) {
   long pm = prof_begin(KC_TRSM, st);
-  hipLaunchKernelGGL(k_u2<TF>, dim3((unsigned)ceil_div(k, 16), (unsigned)ceil_div(w, 64)),
-                     dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz, W.order, k, zcol, w,
-                     static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
-                     W.ctrl);
-  RID_LAUNCH_CHECK();
-  if (P.refine) {
+  if (k > kb) {
+    hipLaunchKernelGGL(k_u2<TF>, dim3((unsigned)ceil_div(k - kb, 16), (unsigned)ceil_div(w, 64)),
+                       dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz, W.order, kb, k, zcol,
+                       w, static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
+                       W.ctrl);
+    RID_LAUNCH_CHECK();
+  }
+  if (P.refine && zcol < P.zr) {
     // keep U's block row in the pivot rows (the refinement solves with U)
     hipLaunchKernelGGL(k_store_u2<TF>, dim3((unsigned)ceil_div((int64_t)k * w, 256)), dim3(256),
                        0, st, static_cast<TF*>(W.z), P.ldz, W.order, k, zcol, w,
@@ -516,10 +519,15 @@ int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm
   pm = prof_begin(KC_SCHUR, st);
   const int nt = (w + 15) / 16;
   dim3 grid((unsigned)P.schur_wgs);
-#define RID_SCHUR(NTV)                                                                         \
-  hipLaunchKernelGGL((k_schur<TF, NTV>), grid, dim3(256), 0, st, static_cast<TF*>(W.z), P.ldz, \
-                     P.n, W.pos, k, zcol, w, static_cast<const TF*>(W.u2t), P.ldu, W.norm,      \
-                     W.ctrl, norm ? 1 : 0)
+#define RID_SCHUR(NTV)                                                                          \
+  if (kb > 0)                                                                                   \
+    hipLaunchKernelGGL((k_schur<TF, NTV, true>), grid, dim3(256), 0, st, static_cast<TF*>(W.z), \
+                       P.ldz, P.n, W.pos, kb, k, zcol, w, static_cast<const TF*>(W.u2t), P.ldu, \
+                       W.norm, W.ctrl, norm ? 1 : 0);                                           \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_schur<TF, NTV>), grid, dim3(256), 0, st, static_cast<TF*>(W.z),       \
+                       P.ldz, P.n, W.pos, 0, k, zcol, w, static_cast<const TF*>(W.u2t), P.ldu,  \
+                       W.norm, W.ctrl, norm ? 1 : 0)
   switch (nt) {
     case 1: RID_SCHUR(1); break;
     case 2: RID_SCHUR(2); break;
@@ -536,9 +544,10 @@ int block_update_t(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm
   return RID_OK;
 }
 
-int block_update(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, hipStream_t st) {
-  return P.dt == RID_F64 ? block_update_t<double>(P, W, k, zcol, w, norm, st)
-                         : block_update_t<float>(P, W, k, zcol, w, norm, st);
+int block_update(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, hipStream_t st,
+                 int kb = 0) {
+  return P.dt == RID_F64 ? block_update_t<double>(P, W, kb, k, zcol, w, norm, st)
+                         : block_update_t<float>(P, W, kb, k, zcol, w, norm, st);
 }
 
 int estimate(const Plan& P, const Ws& W, int w, double tol, int rel, int k, bool fixed,
@@ -629,42 +638,45 @@ int zero_xwords(const Plan& P, const Ws& W, hipStream_t st) {
 }
 
 // ---- Remark-1 estimate of the current rank k (Sec. 3.2) --------------------
-// Z columns [zcol, zcol+p) receive the sample's Schur complement: adaptive
-// calls copy the kept sample there and reduce it with the current factors
-// (U2, Schur kernels); fixed-rank calls pass the oversampling block, already
-// reduced by the caller.  The panel kernel then factors it with the private
-// pivot state (pos_r, order_r, ctrl_r; its words carry tags zcol + s + 1,
-// which repeat from one estimate to the next, hence the zeroing), and
-// k_resid_est applies the stopping test.  Counted as one profiler class.
+// Adaptive calls keep the sample's Schur complement S_r in Z columns
+// [zr, zr+p): after the block that took pivots kb..k-1 the U2 and Schur
+// kernels reduce it by those pivots only (K = k - kb), its non-pivot rows are
+// copied to columns [zs, zs+p), and the panel kernel factors that copy with
+// the private pivot state (pos_r, order_r, ctrl_r; its exchange words carry
+// tags zs + s + 1, which repeat from one estimate to the next, hence the
+// zeroing).  Fixed-rank calls factor their oversampling block (columns
+// [k, k+p), already reduced by the caller) in place.  k_resid_est then forms
+// the estimates and applies the stopping test.  Counted as one profiler
+// class.
 template <typename TF>
-int resid_estimate_body(const Plan& P, const Ws& W, int k, int zcol, int p, bool from_sample,
-                        double tol, int rel, bool fixed, double* est_out, hipStream_t st) {
+int resid_estimate_body(const Plan& P, const Ws& W, int kb, int k, int p, bool adaptive,
+                        double tol, int rel, double* est_out, hipStream_t st) {
+  const int zcol = adaptive ? (int)P.zs : k;
+  if (adaptive) RID_TRY(block_update(P, W, k, (int)P.zr, p, true, st, kb));
   hipLaunchKernelGGL(k_resid_prep<TF>, dim3((unsigned)ceil_div(P.n, 256)), dim3(256), 0, st,
-                     from_sample ? static_cast<const TF*>(W.yr) : nullptr, (int64_t)kResidPMax,
-                     static_cast<TF*>(W.z), P.ldz, zcol, p, P.n, W.pos, W.pos_r, W.ctrl,
-                     W.ctrl_r);
+                     static_cast<TF*>(W.z), P.ldz, adaptive ? (int)P.zr : -1, zcol, p, P.n, W.pos,
+                     W.pos_r, W.ctrl, W.ctrl_r);
   RID_LAUNCH_CHECK();
-  if (from_sample) RID_TRY(block_update(P, W, k, zcol, p, true, st));
   const int f = (int)std::min<int64_t>(p, P.n - k);
   if (f < 1) return RID_OK;  // k = n: the decomposition is exact and done
   RID_TRY(zero_xwords(P, W, st));
   RID_TRY(panel_state_t<TF>(P, W, zcol, p, f, false, W.pos_r, W.order_r, W.ctrl_r, st));
   hipLaunchKernelGGL(k_resid_est<TF>, dim3(1), dim3(256), 0, st, W.ctrl, W.ctrl_r, W.order_r,
                      static_cast<const TF*>(W.z), P.ldz, zcol, p, W.norm, (int)P.schur_wgs, P.n,
-                     P.est, tol, rel, (int)P.kcap, fixed ? 1 : 0, est_out);
+                     P.est, tol, rel, (int)P.kcap, adaptive ? 0 : 1, est_out);
   RID_LAUNCH_CHECK();
   return RID_OK;
 }
 
-int resid_estimate(const Plan& P, const Ws& W, int k, int zcol, int p, bool from_sample,
-                   double tol, int rel, bool fixed, double* est_out, hipStream_t st) {
+int resid_estimate(const Plan& P, const Ws& W, int kb, int k, int p, bool adaptive, double tol,
+                   int rel, double* est_out, hipStream_t st) {
   Profiler& pr = prof();
   const int saved = pr.override_class;
   pr.override_class = KC_RESID;
   const int rc =
       P.dt == RID_F64
-          ? resid_estimate_body<double>(P, W, k, zcol, p, from_sample, tol, rel, fixed, est_out, st)
-          : resid_estimate_body<float>(P, W, k, zcol, p, from_sample, tol, rel, fixed, est_out, st);
+          ? resid_estimate_body<double>(P, W, kb, k, p, adaptive, tol, rel, est_out, st)
+          : resid_estimate_body<float>(P, W, kb, k, p, adaptive, tol, rel, est_out, st);
   pr.override_class = saved;
   return rc;
 }
@@ -842,8 +854,7 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
   if (p > 0) {
     RID_TRY(block_update(P, W, (int)k, (int)k, (int)p, true, stream));
     if (cfg->estimator > 0)
-      RID_TRY(resid_estimate(P, W, (int)k, (int)k, (int)p, false, 0.0, 0, true, cfg->est_out,
-                             stream));
+      RID_TRY(resid_estimate(P, W, 0, (int)k, (int)p, false, 0.0, 0, cfg->est_out, stream));
     else
       RID_TRY(estimate(P, W, (int)p, 0.0, 0, (int)k, true, stream));
   }
@@ -879,10 +890,10 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     // by the estimate of its rank, and no block is drawn only to measure
     const int p = cfg->resid_p;
     RID_TRY(init_est_out(cfg->est_out, stream));
-    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, kResidC0, p, W.yr, kResidPMax, 0, false, true,
+    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, kResidC0, p, W.z, P.ldz, (int)P.zr, false, true,
                          stream));
-    RID_TRY(resid_estimate(P, W, (int)k, (int)P.zr, p, true, tol, cfg->tol_relative, false,
-                           cfg->est_out, stream));
+    RID_TRY(resid_estimate(P, W, 0, (int)k, p, true, tol, cfg->tol_relative, cfg->est_out,
+                           stream));
     while (k < kcap) {
       RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false,
                            true, stream));
@@ -890,8 +901,9 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
       RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, false, stream));
       const int f = (int)std::min<int64_t>(b, kcap - k);
       RID_TRY(panel(P, W, (int)k, (int)b, f, true, stream));
+      const int64_t k0 = k;
       k += f;
-      RID_TRY(resid_estimate(P, W, (int)k, (int)P.zr, p, true, tol, cfg->tol_relative, false,
+      RID_TRY(resid_estimate(P, W, (int)k0, (int)k, p, true, tol, cfg->tol_relative,
                              cfg->est_out, stream));
     }
     return finish(P, W, T, ldt, J, k_out, err_est, status, stream);

@@ -300,12 +300,12 @@ __device__ double wg_block_update(const BSlice<TF>& S, int64_t ldz, int64_t ldl,
         for (int p0 = 0; p0 < k; p0 += 16, ++chunk) {
           const int pa = p0 + 4 * (lane >> 4);
           TF a4[4];
-          load4(Z, (int64_t)i * ldz, pa, k, ok, a4);
+          load4(Z, (int64_t)i * ldz, pa, 0, k, ok, a4);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int col = q * 16 + (lane & 15);
             TF b4[4];
-            load4(U2T, (int64_t)col * ldu, pa, k, col < w, b4);
+            load4(U2T, (int64_t)col * ldu, pa, 0, k, col < w, b4);
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[q] = M::op(a4[j], b4[j], acc[q]);
           }

@@ -58,18 +58,20 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, int* nonfinite) {
 }
 
 // ---------------------------------------------------------------------------
-// Schur block S = (P Y)(non-pivots, block) - L2 U2 (MFMA, K = k), written in
-// place for every non-pivot row; with `want_norm` each workgroup also leaves
+// Schur block S = (P Y)(non-pivots, block) - L2 U2 (MFMA, K = [kb, k)),
+// written in place for every non-pivot row (kb > 0: the block already holds
+// the Schur complement for the first kb pivots and is reduced by the pivots
+// kb..k-1 only); with `want_norm` each workgroup also leaves
 // its FP64 sum of S^2 in normpart[blockIdx.x].  Each wave owns 16 rows and
 // all NT 16-column tiles of the block.  The K index is walked in chunks of
 // 16: a lane loads 4 consecutive K values of its A row and of its U2 column
 // and feeds them to 4 MFMAs (a consistent relabelling of K inside the chunk).
 // FP32: the MFMA accumulator is folded into FP64 every 64 K values.
 // ---------------------------------------------------------------------------
-template <typename TF>
-__device__ __forceinline__ void load4(const TF* p, int64_t base, int kidx, int k, bool ok,
+template <typename TF, bool FROM = false>
+__device__ __forceinline__ void load4(const TF* p, int64_t base, int kidx, int kb, int k, bool ok,
                                       TF out[4]) {
-  if (ok && kidx + 3 < k) {
+  if (ok && (!FROM || kidx >= kb) && kidx + 3 < k) {
     // 16-byte aligned: base and kidx are multiples of 4 elements
     if (sizeof(TF) == 4) {
       const float4 v = *reinterpret_cast<const float4*>(p + base + kidx);
@@ -82,13 +84,15 @@ __device__ __forceinline__ void load4(const TF* p, int64_t base, int kidx, int k
     return;
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) out[j] = (ok && kidx + j < k) ? p[base + kidx + j] : TF(0);
+  for (int j = 0; j < 4; ++j)
+    out[j] = (ok && (!FROM || kidx + j >= kb) && kidx + j < k) ? p[base + kidx + j] : TF(0);
 }
 
-template <typename TF, int NT>
+// FROM: K starts at kb (else at 0; the kb argument is then ignored).
+template <typename TF, int NT, bool FROM = false>
 __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, int64_t n,
-                                               const int* __restrict__ pos, int k, int zcol, int w,
-                                               const TF* __restrict__ U2T, int64_t ldu,
+                                               const int* __restrict__ pos, int kb, int k, int zcol,
+                                               int w, const TF* __restrict__ U2T, int64_t ldu,
                                                double* __restrict__ normpart, const Ctrl* ctrl,
                                                int want_norm) {
   if (ctrl->done) return;
@@ -115,11 +119,11 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
   };
   auto load_ops = [&](Ops& o, int s0) {
     const int kidx = s0 + 4 * (lane >> 4);
-    load4(Z, arow * ldz, kidx, k, arow_ok, o.a4);
+    load4<TF, FROM>(Z, arow * ldz, kidx, kb, k, arow_ok, o.a4);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = t * 16 + (lane & 15);
-      load4(U2T, (int64_t)col * ldu, kidx, k, col < w, o.b4[t]);
+      load4<TF, FROM>(U2T, (int64_t)col * ldu, kidx, kb, k, col < w, o.b4[t]);
     }
   };
   auto mma_ops = [&](const Ops& o, int ci) {
@@ -136,14 +140,15 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
       }
     }
   };
-  const int nchk = (k + 15) / 16;
+  const int kb16 = FROM ? (kb & ~15) : 0;
+  const int nchk = k > kb16 ? (k - kb16 + 15) / 16 : 0;
   Ops o0, o1;
-  if (nchk > 0) load_ops(o0, 0);
+  if (nchk > 0) load_ops(o0, kb16);
   for (int ci = 0; ci < nchk; ci += 2) {
-    if (ci + 1 < nchk) load_ops(o1, 16 * (ci + 1));
+    if (ci + 1 < nchk) load_ops(o1, kb16 + 16 * (ci + 1));
     mma_ops(o0, ci);
     if (ci + 1 >= nchk) break;
-    if (ci + 2 < nchk) load_ops(o0, 16 * (ci + 2));
+    if (ci + 2 < nchk) load_ops(o0, kb16 + 16 * (ci + 2));
     mma_ops(o1, ci + 1);
   }
 #pragma unroll
@@ -876,22 +881,25 @@ __device__ __forceinline__ void wg_tile_ksplit(const TF* arow, BRow brow, int kb
 }
 
 // U2 = L1^{-1} (P Y)(0:k, block) for the w block columns starting at zcol.
-// Grid (ceil(k/16), ceil(w/64)); output U2T (w x ldu, column-major U2).
+// kb > 0: only rows kb..k-1 of U2, from the diagonal block of L1^{-1} on those
+// rows (the block's pivot rows kb.. already hold its Schur complement for the
+// first kb pivots).  Grid (ceil((k-kb)/16), ceil(w/64)); output U2T (w x ldu,
+// column-major U2).
 template <typename TF>
 __global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ Z, int64_t ldz,
-                                            const int* __restrict__ order, int k, int zcol, int w,
-                                            const TF* __restrict__ Linv, int64_t ldl,
+                                            const int* __restrict__ order, int kb, int k, int zcol,
+                                            int w, const TF* __restrict__ Linv, int64_t ldl,
                                             TF* __restrict__ U2T, int64_t ldu, const Ctrl* ctrl) {
   if (ctrl->done) return;
   __shared__ double red[16 * 64];
-  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 64;
+  const int i0 = kb + blockIdx.x * 16, j0 = blockIdx.y * 64;
   const int lane = threadIdx.x & 63;
   const int i = i0 + (lane & 15);
   const TF* arow = (i < k) ? Linv + (int64_t)i * ldl : nullptr;
   const int bcols = (w - j0 < 64) ? w - j0 : 64;
   auto brow = [&](int p) -> const TF* { return Z + (int64_t)order[p] * ldz + zcol + j0; };
   const int ke = (i0 + 16 < k) ? i0 + 16 : k;  // lower triangular: p <= i
-  wg_tile_ksplit<TF>(arow, brow, 0, ke, bcols, red);
+  wg_tile_ksplit<TF>(arow, brow, kb, ke, bcols, red);
   for (int t = threadIdx.x; t < 16 * 64; t += 256) {
     const int ii = t % 16, jj = t / 16;
     if (i0 + ii < k && j0 + jj < w) U2T[(int64_t)(j0 + jj) * ldu + i0 + ii] = (TF)red[ii * 64 + jj];

@@ -1,14 +1,16 @@
 // Residual-triangle estimates (Sec. 3.2, Remark 1) and the a-posteriori
 // certificate of an ID.
 //
-// Estimates.  After the factorisation has k pivots, the set-aside sample
-// Yr^T (n x p) is copied into spare columns of Z; the block update kernels
-// (k_u2, k_schur) turn its non-pivot rows into the Schur complement
+// Estimates.  The set-aside sample Yr^T (n x p) lives in spare columns of Z;
+// after each factored block the block update kernels (k_u2, k_schur) reduce
+// it by that block's pivots, so that its non-pivot rows hold the Schur
+// complement
 //   S_r = (P Yr^T)(rest) - L2 L1^{-1} (P Yr^T)(pivots)
-// with FP64 partial sums of S_r^2, and the panel LUPP kernel factors S_r with
-// a private pivot map and control block (so the decomposition's own state is
-// untouched).  The pivot rows of that factorisation hold U_r; k_resid_est
-// forms the three estimates from it and applies the stopping test.
+// with FP64 partial sums of S_r^2.  The panel LUPP kernel factors a copy of
+// S_r with a private pivot map and control block (so the decomposition's own
+// state is untouched).  The pivot rows of that factorisation hold U_r;
+// k_resid_est forms the three estimates from it and applies the stopping
+// test.
 #pragma once
 
 #include "rid_kernels.hpp"
@@ -21,22 +23,22 @@ constexpr int64_t kResidC0 = int64_t(1) << 31;
 constexpr int kResidPMax = 16;
 constexpr int kCertPMax = 32;  // widest certificate sample
 
-// Before the sample's update at rank k: copy Yr^T (n x ldy, p columns) into
-// Z(:, zcol .. zcol+p) when yr is given, the pivot map into pos_r, and the
-// control block into ctrl_r.  The copy of the control block always happens,
-// so a finished decomposition also ends the private factorisation.
+// Before the sample's factorisation at rank k: copy Z(:, src .. src+p) to
+// Z(:, dst .. dst+p) when src >= 0, the pivot map into pos_r, and the control
+// block into ctrl_r.  The copy of the control block always happens, so a
+// finished decomposition also ends the private factorisation.
 template <typename TF>
-__global__ __launch_bounds__(256) void k_resid_prep(const TF* __restrict__ yr, int64_t ldy,
-                                                    TF* __restrict__ Z, int64_t ldz, int zcol,
-                                                    int p, int64_t n, const int* __restrict__ pos,
+__global__ __launch_bounds__(256) void k_resid_prep(TF* __restrict__ Z, int64_t ldz, int src,
+                                                    int dst, int p, int64_t n,
+                                                    const int* __restrict__ pos,
                                                     int* __restrict__ pos_r, const Ctrl* ctrl,
                                                     Ctrl* ctrl_r) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r == 0) *ctrl_r = *ctrl;
   if (ctrl->done || r >= n) return;
   pos_r[r] = pos[r];
-  if (yr)
-    for (int q = 0; q < p; ++q) Z[r * ldz + zcol + q] = yr[r * ldy + q];
+  if (src >= 0)
+    for (int q = 0; q < p; ++q) Z[r * ldz + dst + q] = Z[r * ldz + src + q];
 }
 
 // gamma(k) = 1 / max(1, k / (4 ln k)), 1 for k < 2.
