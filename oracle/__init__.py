@@ -14,6 +14,8 @@ Method: Pearce, Chen, Dong, Martinsson, arXiv 2310.09417.
   * adaptive blocked loop  -- Sec. 4.2 and Alg. 1 (randLUPPadap)
   * residual triangle      -- Sec. 3.2, Remark 1 (eqs. normUest, maxUest) and
                               the a-posteriori certificate it closes with
+  * row skeletons of A(:,J) -- Sec. 2.4 (second LUPP of CUR / two-sided ID),
+                              Sec. 2.2 (two-sided ID)
 """
 from __future__ import annotations
 
@@ -91,6 +93,8 @@ def _load():
         lib.orc_certificate.restype = cint
         lib.orc_growth_scale.argtypes = [i64]
         lib.orc_growth_scale.restype = dbl
+        lib.orc_lupp_rows.argtypes = [P, i64, i64, i64, P, i64, P, P, i64, P]
+        lib.orc_lupp_rows.restype = cint
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = cint
         _lib = lib
@@ -281,6 +285,39 @@ def certificate(A, J, T, seed: int, c0: int, p: int) -> float:
     if st != OK:
         raise ValueError("certificate: J out of range or repeated")
     return float(out[0])
+
+
+def lupp_rows(A, J):
+    """Row skeletons of C = A(:, J) by LUPP (Sec. 2.4, the second LUPP of the
+    CUR / two-sided ID construction): returns (status, I in pivot order, W_r)
+    with W_r ((m-k) x k) the rows of W = C A(I,J)^{-1} for the non-skeleton
+    rows in ascending index."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    k = len(J)
+    I = np.zeros(max(k, 1), dtype=np.int64)
+    Wr = np.zeros((max(m, 1), max(k, 1)))
+    kk = np.zeros(1, dtype=np.int64)
+    st = lib.orc_lupp_rows(_ptr(A), m, n, n, _ptr(J), k, _ptr(I), _ptr(Wr), max(k, 1), _ptr(kk))
+    kk = int(kk[0])
+    return int(st), I[:kk].copy(), Wr[: m - kk, :kk].copy()
+
+
+def two_sided_residual(A, I, Wr, J, T) -> float:
+    """||A - W A(I,J) X||_F for the two-sided ID (Sec. 2.2): W (m x k) with
+    W(I,:) = I_k and W(I^c,:) = Wr; X (k x n) with X(:,J) = I_k, X(:,J^c) = T."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    k = len(I)
+    W = np.zeros((m, k))
+    W[I] = np.eye(k)
+    W[np.setdiff1d(np.arange(m), I)] = Wr
+    X = np.zeros((k, n))
+    X[:, J] = np.eye(k)
+    X[:, np.setdiff1d(np.arange(n), J)] = T
+    return float(np.linalg.norm(A - W @ A[np.ix_(I, J)] @ X))
 
 
 def lupp_factors(A, l: int, k: int, seed: int):

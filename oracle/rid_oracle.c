@@ -793,6 +793,90 @@ int orc_lupp_factors(const double* A, int64_t m, int64_t n, int64_t lda, int64_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Row skeletons of C = A(:, J) (paper Sec. 2.4: after the column skeletons */
+/* J, a second, direct LUPP on the small m x k matrix C gives the row        */
+/* skeletons I; Sec. 2.2, two-sided ID: A ~= W A(I, J) X with W = C A(I,J)^-1 */
+/* the row interpolation matrix, W(I, :) = I_k).  LU with partial pivoting   */
+/* on C, k steps, physical row swaps, ties to the lowest original row index;  */
+/* an exactly zero pivot stops it (ORC_RANK_DEFICIENT, *k_out = steps).       */
+/* With P C = [L1; L2] U: W(I^c, :) = L2 L1^{-1}, each row by back            */
+/* substitution x L1 = L2(r, :), s descending.  Outputs: I[0..k_out) in pivot */
+/* order; Wr ((m - k_out) x ldw, row-major) row q for the q-th non-skeleton   */
+/* row in ascending index.  A J entry outside [0, n) gives ORC_ERR_ARG.       */
+/* ------------------------------------------------------------------------ */
+int orc_lupp_rows(const double* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
+                  int64_t* I, double* Wr, int64_t ldw, int64_t* k_out) {
+  *k_out = 0;
+  if (k < 1 || k > m || k > n) return ORC_ERR_ARG;
+  for (int64_t s = 0; s < k; ++s)
+    if (J[s] < 0 || J[s] >= n) return ORC_ERR_ARG;
+  double* Z = (double*)malloc(sizeof(double) * (size_t)m * (size_t)k);
+  int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)m);
+  for (int64_t r = 0; r < m; ++r) {
+    perm[r] = r;
+    for (int64_t s = 0; s < k; ++s) Z[r * k + s] = A[r * lda + J[s]];
+  }
+  int st = ORC_OK;
+  int64_t kk = k;
+  for (int64_t s = 0; s < k; ++s) {
+    int64_t piv = s;
+    double best = fabs(Z[s * k + s]);
+    for (int64_t r = s + 1; r < m; ++r) {
+      const double v = fabs(Z[r * k + s]);
+      if (v > best || (v == best && perm[r] < perm[piv])) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (best == 0.0) {
+      st = ORC_RANK_DEFICIENT;
+      kk = s;
+      break;
+    }
+    if (piv != s) {
+      for (int64_t q = 0; q < k; ++q) {
+        const double t = Z[s * k + q];
+        Z[s * k + q] = Z[piv * k + q];
+        Z[piv * k + q] = t;
+      }
+      const int64_t t = perm[s];
+      perm[s] = perm[piv];
+      perm[piv] = t;
+    }
+    for (int64_t r = s + 1; r < m; ++r) {
+      const double l = Z[r * k + s] / Z[s * k + s];
+      Z[r * k + s] = l;
+      for (int64_t q = s + 1; q < k; ++q) Z[r * k + q] = Z[r * k + q] - l * Z[s * k + q];
+    }
+  }
+  for (int64_t s = 0; s < kk; ++s) I[s] = perm[s];
+  /* slot of each non-skeleton row among the non-skeletons, ascending */
+  char* is_skel = (char*)calloc((size_t)m, 1);
+  int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)m);
+  for (int64_t s = 0; s < kk; ++s) is_skel[perm[s]] = 1;
+  int64_t q = 0;
+  for (int64_t r = 0; r < m; ++r)
+    if (!is_skel[r]) slot[r] = q++;
+  double* x = (double*)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1));
+  for (int64_t r = kk; r < m; ++r) {
+    for (int64_t s = kk - 1; s >= 0; --s) {
+      double acc = Z[r * k + s];
+      for (int64_t s2 = s + 1; s2 < kk; ++s2) acc = acc - x[s2] * Z[s2 * k + s];
+      x[s] = acc;
+    }
+    double* w = Wr + slot[perm[r]] * ldw;
+    for (int64_t s = 0; s < kk; ++s) w[s] = x[s];
+  }
+  *k_out = kk;
+  free(x);
+  free(is_skel);
+  free(slot);
+  free(Z);
+  free(perm);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Probe features of the learned rank (one block).  The first 16 sketch     */
 /* vectors (FP64 stream of `seed`), LU with partial pivoting on Y^T for up  */
 /* to 16 steps (ties to the lowest column index), and after s steps the     */
