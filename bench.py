@@ -97,6 +97,8 @@ def main():
                     help="n at which the paper workload also runs b = 32 and 64")
     ap.add_argument("--cert-p", type=int, default=8,
                     help="vectors of the a-posteriori certificate of the fp32 ID (0 skips it)")
+    ap.add_argument("--rows", type=int, default=1,
+                    help="1: time the row-skeleton step (two-sided ID) on the fp32 result")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -271,6 +273,59 @@ def main():
             f"cert/||A|| = {cert['cert_rel']:.3e} (true {resid32:.3e})")
         del workc
 
+    # row skeletons of A(:, J) for the two-sided ID / CUR (a second, direct
+    # LUPP on the 50000 x k matrix C), and the two-sided ID's error
+    two_sided = None
+    if args.rows:
+        cfgr = rid.binding._cfg(rid.RID_F32, seed, True)
+        wbr = rid.rid_rows_workspace_bytes(m, k32, cfgr)
+        workr = torch.empty(wbr, dtype=torch.uint8, device=dev)
+        Jr = out32[0][:k32].contiguous()
+        Ir = torch.zeros(k32, dtype=torch.int64, device=dev)
+        Trr = torch.zeros((k32, m), dtype=torch.float32, device=dev)
+        kor = torch.zeros(1, dtype=torch.int32, device=dev)
+        sor = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def runrows():
+            rc = rid.rid_lupp_rows(A32.data_ptr(), m, n, A32.stride(0), Jr.data_ptr(), k32, cfgr,
+                                   Ir.data_ptr(), Trr.data_ptr(), m, kor.data_ptr(),
+                                   sor.data_ptr(), workr.data_ptr(), wbr, stream)
+            if rc != 0:
+                raise RuntimeError(f"rid_lupp_rows -> {rc}")
+
+        runrows()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            runrows()
+        e1.record()
+        torch.cuda.synchronize()
+        msr_rows = e0.elapsed_time(e1) / 3
+        kr = int(kor.item())
+        # W A(I, J) X in FP64 on the GPU (measurement only)
+        I = Ir[:kr]
+        rmask = torch.ones(m, dtype=torch.bool, device=dev)
+        rmask[I] = False
+        Wd = torch.zeros((m, kr), dtype=torch.float64, device=dev)
+        Wd[I] = torch.eye(kr, dtype=torch.float64, device=dev)
+        Wd[rmask] = Trr[:kr, : m - kr].double().t()
+        cmask = torch.ones(n, dtype=torch.bool, device=dev)
+        cmask[Jr] = False
+        Xd = torch.zeros((kr, n), dtype=torch.float64, device=dev)
+        Xd[:, Jr] = torch.eye(kr, dtype=torch.float64, device=dev)
+        Xd[:, cmask] = out32[1][:kr, : n - kr].double()
+        S = A32[I][:, Jr].double()
+        R = A32.double() - Wd @ (S @ Xd)
+        e_two = float(torch.linalg.vector_norm(R).item()) / fro
+        del R, Wd, Xd, S
+        torch.cuda.empty_cache()
+        two_sided = {"ms": msr_rows, "k": kr, "status": rid.status_string(int(sor.item())),
+                     "err_rel_two_sided": e_two, "err_rel_column_id": resid32}
+        log(f"[bench] row skeletons of A(:,J) ({m}x{kr}): {msr_rows:.2f} ms, two-sided ID "
+            f"error {e_two:.4e} (column ID {resid32:.4e})")
+        del workr
+
     # FP32 path with the FP64-residual refinement step on T
     refine = None
     if args.lp_steps > 0:
@@ -400,6 +455,7 @@ def main():
         "precision_forms": precision,
         "refine": refine,
         "certificate": cert,
+        "two_sided": two_sided,
         "fp64_path": fp64,
         "kernel_breakdown": breakdown,
         "roofline": roof,

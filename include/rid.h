@@ -169,6 +169,34 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
                       size_t work_bytes, hipStream_t stream);
 
 /*
+ * Row skeletons of C = A(:, J) for the two-sided ID and CUR (Sec. 2.4: with
+ * the column skeletons J found, a second, direct LUPP on the small m x k
+ * matrix C selects k rows I; Sec. 2.2: two-sided ID A ~= W A(I, J) X, with X
+ * the column interpolation matrix of J and W = C A(I, J)^{-1} the row
+ * interpolation matrix, W(I, :) = I_k).  LU with partial pivoting over the
+ * m rows (ties to the lowest row index, as for columns); with P C = [L1; L2] U,
+ * W(I^c, :) = L2 L1^{-1}.  CUR takes C = A(:, J) and R = A(I, :) from the
+ * same skeletons.
+ * Arguments: A as for rid_lupp_adaptive, stored in cfg->dtype (RID_F64 or
+ *   RID_F32; no refinement, no estimator); J (device, int64[k]), the column
+ *   skeletons, 1 <= k <= min(m, n); I (device, int64[k]) receives the row
+ *   skeletons in pivot order; Tr (device, cfg->dtype, k rows of ldtr >= m)
+ *   receives W(I^c, :)^T in the layout of T (the row ID is the column ID of
+ *   A^T): Tr(s, q) = W(q-th non-skeleton row in ascending index, s), for
+ *   s < k_out and q < m - k_out; k_out, status (device int32).
+ *   Workspace: rid_rows_workspace_bytes(m, k, cfg).
+ * Outcome (device): status RID_OK with k_out = k; RID_RANK_DEFICIENT with
+ *   k_out = the steps taken when a pivot is exactly zero (C has rank k_out);
+ *   RID_ERR_ARG when a J entry is outside [0, n) (k_out = 0, A not read
+ *   there); RID_ERR_NONFINITE when C holds a NaN or infinity.
+ * Errors (return value): RID_ERR_ARG / RID_ERR_WORKSPACE / RID_ERR_HIP.
+ */
+size_t rid_rows_workspace_bytes(int64_t m, int64_t k, const rid_config* cfg);
+int rid_lupp_rows(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
+                  const rid_config* cfg, int64_t* I, void* Tr, int64_t ldtr, int32_t* k_out,
+                  int32_t* status, void* work, size_t work_bytes, hipStream_t stream);
+
+/*
  * A-posteriori certificate of an ID (the check Remark 1 ends with, after
  * Martinsson and Tropp, 2020): with Yc = Omega_c A for the p Gaussian vectors
  * c0 .. c0+p-1 of cfg->seed's stream,

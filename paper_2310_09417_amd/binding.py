@@ -57,6 +57,10 @@ def library() -> ctypes.CDLL:
         lib.rid_lupp_adaptive.argtypes = [P, i64, i64, i64, i64, dbl, i64, cfgp, P, P, i64, P, P,
                                           P, P, sz, P]
         lib.rid_lupp_adaptive.restype = i32
+        lib.rid_rows_workspace_bytes.argtypes = [i64, i64, cfgp]
+        lib.rid_rows_workspace_bytes.restype = sz
+        lib.rid_lupp_rows.argtypes = [P, i64, i64, i64, P, i64, cfgp, P, P, i64, P, P, P, sz, P]
+        lib.rid_lupp_rows.restype = i32
         lib.rid_certificate_workspace_bytes.argtypes = [i64, i64, i64, cfgp]
         lib.rid_certificate_workspace_bytes.restype = sz
         lib.rid_certificate.argtypes = [P, i64, i64, i64, P, i64, P, i64, i64, i64, cfgp, P, P,
@@ -118,6 +122,16 @@ def rid_workspace_bytes(m, n, kmax, b, cfg: RidConfig) -> int:
 
 def rid_status_string(status: int) -> str:
     return library().rid_status_string(status).decode()
+
+
+def rid_rows_workspace_bytes(m, k, cfg: RidConfig) -> int:
+    return int(library().rid_rows_workspace_bytes(m, k, ctypes.byref(cfg)))
+
+
+def rid_lupp_rows(A, m, n, lda, J, k, cfg: RidConfig, I, Tr, ldtr, k_out, status, work,
+                  work_bytes, stream) -> int:
+    return int(library().rid_lupp_rows(A, m, n, lda, J, k, ctypes.byref(cfg), I, Tr, ldtr, k_out,
+                                       status, work, work_bytes, stream))
 
 
 def rid_certificate_workspace_bytes(m, n, p, cfg: RidConfig) -> int:
@@ -327,6 +341,42 @@ def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
                            out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
     _check(rc, "rid_lupp_adaptive")
     return out.result(n, with_est=bool(estimator))
+
+
+@dataclass
+class RowsOutput:
+    I: "object"        # int64 device tensor [k]: row skeletons, pivot order
+    Tr: "object"       # device tensor k x (m-k): W(I^c, :)^T, column q <-> q-th non-skeleton row
+    k: int
+    status: int
+
+
+def row_skeletons(A, J, work=None) -> RowsOutput:
+    """Row skeletons I of C = A(:, J) by LUPP and the row interpolation matrix
+    of the two-sided ID, A ~= W A(I, J) X (A float64 / float32, J int64 device
+    tensor of column skeletons)."""
+    torch = _torch()
+    m, n = A.shape
+    assert A.stride(1) == 1
+    cfg = _cfg(_dtype_code(A), 0)
+    k = int(J.numel())
+    wb = rid_rows_workspace_bytes(m, k, cfg)
+    if wb == 0:
+        raise RidError("invalid sizes")
+    if work is None:
+        work = _work(wb, A.device)
+    I = torch.zeros(max(k, 1), dtype=torch.int64, device=A.device)
+    Tr = torch.zeros((max(k, 1), m), dtype=A.dtype, device=A.device)
+    ko = torch.zeros(1, dtype=torch.int32, device=A.device)
+    so = torch.zeros(1, dtype=torch.int32, device=A.device)
+    Jc = J.contiguous()
+    rc = rid_lupp_rows(A.data_ptr(), m, n, A.stride(0), Jc.data_ptr(), k, cfg, I.data_ptr(),
+                       Tr.data_ptr(), m, ko.data_ptr(), so.data_ptr(), work.data_ptr(),
+                       work.numel(), _stream_ptr())
+    _check(rc, "rid_lupp_rows")
+    torch.cuda.current_stream().synchronize()
+    kk = int(ko.item())
+    return RowsOutput(I=I[:kk], Tr=Tr[:kk, : m - kk], k=kk, status=int(so.item()))
 
 
 def certificate(A, J, T, p: int, seed: int, c0: int = 1 << 30, col_scale=None,

@@ -19,6 +19,7 @@
 #include "rid_refine.hpp"
 #include "rid_mlp.hpp"
 #include "rid_resid.hpp"
+#include "rid_rows.hpp"
 
 using namespace rid;
 
@@ -294,6 +295,13 @@ bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* c
     return false;
   P.scale = cfg->a_col_scale;
   return true;
+}
+
+// Plan of the row-skeleton step: the m rows of A are the candidates, C has k
+// columns; there is no sketch (one sketch row keeps its buffers minimal).
+bool plan_rows(int64_t m, int64_t k, const rid_config* cfg, Plan& P) {
+  const int64_t wmax = std::min<int64_t>(kMaxW, std::max<int64_t>(std::min<int64_t>(k, kMaxW), 1));
+  return make_plan(1, m, k, wmax, cfg->dtype, cfg->dtype, false, 0, 0, P);
 }
 
 // Pointers into the caller's workspace.
@@ -769,6 +777,12 @@ bool valid_batched_cfg(const rid_config* cfg) {
   return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0;
 }
 
+// The row-skeleton step reads A in the factor type, with no refinement or
+// estimator.
+bool valid_rows_cfg(const rid_config* cfg) {
+  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0 && cfg->estimator == 0;
+}
+
 int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }
 
 // ---- batched path ------------------------------------------------------------
@@ -920,6 +934,69 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     k += f;
   }
   return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+}
+
+size_t rid_rows_workspace_bytes(int64_t m, int64_t k, const rid_config* cfg) {
+  if (m < 1 || k < 1 || k > m || !valid_rows_cfg(cfg)) return 0;
+  Plan P;
+  if (!plan_rows(m, k, cfg, P)) return 0;
+  return P.total;
+}
+
+int rid_lupp_rows(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
+                  const rid_config* cfg, int64_t* I, void* Tr, int64_t ldtr, int32_t* k_out,
+                  int32_t* status, void* work, size_t work_bytes, hipStream_t stream) {
+  if (!A || !J || !I || !Tr || !k_out || !status || !work || !cfg || !valid_rows_cfg(cfg))
+    return RID_ERR_ARG;
+  if (m < 1 || n < 1 || lda < n || k < 1 || k > std::min(m, n) || ldtr < m || m > INT32_MAX ||
+      n > INT32_MAX)
+    return RID_ERR_ARG;
+  if (k > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
+  Plan P;
+  if (!plan_rows(m, k, cfg, P)) return RID_ERR_HIP;
+  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  if (P.lupp_lds > kMaxLds) return RID_ERR_ARG;
+  Ws W = carve(P, work);
+  RID_TRY(init(P, W, stream));
+  const bool f64 = P.dt == RID_F64;
+  if (f64)
+    hipLaunchKernelGGL(k_gather_cols<double>, dim3((unsigned)m), dim3(256), 0, stream,
+                       static_cast<const double*>(A), lda, m, n, J, (int)k,
+                       static_cast<double*>(W.z), P.ldz, W.ctrl);
+  else
+    hipLaunchKernelGGL(k_gather_cols<float>, dim3((unsigned)m), dim3(256), 0, stream,
+                       static_cast<const float*>(A), lda, m, n, J, (int)k,
+                       static_cast<float*>(W.z), P.ldz, W.ctrl);
+  RID_LAUNCH_CHECK();
+  for (int64_t k0 = 0; k0 < k; k0 += kPanel) {
+    const int f = (int)std::min<int64_t>(kPanel, k - k0);
+    if (k0 > 0) RID_TRY(block_update(P, W, (int)k0, (int)k0, f, false, stream));
+    RID_TRY(panel(P, W, (int)k0, f, f, false, stream));
+  }
+  // Tr = W(I^c, :)^T = (L2 L1^{-1})^T: k_out rows of ldtr, column q for the
+  // q-th non-skeleton row in ascending index (the layout of T)
+  hipLaunchKernelGGL(k_nonpiv, dim3(1), dim3(1024), 0, stream, W.pos, P.n, W.nonpiv);
+  RID_LAUNCH_CHECK();
+  {
+    const long pm = prof_begin(KC_TSOLVE, stream);
+    dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(k, 64));
+    if (f64)
+      hipLaunchKernelGGL((k_tgemm<double, 0>), grid, dim3(256), 0, stream,
+                         static_cast<const double*>(W.z), P.ldz, W.nonpiv, P.n,
+                         static_cast<const double*>(W.linv), P.ldl, static_cast<double*>(Tr), ldtr,
+                         static_cast<const double*>(nullptr), (int64_t)0, W.ctrl);
+    else
+      hipLaunchKernelGGL((k_tgemm<float, 0>), grid, dim3(256), 0, stream,
+                         static_cast<const float*>(W.z), P.ldz, W.nonpiv, P.n,
+                         static_cast<const float*>(W.linv), P.ldl, static_cast<float*>(Tr), ldtr,
+                         static_cast<const float*>(nullptr), (int64_t)0, W.ctrl);
+    prof_end(pm, stream);
+    RID_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_outputs, dim3((unsigned)std::max<int64_t>(1, ceil_div(k, 256))), dim3(256),
+                     0, stream, W.ctrl, W.order, I, k_out, W.norm, status);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
 }
 
 size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const rid_config* cfg) {

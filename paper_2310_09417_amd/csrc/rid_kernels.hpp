@@ -36,6 +36,7 @@ enum : int32_t {
   ST_OK = 0,
   ST_NOT_CONVERGED = 1,
   ST_RANK_DEFICIENT = 2,
+  ST_ERR_ARG = -1,
   ST_ERR_NONFINITE = -2,
   ST_ERR_HIP = -3
 };
