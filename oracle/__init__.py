@@ -16,6 +16,7 @@ Method: Pearce, Chen, Dong, Martinsson, arXiv 2310.09417.
                               the a-posteriori certificate it closes with
   * row skeletons of A(:,J) -- Sec. 2.4 (second LUPP of CUR / two-sided ID),
                               Sec. 2.2 (two-sided ID)
+  * sparse sign embedding  -- Sec. 5, random matrix distributions (zeta = 8)
 """
 from __future__ import annotations
 
@@ -95,6 +96,13 @@ def _load():
         lib.orc_growth_scale.restype = dbl
         lib.orc_lupp_rows.argtypes = [P, i64, i64, i64, P, i64, P, P, i64, P]
         lib.orc_lupp_rows.restype = cint
+        lib.orc_omega_sparse.argtypes = [u64, i64, i64, i64, P]
+        lib.orc_omega_sparse.restype = None
+        lib.orc_sketch_sparse.argtypes = [P, i64, i64, i64, u64, i64, i64, P, i64]
+        lib.orc_sketch_sparse.restype = None
+        lib.orc_rid_lupp_emb.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
+                                         cint, P, P, i64, P, i64, ctypes.POINTER(_Result)]
+        lib.orc_rid_lupp_emb.restype = cint
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = cint
         _lib = lib
@@ -187,7 +195,7 @@ class IDResult:
 
 
 def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, estimator=0,
-         resid_p=0) -> IDResult:
+         resid_p=0, embedding=0) -> IDResult:
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
@@ -197,7 +205,11 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, est
     hist = np.zeros(hist_cap, dtype=np.float64)
     est = np.zeros((hist_cap, 3), dtype=np.float64)
     res = _Result()
-    if estimator:
+    if embedding:
+        lib.orc_rid_lupp_emb(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
+                             embedding, _ptr(J), _ptr(T), n, _ptr(hist), hist_cap,
+                             ctypes.byref(res))
+    elif estimator:
         lib.orc_rid_lupp_est(_ptr(A), m, n, n, mode, k_or_b, p, estimator, resid_p, tol,
                              1 if rel else 0, kmax, seed, _ptr(J), _ptr(T), n, _ptr(hist),
                              _ptr(est), hist_cap, ctypes.byref(res))
@@ -248,6 +260,36 @@ def rid_fixed_rank_est(A, k: int, p: int, seed: int, estimator: int) -> IDResult
     """randLUPP at rank k whose p oversampling vectors give the Remark-1
     estimates."""
     return _run(A, 0, k, p, 0.0, False, k, seed, estimator=estimator, resid_p=p)
+
+
+# Embeddings of the sketch: 0 Gaussian, 1 sparse sign (Sec. 5, zeta = 8).
+EMB_GAUSSIAN, EMB_SPARSE_SIGN = 0, 1
+SS_ZETA = 8
+
+
+def omega_sparse(seed: int, c0: int, w: int, m: int) -> np.ndarray:
+    """Sparse sign block (w x m) for the block of w vectors starting at c0."""
+    out = np.zeros((w, m))
+    _load().orc_omega_sparse(seed, c0, w, m, _ptr(out))
+    return out
+
+
+def sketch_sparse(A: np.ndarray, seed: int, c0: int, w: int) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    Y = np.zeros((w, n))
+    _load().orc_sketch_sparse(_ptr(A), m, n, n, seed, c0, w, _ptr(Y), n)
+    return Y
+
+
+def rid_adaptive_emb(A, b: int, tol: float, kmax: int, seed: int, embedding: int,
+                     relative: bool = True) -> IDResult:
+    """randLUPPadap with the blocks drawn from the given embedding."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed, embedding=embedding)
+
+
+def rid_fixed_rank_emb(A, k: int, p: int, seed: int, embedding: int) -> IDResult:
+    return _run(A, 0, k, p, 0.0, False, k, seed, embedding=embedding)
 
 
 def growth_scale(k: int) -> float:

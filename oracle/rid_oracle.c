@@ -187,6 +187,81 @@ void orc_sketch(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t see
   orc_sketch_format(A, m, n, lda, seed, c0, w, 0, Y, ldy);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Sparse sign embedding (paper Sec. 5, random matrix distributions: each    */
+/* row of the embedding carries zeta independent Rademacher entries at       */
+/* uniformly random coordinates; zeta = 8), column form: in the block of w   */
+/* sketch vectors starting at global index c0, column i (row i of A) has     */
+/* zw = min(8, w) nonzeros.  Their rows are a uniformly random zw-subset of  */
+/* the w, drawn by Floyd's algorithm: for q = 0..zw-1, j = w - zw + q,       */
+/* t = floor(u_q (j+1) / 2^32); take t unless already taken, else j.  The    */
+/* words u_0..u_7 are Philox4x32-10 with key (seed lo, seed hi) at counters  */
+/* (i, c0, SS_TAG, 0) and (i, c0, SS_TAG, 1); the sign of the q-th chosen    */
+/* row is bit q of the first word at (i, c0, SS_TAG, 2) (1 = negative).      */
+/* Values +-sqrt(w / zw), so that E[Omega^T Omega] = w I as for the unit     */
+/* Gaussian (the estimate E = ||S||_F / sqrt(w) stays unbiased).             */
+/* ------------------------------------------------------------------------ */
+#define ORC_SS_TAG 0x53534e31u /* distinct from the Gaussian stream's zero word */
+#define ORC_SS_ZETA 8
+
+static void ss_column(uint64_t seed, uint32_t i, uint32_t c0, int64_t w, int64_t* rows,
+                      int* neg, int64_t* zw_out) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t u[8], sg[4];
+  const uint32_t c_a[4] = {i, c0, ORC_SS_TAG, 0}, c_b[4] = {i, c0, ORC_SS_TAG, 1},
+                 c_s[4] = {i, c0, ORC_SS_TAG, 2};
+  orc_philox4x32_10(c_a, key, u);
+  orc_philox4x32_10(c_b, key, u + 4);
+  orc_philox4x32_10(c_s, key, sg);
+  const int64_t zw = w < ORC_SS_ZETA ? w : ORC_SS_ZETA;
+  for (int64_t q = 0; q < zw; ++q) {
+    const int64_t j = w - zw + q;
+    const int64_t t = (int64_t)(((uint64_t)u[q] * (uint64_t)(j + 1)) >> 32);
+    int taken = 0;
+    for (int64_t r = 0; r < q; ++r)
+      if (rows[r] == t) taken = 1;
+    rows[q] = taken ? j : t;
+    neg[q] = (int)((sg[0] >> q) & 1u);
+  }
+  *zw_out = zw;
+}
+
+/* Sparse sign block: out[c * m + i] = Omega(c0 + c, i) for c < w, i < m. */
+void orc_omega_sparse(uint64_t seed, int64_t c0, int64_t w, int64_t m, double* out) {
+  for (int64_t t = 0; t < w * m; ++t) out[t] = 0.0;
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t rows[ORC_SS_ZETA], zw;
+    int neg[ORC_SS_ZETA];
+    ss_column(seed, (uint32_t)i, (uint32_t)c0, w, rows, neg, &zw);
+    const double v = sqrt((double)w / (double)zw);
+    for (int64_t q = 0; q < zw; ++q) out[rows[q] * m + i] = neg[q] ? -v : v;
+  }
+}
+
+/* Sketch with the sparse sign block: Y(c, j) = sum_i Omega(c0+c, i) A(i, j). */
+void orc_sketch_sparse(const double* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                       int64_t c0, int64_t w, double* Y, int64_t ldy) {
+  double* om = (double*)malloc(sizeof(double) * (size_t)w * (size_t)m);
+  orc_omega_sparse(seed, c0, w, m, om);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t c = 0; c < w; ++c) {
+      double acc = 0.0;
+      for (int64_t i = 0; i < m; ++i) acc = acc + om[c * m + i] * A[i * lda + j];
+      Y[c * ldy + j] = acc;
+    }
+  free(om);
+}
+
+/* Sketch of a block in the chosen embedding (0 Gaussian, 1 sparse sign). */
+static void sketch_emb(int embedding, const double* A, int64_t m, int64_t n, int64_t lda,
+                       uint64_t seed, int64_t c0, int64_t w, double* Y, int64_t ldy) {
+  if (embedding == 1)
+    orc_sketch_sparse(A, m, n, lda, seed, c0, w, Y, ldy);
+  else
+    orc_sketch(A, m, n, lda, seed, c0, w, Y, ldy);
+}
+
 /* Sum of squares of A in ascending (row, column) order. */
 static double frob2(const double* A, int64_t m, int64_t n, int64_t lda, int* nonfinite) {
   double s = 0.0;
@@ -243,15 +318,25 @@ typedef struct {
 static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                          int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
-                         int64_t* J, double* T, int64_t ldt, double* E_hist, double* est_hist,
-                         int64_t hist_cap, orc_result* res);
+                         int embedding, int64_t* J, double* T, int64_t ldt, double* E_hist,
+                         double* est_hist, int64_t hist_cap, orc_result* res);
 
 int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                  int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                  uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                  int64_t hist_cap, orc_result* res) {
-  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, J,
-                       T, ldt, E_hist, NULL, hist_cap, res);
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, 0,
+                       J, T, ldt, E_hist, NULL, hist_cap, res);
+}
+
+/* Same as orc_rid_lupp with the blocks drawn from the sparse sign embedding
+ * (embedding 1) instead of the Gaussian one (0). */
+int orc_rid_lupp_emb(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                     int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
+                     uint64_t seed, int embedding, int64_t* J, double* T, int64_t ldt,
+                     double* E_hist, int64_t hist_cap, orc_result* res) {
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0,
+                       embedding, J, T, ldt, E_hist, NULL, hist_cap, res);
 }
 
 /* Same as orc_rid_lupp with the stopping estimate taken from the residual
@@ -268,7 +353,7 @@ int orc_rid_lupp_est(const double* A, int64_t m, int64_t n, int64_t lda, int mod
                      int64_t ldt, double* E_hist, double* est_hist, int64_t hist_cap,
                      orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, estimator,
-                       resid_p, J, T, ldt, E_hist, est_hist, hist_cap, res);
+                       resid_p, 0, J, T, ldt, E_hist, est_hist, hist_cap, res);
 }
 
 /* Adaptive variant whose first factored block has first_width vectors
@@ -278,8 +363,8 @@ int orc_rid_adaptive_first(const double* A, int64_t m, int64_t n, int64_t lda, i
                            int64_t first_width, double tol, int tol_relative, int64_t kmax,
                            uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                            int64_t hist_cap, orc_result* res) {
-  return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, 0, 0, J,
-                       T, ldt, E_hist, NULL, hist_cap, res);
+  return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, 0, 0, 0,
+                       J, T, ldt, E_hist, NULL, hist_cap, res);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -482,8 +567,8 @@ int orc_certificate(const double* A, int64_t m, int64_t n, int64_t lda, const in
 static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                          int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
-                         int64_t* J, double* T, int64_t ldt, double* E_hist, double* est_hist,
-                         int64_t hist_cap, orc_result* res) {
+                         int embedding, int64_t* J, double* T, int64_t ldt, double* E_hist,
+                         double* est_hist, int64_t hist_cap, orc_result* res) {
   memset(res, 0, sizeof(*res));
   res->err_est = -1.0;
   res->min_gap = INFINITY;
@@ -548,7 +633,7 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
     int64_t w = first ? first_w : later_w;
     if (w == 0) break; /* fixed rank with p = 0: no estimate */
     /* Draw the next block and apply the current row permutation (P Y^T). */
-    orc_sketch(A, m, n, lda, seed, cnext, w, Ynew, n);
+    sketch_emb(embedding, A, m, n, lda, seed, cnext, w, Ynew, n);
     cnext += w;
     for (int64_t t = 0; t < w * n; ++t)
       if (fabs(Ynew[t]) > ymax) ymax = fabs(Ynew[t]);
