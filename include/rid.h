@@ -90,7 +90,25 @@ typedef struct {
                            rank when the ID then became exact (k = min(m, n))
                            or the sketch rank-deficient; -1 each when none was
                            taken.  Pass the same cfg to rid_workspace_bytes.  */
+  int embedding;        /* rid_embedding of the sketch: RID_EMB_GAUSSIAN (the
+                           default) or RID_EMB_SPARSE_SIGN (a_type == dtype
+                           only; not on the batched path)                      */
 } rid_config;
+
+/*
+ * Random embeddings of the sketch (Sec. 5, random matrix distributions).
+ *   RID_EMB_GAUSSIAN     unit-variance Gaussian entries, a pure function of
+ *                        (seed, vector, row) (Philox4x32-10 + Box-Muller).
+ *   RID_EMB_SPARSE_SIGN  sparse sign, zeta = 8: in each draw of w vectors
+ *                        (a block of the method), column i of Omega (row i of
+ *                        A) holds min(8, w) entries +-sqrt(w / min(8, w)) at a
+ *                        uniformly random subset of the draw's w rows (Floyd
+ *                        sampling on Philox words at counter (i, first vector
+ *                        of the draw, 0x53534e31, 0..2)), so that
+ *                        E[Omega^T Omega] = w I and the estimate keeps its
+ *                        scale.  The certificate always draws Gaussian vectors.
+ */
+typedef enum { RID_EMB_GAUSSIAN = 0, RID_EMB_SPARSE_SIGN = 1 } rid_embedding;
 
 /*
  * Stopping estimates (Sec. 3.2, Remark 1).  With P the row permutation of the

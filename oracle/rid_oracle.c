@@ -617,7 +617,7 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
   double* Yr = NULL;
   if (estimator > 0 && mode == 1) {
     Yr = (double*)malloc(sizeof(double) * (size_t)resid_p * (size_t)n);
-    orc_sketch(A, m, n, lda, seed, ORC_RESID_C0, resid_p, Yr, n);
+    sketch_emb(embedding, A, m, n, lda, seed, ORC_RESID_C0, resid_p, Yr, n);
   }
   double est[3];
 

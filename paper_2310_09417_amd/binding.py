@@ -30,7 +30,7 @@ class RidConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("a_type", ctypes.c_int),
                 ("a_col_scale", ctypes.c_void_p), ("refine", ctypes.c_int),
                 ("estimator", ctypes.c_int), ("resid_p", ctypes.c_int),
-                ("est_out", ctypes.c_void_p)]
+                ("est_out", ctypes.c_void_p), ("embedding", ctypes.c_int)]
 
 
 _lib = None
@@ -103,15 +103,17 @@ def library() -> ctypes.CDLL:
 # Stopping estimates (rid_estimator): Schur estimate on the next block, and the
 # residual-triangle estimates of Remark 1 (sample Schur, normUest, maxUest).
 RID_EST_SCHUR, RID_EST_SAMPLE, RID_EST_UR_FRO, RID_EST_UR_MAX = 0, 1, 2, 3
+# Embeddings of the sketch (rid_embedding): Gaussian, sparse sign (zeta = 8).
+RID_EMB_GAUSSIAN, RID_EMB_SPARSE_SIGN = 0, 1
 
 
 def _cfg(dtype: int, seed: int, tol_relative: bool = True, a_type: int | None = None,
          col_scale: int = 0, refine: bool = False, estimator: int = 0, resid_p: int = 0,
-         est_out: int = 0) -> RidConfig:
+         est_out: int = 0, embedding: int = 0) -> RidConfig:
     return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed,
                      a_type=dtype if a_type is None else a_type, a_col_scale=col_scale or None,
                      refine=1 if refine else 0, estimator=estimator, resid_p=resid_p,
-                     est_out=est_out or None)
+                     est_out=est_out or None, embedding=embedding)
 
 
 # ---- raw C-ABI mirrors (pointers as ints) ----------------------------------
@@ -214,13 +216,14 @@ def _dtype_code(t) -> int:
 
 
 def _config_for(A, seed: int, relative: bool = True, col_scale=None, refine: bool = False,
-                estimator: int = 0, resid_p: int = 0, est_out: int = 0):
+                estimator: int = 0, resid_p: int = 0, est_out: int = 0, embedding: int = 0):
     """Config for A's storage: float64 / float32 run the whole path in that
     type; bfloat16 A, or float8_e4m3fn (or uint8 codes) A with col_scale
     (float32 device tensor, ceil(n/128) powers of two), run the sketch in that
     format and the factorisation in FP32.  Returns (cfg, dtype of T)."""
     torch = _torch()
-    ex = dict(refine=refine, estimator=estimator, resid_p=resid_p, est_out=est_out)
+    ex = dict(refine=refine, estimator=estimator, resid_p=resid_p, est_out=est_out,
+              embedding=embedding)
     if A.dtype in (torch.float64, torch.float32):
         if col_scale is not None:
             raise RidError("col_scale applies to FP8 storage only")
@@ -293,17 +296,18 @@ def _work(nbytes, device):
 
 
 def fixed_rank(A, k: int, p: int, seed: int, work=None, col_scale=None,
-               refine: bool = False, estimator: int = 0) -> IDOutput:
+               refine: bool = False, estimator: int = 0, embedding: int = 0) -> IDOutput:
     """randLUPP at rank k with p estimation vectors (A: m x n device tensor;
     BF16 / FP8 storage as described in _config_for).  estimator > 0: the p
     vectors give the Remark-1 estimates (returned in est3)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
-    cfg, tdt = _config_for(A, seed, True, col_scale, refine)
+    cfg, tdt = _config_for(A, seed, True, col_scale, refine, embedding=embedding)
     out = _Outputs(k, n, tdt, A.device)
     if estimator:
-        cfg, tdt = _config_for(A, seed, True, col_scale, refine, estimator, 0, out.est.data_ptr())
+        cfg, tdt = _config_for(A, seed, True, col_scale, refine, estimator, 0, out.est.data_ptr(),
+                               embedding)
     wb = rid_workspace_bytes(m, n, k + p, p, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
@@ -318,7 +322,7 @@ def fixed_rank(A, k: int, p: int, seed: int, work=None, col_scale=None,
 
 def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
              work=None, col_scale=None, refine: bool = False, estimator: int = 0,
-             resid_p: int = 8) -> IDOutput:
+             resid_p: int = 8, embedding: int = 0) -> IDOutput:
     """randLUPPadap with block size b, tolerance tol, rank cap kmax (BF16 /
     FP8 storage as described in _config_for).  estimator > 0 stops on a
     Remark-1 estimate from resid_p set-aside vectors (estimates in est3)."""
@@ -326,11 +330,11 @@ def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
     lda = A.stride(0)
     assert A.stride(1) == 1
     cap = min(kmax, m, n)
-    cfg, tdt = _config_for(A, seed, relative, col_scale, refine)
+    cfg, tdt = _config_for(A, seed, relative, col_scale, refine, embedding=embedding)
     out = _Outputs(cap, n, tdt, A.device)
     if estimator:
         cfg, tdt = _config_for(A, seed, relative, col_scale, refine, estimator, resid_p,
-                               out.est.data_ptr())
+                               out.est.data_ptr(), embedding)
     wb = rid_workspace_bytes(m, n, kmax, b, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
@@ -429,12 +433,13 @@ def debug_mfma_probe(kind: int, A, B):
     return D
 
 
-def debug_sketch(A, seed: int, c0: int, w: int, col_scale=None):
+def debug_sketch(A, seed: int, c0: int, w: int, col_scale=None, embedding: int = 0):
     """(Omega(c0:c0+w) A)^T as an n x w tensor, computed by the sketch kernels
-    (BF16 / FP8 storage as described in _config_for; result in FP32 then)."""
+    (BF16 / FP8 storage as described in _config_for; result in FP32 then).
+    With the sparse sign embedding the w vectors form one draw."""
     torch = _torch()
     m, n = A.shape
-    cfg, ydt = _config_for(A, seed, True, col_scale)
+    cfg, ydt = _config_for(A, seed, True, col_scale, embedding=embedding)
     wb = rid_workspace_bytes(m, n, w, w, cfg)
     work = _work(wb, A.device)
     Yt = torch.empty((n, w), dtype=ydt, device=A.device)

@@ -20,6 +20,7 @@
 #include "rid_mlp.hpp"
 #include "rid_resid.hpp"
 #include "rid_rows.hpp"
+#include "rid_sparse.hpp"
 
 using namespace rid;
 
@@ -177,6 +178,7 @@ struct Plan {
   const float* scale = nullptr;  // FP8 column-tile scales (device)
   bool refine = false;           // FP64-residual refinement step on T
   int est = 0;                   // rid_estimator of the stopping test
+  int emb = 0;                   // rid_embedding of the sketch
   int resid_p = 0;               // set-aside sample width (adaptive, est > 0)
   int64_t zr = 0;                // first Z column of the sample (adaptive, est > 0)
   int64_t zs = 0;                // first Z column of its copy that the private LU factors
@@ -293,6 +295,7 @@ bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* c
   if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, cfg->refine != 0, est,
                  sample && est > 0 ? cfg->resid_p : 0, P))
     return false;
+  P.emb = cfg->embedding;
   P.scale = cfg->a_col_scale;
   return true;
 }
@@ -368,18 +371,29 @@ Ws carve(const Plan& P, void* work) {
   } while (0)
 
 // ---- sketch dispatch -------------------------------------------------------
+// The method's draw that a launch belongs to: vectors [c0, c0 + w).  The
+// sparse sign embedding is defined per draw, the Gaussian per vector.
+struct Draw {
+  int64_t c0;
+  int w;
+};
+
 template <typename TC, int MT, int KC, bool VEC>
 int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                     int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
-                    hipStream_t st) {
+                    const Draw& dr, hipStream_t st) {
   dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
   TC* om = static_cast<TC*>(W.omega);
   const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
   long pm = prof_begin(KC_OMEGA, st);
-  hipLaunchKernelGGL(k_omega<TC>, dim3((unsigned)ceil_div(mpad / 4 * g.wp, 256)), dim3(256), 0, st,
-                     k0, k1, (uint32_t)c0, w, g.wp, P.m, mpad, om, ctrl);
+  if (P.emb == RID_EMB_SPARSE_SIGN)
+    hipLaunchKernelGGL(k_omega_ss<TC>, dim3((unsigned)ceil_div(mpad, 256)), dim3(256), 0, st, k0,
+                       k1, (uint32_t)dr.c0, dr.w, (int)(c0 - dr.c0), w, g.wp, P.m, mpad, om, ctrl);
+  else
+    hipLaunchKernelGGL(k_omega<TC>, dim3((unsigned)ceil_div(mpad / 4 * g.wp, 256)), dim3(256), 0,
+                       st, k0, k1, (uint32_t)c0, w, g.wp, P.m, mpad, om, ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   pm = prof_begin(KC_SKETCH, st);
@@ -399,24 +413,28 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
 template <typename TC, int KC, bool VEC>
 int launch_sketch_mt(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                      int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
-                     hipStream_t st) {
+                     const Draw& dr, hipStream_t st) {
   switch (g.mt) {
-    case 1: return launch_sketch_t<TC, 1, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
-    case 2: return launch_sketch_t<TC, 2, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
-    default: return launch_sketch_t<TC, 4, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+    case 1:
+      return launch_sketch_t<TC, 1, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, dr, st);
+    case 2:
+      return launch_sketch_t<TC, 2, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, dr, st);
+    default:
+      return launch_sketch_t<TC, 4, KC, VEC>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, dr, st);
   }
 }
 
 template <typename TC, int KC>
 int launch_sketch(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                   int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
-                  hipStream_t st) {
+                  const Draw& dr, hipStream_t st) {
   // vector loads of NQ consecutive entries need lda % NQ == 0 and a base
   // aligned to 16 bytes (FP32: one 16-byte load; FP64: 16-byte pairs)
   constexpr int NQ = SketchShape<TC>::NQ;
   const bool vec = (lda % NQ == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
-  return vec ? launch_sketch_mt<TC, KC, true>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st)
-             : launch_sketch_mt<TC, KC, false>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, st);
+  return vec ? launch_sketch_mt<TC, KC, true>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, dr, st)
+             : launch_sketch_mt<TC, KC, false>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, dr,
+                                               st);
 }
 
 template <int FMT, bool NORM>
@@ -482,8 +500,10 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
     }
     SketchGeom g = sketch_geom(P.m, P.n, wc, P.dt, P.cu);
     int rc = (P.dt == RID_F64)
-                 ? launch_sketch<double, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st)
-                 : launch_sketch<float, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl, st);
+                 ? launch_sketch<double, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl,
+                                             Draw{c0, w}, st)
+                 : launch_sketch<float, 32>(P, W, A, lda, seed, c0 + off, wc, g, norm, use_ctrl,
+                                            Draw{c0, w}, st);
     if (rc != RID_OK) return rc;
     const long pm = prof_begin(KC_REDUCE, st);
     if (P.dt == RID_F64)
@@ -765,6 +785,9 @@ int init_est_out(double* est_out, hipStream_t st) {
 bool valid_cfg(const rid_config* cfg) {
   if (!cfg || (cfg->dtype != RID_F64 && cfg->dtype != RID_F32)) return false;
   if (cfg->estimator < RID_EST_SCHUR || cfg->estimator > RID_EST_UR_MAX) return false;
+  if (cfg->embedding != RID_EMB_GAUSSIAN && cfg->embedding != RID_EMB_SPARSE_SIGN) return false;
+  // the low-precision sketch generates Gaussian entries inside its kernel
+  if (cfg->embedding == RID_EMB_SPARSE_SIGN && cfg->a_type != cfg->dtype) return false;
   if (cfg->a_type != cfg->dtype) {
     if (cfg->dtype != RID_F32 || !low_precision(cfg->a_type)) return false;
     if (cfg->a_type == RID_FP8_E4M3 && !cfg->a_col_scale) return false;
@@ -774,7 +797,8 @@ bool valid_cfg(const rid_config* cfg) {
 
 // The batched path reads A in the factor type only.
 bool valid_batched_cfg(const rid_config* cfg) {
-  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0;
+  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0 &&
+         cfg->embedding == RID_EMB_GAUSSIAN;
 }
 
 // The row-skeleton step reads A in the factor type, with no refinement or
@@ -855,11 +879,12 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
   Ws W = carve(P, work);
   RID_TRY(init(P, W, stream));
   RID_TRY(init_est_out(cfg->estimator > 0 ? cfg->est_out : nullptr, stream));
-  // one pass per <= 128 sketch vectors: all k + p vectors up front
-  for (int64_t c = 0; c < k + p; c += P.wmax) {
-    const int w = (int)std::min<int64_t>(P.wmax, k + p - c);
-    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, c, w, W.z, P.ldz, (int)c, c == 0, true, stream));
-  }
+  // all k + p vectors up front, as two draws of the method (k for the
+  // pivots, p for the estimate); each sketch launch covers <= 64 vectors
+  RID_TRY(sketch_block(P, W, A, lda, cfg->seed, 0, (int)k, W.z, P.ldz, 0, true, true, stream));
+  if (p > 0)
+    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, k, (int)p, W.z, P.ldz, (int)k, false, true,
+                         stream));
   for (int64_t k0 = 0; k0 < k; k0 += kPanel) {
     const int f = (int)std::min<int64_t>(kPanel, k - k0);
     if (k0 > 0) RID_TRY(block_update(P, W, (int)k0, (int)k0, f, false, stream));
@@ -1003,6 +1028,7 @@ size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const ri
   if (m < 1 || n < 1 || p < 1 || p > kCertPMax || !valid_cfg(cfg)) return 0;
   rid_config c = *cfg;
   c.estimator = 0;
+  c.embedding = RID_EMB_GAUSSIAN;  // the certificate draws Gaussian vectors
   Plan P;
   if (!plan_for(m, n, p, p, &c, P)) return 0;
   return P.total;
@@ -1018,6 +1044,7 @@ int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int6
     return RID_ERR_ARG;
   rid_config c = *cfg;
   c.estimator = 0;
+  c.embedding = RID_EMB_GAUSSIAN;  // the certificate draws Gaussian vectors
   Plan P;
   if (!plan_for(m, n, p, p, &c, P)) return RID_ERR_HIP;
   if (work_bytes < P.total) return RID_ERR_WORKSPACE;
