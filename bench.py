@@ -130,10 +130,10 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     kcap = min(kmax, m, n)
 
-    def make_run(A, dtype_code, a_type=None, col_scale=None, refine=False):
+    def make_run(A, dtype_code, a_type=None, col_scale=None, refine=False, embedding=0):
         cfg = rid.binding._cfg(dtype_code, seed, True, a_type=a_type,
                                col_scale=col_scale.data_ptr() if col_scale is not None else 0,
-                               refine=refine)
+                               refine=refine, embedding=embedding)
         wb = rid.rid_workspace_bytes(m, n, kmax, b, cfg)
         work = torch.empty(wb, dtype=torch.uint8, device=dev)
         J = torch.zeros(kcap, dtype=torch.int64, device=dev)
@@ -346,6 +346,31 @@ def main():
             f"(unrefined {resid32:.4e})")
         del runr, outr
 
+    # the same FP32 decomposition drawn from the sparse sign embedding (zeta =
+    # 8): same MFMA sketch kernel, Omega tiles from the sparse generator
+    sparse = None
+    if args.lp_steps > 0:
+        runs_, outs_, _ = make_run(A32, rid.RID_F32, embedding=rid.RID_EMB_SPARSE_SIGN)
+        runs_()
+        torch.cuda.synchronize()
+        rid.rid_profile_start()
+        t0 = time.perf_counter()
+        for _ in range(args.lp_steps):
+            runs_()
+        torch.cuda.synchronize()
+        mss = (time.perf_counter() - t0) * 1e3 / args.lp_steps
+        profs = rid.rid_profile_stop()
+        ks = int(outs_[2].item())
+        rs = true_resid(A32, outs_[0][:ks], outs_[1]) / fro
+        sparse = {"ms_per_step": mss, "k": ks, "status": rid.status_string(int(outs_[4].item())),
+                  "err_est_rel": float(outs_[3].item()) / fro, "resid_rel_true": rs,
+                  "resid_rel_true_gaussian": resid32,
+                  "omega_ms_per_step": profs["omega"][0] / args.lp_steps,
+                  "omega_ms_per_step_gaussian": prof["omega"][0] / args.steps}
+        log(f"[bench] fp32 sparse sign: {mss:.2f} ms/step, k={ks}, resid {rs:.4e} "
+            f"(gaussian {resid32:.4e}), generator {sparse['omega_ms_per_step']:.3f} ms/step")
+        del runs_, outs_
+
     # precision forms: A stored in BF16 / FP8-e4m3 (per-128-column power-of-two
     # scale), sketch on matrix cores with FP32 accumulation, FP32 factorisation
     precision = {}
@@ -455,6 +480,7 @@ def main():
         "precision_forms": precision,
         "refine": refine,
         "certificate": cert,
+        "sparse_sign": sparse,
         "two_sided": two_sided,
         "fp64_path": fp64,
         "kernel_breakdown": breakdown,
