@@ -244,7 +244,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   }
   P.part_bytes = pb;
   P.fro_count = fc;
-  P.schur_wgs = ceil_div(n, 64);
+  P.schur_wgs = ceil_div(n, 16);  // most Schur workgroups of any launch (16 rows each)
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -523,6 +523,18 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
 }
 
 // ---- block update: U2 (triangular solve) then S (Schur GEMM) --------------
+// Column groups of a Schur launch for a block of w columns: split the
+// workgroup's waves over columns when 64-row workgroups would leave the chip
+// under-filled (fewer than 512 of them, two waves per SIMD).
+int schur_cg(const Plan& P, int w) {
+  const int nt = (w + 15) / 16;
+  if (ceil_div(P.n, 64) >= 512 || nt < 2) return 1;
+  if (ceil_div(P.n, 32) >= 512 || nt < 4) return 2;
+  return 4;
+}
+// Workgroups (and FP64 norm partials) of that launch.
+int64_t schur_parts(const Plan& P, int w) { return ceil_div(P.n, 64 / schur_cg(P, w)); }
+
 // kb > 0 (the Remark-1 sample only): the columns already hold the Schur
 // complement for the first kb pivots and are reduced by pivots kb..k-1.
 template <typename TF>
@@ -545,28 +557,44 @@ int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, b
   }
   prof_end(pm, st);
   pm = prof_begin(KC_SCHUR, st);
-  const int nt = (w + 15) / 16;
-  dim3 grid((unsigned)P.schur_wgs);
-#define RID_SCHUR(NTV)                                                                          \
-  if (kb > 0)                                                                                   \
-    hipLaunchKernelGGL((k_schur<TF, NTV, true>), grid, dim3(256), 0, st, static_cast<TF*>(W.z), \
-                       P.ldz, P.n, W.pos, kb, k, zcol, w, static_cast<const TF*>(W.u2t), P.ldu, \
-                       W.norm, W.ctrl, norm ? 1 : 0);                                           \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_schur<TF, NTV>), grid, dim3(256), 0, st, static_cast<TF*>(W.z),       \
-                       P.ldz, P.n, W.pos, 0, k, zcol, w, static_cast<const TF*>(W.u2t), P.ldu,  \
-                       W.norm, W.ctrl, norm ? 1 : 0)
-  switch (nt) {
-    case 1: RID_SCHUR(1); break;
-    case 2: RID_SCHUR(2); break;
-    case 3: RID_SCHUR(3); break;
-    case 4: RID_SCHUR(4); break;
-    case 5: RID_SCHUR(5); break;
-    case 6: RID_SCHUR(6); break;
-    case 7: RID_SCHUR(7); break;
-    default: RID_SCHUR(8); break;
+  const int cg = schur_cg(P, w);
+  const int nt = ((w + 15) / 16 + cg - 1) / cg;  // column tiles per wave
+  dim3 grid((unsigned)schur_parts(P, w));
+#define RID_SCHUR(NTV, CGV)                                                                   \
+  hipLaunchKernelGGL((k_schur<TF, NTV, false, CGV>), grid, dim3(256), 0, st,                  \
+                     static_cast<TF*>(W.z), P.ldz, P.n, W.pos, 0, k, zcol, w,                 \
+                     static_cast<const TF*>(W.u2t), P.ldu, W.norm, W.ctrl, norm ? 1 : 0)
+#define RID_SCHUR_FROM(NTV)                                                                   \
+  hipLaunchKernelGGL((k_schur<TF, NTV, true, 1>), grid, dim3(256), 0, st,                     \
+                     static_cast<TF*>(W.z), P.ldz, P.n, W.pos, kb, k, zcol, w,                \
+                     static_cast<const TF*>(W.u2t), P.ldu, W.norm, W.ctrl, norm ? 1 : 0)
+  if (kb > 0) {
+    // the Remark-1 sample only (w <= 16, one column group)
+    if (cg != 1 || nt != 1) return RID_ERR_ARG;
+    RID_SCHUR_FROM(1);
+  } else if (cg == 4) {
+    if (nt == 1) RID_SCHUR(1, 4); else RID_SCHUR(2, 4);
+  } else if (cg == 2) {
+    switch (nt) {
+      case 1: RID_SCHUR(1, 2); break;
+      case 2: RID_SCHUR(2, 2); break;
+      case 3: RID_SCHUR(3, 2); break;
+      default: RID_SCHUR(4, 2); break;
+    }
+  } else {
+    switch (nt) {
+      case 1: RID_SCHUR(1, 1); break;
+      case 2: RID_SCHUR(2, 1); break;
+      case 3: RID_SCHUR(3, 1); break;
+      case 4: RID_SCHUR(4, 1); break;
+      case 5: RID_SCHUR(5, 1); break;
+      case 6: RID_SCHUR(6, 1); break;
+      case 7: RID_SCHUR(7, 1); break;
+      default: RID_SCHUR(8, 1); break;
+    }
   }
 #undef RID_SCHUR
+#undef RID_SCHUR_FROM
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;
@@ -580,7 +608,7 @@ int block_update(const Plan& P, const Ws& W, int k, int zcol, int w, bool norm, 
 
 int estimate(const Plan& P, const Ws& W, int w, double tol, int rel, int k, bool fixed,
              hipStream_t st) {
-  hipLaunchKernelGGL(k_estimate, dim3(1), dim3(256), 0, st, W.ctrl, W.norm, (int)P.schur_wgs, w,
+  hipLaunchKernelGGL(k_estimate, dim3(1), dim3(256), 0, st, W.ctrl, W.norm, (int)schur_parts(P, w), w,
                      tol, rel, k, (int)P.kcap, fixed ? 1 : 0);
   RID_LAUNCH_CHECK();
   return RID_OK;
@@ -690,7 +718,7 @@ int resid_estimate_body(const Plan& P, const Ws& W, int kb, int k, int p, bool a
   RID_TRY(zero_xwords(P, W, st));
   RID_TRY(panel_state_t<TF>(P, W, zcol, p, f, false, W.pos_r, W.order_r, W.ctrl_r, st));
   hipLaunchKernelGGL(k_resid_est<TF>, dim3(1), dim3(256), 0, st, W.ctrl, W.ctrl_r, W.order_r,
-                     static_cast<const TF*>(W.z), P.ldz, zcol, p, W.norm, (int)P.schur_wgs, P.n,
+                     static_cast<const TF*>(W.z), P.ldz, zcol, p, W.norm, (int)schur_parts(P, p), P.n,
                      P.est, tol, rel, (int)P.kcap, adaptive ? 0 : 1, est_out);
   RID_LAUNCH_CHECK();
   return RID_OK;

@@ -90,7 +90,10 @@ __device__ __forceinline__ void load4(const TF* p, int64_t base, int kidx, int k
 }
 
 // FROM: K starts at kb (else at 0; the kb argument is then ignored).
-template <typename TF, int NT, bool FROM = false>
+// CG: the four waves cover 64/CG rows and CG groups of NT column tiles (wave
+// = row group * CG + column group), so narrow matrices still fill the chip;
+// every output keeps the same K order, whatever CG.
+template <typename TF, int NT, bool FROM = false, int CG = 1>
 __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, int64_t n,
                                                const int* __restrict__ pos, int kb, int k, int zcol,
                                                int w, const TF* __restrict__ U2T, int64_t ldu,
@@ -101,7 +104,8 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
   using acc_t = typename M::acc_t;
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t rbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t rbase = (int64_t)blockIdx.x * (64 / CG) + (wave / CG) * 16;
+  const int col0 = (wave % CG) * NT * 16;
   const int64_t arow = rbase + (lane & 15);
   const bool arow_ok = arow < n;
   acc_t acc[NT];
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
     load4<TF, FROM>(Z, arow * ldz, kidx, kb, k, arow_ok, o.a4);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int col = t * 16 + (lane & 15);
+      const int col = col0 + t * 16 + (lane & 15);
       load4<TF, FROM>(U2T, (int64_t)col * ldu, kidx, kb, k, col < w, o.b4[t]);
     }
   };
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
   double ss = 0.0;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int col = t * 16 + (lane & 15);
+    const int col = col0 + t * 16 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = rbase + M::row(lane, r);
