@@ -83,19 +83,32 @@ def test_estimator_runs_its_own_kernels(torch, rid, orc):
     assert p1["resid_est"][1] > 0 and p0["resid_est"][1] == 0
 
 
-@pytest.mark.parametrize("tol,rel_s,rel_u", [(1e-3, 0.05, 0.25), (1e-4, 0.5, 0.5)])
-def test_adaptive_estimator_fp32(torch, rid, orc, tol, rel_s, rel_u):
-    """FP32: same status, rank within one block, and the estimates close to
-    the oracle's on the same FP32-rounded input.  S_r is formed by
-    cancellation: its entries (about E sqrt(p) / sqrt(p (n-k)), 2e-5 at
-    tol 1e-4 here) come from sketch entries near 0.17 minus k ~ 300 products,
-    so FP32 rounding (u = 6e-8, times sqrt(k) and the size of U2) puts a few
-    percent of error on them at 1e-4 and ten times less at 1e-3.  The error
-    spread over all (n-k) p entries adds to ||S_r||_F and reaches the later
-    elimination steps of U_r (measured at 1e-4: 7-25% on the sample estimate,
-    2-28% on the triangle estimates), so the strict bounds are checked at
-    1e-3 and only agreement within 50% at 1e-4, where the stopping decision
-    itself (status, rank) still matches."""
+def _fp32_schur_floor(orc, A, J, seed, p):
+    """FP32 rounding floor of ||S_r||_F / sqrt(p): S_r = Y_r(rest) - L2 U2
+    cancels the products L2 U2 against Y_r, so its rounding error is about
+    u32 sqrt(k) || |L2| |U2| ||_F (the factors formed here in FP64 from the
+    oracle's sketch: L2 L1^{-1} = Y^T(rest) Y^T(J)^{-1}, U2 = L1^{-1} Y_r^T(J))."""
+    import scipy.linalg as sl
+    n, k = A.shape[1], len(J)
+    Y = orc.sketch(A, seed, 0, k).T
+    Yr = orc.sketch(A, seed, orc.RESID_C0, p).T
+    rest = np.setdiff1d(np.arange(n), J)
+    _, L1, U1 = sl.lu(Y[J])
+    L2 = Y[rest] @ np.linalg.inv(U1)
+    U2 = sl.solve_triangular(L1, Yr[J], lower=True, unit_diagonal=True)
+    prod = np.abs(L2) @ np.abs(U2)
+    return 2.0 ** -24 * math.sqrt(k) * np.linalg.norm(prod) / math.sqrt(p)
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-4])
+def test_adaptive_estimator_fp32(torch, rid, orc, tol):
+    """FP32: same status and rank as the oracle on the same FP32-rounded
+    input (the stopping decision), and the estimates within the FP32 floor
+    of S_r derived from the factors (_fp32_schur_floor; measured 1.3x that
+    floor at 1e-3, where it is 10% of the estimate): the sample estimate
+    within 4 floors, the triangle estimates within a relative error of 8
+    times the floor-to-estimate ratio (U_r takes p more elimination steps on
+    the perturbed S_r)."""
     m, n, b, p = 1500, 1000, 32, 8
     A, _ = workloads.fast_decay(m, n, decades=8.0, seed=31)
     A32 = A.astype(np.float32).astype(np.float64)
@@ -107,9 +120,11 @@ def test_adaptive_estimator_fp32(torch, rid, orc, tol, rel_s, rel_u):
         assert g.status == o.status
         assert abs(g.k - o.k) <= b
         if g.k == o.k:
-            assert _close(g.est3[0], o.est3[0], rel_s), (g.est3, o.est3)
-            assert _close(g.est3[1], o.est3[1], rel_u), (g.est3, o.est3)
-            assert _close(g.est3[2], o.est3[2], rel_u), (g.est3, o.est3)
+            floor = _fp32_schur_floor(orc, A32, o.J, 3, p)
+            assert _close(g.est3[0], o.est3[0], 0.0, 4 * floor), (g.est3, o.est3, floor)
+            rel = min(1.0, 8 * floor / o.est3[0])
+            assert _close(g.est3[1], o.est3[1], rel), (g.est3, o.est3, floor)
+            assert _close(g.est3[2], o.est3[2], rel), (g.est3, o.est3, floor)
 
 
 @pytest.mark.parametrize("est", [1, 2, 3])
