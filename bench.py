@@ -560,6 +560,32 @@ def bench_paper(args, torch, rid, workloads):
                 del R, mask
             log(f"[bench] paper workload n={n} b={b} tol={tol:g} est={est}: {ms:.2f} ms, k={k}, "
                 f"{r['status']}, E={E:.2e}, {r['gflops']:.0f} GFLOP/s")
+            if b == 128 and est == 0 and 0 < k < n:
+                # the paper's non-adaptive comparison: randLUPP at the rank
+                # the adaptive run found (one block of k vectors, no estimate)
+                cfgf = rid.binding._cfg(rid.RID_F64, args.seed, False)
+                wbf = rid.rid_workspace_bytes(n, n, k, 0, cfgf)
+                workf = torch.empty(wbf, dtype=torch.uint8, device=dev)
+
+                def runf():
+                    rc = rid.rid_lupp_fixed_rank(A.data_ptr(), n, n, n, k, 0, cfgf, J.data_ptr(),
+                                                 T.data_ptr(), n, ko.data_ptr(), eo.data_ptr(),
+                                                 so.data_ptr(), workf.data_ptr(), wbf, stream)
+                    if rc != 0:
+                        raise RuntimeError(f"rid_lupp_fixed_rank -> {rc}")
+
+                runf()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.paper_steps):
+                    runf()
+                e1.record()
+                torch.cuda.synchronize()
+                r["fixed_rank_ms"] = e0.elapsed_time(e1) / args.paper_steps
+                log(f"[bench]   randLUPP at k={k} (non-adaptive): {r['fixed_rank_ms']:.2f} ms "
+                    f"(adaptive / fixed {ms / r['fixed_rank_ms']:.2f})")
+                del workf
             if b == 128:
                 # time split over kernel classes, from one more (untimed) call
                 rid.rid_profile_start()
