@@ -111,3 +111,25 @@ def test_sparse_rejected_where_unsupported(torch, rid):
     A = torch.zeros((64, 64), dtype=torch.bfloat16, device="cuda")
     with pytest.raises(rid.RidError):
         rid.adaptive(A, 8, 1e-3, 64, 1, embedding=rid.RID_EMB_SPARSE_SIGN)
+
+
+def test_config_validation(torch, rid):
+    """Workspace queries reject what the calls reject: an unknown estimator or
+    embedding, the sparse sign on BF16 storage, a certificate sample over 32,
+    a row-skeleton rank above m; and accept the valid forms."""
+    b = rid.binding
+    ok = b._cfg(rid.RID_F32, 1)
+    assert rid.rid_workspace_bytes(1000, 500, 64, 16, ok) > 0
+    assert rid.rid_workspace_bytes(1000, 500, 64, 16, b._cfg(rid.RID_F32, 1, estimator=4)) == 0
+    assert rid.rid_workspace_bytes(1000, 500, 64, 16, b._cfg(rid.RID_F32, 1, embedding=2)) == 0
+    assert rid.rid_workspace_bytes(1000, 500, 64, 16, b._cfg(rid.RID_F32, 1, embedding=1)) > 0
+    bf = b._cfg(rid.RID_F32, 1, a_type=rid.RID_BF16, embedding=1)
+    assert rid.rid_workspace_bytes(1000, 500, 64, 16, bf) == 0
+    assert rid.rid_certificate_workspace_bytes(1000, 500, 32, ok) > 0
+    assert rid.rid_certificate_workspace_bytes(1000, 500, 33, ok) == 0
+    assert rid.rid_rows_workspace_bytes(1000, 64, ok) > 0
+    assert rid.rid_rows_workspace_bytes(50, 64, ok) == 0
+    # a sample-estimate workspace is at least the plain one (extra Z columns)
+    est = b._cfg(rid.RID_F32, 1, estimator=2, resid_p=8)
+    assert rid.rid_workspace_bytes(1000, 500, 64, 16, est) >= \
+        rid.rid_workspace_bytes(1000, 500, 64, 16, ok)
