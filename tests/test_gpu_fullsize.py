@@ -86,3 +86,67 @@ def test_first_pivots_match_oracle(setup, orc):
     upto = q if o.min_gap > 1e-4 else o.min_gap_step
     assert upto >= 1
     assert list(J[:upto]) == list(o.J[:upto])
+
+
+def _true_rel(torch, A32, J, T):
+    mask = torch.ones(N, dtype=torch.bool, device="cuda")
+    mask[J] = False
+    Ad = A32.double()
+    R = Ad[:, mask] - Ad[:, J] @ T.double()
+    return float(torch.linalg.vector_norm(R)) / float(torch.linalg.vector_norm(Ad))
+
+
+def test_certificate_full_size(setup):
+    """The a-posteriori certificate (8 fresh Gaussian vectors) of the full-size
+    ID: cert^2 is unbiased for the squared error and, with the residual's
+    energy spread over thousands of directions, concentrates well within a
+    factor 1.5 of it."""
+    torch, rid, A32, sig, g = setup
+    cert = rid.certificate(A32, g.J, g.T.contiguous(), 8, SEED)
+    fro = float(torch.linalg.vector_norm(A32.double()))
+    true = _true_rel(torch, A32, g.J, g.T)
+    assert 0.67 <= (cert / fro) / true <= 1.5
+
+
+def test_row_skeletons_full_size(setup, orc):
+    """Row skeletons of C = A(:, J) (50000 x 2048): the first 16 row pivots
+    depend only on C's first 16 columns, so the oracle's LUPP of those gives
+    them; the two-sided ID's error stays within the FP32 floor of forming
+    W = C A(I,J)^{-1} above the column ID's."""
+    torch, rid, A32, sig, g = setup
+    r = rid.row_skeletons(A32, g.J)
+    assert (r.status, r.k) == (rid.RID_OK, KMAX)
+    I = r.I
+    C16 = A32[:, g.J[:16]].double().cpu().numpy()
+    st, I_o, _ = orc.lupp_rows(C16, np.arange(16))
+    assert st == 0 and np.array_equal(I[:16].cpu().numpy(), I_o)
+    fro = float(torch.linalg.vector_norm(A32.double()))
+    rmask = torch.ones(M, dtype=torch.bool, device="cuda")
+    rmask[I] = False
+    W = torch.zeros((M, KMAX), dtype=torch.float64, device="cuda")
+    W[I] = torch.eye(KMAX, dtype=torch.float64, device="cuda")
+    W[rmask] = r.Tr.double().t()
+    cmask = torch.ones(N, dtype=torch.bool, device="cuda")
+    cmask[g.J] = False
+    X = torch.zeros((KMAX, N), dtype=torch.float64, device="cuda")
+    X[:, g.J] = torch.eye(KMAX, dtype=torch.float64, device="cuda")
+    X[:, cmask] = g.T.double()
+    R = A32.double() - W @ (A32[I][:, g.J].double() @ X)
+    e2 = float(torch.linalg.vector_norm(R)) / fro
+    del R
+    e1 = _true_rel(torch, A32, g.J, g.T)
+    floor = 4 * 2.0 ** -24 * float(torch.linalg.vector_norm(W)) * \
+        float(torch.linalg.vector_norm(X)) / math.sqrt(KMAX)
+    assert e1 <= e2 <= e1 + floor, (e1, e2, floor)
+
+
+def test_sparse_sign_full_size(setup):
+    """The sparse sign embedding at full size: the spectrum forces the same
+    outcome (NOT_CONVERGED at kmax), and the ID's error is within 10% of the
+    Gaussian run's."""
+    torch, rid, A32, sig, g = setup
+    s = rid.adaptive(A32, B, TOL, KMAX, seed=SEED, embedding=rid.RID_EMB_SPARSE_SIGN)
+    assert s.status == rid.RID_NOT_CONVERGED and s.k == KMAX
+    e_s = _true_rel(torch, A32, s.J, s.T)
+    e_g = _true_rel(torch, A32, g.J, g.T)
+    assert e_s <= 1.1 * e_g
