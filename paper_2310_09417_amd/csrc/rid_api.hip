@@ -182,7 +182,7 @@ struct Plan {
   int resid_p = 0;               // set-aside sample width (adaptive, est > 0)
   int64_t zr = 0;                // first Z column of the sample (adaptive, est > 0)
   int64_t zs = 0;                // first Z column of its copy that the private LU factors
-  int64_t ldz = 0, ldu = 0, ldl = 0;
+  int64_t ldz = 0, ldu = 0, ldl = 0, ldg = 0;
   int cu = 0;
   int lupp_g = 0, lupp_rows = 0;
   size_t lupp_lds = 0;
@@ -192,7 +192,7 @@ struct Plan {
   size_t xwords_end = 0;  // end of the panel exchange words (zeroed per call)
   size_t o_ctrl, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
       o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, o_posr, o_orderr,
-      o_ctrlr, total;
+      o_ctrlr, o_ytop, total;
 };
 
 // est > 0: a Remark-1 stopping estimate; sample_cols > 0 (adaptive calls)
@@ -258,6 +258,9 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.o_nonpiv = take((size_t)n * 4);
   P.o_z = take((size_t)n * P.ldz * es);
   P.o_u2t = take((size_t)wmax * P.ldu * es);
+  // the block's pivot rows, gathered for the U2 product (kcap x ldg)
+  P.ldg = (int64_t)align_up((size_t)std::max<int64_t>(wmax, kResidPMax), 4);
+  P.o_ytop = take((size_t)kcap * P.ldg * es);
   P.o_part = take(P.part_bytes);
   P.o_fro = take(P.fro_count * 8);
   P.o_norm = take((size_t)P.schur_wgs * 8);
@@ -316,6 +319,7 @@ struct Ws {
   int* nonpiv;
   void* z;
   void* u2t;
+  void* ytop;
   double* part;
   double* fro;
   double* norm;
@@ -342,6 +346,7 @@ Ws carve(const Plan& P, void* work) {
   w.nonpiv = reinterpret_cast<int*>(b + P.o_nonpiv);
   w.z = b + P.o_z;
   w.u2t = b + P.o_u2t;
+  w.ytop = b + P.o_ytop;
   w.part = reinterpret_cast<double*>(b + P.o_part);
   w.fro = reinterpret_cast<double*>(b + P.o_fro);
   w.norm = reinterpret_cast<double*>(b + P.o_norm);
@@ -542,9 +547,13 @@ int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, b
                    hipStream_t st) {
   long pm = prof_begin(KC_TRSM, st);
   if (k > kb) {
-    hipLaunchKernelGGL(k_u2<TF>, dim3((unsigned)ceil_div(k - kb, 16), (unsigned)ceil_div(w, 64)),
+    hipLaunchKernelGGL(k_gather_top<TF>, dim3((unsigned)ceil_div((int64_t)(k - kb) * w, 256)),
                        dim3(256), 0, st, static_cast<const TF*>(W.z), P.ldz, W.order, kb, k, zcol,
-                       w, static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
+                       w, static_cast<TF*>(W.ytop), P.ldg, W.ctrl);
+    RID_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_u2<TF>, dim3((unsigned)ceil_div(k - kb, 16), (unsigned)ceil_div(w, 64)),
+                       dim3(256), 0, st, static_cast<const TF*>(W.ytop), P.ldg, kb, k, w,
+                       static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
                        W.ctrl);
     RID_LAUNCH_CHECK();
   }

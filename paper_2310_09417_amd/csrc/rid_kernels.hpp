@@ -885,14 +885,28 @@ __device__ __forceinline__ void wg_tile_ksplit(const TF* arow, BRow brow, int kb
   }
 }
 
-// U2 = L1^{-1} (P Y)(0:k, block) for the w block columns starting at zcol.
-// kb > 0: only rows kb..k-1 of U2, from the diagonal block of L1^{-1} on those
-// rows (the block's pivot rows kb.. already hold its Schur complement for the
-// first kb pivots).  Grid (ceil((k-kb)/16), ceil(w/64)); output U2T (w x ldu,
-// column-major U2).
+// (P Y)(kb:k, block): the block's pivot rows gathered into G (row p =
+// Z(order[p], zcol .. zcol+w), pitch ldg, 16-byte aligned), so that the U2
+// product reads its B operand without an index load per row.
 template <typename TF>
-__global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ Z, int64_t ldz,
-                                            const int* __restrict__ order, int kb, int k, int zcol,
+__global__ __launch_bounds__(256) void k_gather_top(const TF* __restrict__ Z, int64_t ldz,
+                                                    const int* __restrict__ order, int kb, int k,
+                                                    int zcol, int w, TF* __restrict__ G,
+                                                    int64_t ldg, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(k - kb) * w) return;
+  const int p = kb + (int)(t / w), c = (int)(t % w);
+  G[(int64_t)p * ldg + c] = Z[(int64_t)order[p] * ldz + zcol + c];
+}
+
+// U2 = L1^{-1} (P Y)(0:k, block) for the w block columns, (P Y)(0:k) gathered
+// in G (k_gather_top).  kb > 0: only rows kb..k-1 of U2, from the diagonal
+// block of L1^{-1} on those rows (the block's pivot rows kb.. already hold its
+// Schur complement for the first kb pivots).  Grid (ceil((k-kb)/16),
+// ceil(w/64)); output U2T (w x ldu, column-major U2).
+template <typename TF>
+__global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ G, int64_t ldg, int kb, int k,
                                             int w, const TF* __restrict__ Linv, int64_t ldl,
                                             TF* __restrict__ U2T, int64_t ldu, const Ctrl* ctrl) {
   if (ctrl->done) return;
@@ -902,7 +916,7 @@ __global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ Z, int64_t ld
   const int i = i0 + (lane & 15);
   const TF* arow = (i < k) ? Linv + (int64_t)i * ldl : nullptr;
   const int bcols = (w - j0 < 64) ? w - j0 : 64;
-  auto brow = [&](int p) -> const TF* { return Z + (int64_t)order[p] * ldz + zcol + j0; };
+  auto brow = [&](int p) -> const TF* { return G + (int64_t)p * ldg + j0; };
   const int ke = (i0 + 16 < k) ? i0 + 16 : k;  // lower triangular: p <= i
   wg_tile_ksplit<TF>(arow, brow, kb, ke, bcols, red);
   for (int t = threadIdx.x; t < 16 * 64; t += 256) {
