@@ -62,6 +62,63 @@ DeviceInfo device_info() {
 
 inline size_t esize(rid_dtype t) { return t == RID_F64 ? 8 : 4; }
 
+// ---- a second stream for work off the critical path --------------------------
+// The growth of L1^{-1} after a panel is needed only by the next block's U2
+// product, not by its sketch, so the adaptive loop runs it on a second stream
+// (default priority) forked from the caller's stream by an event and joined
+// back before that product.  Sets of (stream, fork event, join event) come from
+// a per-process pool; a call holds one set while it enqueues, so calls from
+// different host threads never share events.  Without a set (creation failed,
+// pool exhausted) the work stays on the caller's stream.
+struct SideSet {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int dev = -1;
+  bool busy = false;
+};
+std::mutex side_mu;
+SideSet side_pool[32];
+
+class SideLease {
+ public:
+  SideLease() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(side_mu);
+    for (SideSet& e : side_pool)
+      if (!e.busy && e.dev == dev) {
+        e.busy = true;
+        set_ = &e;
+        return;
+      }
+    for (SideSet& e : side_pool)
+      if (e.dev < 0) {
+        if (hipStreamCreateWithFlags(&e.s, hipStreamNonBlocking) != hipSuccess) return;
+        if (hipEventCreateWithFlags(&e.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e.join, hipEventDisableTiming) != hipSuccess) {
+          (void)hipGetLastError();
+          return;  // the stream stays unused; this slot is not handed out
+        }
+        e.dev = dev;
+        e.busy = true;
+        set_ = &e;
+        return;
+      }
+  }
+  ~SideLease() {
+    if (!set_) return;
+    std::lock_guard<std::mutex> lk(side_mu);
+    set_->busy = false;
+  }
+  SideLease(const SideLease&) = delete;
+  SideLease& operator=(const SideLease&) = delete;
+  SideSet* get() const { return set_; }
+  bool pending = false;  // forked work not yet joined
+
+ private:
+  SideSet* set_ = nullptr;
+};
+
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
 enum KClass {
   KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA,
@@ -684,6 +741,36 @@ int linv_update_t(const Plan& P, const Ws& W, int k0, int f, hipStream_t st) {
   return RID_OK;
 }
 
+// The caller's stream waits for the work forked to the side stream.
+int side_join(SideLease& side, hipStream_t st) {
+  if (!side.pending) return RID_OK;
+  side.pending = false;
+  return hipStreamWaitEvent(st, side.get()->join, 0) == hipSuccess ? RID_OK : RID_ERR_HIP;
+}
+
+// Panel on the caller's stream, then the growth of L1^{-1} forked to the side
+// stream (on the caller's stream when there is none).  The caller joins
+// before anything reads L1^{-1}.
+int panel_fork(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full, hipStream_t st,
+               SideLease& side) {
+  int rc = P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, stop_full, st)
+                           : panel_t<float>(P, W, zcol, w, f, stop_full, st);
+  if (rc != RID_OK) return rc;
+  SideSet* ss = side.get();
+  if (!ss)
+    return P.dt == RID_F64 ? linv_update_t<double>(P, W, zcol, f, st)
+                           : linv_update_t<float>(P, W, zcol, f, st);
+  RID_TRY(side_join(side, st));  // at most one forked update at a time
+  if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->s, ss->fork, 0) != hipSuccess)
+    return RID_ERR_HIP;
+  rc = P.dt == RID_F64 ? linv_update_t<double>(P, W, zcol, f, ss->s)
+                       : linv_update_t<float>(P, W, zcol, f, ss->s);
+  if (rc != RID_OK) return rc;
+  if (hipEventRecord(ss->join, ss->s) != hipSuccess) return RID_ERR_HIP;
+  side.pending = true;
+  return RID_OK;
+}
+
 int panel(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full,
           hipStream_t st) {
   int rc = P.dt == RID_F64 ? panel_t<double>(P, W, zcol, w, f, stop_full, st)
@@ -959,9 +1046,9 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
   RID_TRY(init(P, W, stream));
   const int w0 = (int)std::min<int64_t>(b, kcap);
   RID_TRY(sketch_block(P, W, A, lda, cfg->seed, 0, w0, W.z, P.ldz, 0, true, true, stream));
-  RID_TRY(panel(P, W, 0, w0, w0, true, stream));
   int64_t k = w0, cnext = w0;
   if (est > 0) {
+    RID_TRY(panel(P, W, 0, w0, w0, true, stream));
     // Remark 1: the sample is drawn once; every factored block is followed
     // by the estimate of its rank, and no block is drawn only to measure
     const int p = cfg->resid_p;
@@ -984,17 +1071,22 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     }
     return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
   }
+  // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch
+  SideLease side;
+  RID_TRY(panel_fork(P, W, 0, w0, w0, true, stream, side));
   while (k < mn) {
     RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false, true,
                          stream));
     cnext += b;
+    RID_TRY(side_join(side, stream));
     RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, true, stream));
     RID_TRY(estimate(P, W, (int)b, tol, cfg->tol_relative, (int)k, false, stream));
     if (k >= kcap) break;
     const int f = (int)std::min<int64_t>(b, kcap - k);
-    RID_TRY(panel(P, W, (int)k, (int)b, f, true, stream));
+    RID_TRY(panel_fork(P, W, (int)k, (int)b, f, true, stream, side));
     k += f;
   }
+  RID_TRY(side_join(side, stream));
   return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
 }
 
