@@ -1048,27 +1048,40 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
   RID_TRY(sketch_block(P, W, A, lda, cfg->seed, 0, w0, W.z, P.ldz, 0, true, true, stream));
   int64_t k = w0, cnext = w0;
   if (est > 0) {
-    RID_TRY(panel(P, W, 0, w0, w0, true, stream));
     // Remark 1: the sample is drawn once; every factored block is followed
-    // by the estimate of its rank, and no block is drawn only to measure
+    // by the estimate of its rank, and no block is drawn only to measure.
+    // The next block is sketched while L1^{-1} grows on the side stream (a
+    // pass that is wasted only when the estimate then stops the call).
     const int p = cfg->resid_p;
+    SideLease side;
     RID_TRY(init_est_out(cfg->est_out, stream));
+    RID_TRY(panel_fork(P, W, 0, w0, w0, true, stream, side));
     RID_TRY(sketch_block(P, W, A, lda, cfg->seed, kResidC0, p, W.z, P.ldz, (int)P.zr, false, true,
                          stream));
-    RID_TRY(resid_estimate(P, W, 0, (int)k, p, true, tol, cfg->tol_relative, cfg->est_out,
-                           stream));
-    while (k < kcap) {
+    if (k < kcap) {
       RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false,
                            true, stream));
       cnext += b;
+    }
+    RID_TRY(side_join(side, stream));
+    RID_TRY(resid_estimate(P, W, 0, (int)k, p, true, tol, cfg->tol_relative, cfg->est_out,
+                           stream));
+    while (k < kcap) {
       RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, false, stream));
       const int f = (int)std::min<int64_t>(b, kcap - k);
-      RID_TRY(panel(P, W, (int)k, (int)b, f, true, stream));
+      RID_TRY(panel_fork(P, W, (int)k, (int)b, f, true, stream, side));
       const int64_t k0 = k;
       k += f;
+      if (k < kcap) {
+        RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false,
+                             true, stream));
+        cnext += b;
+      }
+      RID_TRY(side_join(side, stream));
       RID_TRY(resid_estimate(P, W, (int)k0, (int)k, p, true, tol, cfg->tol_relative,
                              cfg->est_out, stream));
     }
+    RID_TRY(side_join(side, stream));
     return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
   }
   // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch
