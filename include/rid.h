@@ -20,6 +20,12 @@
  *  - The caller owns every buffer, including the device workspace `work` of
  *    at least rid_workspace_bytes(...) bytes, exclusively for the duration of
  *    the call.  The library allocates nothing.
+ *  - Besides device memory, the library keeps a small per-process pool of HIP
+ *    streams and events (default priority, created on first use on a device,
+ *    kept until the process ends).  The adaptive calls fork independent work
+ *    (the growth of L1^{-1}) from `stream` to one of those streams and join it
+ *    back by events before returning, so all of a call's work is ordered
+ *    before any later work on `stream`; this also holds under stream capture.
  *  - Calls are asynchronous on `stream` and never synchronize with the host.
  *    The return value reports only argument / workspace / launch errors that
  *    the host can see.  The numerical outcome (rank, estimate, status) is
