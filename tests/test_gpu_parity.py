@@ -273,3 +273,36 @@ def test_adaptive_fp32_paper_timing_workload_b128(torch, rid, orc):
     floor32 = 4.0 * 2.0**-24 * np.linalg.norm(A32) * np.linalg.norm(T_g)
     assert res_g <= 1.25 * res_o + floor32
     assert g.status != rid.RID_OK or (res_g <= 1e-4 and g.err_est <= 1e-4)
+
+
+def test_concurrent_calls_match_sequential(torch, rid):
+    """Two host threads, each on its own stream, run adaptive decompositions
+    at the same time: every call forks its L1^-1 growth to a pooled side
+    stream of its own, and the results equal the sequential ones bit for
+    bit (FP64)."""
+    import threading
+    mats = [workloads.fast_decay(1500, 1000, decades=10.0, seed=s)[0] for s in (1, 2)]
+    dev = [_dev(torch, A, torch.float64) for A in mats]
+    seq = [rid.adaptive(d, 64, 1e-7, 1000, 5) for d in dev]
+    seq = [(g.J.cpu().numpy(), g.T.cpu().numpy(), g.k, g.status) for g in seq]
+    out = [None, None]
+
+    def work(i):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            res = []
+            for _ in range(3):
+                g = rid.adaptive(dev[i], 64, 1e-7, 1000, 5)
+                res.append((g.J.cpu().numpy(), g.T.cpu().numpy(), g.k, g.status))
+            out[i] = res
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for i in range(2):
+        assert out[i] is not None
+        for J, T, k, st in out[i]:
+            assert (k, st) == (seq[i][2], seq[i][3])
+            assert np.array_equal(J, seq[i][0]) and np.array_equal(T, seq[i][1])
