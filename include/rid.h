@@ -129,7 +129,7 @@ typedef enum { RID_EMB_GAUSSIAN = 0, RID_EMB_SPARSE_SIGN = 1 } rid_embedding;
  *   RID_EST_UR_MAX  gamma(k) sqrt(nr) max |U_r(i, j)|    (eq. maxUest; may
  *                   under-estimate, as the remark notes)
  * Adaptive calls draw the p sample vectors once (stream indices 2^31 + j of
- * the seed's Gaussian stream) and take the estimate of the current rank after
+ * the seed's stream, in the call's embedding) and take the estimate of the current rank after
  * every factored block, so no block is drawn only to be measured; the rank
  * returned is the first block edge whose estimate meets the tolerance.
  * Fixed-rank calls use their p oversampling vectors as the sample.  The LU of

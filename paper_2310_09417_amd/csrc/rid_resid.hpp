@@ -18,7 +18,8 @@
 namespace rid {
 
 // Stream index of the first set-aside vector (vectors 2^31 .. 2^31 + p - 1 of
-// the seed's Gaussian stream; the decomposition itself draws fewer than 2^31).
+// the seed's stream, in the call's embedding; the decomposition itself draws
+// fewer than 2^31).
 constexpr int64_t kResidC0 = int64_t(1) << 31;
 constexpr int kResidPMax = 16;
 constexpr int kCertPMax = 32;  // widest certificate sample
@@ -142,10 +143,10 @@ __global__ __launch_bounds__(256) void k_cert_mark(const int64_t* __restrict__ J
   if (s >= k) return;
   const int64_t j = J[s];
   if (j < 0 || j >= n) {
-    ctrl->status = ST_ERR_HIP;
+    ctrl->status = ST_ERR_ARG;
     return;
   }
-  if (atomicCAS(pos + j, -1, (int)s) != -1) ctrl->status = ST_ERR_HIP;
+  if (atomicCAS(pos + j, -1, (int)s) != -1) ctrl->status = ST_ERR_ARG;
 }
 
 // Partial sums of the certificate: thread q (one non-skeleton column, in
