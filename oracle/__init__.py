@@ -86,7 +86,8 @@ def _load():
                                                P, P, i64, P, i64, ctypes.POINTER(_Result)]
         lib.orc_rid_adaptive_first.restype = cint
         lib.orc_rid_lupp_est.argtypes = [P, i64, i64, i64, cint, i64, i64, cint, i64, dbl, cint,
-                                         i64, u64, P, P, i64, P, P, i64, ctypes.POINTER(_Result)]
+                                         i64, u64, cint, P, P, i64, P, P, i64,
+                                         ctypes.POINTER(_Result)]
         lib.orc_rid_lupp_est.restype = cint
         lib.orc_resid_triangle.argtypes = [P, i64, i64, i64, i64, i64, u64, i64, i64, P, P, P]
         lib.orc_resid_triangle.restype = cint
@@ -205,14 +206,14 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, est
     hist = np.zeros(hist_cap, dtype=np.float64)
     est = np.zeros((hist_cap, 3), dtype=np.float64)
     res = _Result()
-    if embedding:
+    if embedding and not estimator:
         lib.orc_rid_lupp_emb(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
                              embedding, _ptr(J), _ptr(T), n, _ptr(hist), hist_cap,
                              ctypes.byref(res))
     elif estimator:
         lib.orc_rid_lupp_est(_ptr(A), m, n, n, mode, k_or_b, p, estimator, resid_p, tol,
-                             1 if rel else 0, kmax, seed, _ptr(J), _ptr(T), n, _ptr(hist),
-                             _ptr(est), hist_cap, ctypes.byref(res))
+                             1 if rel else 0, kmax, seed, embedding, _ptr(J), _ptr(T), n,
+                             _ptr(hist), _ptr(est), hist_cap, ctypes.byref(res))
     elif first_w > 0:
         lib.orc_rid_adaptive_first(_ptr(A), m, n, n, k_or_b, first_w, tol, 1 if rel else 0, kmax,
                                    seed, _ptr(J), _ptr(T), n, _ptr(hist), hist_cap,
@@ -249,11 +250,12 @@ RESID_C0 = 1 << 31   # stream index of the first set-aside vector
 
 
 def rid_adaptive_est(A, b: int, tol: float, kmax: int, seed: int, estimator: int, resid_p: int,
-                     relative: bool = True) -> IDResult:
+                     relative: bool = True, embedding: int = 0) -> IDResult:
     """randLUPPadap stopped by a residual-triangle estimate (Remark 1): the
     resid_p sample vectors are drawn once and the estimate of the rank-k ID
-    is taken after every factored block."""
-    return _run(A, 1, b, 0, tol, relative, kmax, seed, estimator=estimator, resid_p=resid_p)
+    is taken after every factored block (all draws from `embedding`)."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed, estimator=estimator, resid_p=resid_p,
+                embedding=embedding)
 
 
 def rid_fixed_rank_est(A, k: int, p: int, seed: int, estimator: int) -> IDResult:

@@ -346,14 +346,15 @@ int orc_rid_lupp_emb(const double* A, int64_t m, int64_t n, int64_t lda, int mod
  * estimate of the current rank is taken after every factored block, so no
  * block is drawn only to be measured.  Fixed-rank mode: the p oversampling
  * vectors are the sample.  est_hist receives the three estimates of every
- * step (3 entries per step). */
+ * step (3 entries per step).  embedding: 0 Gaussian, 1 sparse sign (the
+ * sample is drawn from the same embedding). */
 int orc_rid_lupp_est(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                      int64_t k_or_b, int64_t p, int estimator, int64_t resid_p, double tol,
-                     int tol_relative, int64_t kmax, uint64_t seed, int64_t* J, double* T,
-                     int64_t ldt, double* E_hist, double* est_hist, int64_t hist_cap,
+                     int tol_relative, int64_t kmax, uint64_t seed, int embedding, int64_t* J,
+                     double* T, int64_t ldt, double* E_hist, double* est_hist, int64_t hist_cap,
                      orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, estimator,
-                       resid_p, 0, J, T, ldt, E_hist, est_hist, hist_cap, res);
+                       resid_p, embedding, J, T, ldt, E_hist, est_hist, hist_cap, res);
 }
 
 /* Adaptive variant whose first factored block has first_width vectors

@@ -133,3 +133,18 @@ def test_config_validation(torch, rid):
     est = b._cfg(rid.RID_F32, 1, estimator=2, resid_p=8)
     assert rid.rid_workspace_bytes(1000, 500, 64, 16, est) >= \
         rid.rid_workspace_bytes(1000, 500, 64, 16, ok)
+
+
+def test_sparse_with_estimator_fp64(torch, rid, orc):
+    """A Remark-1 estimator on the sparse sign embedding (the sample drawn
+    from it too): same ID and estimates as the oracle."""
+    A, _ = workloads.fast_decay(1200, 800, decades=10.0, seed=17)
+    o = orc.rid_adaptive_est(A, 32, 1e-7, 800, 3, orc.EST_UR_FRO, 8,
+                             embedding=orc.EMB_SPARSE_SIGN)
+    g = rid.adaptive(_dev(torch, A, torch.float64), 32, 1e-7, 800, 3, estimator=2, resid_p=8,
+                     embedding=rid.RID_EMB_SPARSE_SIGN)
+    check_fp64(A, g.J.cpu().numpy(), g.T.cpu().numpy(), g.k, g.status, g.err_est, o, 32)
+    if g.k == o.k and np.array_equal(g.J.cpu().numpy(), o.J):
+        floor = 64 * 2.0 ** -53 * o.fro_a * math.sqrt(800)
+        for i in range(3):
+            assert abs(g.est3[i] - o.est3[i]) <= 1e-7 * o.est3[i] + floor

@@ -97,3 +97,23 @@ def test_sparse_adaptive_quality(orc):
     res = orc.true_residual(A, r.J, r.T)
     assert res <= 3e-6 * r.fro_a
     assert 0.3 <= r.err_est / res <= 3.0
+
+
+def test_sparse_estimator_mode_keeps_pivots(orc):
+    """Remark-1 estimates on the sparse sign embedding: the blocks are the
+    same draws as the plain sparse method's, so its pivots are a prefix of
+    that method's, and the sample estimate of the final rank equals the
+    solve-route Schur estimate of the sparse sample vectors."""
+    m, n, b, p, seed = 400, 260, 16, 8, 7
+    A, _ = workloads.fast_decay(m, n, decades=10.0, seed=5)
+    r = orc.rid_adaptive_est(A, b, 1e-6, n, seed, orc.EST_SAMPLE, p,
+                             embedding=orc.EMB_SPARSE_SIGN)
+    full = orc.rid_adaptive_emb(A, b, 0.0, n, seed, orc.EMB_SPARSE_SIGN)
+    assert r.status == orc.OK
+    assert np.array_equal(r.J, full.J[: r.k])
+    # the sketch of the first k vectors, draw by draw (blocks of b)
+    Y = np.vstack([orc.sketch_sparse(A, seed, c, b) for c in range(0, r.k, b)]).T
+    Yr = orc.sketch_sparse(A, seed, orc.RESID_C0, p).T
+    rest = np.setdiff1d(np.arange(n), r.J)
+    S = Yr[rest] - Y[rest] @ np.linalg.solve(Y[r.J], Yr[r.J])
+    assert abs(r.est3[0] - np.linalg.norm(S) / math.sqrt(p)) <= 1e-7 * r.est3[0]
