@@ -227,3 +227,18 @@ def test_certificate_fp32_and_edges(torch, rid, orc):
     assert rid.certificate(Ad64, Jbad, T2, 8, 6) == -1.0
     Jbad = torch.tensor([3, 500], dtype=torch.int64, device="cuda")
     assert rid.certificate(Ad64, Jbad, T2, 8, 6) == -1.0
+
+
+def test_certificate_bf16_storage(torch, rid, orc):
+    """Certificate of an ID of a BF16-stored matrix: the sketch multiplies in
+    BF16 with the Gaussian entries rounded to BF16 (relative change <= 2^-9
+    per entry, the same draw), so it matches the oracle's FP64 certificate of
+    the decoded matrix within 2%."""
+    A, _ = workloads.fast_decay(1500, 900, decades=4.0, seed=23)
+    Ab = torch.tensor(A, dtype=torch.bfloat16, device="cuda")
+    g = rid.adaptive(Ab, 32, 1e-2, 900, 4)
+    c_gpu = rid.certificate(Ab, g.J, g.T.contiguous(), 8, 4)
+    Adec = Ab.float().double().cpu().numpy()
+    c_orc = orc.certificate(Adec, g.J.cpu().numpy(), g.T.cpu().numpy().astype(np.float64), 4,
+                            1 << 30, 8)
+    assert _close(c_gpu, c_orc, 0.02), (c_gpu, c_orc)
