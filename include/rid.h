@@ -26,6 +26,8 @@
  *    (the growth of L1^{-1}) from `stream` to one of those streams and join it
  *    back by events before returning, so all of a call's work is ordered
  *    before any later work on `stream`; this also holds under stream capture.
+ *    After hipDeviceReset the pooled streams are gone and the adaptive calls
+ *    return RID_ERR_HIP.
  *  - Calls are asynchronous on `stream` and never synchronize with the host.
  *    The return value reports only argument / workspace / launch errors that
  *    the host can see.  The numerical outcome (rank, estimate, status) is
