@@ -85,7 +85,8 @@ def main():
     ap.add_argument("--cpu-kmax", type=int, default=64,
                     help="rank cap of the bounded oracle sample")
     ap.add_argument("--batched", action="store_true",
-                    help="also time the 4096-block batched workload (off: see DESIGN.md)")
+                    help="also time the 4096-block batched workload (off by default: its FP32 "
+                         "batches beyond one block per compute unit are refused)")
     ap.add_argument("--nblk", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--learned-blocks", type=int, default=1536,
