@@ -360,6 +360,11 @@ bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* c
   return true;
 }
 
+// FP64 partials of the certificate products: kCertSplitMax ranges x p x n.
+size_t cert_part_bytes(int64_t n, int64_t p) {
+  return align_up((size_t)kCertSplitMax * (size_t)p * (size_t)n * 8, kAlign);
+}
+
 // Plan of the row-skeleton step: the m rows of A are the candidates, C has k
 // columns; there is no sketch (one sketch row keeps its buffers minimal).
 bool plan_rows(int64_t m, int64_t k, const rid_config* cfg, Plan& P) {
@@ -1167,13 +1172,14 @@ int rid_lupp_rows(const void* A, int64_t m, int64_t n, int64_t lda, const int64_
 }
 
 size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const rid_config* cfg) {
+  // the sketch's plan, then the FP64 partials of the split certificate products
   if (m < 1 || n < 1 || p < 1 || p > kCertPMax || !valid_cfg(cfg)) return 0;
   rid_config c = *cfg;
   c.estimator = 0;
   c.embedding = RID_EMB_GAUSSIAN;  // the certificate draws Gaussian vectors
   Plan P;
   if (!plan_for(m, n, p, p, &c, P)) return 0;
-  return P.total;
+  return align_up(P.total, kAlign) + cert_part_bytes(n, p);
 }
 
 int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
@@ -1189,8 +1195,9 @@ int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int6
   c.embedding = RID_EMB_GAUSSIAN;  // the certificate draws Gaussian vectors
   Plan P;
   if (!plan_for(m, n, p, p, &c, P)) return RID_ERR_HIP;
-  if (work_bytes < P.total) return RID_ERR_WORKSPACE;
+  if (work_bytes < align_up(P.total, kAlign) + cert_part_bytes(n, p)) return RID_ERR_WORKSPACE;
   Ws W = carve(P, work);
+  double* cpart = reinterpret_cast<double*>(static_cast<char*>(work) + align_up(P.total, kAlign));
   const unsigned gn = (unsigned)ceil_div(n, 256);
   hipLaunchKernelGGL(k_cert_clear, dim3(gn), dim3(256), 0, stream, W.pos, n, W.ctrl);
   RID_LAUNCH_CHECK();
@@ -1204,19 +1211,31 @@ int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int6
   hipLaunchKernelGGL(k_nonpiv, dim3(1), dim3(1024), 0, stream, W.pos, n, W.nonpiv);
   RID_LAUNCH_CHECK();
   const int64_t nr = n - k;
-  // partials: one per 256 non-skeleton columns, in the Schur partials' buffer
-  // (ceil(n/64) entries)
+  // squared residual sums: one per 256 non-skeleton columns, in the Schur
+  // partials' buffer (ceil(n/16) entries)
   const int nparts = (int)std::max<int64_t>(1, ceil_div(nr, 256));
   const bool f64 = P.dt == RID_F64;
   if (nr > 0) {
-    if (f64)
-      hipLaunchKernelGGL((k_cert<double, kCertPMax>), dim3((unsigned)nparts), dim3(256), 0, stream,
-                         static_cast<const double*>(W.z), P.ldz, (int)p, J, k, W.nonpiv, n,
-                         static_cast<const double*>(T), ldt, W.norm, W.ctrl);
-    else
-      hipLaunchKernelGGL((k_cert<float, kCertPMax>), dim3((unsigned)nparts), dim3(256), 0, stream,
-                         static_cast<const float*>(W.z), P.ldz, (int)p, J, k, W.nonpiv, n,
-                         static_cast<const float*>(T), ldt, W.norm, W.ctrl);
+    // skeleton ranges of about 128 each, so that the products fill the chip
+    const int S = (int)std::max<int64_t>(1, std::min<int64_t>(kCertSplitMax, ceil_div(k, 128)));
+    dim3 gp((unsigned)nparts, (unsigned)S);
+    if (f64) {
+      hipLaunchKernelGGL((k_cert<double, kCertPMax>), gp, dim3(256), 0, stream,
+                         static_cast<const double*>(W.z), P.ldz, (int)p, J, k, nr,
+                         static_cast<const double*>(T), ldt, cpart, W.ctrl);
+      RID_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_cert_resid<double>, dim3((unsigned)nparts), dim3(256), 0, stream,
+                         static_cast<const double*>(W.z), P.ldz, (int)p, W.nonpiv, nr, cpart, S,
+                         W.norm, W.ctrl);
+    } else {
+      hipLaunchKernelGGL((k_cert<float, kCertPMax>), gp, dim3(256), 0, stream,
+                         static_cast<const float*>(W.z), P.ldz, (int)p, J, k, nr,
+                         static_cast<const float*>(T), ldt, cpart, W.ctrl);
+      RID_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_cert_resid<float>, dim3((unsigned)nparts), dim3(256), 0, stream,
+                         static_cast<const float*>(W.z), P.ldz, (int)p, W.nonpiv, nr, cpart, S,
+                         W.norm, W.ctrl);
+    }
     RID_LAUNCH_CHECK();
   } else {
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, stream, W.norm, 1, 0.0);

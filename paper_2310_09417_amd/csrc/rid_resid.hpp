@@ -22,7 +22,8 @@ namespace rid {
 // fewer than 2^31).
 constexpr int64_t kResidC0 = int64_t(1) << 31;
 constexpr int kResidPMax = 16;
-constexpr int kCertPMax = 32;  // widest certificate sample
+constexpr int kCertPMax = 32;    // widest certificate sample
+constexpr int kCertSplitMax = 16;  // skeleton ranges of the certificate products
 
 // Before the sample's factorisation at rank k: copy Z(:, src .. src+p) to
 // Z(:, dst .. dst+p) when src >= 0, the pivot map into pos_r, and the control
@@ -149,29 +150,30 @@ __global__ __launch_bounds__(256) void k_cert_mark(const int64_t* __restrict__ J
   if (atomicCAS(pos + j, -1, (int)s) != -1) ctrl->status = ST_ERR_ARG;
 }
 
-// Partial sums of the certificate: thread q (one non-skeleton column, in
-// ascending index) forms r_c = Yc(c, J^c[q]) - sum_s Yc(c, J[s]) T(s, q) for
-// c < p (FP64, s ascending) and the workgroup sums r_c^2 (fixed order).
-// The k x p block Yc(:, J)^T is staged through LDS 64 rows at a time.  Yt is
-// Yc^T (n rows of ldy).
+// Certificate products, split over skeleton ranges: workgroup (x, z) takes
+// 256 non-skeleton columns q (ascending index) and the z-th of S ranges of
+// the skeletons, and leaves part[(z * p + c) * nr + q] = sum over s in the
+// range of Yc(c, J[s]) T(s, q) (FP64, s ascending).  The range's rows of
+// Yc(:, J)^T are staged through LDS 64 at a time.  Yt is Yc^T (n rows of ldy).
 template <typename TF, int PMAX>
 __global__ __launch_bounds__(256) void k_cert(const TF* __restrict__ Yt, int64_t ldy, int p,
                                               const int64_t* __restrict__ J, int64_t k,
-                                              const int* __restrict__ nonpiv, int64_t n,
-                                              const TF* __restrict__ T, int64_t ldt,
+                                              int64_t nr, const TF* __restrict__ T, int64_t ldt,
                                               double* __restrict__ part, const Ctrl* ctrl) {
   if (ctrl->status != ST_OK) return;
   __shared__ double yj[64][PMAX + 1];
-  __shared__ double red[256];
   const int tid = threadIdx.x;
-  const int64_t nr = n - k;
   const int64_t q = (int64_t)blockIdx.x * 256 + tid;
   const bool live = q < nr;
+  const int S = gridDim.y;
+  const int64_t per = (k + S - 1) / S;
+  const int64_t sb = (int64_t)blockIdx.y * per;
+  const int64_t se = (sb + per < k) ? sb + per : k;
   double acc[PMAX];
 #pragma unroll
   for (int c = 0; c < PMAX; ++c) acc[c] = 0.0;
-  for (int64_t s0 = 0; s0 < k; s0 += 64) {
-    const int cnt = (int)((k - s0 < 64) ? k - s0 : 64);
+  for (int64_t s0 = sb; s0 < se; s0 += 64) {
+    const int cnt = (int)((se - s0 < 64) ? se - s0 : 64);
     __syncthreads();
     for (int t = tid; t < cnt * p; t += 256) {
       const int ss = t / p, c = t % p;
@@ -186,15 +188,34 @@ __global__ __launch_bounds__(256) void k_cert(const TF* __restrict__ Yt, int64_t
           if (c < p) acc[c] += yj[ss][c] * tv;
       }
   }
-  double r2 = 0.0;
-  if (live) {
-    const TF* yr = Yt + (int64_t)nonpiv[q] * ldy;
+  if (live)
 #pragma unroll
     for (int c = 0; c < PMAX; ++c)
-      if (c < p) {
-        const double r = (double)yr[c] - acc[c];
-        r2 += r * r;
-      }
+      if (c < p) part[((int64_t)blockIdx.y * p + c) * nr + q] = acc[c];
+}
+
+// Residuals of the certificate: thread q sums its S range partials (range
+// order), forms r_c = Yc(c, J^c[q]) - that sum for c < p, and the workgroup
+// leaves the sum of r_c^2 (fixed order) in sq[blockIdx.x].
+template <typename TF>
+__global__ __launch_bounds__(256) void k_cert_resid(const TF* __restrict__ Yt, int64_t ldy,
+                                                    int p, const int* __restrict__ nonpiv,
+                                                    int64_t nr, const double* __restrict__ part,
+                                                    int S, double* __restrict__ sq,
+                                                    const Ctrl* ctrl) {
+  if (ctrl->status != ST_OK) return;
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * 256 + tid;
+  double r2 = 0.0;
+  if (q < nr) {
+    const TF* yr = Yt + (int64_t)nonpiv[q] * ldy;
+    for (int c = 0; c < p; ++c) {
+      double a = 0.0;
+      for (int z = 0; z < S; ++z) a += part[((int64_t)z * p + c) * nr + q];
+      const double r = (double)yr[c] - a;
+      r2 += r * r;
+    }
   }
   red[tid] = r2;
   __syncthreads();
@@ -202,7 +223,7 @@ __global__ __launch_bounds__(256) void k_cert(const TF* __restrict__ Yt, int64_t
     if (tid < off) red[tid] += red[tid + off];
     __syncthreads();
   }
-  if (tid == 0) part[blockIdx.x] = red[0];
+  if (tid == 0) sq[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_cert_reduce(const double* __restrict__ part, int nparts,
