@@ -940,25 +940,18 @@ int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }
 
 // ---- batched path ------------------------------------------------------------
 struct BPlan {
-  int64_t ldz = 0, ldl = 0, ldu = 0;
-  size_t slice = 0, total = 0;
+  rid::BLayout L{};
+  size_t total = 0;
   int G = 0;
 };
 
 bool bplan(int32_t maxn, int32_t maxk, int32_t b, rid_dtype dt, BPlan& P) {
   DeviceInfo di = device_info();
   if (!di.ok) return false;
-  const size_t es = esize(dt);
-  P.ldz = (int64_t)align_up((size_t)maxk + (size_t)std::max<int32_t>(b, 64), 4);
-  P.ldl = (int64_t)align_up((size_t)maxk, 64);
-  P.ldu = (int64_t)align_up((size_t)maxk, 16);
-  auto a = [](size_t x) { return align_up(x, kAlign); };
-  // same sequence as the slice carving in k_batched
-  P.slice = a((size_t)maxn * P.ldz * es) + a((size_t)maxk * P.ldl * es) +
-            a((size_t)kBPW * P.ldl * es) + a((size_t)64 * P.ldu * es) + a((size_t)maxn * 4) +
-            a((size_t)(maxk + 64) * 4) + a((size_t)maxn * 4);
+  // the same layout function gives the kernel its slice carving
+  P.L = rid::batched_layout(maxn, maxk, b, (int64_t)esize(dt), 0);
   P.G = di.cu;
-  P.total = kAlign + (size_t)P.G * P.slice;
+  P.total = kAlign + (size_t)P.G * (size_t)P.L.slice;
   return true;
 }
 
@@ -1317,13 +1310,11 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
   if (cfg->dtype == RID_F64)
     hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
                        b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
-                       err_est, status, passes, order, queue, base, P.slice, max_n, maxk, P.ldz,
-                       P.ldl, P.ldu);
+                       err_est, status, passes, order, queue, base, P.L, max_n, maxk);
   else
     hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
                        b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
-                       err_est, status, passes, order, queue, base, P.slice, max_n, maxk, P.ldz,
-                       P.ldl, P.ldu);
+                       err_est, status, passes, order, queue, base, P.L, max_n, maxk);
   prof_end(pm, stream);
   RID_LAUNCH_CHECK();
   return RID_OK;

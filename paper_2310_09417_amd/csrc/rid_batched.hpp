@@ -15,7 +15,7 @@
 // estimates it (w0 + b vectors, in passes of at most 64), saving one pass over
 // every block.
 #pragma once
-#include "rid_kernels.hpp"
+#include "rid_tile.hpp"
 
 namespace rid {
 
@@ -251,6 +251,42 @@ struct BSlice {
   int* nonpiv;  // maxn
 };
 
+// Leading dimensions and byte offsets of one workgroup's slice, computed once
+// on the host and handed to the kernel, so that the host's workspace size and
+// the kernel's carving come from the same arithmetic.  Every part starts on a
+// 256-byte boundary; `gap` extra bytes follow each part (zero for the GPU; a
+// host emulation of the kernel marks them as forbidden to catch overruns).
+struct BLayout {
+  int64_t ldz, ldl, ldu;
+  int64_t z, linv, mtmp, u2t, pos, order, nonpiv;  // byte offsets within a slice
+  int64_t slice;                                    // bytes per slice (multiple of 256)
+};
+
+inline BLayout batched_layout(int64_t maxn, int64_t maxk, int64_t b, int64_t es, int64_t gap) {
+  auto up = [](int64_t x, int64_t a) { return (x + a - 1) / a * a; };
+  BLayout L{};
+  // Z holds the factored columns (< kcap <= maxk) and one block of at most
+  // max(b, 64) sketch columns beyond them
+  L.ldz = up(maxk + (b > 64 ? b : 64), 4);
+  L.ldl = up(maxk, 64);
+  L.ldu = up(maxk, 16);
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o = up(o + bytes + gap, 256);
+    return at;
+  };
+  L.z = take(maxn * L.ldz * es);
+  L.linv = take(maxk * L.ldl * es);
+  L.mtmp = take((int64_t)kBPW * L.ldl * es);
+  L.u2t = take((int64_t)64 * L.ldu * es);
+  L.pos = take(maxn * 4);
+  L.order = take((maxk + 64) * 4);
+  L.nonpiv = take(maxn * 4);
+  L.slice = o;
+  return L;
+}
+
 // Block update for Z columns [zcol, zcol+w) against the k pivots taken so far:
 // U2 = L1^{-1} (P Y)(top) -> U2T, then S = (P Y)(bottom) - L2 U2 in place;
 // returns sum S^2 (FP64) to every thread.
@@ -456,8 +492,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
     int32_t* const* __restrict__ Jptr, void* const* __restrict__ Tptr,
     const int64_t* __restrict__ ldtv, int32_t* __restrict__ k_out, double* __restrict__ err_out,
     int32_t* __restrict__ st_out, int32_t* __restrict__ pass_out, const int32_t* __restrict__ perm,
-    unsigned* queue, unsigned char* __restrict__ wbase, size_t slice_bytes, int maxn, int maxk,
-    int64_t ldz, int64_t ldl, int64_t ldu) {
+    unsigned* queue, unsigned char* __restrict__ wbase, BLayout lay, int maxn, int maxk) {
   constexpr int LDO = 64 + 16;
   constexpr int KC = sizeof(TF) == 4 ? 64 : 32;
   __shared__ TF om[KC * LDO];
@@ -467,23 +502,16 @@ __global__ __launch_bounds__(kBT) void k_batched(
   __shared__ int cnt[kBMaxN];
   __shared__ int s_blk;
   const int tid = threadIdx.x;
-  unsigned char* base = wbase + (size_t)blockIdx.x * slice_bytes;
+  const int64_t ldz = lay.ldz, ldl = lay.ldl, ldu = lay.ldu;
+  unsigned char* base = wbase + (size_t)blockIdx.x * (size_t)lay.slice;
   BSlice<TF> S;
-  {
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-      unsigned char* p = base + o;
-      o += (bytes + 255) & ~(size_t)255;
-      return p;
-    };
-    S.Z = reinterpret_cast<TF*>(take((size_t)maxn * ldz * sizeof(TF)));
-    S.Linv = reinterpret_cast<TF*>(take((size_t)maxk * ldl * sizeof(TF)));
-    S.Mtmp = reinterpret_cast<TF*>(take((size_t)kBPW * ldl * sizeof(TF)));
-    S.U2T = reinterpret_cast<TF*>(take((size_t)64 * ldu * sizeof(TF)));
-    S.pos = reinterpret_cast<int*>(take((size_t)maxn * 4));
-    S.order = reinterpret_cast<int*>(take((size_t)(maxk + 64) * 4));
-    S.nonpiv = reinterpret_cast<int*>(take((size_t)maxn * 4));
-  }
+  S.Z = reinterpret_cast<TF*>(base + lay.z);
+  S.Linv = reinterpret_cast<TF*>(base + lay.linv);
+  S.Mtmp = reinterpret_cast<TF*>(base + lay.mtmp);
+  S.U2T = reinterpret_cast<TF*>(base + lay.u2t);
+  S.pos = reinterpret_cast<int*>(base + lay.pos);
+  S.order = reinterpret_cast<int*>(base + lay.order);
+  S.nonpiv = reinterpret_cast<int*>(base + lay.nonpiv);
   for (;;) {
     if (tid == 0) {
       const unsigned q = atomicAdd(queue, 1u);
@@ -519,27 +547,31 @@ __global__ __launch_bounds__(kBT) void k_batched(
     int w0 = b;
     if (khint && khint[blk] > 0) w0 = khint[blk];
     if (w0 > kcap) w0 = kcap;
-    int sketched = 0, passes = 0;
+    // Sketch vectors are numbered in the order they are drawn (cnext is the
+    // next unused one); Z columns [zcol, zcol + w) receive the next w.  Columns
+    // [k, have) hold drawn vectors not yet used by a block update.
+    int cnext = 0, have = 0, passes = 0;
     double fro = 0.0, E = -1.0;
     bool bad = false;
     int status = ST_OK;
-    // sketch vectors [sketched, upto) in passes of <= 64
-    auto sketch_to = [&](int upto) {
-      while (sketched < upto) {
-        const int wc = (upto - sketched < 64) ? upto - sketched : 64;
-        const bool norm = (sketched == 0);
+    auto sketch = [&](int zcol, int w) {
+      for (int d = 0; d < w;) {
+        const int wc = (w - d < 64) ? w - d : 64;
+        const bool norm = (cnext == 0);
         if (wc <= 16)
-          wg_sketch<TF, 1>(A, la, m, n, key0, key1, sketched, wc, S.Z, ldz, sketched, om, norm, fro, bad);
+          wg_sketch<TF, 1>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         else if (wc <= 32)
-          wg_sketch<TF, 2>(A, la, m, n, key0, key1, sketched, wc, S.Z, ldz, sketched, om, norm, fro, bad);
+          wg_sketch<TF, 2>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         else
-          wg_sketch<TF, 4>(A, la, m, n, key0, key1, sketched, wc, S.Z, ldz, sketched, om, norm, fro, bad);
-        sketched += wc;
+          wg_sketch<TF, 4>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+        cnext += wc;
+        d += wc;
         ++passes;
       }
+      have = zcol + w;
     };
     // first passes: the first block together with the block that estimates it
-    sketch_to(w0 < mn ? w0 + b : w0);
+    sketch(0, w0 < mn ? w0 + b : w0);
     // ||A||_F^2 and non-finite check, reduced over the workgroup
     {
       double f = wave_sum(fro);
@@ -574,7 +606,9 @@ __global__ __launch_bounds__(kBT) void k_batched(
           E = 0.0;
           break;
         }
-        sketch_to(k + b);
+        // the estimating block: b fresh vectors at column k unless the
+        // previous passes already drew them there
+        if (have < k + b) sketch(k, b);
         const double ss = wg_block_update<TF>(S, ldz, ldl, ldu, n, k, k, b, red);
         E = sqrt(ss) / sqrt((double)b);
         if (E <= thr) break;
@@ -582,8 +616,11 @@ __global__ __launch_bounds__(kBT) void k_batched(
           status = ST_NOT_CONVERGED;
           break;
         }
+        // factor f <= b of the block's columns; the rest of the block has been
+        // reduced by the panel and is not reused (the next block is fresh)
         const int f = (b < kcap - k) ? b : kcap - k;
         const int k2 = wg_factor<TF>(S, ldz, ldl, ldu, n, k, b, f, rowbuf, red, red_i);
+        have = k2;
         if (k2 < k + f) {
           k = k2;
           status = ST_RANK_DEFICIENT;

@@ -1,0 +1,116 @@
+"""The batched persistent kernel's own source executed on the CPU (host
+emulation of its 256-work-item workgroups, tests/emu), under
+AddressSanitizer, against the oracle.
+
+Every buffer the kernel receives is an allocation of exactly the size the
+interface promises, and each part of a workgroup's workspace slice is
+followed by a poisoned gap, so an index outside its array ends the run.
+Each emulated workgroup takes several blocks from the kernel's queue, so the
+per-block resets and the second-block path are exercised on every case.
+FP64 results follow the same parity rule as the GPU tests."""
+import numpy as np
+import pytest
+
+import workloads
+from batched_emu_util import build, run
+from parity_util import check_fp64
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    return build(str(tmp_path_factory.mktemp("emu")))
+
+
+def _blocks(nblk, seed, lo=64, hi=200):
+    return [workloads.kernel_block(m, n, sep, s)
+            for (m, n, sep, s) in workloads.kernel_batch_shapes(nblk, seed, lo, hi)]
+
+
+@pytest.mark.parametrize("tol,b", [(1e-8, 32), (1e-10, 8)])
+def test_emu_fp64_matches_oracle(exe, orc, tol, b):
+    blocks = _blocks(12, seed=3)
+    out = run(exe, blocks, b, tol, seed=100, groups=3)
+    for i, A in enumerate(blocks):
+        o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=100 + i)
+        check_fp64(A, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
+                   float(out.err_est[i]), o, b, tag=i)
+
+
+def test_emu_cap_matches_oracle(exe, orc):
+    """Rank cap that is not a multiple of b: the last panel factors only
+    kmax - k columns of its block, and the estimate at the cap comes from b
+    fresh sketch vectors (the oracle's draw), not from the partly reduced
+    rest of that block."""
+    blocks = _blocks(8, seed=13, lo=120, hi=220)
+    b, tol, kmax = 16, 1e-13, 24
+    out = run(exe, blocks, b, tol, seed=300, kmax=kmax, groups=2)
+    for i, A in enumerate(blocks):
+        o = orc.rid_adaptive(A, b, tol, kmax, seed=300 + i)
+        assert o.status == 1 and o.k == kmax, i      # the cap, tolerance missed
+        assert o.robust_k == o.k, i
+        check_fp64(A, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
+                   float(out.err_est[i]), o, b, tag=i)
+    # one block where the cap lies at a block edge of the first width
+    out2 = run(exe, blocks[:2], b, tol, seed=300, kmax=16, groups=1)
+    for i, A in enumerate(blocks[:2]):
+        o = orc.rid_adaptive(A, b, tol, 16, seed=300 + i)
+        check_fp64(A, out2.J[i], out2.T[i], int(out2.k[i]), int(out2.status[i]),
+                   float(out2.err_est[i]), o, b, tag=("edge", i))
+
+
+def test_emu_hint_matches_oracle(exe, orc):
+    blocks = _blocks(8, seed=9)
+    b, tol = 32, 1e-8
+    hints = [int(h) for h in np.random.default_rng(1).integers(4, 90, size=len(blocks))]
+    out = run(exe, blocks, b, tol, seed=50, hints=hints, groups=2)
+    for i, A in enumerate(blocks):
+        o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=50 + i, first_width=hints[i])
+        check_fp64(A, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
+                   float(out.err_est[i]), o, b, tag=i)
+
+
+def test_emu_edge_blocks(exe, orc):
+    rng = np.random.default_rng(2)
+    Z = np.zeros((70, 50))
+    C = np.zeros((90, 60))
+    C[:, [3, 40, 41]] = rng.standard_normal((90, 3))
+    N = rng.standard_normal((80, 80))
+    N[5, 7] = np.nan
+    F = rng.standard_normal((9, 13))
+    one = rng.standard_normal((1, 1))
+    out = run(exe, [Z, C, N, F, one], 32, 1e-10, seed=3, groups=2)
+    assert (out.status[0], out.k[0]) == (2, 0)
+    assert (out.status[1], out.k[1]) == (2, 3) and sorted(out.J[1]) == [3, 40, 41]
+    assert (out.status[2], out.k[2]) == (-2, 0)
+    assert (out.status[3], out.k[3], out.err_est[3]) == (0, 9, 0.0)
+    assert (out.status[4], out.k[4]) == (0, 1)
+
+
+def test_emu_fp32_full_rank_many_blocks_per_workgroup(exe):
+    """FP32 blocks at a tolerance below the FP32 floor run to full rank (the
+    longest control path: every block size, every cap and partial panel),
+    several blocks per workgroup, with every access checked."""
+    shapes = workloads.kernel_batch_shapes(24, 5, 64, 300)
+    blocks = [workloads.kernel_block(m, n, s, sd).astype(np.float32) for (m, n, s, sd) in shapes]
+    out = run(exe, blocks, 8, 1e-10, seed=100, dtype=np.float32, groups=4)
+    assert np.all(out.status == 0)
+    assert np.array_equal(out.k, [min(a.shape) for a in blocks])
+    for i, A in enumerate(blocks):
+        assert sorted(out.J[i]) == sorted(set(out.J[i].tolist()))
+        assert np.all((out.J[i] >= 0) & (out.J[i] < A.shape[1]))
+
+
+def test_emu_fp32_bench_shapes(exe):
+    """The benchmark's FP32 configuration on a sample of its blocks (sizes up
+    to 1024, b = 32, processing order by decreasing cost, a workspace planned
+    for 1024 x 1024)."""
+    shapes = workloads.kernel_batch_shapes(4096, 7, 64, 1024)
+    pick = [0, 1, 2, 3] + [i for i, s in enumerate(shapes) if max(s[0], s[1]) > 1000][:4]
+    sub = [shapes[i] for i in pick]
+    blocks = [workloads.kernel_block(m, n, s, sd).astype(np.float32) for (m, n, s, sd) in sub]
+    cost = np.array([m * n for (m, n, _, _) in sub], dtype=np.float64)
+    order = list(np.argsort(-cost, kind="stable"))
+    for tol in (1e-6, 1e-8):
+        out = run(exe, blocks, 32, tol, seed=7, dtype=np.float32, order=order, groups=2,
+                  max_n=1024, max_kmax=1024)
+        assert np.all(out.status >= 0) and np.all(out.k >= 1)
