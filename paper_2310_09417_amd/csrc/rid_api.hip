@@ -105,15 +105,20 @@ class SideLease {
         return;
       }
   }
+  // An error return between a fork and its join leaves forked work running:
+  // the caller's stream still waits for it here, before the set is released,
+  // so nothing the caller enqueues next (e.g. freeing the workspace) overtakes it.
   ~SideLease() {
     if (!set_) return;
+    if (pending) (void)hipStreamWaitEvent(caller, set_->join, 0);
     std::lock_guard<std::mutex> lk(side_mu);
     set_->busy = false;
   }
   SideLease(const SideLease&) = delete;
   SideLease& operator=(const SideLease&) = delete;
   SideSet* get() const { return set_; }
-  bool pending = false;  // forked work not yet joined
+  bool pending = false;          // forked work not yet joined
+  hipStream_t caller = nullptr;  // the stream the work was forked from
 
  private:
   SideSet* set_ = nullptr;
@@ -768,12 +773,15 @@ int panel_fork(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_ful
   RID_TRY(side_join(side, st));  // at most one forked update at a time
   if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->s, ss->fork, 0) != hipSuccess)
     return RID_ERR_HIP;
+  // from here on the side stream holds this call's work (joined by the lease
+  // on an error return)
+  side.caller = st;
+  side.pending = true;
   rc = P.dt == RID_F64 ? linv_update_t<double>(P, W, zcol, f, ss->s)
                        : linv_update_t<float>(P, W, zcol, f, ss->s);
+  const bool recorded = hipEventRecord(ss->join, ss->s) == hipSuccess;
   if (rc != RID_OK) return rc;
-  if (hipEventRecord(ss->join, ss->s) != hipSuccess) return RID_ERR_HIP;
-  side.pending = true;
-  return RID_OK;
+  return recorded ? RID_OK : RID_ERR_HIP;
 }
 
 int panel(const Plan& P, const Ws& W, int zcol, int w, int f, bool stop_full,
