@@ -175,6 +175,29 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
                         hipStream_t stream);
 
 /*
+ * rid_lupp_fixed_rank without a caller workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, arithmetic and results
+ * as rid_lupp_fixed_rank, minus work / work_bytes: the workspace is a
+ * file-scope device array of rid_noalloc_max_bytes() bytes (64 MiB) that
+ * every device using the library holds until the process ends.  Its device
+ * address is looked up on the first call on each device.  The call
+ * allocates nothing and clears what must start at zero.
+ * All calls on one device share that array: calls that overlap on one device
+ * (two streams, two host threads) race and give undefined results; order
+ * them on one stream or serialize them.
+ * Errors: RID_ERR_WORKSPACE when the sizes need more than
+ *   rid_noalloc_max_bytes() (rid_workspace_bytes(m, n, k + p, p, cfg) tells);
+ *   RID_ERR_HIP when the array's address cannot be found; otherwise as
+ *   rid_lupp_fixed_rank.
+ */
+size_t rid_noalloc_max_bytes(void);
+int rid_lupp_fixed_rank_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                                int64_t p, const rid_config* cfg, int64_t* J, void* T,
+                                int64_t ldt, int32_t* k_out, double* err_est, int32_t* status,
+                                hipStream_t stream);
+
+/*
  * Adaptive blocked randomized LUPP ID (randLUPPadap; Alg. 1, Sec. 4.2).
  *   The first block of b sketch vectors is factored.  Each further block
  *   Y^(t) is reduced by the current factors, U2 = L1^{-1} (P Y^(t))(top) and

@@ -54,6 +54,11 @@ def library() -> ctypes.CDLL:
         lib.rid_lupp_fixed_rank.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, P, i64, P, P, P,
                                             P, sz, P]
         lib.rid_lupp_fixed_rank.restype = i32
+        lib.rid_noalloc_max_bytes.argtypes = []
+        lib.rid_noalloc_max_bytes.restype = sz
+        lib.rid_lupp_fixed_rank_noalloc.argtypes = [P, i64, i64, i64, i64, i64, cfgp, P, P, i64,
+                                                    P, P, P, P]
+        lib.rid_lupp_fixed_rank_noalloc.restype = i32
         lib.rid_lupp_adaptive.argtypes = [P, i64, i64, i64, i64, dbl, i64, cfgp, P, P, i64, P, P,
                                           P, P, sz, P]
         lib.rid_lupp_adaptive.restype = i32
@@ -150,6 +155,16 @@ def rid_lupp_fixed_rank(A, m, n, lda, k, p, cfg, J, T, ldt, k_out, err_est, stat
                         work_bytes, stream) -> int:
     return int(library().rid_lupp_fixed_rank(A, m, n, lda, k, p, ctypes.byref(cfg), J, T, ldt,
                                               k_out, err_est, status, work, work_bytes, stream))
+
+
+def rid_noalloc_max_bytes() -> int:
+    return int(library().rid_noalloc_max_bytes())
+
+
+def rid_lupp_fixed_rank_noalloc(A, m, n, lda, k, p, cfg, J, T, ldt, k_out, err_est, status,
+                                stream) -> int:
+    return int(library().rid_lupp_fixed_rank_noalloc(A, m, n, lda, k, p, ctypes.byref(cfg), J, T,
+                                                      ldt, k_out, err_est, status, stream))
 
 
 def rid_lupp_adaptive(A, m, n, lda, b, tol, kmax, cfg, J, T, ldt, k_out, err_est, status, work,

@@ -963,6 +963,35 @@ bool bplan(int32_t maxn, int32_t maxk, int32_t b, rid_dtype dt, BPlan& P) {
   return true;
 }
 
+// ---- workspace for callers that cannot allocate ------------------------------
+// A file-scope device array serves as the fixed-rank call's workspace for
+// callers that cannot call hipMalloc.  Each device that loads the library
+// holds its own copy until the process ends.  In host code the array's name is
+// only a stand-in for the device symbol: its device address is looked up once
+// per device (hipGetSymbolAddress, with that device current) and only that
+// address is ever handed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void* scratch_addr[64] = {};
+std::mutex scratch_mu;
+
+// Device address of the current device's copy of `scratch` (nullptr on error).
+void* scratch_address() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    scratch_addr[dev] = p;
+  }
+  return scratch_addr[dev];
+}
+
 }  // namespace
 
 
@@ -1028,6 +1057,24 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
       RID_TRY(estimate(P, W, (int)p, 0.0, 0, (int)k, true, stream));
   }
   return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+}
+
+size_t rid_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int rid_lupp_fixed_rank_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                                int64_t p, const rid_config* cfg, int64_t* J, void* T,
+                                int64_t ldt, int32_t* k_out, double* err_est, int32_t* status,
+                                hipStream_t stream) {
+  if (!A || !J || !T || !k_out || !err_est || !status || !valid_cfg(cfg)) return RID_ERR_ARG;
+  if (m < 1 || n < 1 || k < 1 || k > std::min(m, n) || p < 0 || p > kMaxW) return RID_ERR_ARG;
+  Plan P;  // the plan rid_lupp_fixed_rank makes for these sizes
+  if (!plan_for(m, n, k + p, p, cfg, P)) return RID_ERR_HIP;
+  if (P.total > kScratchBytes) return RID_ERR_WORKSPACE;
+  void* ws = scratch_address();
+  if (!ws) return RID_ERR_HIP;
+  // the same enqueue as the workspace form; init() clears what must start at zero
+  return rid_lupp_fixed_rank(A, m, n, lda, k, p, cfg, J, T, ldt, k_out, err_est, status, ws,
+                             kScratchBytes, stream);
 }
 
 int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t b, double tol,
