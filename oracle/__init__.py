@@ -80,6 +80,9 @@ def _load():
         lib.orc_rid_lupp.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
                                      P, P, i64, P, i64, ctypes.POINTER(_Result)]
         lib.orc_rid_lupp.restype = cint
+        lib.orc_rid_lupp_gaps.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
+                                          P, P, i64, P, i64, P, ctypes.POINTER(_Result)]
+        lib.orc_rid_lupp_gaps.restype = cint
         lib.orc_lupp_factors.argtypes = [P, i64, i64, i64, i64, i64, u64, P, P, P]
         lib.orc_lupp_factors.restype = cint
         lib.orc_rid_adaptive_first.argtypes = [P, i64, i64, i64, i64, i64, dbl, cint, i64, u64,
@@ -177,6 +180,9 @@ class IDResult:
     fro_a: float = 0.0
     robust_k: int = 0       # leading pivots decided above the FP64 rounding floor
     est_hist: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    # decision margin of every pivot step (with gaps=True): (|best| - |runner-up|)
+    # / (sqrt(s + 1) max|Y|); see robust_prefix
+    gaps: np.ndarray = field(default_factory=lambda: np.zeros(0))
     # residual-triangle estimates per step (Remark 1): columns = Schur estimate
     # on the set-aside sample, eq. normUest, eq. maxUest
 
@@ -195,8 +201,16 @@ class IDResult:
         return X
 
 
+def robust_prefix(gaps, eps: float) -> int:
+    """Number of leading pivot steps decided by more than the rounding floor
+    64 eps sqrt(s + 1) max|Y| of a precision with machine epsilon eps
+    (2^-52: FP64, the oracle's robust_k; 2^-23: FP32)."""
+    bad = np.nonzero(np.asarray(gaps) <= 64.0 * eps)[0]
+    return int(bad[0]) if len(bad) else len(gaps)
+
+
 def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, estimator=0,
-         resid_p=0, embedding=0) -> IDResult:
+         resid_p=0, embedding=0, gaps=False) -> IDResult:
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
@@ -206,7 +220,14 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, est
     hist = np.zeros(hist_cap, dtype=np.float64)
     est = np.zeros((hist_cap, 3), dtype=np.float64)
     res = _Result()
-    if embedding and not estimator:
+    gap = np.full(cap, np.inf)
+    if gaps:
+        if embedding or estimator or first_w > 0:
+            raise ValueError("gaps: plain Gaussian fixed-rank or adaptive calls only")
+        lib.orc_rid_lupp_gaps(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
+                              _ptr(J), _ptr(T), n, _ptr(hist), hist_cap, _ptr(gap),
+                              ctypes.byref(res))
+    elif embedding and not estimator:
         lib.orc_rid_lupp_emb(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
                              embedding, _ptr(J), _ptr(T), n, _ptr(hist), hist_cap,
                              ctypes.byref(res))
@@ -226,20 +247,22 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, est
                     status=int(res.status), E_hist=hist[: res.nsteps].copy(),
                     min_gap=float(res.min_gap), min_gap_step=int(res.min_gap_step),
                     fro_a=float(res.fro_a), robust_k=int(res.robust_k),
-                    est_hist=est[: res.nsteps].copy() if estimator else np.zeros((0, 3)))
+                    est_hist=est[: res.nsteps].copy() if estimator else np.zeros((0, 3)),
+                    gaps=gap[:k].copy() if gaps else np.zeros(0))
 
 
-def rid_fixed_rank(A, k: int, p: int, seed: int) -> IDResult:
+def rid_fixed_rank(A, k: int, p: int, seed: int, gaps: bool = False) -> IDResult:
     """randLUPP at fixed rank k with p extra sketch vectors for E_Schur."""
-    return _run(A, 0, k, p, 0.0, False, k, seed)
+    return _run(A, 0, k, p, 0.0, False, k, seed, gaps=gaps)
 
 
 def rid_adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
-                 first_width: int = 0) -> IDResult:
+                 first_width: int = 0, gaps: bool = False) -> IDResult:
     """randLUPPadap (Alg. 1): blocks of b sketch vectors until E <= tol.
     first_width > 0 makes the first factored block that wide (a rank known
-    or predicted beforehand); the rest of the method is unchanged."""
-    return _run(A, 1, b, 0, tol, relative, kmax, seed, first_w=first_width)
+    or predicted beforehand); the rest of the method is unchanged.  gaps:
+    also return every pivot step's decision margin."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed, first_w=first_width, gaps=gaps)
 
 
 # Estimators of Remark 1 (Sec. 3.2): 0 = Schur estimate on the next block

@@ -285,7 +285,8 @@ typedef struct {
   int64_t min_gap_step;
   double fro_a;       /* ||A||_F                                                 */
   int64_t robust_k;   /* leading pivots decided by more than the rounding floor: */
-                      /* (|1st| - |2nd|) > 64 u sqrt(s+1) max|Y| at every step   */
+                      /* (|1st| - |2nd|) > 64 eps sqrt(s+1) max|Y| at every step */
+                      /* s < robust_k, eps = 2^-52 (128 units of roundoff)       */
                       /* s < robust_k; later ones may legitimately differ in     */
                       /* any other correct evaluation order                      */
 } orc_result;
@@ -319,14 +320,14 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                          int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
                          int embedding, int64_t* J, double* T, int64_t ldt, double* E_hist,
-                         double* est_hist, int64_t hist_cap, orc_result* res);
+                         double* est_hist, int64_t hist_cap, double* gap_hist, orc_result* res);
 
 int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                  int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                  uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                  int64_t hist_cap, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, 0,
-                       J, T, ldt, E_hist, NULL, hist_cap, res);
+                       J, T, ldt, E_hist, NULL, hist_cap, NULL, res);
 }
 
 /* Same as orc_rid_lupp with the blocks drawn from the sparse sign embedding
@@ -336,7 +337,7 @@ int orc_rid_lupp_emb(const double* A, int64_t m, int64_t n, int64_t lda, int mod
                      uint64_t seed, int embedding, int64_t* J, double* T, int64_t ldt,
                      double* E_hist, int64_t hist_cap, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0,
-                       embedding, J, T, ldt, E_hist, NULL, hist_cap, res);
+                       embedding, J, T, ldt, E_hist, NULL, hist_cap, NULL, res);
 }
 
 /* Same as orc_rid_lupp with the stopping estimate taken from the residual
@@ -354,7 +355,7 @@ int orc_rid_lupp_est(const double* A, int64_t m, int64_t n, int64_t lda, int mod
                      double* T, int64_t ldt, double* E_hist, double* est_hist, int64_t hist_cap,
                      orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, estimator,
-                       resid_p, embedding, J, T, ldt, E_hist, est_hist, hist_cap, res);
+                       resid_p, embedding, J, T, ldt, E_hist, est_hist, hist_cap, NULL, res);
 }
 
 /* Adaptive variant whose first factored block has first_width vectors
@@ -365,7 +366,20 @@ int orc_rid_adaptive_first(const double* A, int64_t m, int64_t n, int64_t lda, i
                            uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                            int64_t hist_cap, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, 0, 0, 0,
-                       J, T, ldt, E_hist, NULL, hist_cap, res);
+                       J, T, ldt, E_hist, NULL, hist_cap, NULL, res);
+}
+
+/* Same as orc_rid_lupp, also reporting every pivot step's decision margin:
+ * gap_hist[s] = (|best| - |runner-up|) / (sqrt(s + 1) max|Y|) for s < k (+inf
+ * when step s had a single candidate).  A step is decided above the rounding
+ * floor of a precision with machine epsilon eps when gap_hist[s] > 64 eps
+ * (robust_k is that count for eps = 2^-52); test diagnostics only. */
+int orc_rid_lupp_gaps(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                      int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
+                      uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
+                      int64_t hist_cap, double* gap_hist, orc_result* res) {
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, 0,
+                       J, T, ldt, E_hist, NULL, hist_cap, gap_hist, res);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -569,7 +583,7 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                          int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
                          int embedding, int64_t* J, double* T, int64_t ldt, double* E_hist,
-                         double* est_hist, int64_t hist_cap, orc_result* res) {
+                         double* est_hist, int64_t hist_cap, double* gap_hist, orc_result* res) {
   memset(res, 0, sizeof(*res));
   res->err_est = -1.0;
   res->min_gap = INFINITY;
@@ -711,7 +725,9 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
           double v = fabs(Z[r * zc + s]);
           if (v > second) second = v;
         }
+      if (gap_hist) gap_hist[s] = INFINITY;
       if (best > 0.0 && second >= 0.0) {
+        if (gap_hist) gap_hist[s] = (best - second) / (sqrt((double)(s + 1)) * ymax);
         double gap = (best - second) / best;
         if (gap < res->min_gap) {
           res->min_gap = gap;

@@ -33,7 +33,8 @@ def test_emu_fp64_matches_oracle(exe, orc, tol, b):
     for i, A in enumerate(blocks):
         o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=100 + i)
         check_fp64(A, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
-                   float(out.err_est[i]), o, b, tag=i)
+                   float(out.err_est[i]), o, b, tag=i, exact=o.robust_k == o.k,
+                   at_rank=lambda kk, A=A, i=i: orc.rid_fixed_rank(A, kk, b, seed=100 + i))
 
 
 def test_emu_cap_matches_oracle(exe, orc):
@@ -66,7 +67,8 @@ def test_emu_hint_matches_oracle(exe, orc):
     for i, A in enumerate(blocks):
         o = orc.rid_adaptive(A, b, tol, min(A.shape), seed=50 + i, first_width=hints[i])
         check_fp64(A, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
-                   float(out.err_est[i]), o, b, tag=i)
+                   float(out.err_est[i]), o, b, tag=i, exact=o.robust_k == o.k,
+                   at_rank=lambda kk, A=A, i=i: orc.rid_fixed_rank(A, kk, b, seed=50 + i))
 
 
 def test_emu_edge_blocks(exe, orc):

@@ -308,6 +308,36 @@ def test_robust_prefix_diagnostic(orc):
     assert 0 < o2.robust_k < 190
 
 
+def test_decision_margins(orc):
+    """The per-step decision margins reproduce robust_k at the FP64 epsilon,
+    leave the decomposition unchanged, and give a shorter prefix at the FP32
+    epsilon.  Each margin is checked against the pivot column recomputed
+    independently: the Schur complement of the oracle's first s pivot rows in
+    sketch column s, formed by a library linear solve, whose largest and
+    second-largest magnitudes define step s."""
+    B, _ = workloads.fast_decay(300, 200, decades=16.0, seed=2)
+    o = orc.rid_fixed_rank(B, 190, 0, seed=3, gaps=True)
+    ref = orc.rid_fixed_rank(B, 190, 0, seed=3)
+    assert list(o.J) == list(ref.J) and np.array_equal(o.T, ref.T)
+    assert orc.robust_prefix(o.gaps, 2.0 ** -52) == o.robust_k == ref.robust_k
+    assert orc.robust_prefix(o.gaps, 2.0 ** -23) < o.robust_k
+    Yt = orc.sketch(B, 3, 0, 190).T          # n x k, rows = candidate columns
+    ymax = np.abs(Yt).max()
+    for s in (0, 1, 5, 20, 60):
+        if s == 0:
+            col = np.abs(Yt[:, 0])
+        else:
+            # Schur complement of the pivot rows J[:s] in column s
+            P = list(o.J[:s])
+            rest = [r for r in range(Yt.shape[0]) if r not in P]
+            X = np.linalg.solve(Yt[P, :s].T, Yt[rest, :s].T).T
+            col = np.abs(Yt[rest, s] - X @ Yt[P, s])
+            col = np.concatenate([col, [0.0]])
+        top = np.sort(col)[::-1]
+        want = (top[0] - top[1]) / (np.sqrt(s + 1) * ymax)
+        assert abs(o.gaps[s] - want) <= 1e-6 * want + 1e-13, (s, o.gaps[s], want)
+
+
 # ---- rounding into BF16 / OCP e4m3 and the rounded-Gaussian sketch --------
 
 def test_round_format_matches_torch_conversions(orc):
