@@ -271,25 +271,31 @@ int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int6
  * launch (the batch extension named as future work in the paper's
  * conclusions, applied to Alg. 1 per block).  Every array argument is a
  * DEVICE array of length nblk:
- *   A[i]  (device pointer, dtype)  block i, m[i] x n[i], row-major, ld lda[i]
+ *   A[i]  (device pointer, a_type) block i, m[i] x n[i], row-major, ld lda[i]
  *   kmax[i]  rank cap;  k_hint[i] (nullable array; entries <= 0 mean none):
  *            width of the first factored block, e.g. a predicted rank, so
  *            that the first pass can certify it; otherwise the first block
  *            has b vectors (Alg. 1);
  *   J[i]  (device pointer, int32, capacity min(kmax[i], m[i], n[i]))
- *   T[i]  (device pointer, dtype, capacity min(kmax, m, n) rows of ldt[i])
+ *   T[i]  (device pointer, dtype (the factor type), capacity min(kmax, m, n)
+ *         rows of ldt[i])
  *   k_out, err_est, status, passes (nullable): per-block results, with
  *   passes[i] = number of sketch passes over block i.
  *   order (nullable): processing order (a permutation of 0..nblk-1), e.g.
  *   largest blocks first.
+ * Storage and factor types: cfg->a_type == cfg->dtype (RID_F64 or RID_F32),
+ * or FP32 blocks factored in FP64 (cfg->dtype RID_F64, cfg->a_type RID_F32:
+ * the blocks are read at 4 bytes per entry and every step after the load runs
+ * in FP64; T[i] is FP64).  No refinement, estimator or sparse embedding.
  * Block i uses the Gaussian stream of seed cfg->seed + i.  b <= 32; every n[i]
  * must be <= max_n <= 1024 (blocks outside the plan get status RID_ERR_ARG);
  * ranks are capped at min(max_kmax, max_n).  Workspace:
- * rid_batched_workspace_bytes(max_n, max_kmax, b, cfg).  An FP32 call takes
- * at most as many blocks as the device has compute units (one block per
- * resident workgroup; more returns RID_ERR_ARG): FP32 batches in which a
- * workgroup went on to a second block ended with a GPU memory fault whose
- * cause has not been found.  FP64 calls take any number of blocks.
+ * rid_batched_workspace_bytes(max_n, max_kmax, b, cfg).  A call factored in
+ * FP32 takes at most as many blocks as the device has compute units (one
+ * block per resident workgroup; more returns RID_ERR_ARG): such batches in
+ * which a workgroup went on to a second block ended with a GPU memory fault
+ * whose cause has not been found.  Calls factored in FP64 (FP64 or FP32
+ * storage) take any number of blocks.
  */
 size_t rid_batched_workspace_bytes(int32_t max_n, int32_t max_kmax, int32_t b,
                                    const rid_config* cfg);

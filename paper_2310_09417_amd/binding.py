@@ -480,14 +480,23 @@ class BatchPlan:
     them).  blocks: list of 2-D device tensors of one dtype."""
 
     def __init__(self, blocks, b: int, tol: float, kmax=None, seed: int = 0, relative=True,
-                 k_hint=None, order=None):
+                 k_hint=None, order=None, factor=None):
+        """factor: the factorisation's type; torch.float64 with float32 blocks
+        factors FP32-stored blocks in FP64 (T in FP64); default: the blocks'."""
         torch = _torch()
         dev = blocks[0].device
         dt = _dtype_code(blocks[0])
         self.blocks = blocks
         self.nblk = len(blocks)
         self.b, self.tol = b, tol
-        self.cfg = _cfg(dt, seed, relative)
+        tdtype = blocks[0].dtype
+        if factor is None or factor == blocks[0].dtype:
+            self.cfg = _cfg(dt, seed, relative)
+        elif factor == torch.float64 and dt == RID_F32:
+            self.cfg = _cfg(RID_F64, seed, relative, a_type=RID_F32)
+            tdtype = torch.float64
+        else:
+            raise RidError(f"factor {factor} with {blocks[0].dtype} blocks is not supported")
         ms = [int(a.shape[0]) for a in blocks]
         ns = [int(a.shape[1]) for a in blocks]
         if kmax is None:
@@ -506,7 +515,7 @@ class BatchPlan:
         self.k_hint = (torch.as_tensor(k_hint, dtype=i32).to(dev) if k_hint is not None else None)
         self.order = (torch.as_tensor(order, dtype=i32).to(dev) if order is not None else None)
         self.Jbufs = [torch.zeros(max(c, 1), dtype=i32, device=dev) for c in caps]
-        self.Tbufs = [torch.zeros((max(c, 1), n_), dtype=blocks[0].dtype, device=dev)
+        self.Tbufs = [torch.zeros((max(c, 1), n_), dtype=tdtype, device=dev)
                       for c, n_ in zip(caps, ns)]
         self.J = torch.tensor([t.data_ptr() for t in self.Jbufs], dtype=i64, device=dev)
         self.T = torch.tensor([t.data_ptr() for t in self.Tbufs], dtype=i64, device=dev)
@@ -515,7 +524,8 @@ class BatchPlan:
         self.err = torch.zeros(self.nblk, dtype=torch.float64, device=dev)
         self.st = torch.zeros(self.nblk, dtype=i32, device=dev)
         self.passes = torch.zeros(self.nblk, dtype=i32, device=dev)
-        if dt == RID_F32 and self.nblk > torch.cuda.get_device_properties(dev).multi_processor_count:
+        if (self.cfg.dtype == RID_F32
+                and self.nblk > torch.cuda.get_device_properties(dev).multi_processor_count):
             raise RidError("an FP32 batch takes at most one block per compute unit (an FP32 "
                            "batch with more blocks faulted the GPU; cause not found yet)")
         wb = rid_batched_workspace_bytes(self.max_n, self.max_kmax, b, self.cfg)
@@ -546,10 +556,10 @@ class BatchPlan:
 
 
 def batched(blocks, b: int, tol: float, kmax=None, seed: int = 0, relative=True, k_hint=None,
-            order=None) -> BatchOutput:
+            order=None, factor=None) -> BatchOutput:
     """Adaptive LUPP IDs of a list of device blocks in one persistent launch;
     block i uses the Gaussian stream of seed + i."""
-    plan = BatchPlan(blocks, b, tol, kmax, seed, relative, k_hint, order)
+    plan = BatchPlan(blocks, b, tol, kmax, seed, relative, k_hint, order, factor)
     plan.launch()
     return plan.result()
 

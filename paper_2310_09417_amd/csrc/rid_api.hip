@@ -932,10 +932,13 @@ bool valid_cfg(const rid_config* cfg) {
   return cfg->refine == 0 || (cfg->refine == 1 && cfg->dtype == RID_F32);
 }
 
-// The batched path reads A in the factor type only.
+// The batched path reads A in the factor type, or FP32 blocks under an FP64
+// factorisation.
 bool valid_batched_cfg(const rid_config* cfg) {
-  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0 &&
-         cfg->embedding == RID_EMB_GAUSSIAN;
+  if (!cfg || cfg->refine != 0 || cfg->embedding != RID_EMB_GAUSSIAN || cfg->estimator != 0)
+    return false;
+  if (cfg->dtype == RID_F64 && cfg->a_type == RID_F32) return true;
+  return valid_cfg(cfg) && cfg->a_type == cfg->dtype;
 }
 
 // The row-skeleton step reads A in the factor type, with no refinement or
@@ -1362,7 +1365,11 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
   RID_LAUNCH_CHECK();
   const int grid = std::min<int>(P.G, nblk);
   const long pm = prof_begin(KC_BATCHED, stream);
-  if (cfg->dtype == RID_F64)
+  if (cfg->dtype == RID_F64 && cfg->a_type == RID_F32)
+    hipLaunchKernelGGL((k_batched<double, float>), dim3(grid), dim3(rid::kBT), 0, stream, nblk, A,
+                       lda, m, n, b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt,
+                       k_out, err_est, status, passes, order, queue, base, P.L, max_n, maxk);
+  else if (cfg->dtype == RID_F64)
     hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
                        b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
                        err_est, status, passes, order, queue, base, P.L, max_n, maxk);

@@ -35,8 +35,10 @@ struct BatchOut {
 
 // --- sketch of vectors [c0, c0+w) (w <= 64) of one block into Z columns
 // [zcol, zcol+w); returns sum A^2 and the non-finite flag when norm is set.
-template <typename TF, int MT>
-__device__ void wg_sketch(const TF* __restrict__ A, int64_t lda, int m, int n, uint32_t key0,
+// A is stored in TA (TF, or FP32 under an FP64 factorisation) and converted
+// to TF as it is loaded.
+template <typename TF, typename TA, int MT>
+__device__ void wg_sketch(const TA* __restrict__ A, int64_t lda, int m, int n, uint32_t key0,
                           uint32_t key1, uint32_t c0, int w, TF* __restrict__ Z, int64_t ldz,
                           int zcol, TF* om, bool norm, double& fro, bool& bad) {
   constexpr int WP = MT * 16, LDO = WP + 16;
@@ -71,8 +73,9 @@ __device__ void wg_sketch(const TF* __restrict__ A, int64_t lda, int m, int n, u
       if (active) {
 #pragma unroll 4
         for (int j = 0; j < KS; ++j) {
-          TF b4[4];
-          load_row4<TF, false>(A, r0 + 4 * j + (lane >> 4), m, col4, n, lda, b4);
+          TA a4[4];
+          load_row4<TA, false>(A, r0 + 4 * j + (lane >> 4), m, col4, n, lda, a4);
+          const TF b4[4] = {(TF)a4[0], (TF)a4[1], (TF)a4[2], (TF)a4[3]};
           TF av[MT];
 #pragma unroll
           for (int a = 0; a < MT; ++a) av[a] = om[(4 * j + (lane >> 4)) * LDO + a * 16 + (lane & 15)];
@@ -483,8 +486,9 @@ __device__ void wg_outputs(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int n,
 }
 
 // The persistent kernel.  Block ids come from queue (zeroed beforehand),
-// optionally remapped by perm (e.g. largest blocks first).
-template <typename TF>
+// optionally remapped by perm (e.g. largest blocks first).  Blocks are stored
+// in TA: TF, or FP32 blocks factored in FP64 (TF = double, TA = float).
+template <typename TF, typename TA = TF>
 __global__ __launch_bounds__(kBT) void k_batched(
     int nblk, const void* const* __restrict__ Aptr, const int64_t* __restrict__ lda,
     const int32_t* __restrict__ mv, const int32_t* __restrict__ nv, int b, double tol, int rel,
@@ -521,7 +525,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
     const int blk = s_blk;
     __syncthreads();
     if (blk < 0) break;
-    const TF* A = static_cast<const TF*>(Aptr[blk]);
+    const TA* A = static_cast<const TA*>(Aptr[blk]);
     const int m = mv[blk], n = nv[blk];
     const int64_t la = lda[blk];
     if (m < 1 || n < 1 || n > maxn || la < n) {  // outside this workspace's plan
@@ -559,11 +563,11 @@ __global__ __launch_bounds__(kBT) void k_batched(
         const int wc = (w - d < 64) ? w - d : 64;
         const bool norm = (cnext == 0);
         if (wc <= 16)
-          wg_sketch<TF, 1>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+          wg_sketch<TF, TA, 1>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         else if (wc <= 32)
-          wg_sketch<TF, 2>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+          wg_sketch<TF, TA, 2>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         else
-          wg_sketch<TF, 4>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+          wg_sketch<TF, TA, 4>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         cnext += wc;
         d += wc;
         ++passes;

@@ -39,7 +39,9 @@ class EmuOut:
 
 def run(exe: str, blocks, b: int, tol: float, seed: int, dtype=np.float64, kmax=None, hints=None,
         order=None, relative=True, groups: int = 2, gap: int = 1 << 16, max_n=None,
-        max_kmax=None, timeout=1200) -> EmuOut:
+        max_kmax=None, timeout=1200, factor=None) -> EmuOut:
+    """dtype: storage type of the blocks; factor: np.float64 with float32
+    blocks runs the FP32-storage, FP64-factorisation instantiation."""
     nblk = len(blocks)
     ms = [int(a.shape[0]) for a in blocks]
     ns = [int(a.shape[1]) for a in blocks]
@@ -50,7 +52,12 @@ def run(exe: str, blocks, b: int, tol: float, seed: int, dtype=np.float64, kmax=
     caps = [min(k, a, c) for k, a, c in zip(kmax, ms, ns)]
     max_n = max(ns) if max_n is None else max_n
     max_kmax = max(caps) if max_kmax is None else max_kmax
-    dt = 0 if dtype == np.float64 else 1
+    if factor is not None and factor != dtype:
+        assert factor == np.float64 and dtype == np.float32
+        dt = 2
+    else:
+        dt = 0 if dtype == np.float64 else 1
+    tdtype = np.float64 if dt != 1 else np.float32
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
         with open(fin, "wb") as f:
@@ -71,7 +78,7 @@ def run(exe: str, blocks, b: int, tol: float, seed: int, dtype=np.float64, kmax=
         if r.returncode != 0:
             raise RuntimeError(f"batched_emu failed ({r.returncode}):\n{r.stderr[-6000:]}")
         data = open(fout, "rb").read()
-    es = np.dtype(dtype).itemsize
+    es = np.dtype(tdtype).itemsize
     off = 0
     ks, sts, ps, Es, Js, Ts = [], [], [], [], [], []
     for i in range(nblk):
@@ -83,7 +90,7 @@ def run(exe: str, blocks, b: int, tol: float, seed: int, dtype=np.float64, kmax=
         J = np.frombuffer(data, dtype="<i4", count=kk, offset=off).copy()
         off += 4 * kk
         nt = kk * (ns[i] - kk)
-        T = np.frombuffer(data, dtype=dtype, count=nt, offset=off).reshape(kk, ns[i] - kk).copy()
+        T = np.frombuffer(data, dtype=tdtype, count=nt, offset=off).reshape(kk, ns[i] - kk).copy()
         off += es * nt
         ks.append(k), sts.append(st), ps.append(p), Es.append(E), Js.append(J), Ts.append(T)
     return EmuOut(np.array(ks), np.array(sts), np.array(ps), np.array(Es), Js, Ts)

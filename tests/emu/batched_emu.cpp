@@ -8,14 +8,15 @@
 // carries `gap` poisoned bytes after each of its parts, so any access outside
 // the intended array stops the run with a report.
 //
-// Input file (little endian): int32 dtype (0 FP64, 1 FP32), nblk, b, rel,
+// Input file (little endian): int32 dtype (0 FP64, 1 FP32, 2 FP32 blocks
+// factored in FP64), nblk, b, rel,
 // max_n, max_kmax, groups, has_hint, has_perm; double tol; uint64 seed, gap;
 // per block int32 m, n, kmax, hint; nblk int32 perm (if has_perm); then per
-// block its m x n row-major matrix in the dtype.  Blocks are dealt to the
+// block its m x n row-major matrix in the storage type.  Blocks are dealt to the
 // emulated workgroups round robin in processing order, each workgroup taking
 // its blocks from the kernel's own queue.
 // Output file: per block int32 k, status, passes; double E; k int32 J; then
-// k x (n - k) entries of T in the dtype.
+// k x (n - k) entries of T in the factor type.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -70,7 +71,11 @@ struct Args {
 
 void body(void* p) {
   Args& a = *static_cast<Args*>(p);
-  if (a.dtype == 0)
+  if (a.dtype == 2)
+    rid::k_batched<double, float>(a.nblk, a.A, a.lda, a.m, a.n, a.b, a.tol, a.rel, a.kmax, a.hint,
+                                  a.seed, a.J, a.T, a.ldt, a.k, a.E, a.st, a.passes, a.perm,
+                                  a.queue, a.wbase, a.lay, a.max_n, a.maxk);
+  else if (a.dtype == 0)
     rid::k_batched<double>(a.nblk, a.A, a.lda, a.m, a.n, a.b, a.tol, a.rel, a.kmax, a.hint, a.seed,
                            a.J, a.T, a.ldt, a.k, a.E, a.st, a.passes, a.perm, a.queue, a.wbase,
                            a.lay, a.max_n, a.maxk);
@@ -98,7 +103,8 @@ int main(int argc, char** argv) {
   rd(f, &tol);
   rd(f, &seed);
   rd(f, &gap);
-  const size_t es = dtype == 0 ? 8 : 4;
+  const size_t es = dtype == 1 ? 4 : 8;  // factor type (T and the workspace)
+  const size_t ea = dtype == 0 ? 8 : 4;  // storage type of the blocks
   std::vector<int32_t> m(nblk), n(nblk), kmax(nblk), hint(nblk), perm(nblk);
   for (int i = 0; i < nblk; ++i) {
     int32_t r[4];
@@ -116,8 +122,8 @@ int main(int argc, char** argv) {
   std::vector<int64_t> lda(nblk), ldt(nblk);
   for (int i = 0; i < nblk; ++i) {
     const size_t cnt = (size_t)m[i] * n[i];
-    A[i] = malloc(cnt * es);
-    rd(f, static_cast<unsigned char*>(A[i]), cnt * es);
+    A[i] = malloc(cnt * ea);
+    rd(f, static_cast<unsigned char*>(A[i]), cnt * ea);
     lda[i] = n[i];
     ldt[i] = n[i];
     int kc = kmax[i] < m[i] ? kmax[i] : m[i];

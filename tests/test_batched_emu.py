@@ -116,3 +116,23 @@ def test_emu_fp32_bench_shapes(exe):
         out = run(exe, blocks, 32, tol, seed=7, dtype=np.float32, order=order, groups=2,
                   max_n=1024, max_kmax=1024)
         assert np.all(out.status >= 0) and np.all(out.k >= 1)
+
+
+def test_emu_fp32_storage_fp64_factor_matches_oracle(exe, orc):
+    """FP32-stored blocks factored in FP64: the oracle runs in FP64 on the
+    same FP32 values, so the FP64 parity rule applies unchanged; each
+    workgroup takes several blocks from the queue."""
+    blocks = _blocks(12, seed=31)
+    b, tol = 8, 1e-7
+    A32 = [A.astype(np.float32) for A in blocks]
+    out = run(exe, A32, b, tol, seed=70, dtype=np.float32, factor=np.float64, groups=3)
+    exact = 0
+    for i, A in enumerate(A32):
+        A64 = A.astype(np.float64)
+        o = orc.rid_adaptive(A64, b, tol, min(A.shape), seed=70 + i)
+        ex = o.robust_k == o.k
+        exact += ex
+        check_fp64(A64, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
+                   float(out.err_est[i]), o, b, tag=i, exact=ex,
+                   at_rank=lambda kk, A64=A64, i=i: orc.rid_fixed_rank(A64, kk, b, seed=70 + i))
+    assert exact >= 9, exact

@@ -84,6 +84,61 @@ def test_batched_fp32_matches_oracle(env, orc):
         assert abs(out.err_est[i] - res) <= 0.6 * res + 1e-6 * fro, i
 
 
+def test_batched_fp32_storage_fp64_factor_matches_oracle(env, orc):
+    """FP32-stored blocks factored in FP64 (the FP32 batched form that reads
+    half the bytes of the FP64 path): the oracle runs in FP64 on the same FP32
+    values, so the FP64 parity rule applies."""
+    torch, rid = env
+    print("batched fp32-storage", file=sys.stderr, flush=True)
+    blocks = [A.astype(np.float32) for A in _blocks(24, seed=31)]
+    dev = [torch.tensor(A, device="cuda") for A in blocks]
+    b, tol = 8, 1e-7   # ranks 16-40: two to five panels per block
+    out = rid.batched(dev, b, tol, seed=70, factor=torch.float64)
+    exact = 0
+    for i, A in enumerate(blocks):
+        A64 = A.astype(np.float64)
+        o = orc.rid_adaptive(A64, b, tol, min(A.shape), seed=70 + i)
+        ex = o.robust_k == o.k
+        exact += ex
+        assert out.T[i].dtype == torch.float64
+        check_fp64(A64, out.J[i].cpu().numpy(), out.T[i].cpu().numpy(), int(out.k[i]),
+                   int(out.status[i]), float(out.err_est[i]), o, b, tag=i, exact=ex,
+                   at_rank=lambda kk, A64=A64, i=i: orc.rid_fixed_rank(A64, kk, b, seed=70 + i))
+    assert exact == 24, exact  # every decision above the FP64 floor
+
+
+def test_batched_fp32_storage_many_blocks_per_workgroup(env, orc):
+    """600 FP32-stored blocks (64-256 per side) on at most one workgroup per
+    compute unit, largest first, so that workgroups take several blocks from
+    the queue: a seeded sample of 32 blocks against the oracle, and every
+    block's outcome valid."""
+    torch, rid = env
+    print("batched fp32-storage, 600 blocks", file=sys.stderr, flush=True)
+    shapes = workloads.kernel_batch_shapes(600, 41, 64, 256)
+    blocks = [workloads.kernel_block(m, n, sep, s).astype(np.float32)
+              for (m, n, sep, s) in shapes]
+    dev = [torch.tensor(A, device="cuda") for A in blocks]
+    cost = np.array([a.shape[0] * a.shape[1] for a in blocks])
+    order = list(np.argsort(-cost, kind="stable"))
+    b, tol = 16, 1e-7
+    out = rid.batched(dev, b, tol, seed=900, order=order, factor=torch.float64)
+    assert np.all(out.status == rid.RID_OK)
+    for i, A in enumerate(blocks):
+        k = int(out.k[i])
+        J = out.J[i].cpu().numpy()
+        assert 1 <= k <= min(A.shape) and len(np.unique(J)) == k
+        assert J.min() >= 0 and J.max() < A.shape[1]
+    sample = np.random.default_rng(5).choice(len(blocks), size=32, replace=False)
+    for i in sample:
+        A64 = blocks[i].astype(np.float64)
+        o = orc.rid_adaptive(A64, b, tol, min(A64.shape), seed=900 + int(i))
+        check_fp64(A64, out.J[i].cpu().numpy(), out.T[i].cpu().numpy(), int(out.k[i]),
+                   int(out.status[i]), float(out.err_est[i]), o, b, tag=int(i),
+                   exact=o.robust_k == o.k,
+                   at_rank=lambda kk, A64=A64, i=i: orc.rid_fixed_rank(A64, kk, b,
+                                                                      seed=900 + int(i)))
+
+
 def test_batched_hint_and_order(env, orc):
     """A first-block width (predicted rank) follows the oracle's variant with
     the same first width; the processing order does not change any result."""
