@@ -88,8 +88,11 @@ def main():
                     help="1: time the 4096-block batched workload (0 skips it)")
     ap.add_argument("--nblk", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=5)
-    ap.add_argument("--learned-blocks", type=int, default=1536,
-                    help="training blocks of the learned-rank section (0 skips it)")
+    ap.add_argument("--learned-blocks", type=int, default=65536,
+                    help="training blocks per form of the learned-rank section, in chunks of "
+                         "4096 (0 skips it)")
+    ap.add_argument("--learned-test-blocks", type=int, default=16384,
+                    help="held-out blocks of the learned-rank comparison")
     ap.add_argument("--paper-sizes", type=str, default="2048,4096,8192,16384",
                     help="n of the paper's n x n Fast Decay timing workload (empty: skip)")
     ap.add_argument("--paper-steps", type=int, default=2)
@@ -619,43 +622,79 @@ def bench_paper(args, torch, rid, workloads):
 
 
 def bench_learned(args, torch, rid, workloads):
-    """Learned rank: train the rank MLP on the GPU (labels from the FP64
-    batched path) and compare FP64 batched runs with and without its hints
-    on held-out kernel blocks (64-384 per side, tol 1e-10, b = 8)."""
+    """Learned rank on the batched workload: the rank MLP is trained on the
+    GPU with labels that the batched path itself produces on generated
+    kernel blocks (64-1024 per side; FP64 at 1e-8 and FP32 storage at 1e-6,
+    the tolerance a feature; labels at block size 4 so that a hint can be
+    finer than b = 32), its hint margin is chosen on a validation set, and
+    on 16384 held-out blocks the batched call with hints (probe features and
+    MLP in the same HIP graph) is compared with the plain adaptive batched
+    call at b = 32."""
     import numpy as np
     from paper_2310_09417_amd import learned_rank as lr
     dev = torch.device("cuda:0")
-    tol, b, seed = 1e-10, 8, 100
+    b, seed, chunk = 32, 100, 4096
+    b_label = 4  # labels at a fine rank granularity, so hints can undercut b
+    n_chunks = max(1, args.learned_blocks // chunk)
+    forms = ((1e-8, torch.float64, None), (1e-6, torch.float32, torch.float64))
     t0 = time.time()
-    tr, _ = workloads.kernel_blocks_device(args.learned_blocks, 21, device=dev, lo=64, hi=384)
-    k, _ = lr.labels(tr, b, tol, seed)
-    F = rid.rank_features(tr, tol, seed)
+    F, k = lr.training_set(
+        lambda i: workloads.kernel_blocks_device(chunk, 1000 + i, device=dev)[0], n_chunks,
+        forms, b_label, seed)
+    torch.cuda.synchronize()
     t1 = time.time()
-    model, hist = lr.fit(F, k, epochs=40, batch=256, seed=0)
+    model, hist = lr.fit(F, k, epochs=30, batch=1024, seed=0)
     torch.cuda.synchronize()
     t2 = time.time()
-    del tr, F
-    te, _ = workloads.kernel_blocks_device(512, 77, device=dev, lo=64, hi=384)
-    res = lr.evaluate(te, model, b, tol, seed)
-    a, l = res["adaptive"], res["learned"]
-    out = {
-        "workload": "FP64 kernel blocks 1/|x-y| (cube separation 3-6), m,n uniform in "
-                    f"[64,384], tol {tol:g} relative, b={b}; {args.learned_blocks} training "
-                    "blocks, 512 held out",
-        "train_blocks": args.learned_blocks, "label_and_feature_s": t1 - t0,
-        "train_s": t2 - t1, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-        "adaptive": {"ms": a["ms"], "mean_passes": float(a["passes"].mean()),
-                     "mean_k": float(a["k"].mean()),
-                     "all_ok": bool(np.all(a["status"] == rid.RID_OK))},
-        "learned": {"ms": l["ms"], "mean_passes": float(l["passes"].mean()),
-                    "mean_k": float(l["k"].mean()), "fallback": l["fallback"],
-                    "all_ok": bool(np.all(l["status"] == rid.RID_OK))},
-        "speedup": a["ms"] / l["ms"],
-    }
-    log(f"[bench] learned rank: adaptive {a['ms']:.2f} ms ({out['adaptive']['mean_passes']:.2f} "
-        f"passes), learned {l['ms']:.2f} ms ({out['learned']['mean_passes']:.2f} passes, "
-        f"fallback {l['fallback']}/512), mean k {out['adaptive']['mean_k']:.1f} -> "
-        f"{out['learned']['mean_k']:.1f}")
+    log(f"[bench] learned rank: {len(k)} labelled blocks ({n_chunks} x {chunk} per form) in "
+        f"{t1 - t0:.1f}s, trained in {t2 - t1:.1f}s, pinball loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+    del F
+    val, _ = workloads.kernel_blocks_device(4096, 555, device=dev)
+    test, shapes = workloads.kernel_blocks_device(args.learned_test_blocks, 77, device=dev)
+    cost = np.array([m * n for (m, n, _, _) in shapes])
+    order = list(np.argsort(-cost, kind="stable"))
+    out = {"workload": f"{args.learned_test_blocks} held-out kernel blocks 1/|x-y|, m,n uniform "
+                       f"in [64,1024], b={b}; hints from the rank MLP vs the plain adaptive "
+                       f"batched call, both in HIP graphs, largest blocks first",
+           "train_blocks": int(len(k)), "train_blocks_per_form": n_chunks * chunk,
+           "label_and_feature_s": t1 - t0, "train_s": t2 - t1,
+           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "forms": {}}
+    for tol, storage, factor in forms:
+        name = "fp64_tol1e-8" if storage == torch.float64 else "fp32_storage_fp64_factor_tol1e-6"
+        vb = val if storage == torch.float64 else [a.to(storage) for a in val]
+        tb = test if storage == torch.float64 else [a.to(storage) for a in test]
+        margin = lr.choose_margin(vb, model, b, tol, seed, factor=factor)
+        res = lr.evaluate(tb, model, b, tol, seed, margin=margin, factor=factor, order=order,
+                          graph=True, reps=3)
+        a, l = res["adaptive"], res["learned"]
+        ok_a = bool(np.all(a["status"] == rid.RID_OK))
+        ok_l = bool(np.all(l["status"] == rid.RID_OK))
+        r = {"margin": margin,
+             "adaptive": {"ms": a["ms"], "blocks_per_s": len(tb) / (a["ms"] * 1e-3),
+                          "mean_passes": float(a["passes"].mean()),
+                          "mean_k": float(a["k"].mean()), "all_ok": ok_a},
+             "learned": {"ms": l["ms"], "predict_ms": l["predict_ms"],
+                         "blocks_per_s": len(tb) / (l["ms"] * 1e-3),
+                         "mean_passes": float(l["passes"].mean()),
+                         "mean_k": float(l["k"].mean()), "fallback": l["fallback"],
+                         "fallback_rate": l["fallback"] / len(tb), "all_ok": ok_l},
+             "speedup": a["ms"] / l["ms"]}
+        out["forms"][name] = r
+        log(f"[bench] learned rank {name} (margin {margin}): adaptive {a['ms']:.2f} ms "
+            f"({r['adaptive']['mean_passes']:.2f} passes, mean k {r['adaptive']['mean_k']:.1f}), "
+            f"learned {l['ms']:.2f} ms incl. {l['predict_ms']:.2f} ms features and MLP "
+            f"({r['learned']['mean_passes']:.2f} passes, mean k {r['learned']['mean_k']:.1f}, "
+            f"fallback {l['fallback']}/{len(tb)}), speedup {r['speedup']:.2f}x")
+        del vb, tb
+    # the plain FP64 path at the same tolerance as the FP32-storage form
+    p64 = lr.evaluate(test, None, b, 1e-6, seed, order=order, graph=True, reps=3)["adaptive"]
+    out["fp64_plain_tol1e-6_ms"] = p64["ms"]
+    out["speedup_fp32_storage_learned_vs_fp64_plain_tol1e-6"] = (
+        p64["ms"] / out["forms"]["fp32_storage_fp64_factor_tol1e-6"]["learned"]["ms"])
+    log(f"[bench] learned rank: plain FP64 at 1e-6 {p64['ms']:.2f} ms; FP32-storage learned form "
+        f"{out['speedup_fp32_storage_learned_vs_fp64_plain_tol1e-6']:.2f}x faster")
+    del val, test
+    torch.cuda.empty_cache()
     return out
 
 

@@ -533,6 +533,19 @@ class BatchPlan:
             raise RidError("invalid batch sizes (every block needs n <= 1024, b <= 32)")
         self.work = torch.empty(wb, dtype=torch.uint8, device=dev)
 
+    def features(self, tol=None, stream=None):
+        """Probe features of the plan's blocks (nblk x 19 FP32 device tensor)
+        from its device argument arrays: no host work per block and no
+        synchronisation, so it can be captured with the launch."""
+        torch = _torch()
+        F = torch.empty((self.nblk, N_FEATURES), dtype=torch.float32, device=self.A.device)
+        cfgf = _cfg(self.cfg.a_type, self.cfg.seed, bool(self.cfg.tol_relative))
+        _check(int(library().rid_rank_features(
+            self.nblk, self.A.data_ptr(), self.lda.data_ptr(), self.m.data_ptr(),
+            self.n.data_ptr(), self.tol if tol is None else tol, ctypes.byref(cfgf), F.data_ptr(),
+            stream if stream is not None else _stream_ptr())), "rid_rank_features")
+        return F
+
     def launch(self, stream=None):
         rc = rid_lupp_batched(
             self.nblk, self.A.data_ptr(), self.lda.data_ptr(), self.m.data_ptr(),

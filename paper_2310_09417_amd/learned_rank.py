@@ -88,13 +88,36 @@ def feature_norm(F):
     return torch.cat([mu, 1.0 / sd]).float().contiguous()
 
 
-def labels(blocks, b: int, tol: float, seed: int, kmax=None, relative: bool = True):
+def labels(blocks, b: int, tol: float, seed: int, kmax=None, relative: bool = True,
+           factor=None):
     """Ranks (numpy int32) and statuses the adaptive method reaches on the
-    blocks through the batched path (pass FP64 blocks for FP64 labels)."""
-    plan = B.BatchPlan(blocks, b, tol, kmax=kmax, seed=seed, relative=relative)
+    blocks through the batched path (pass FP64 blocks for FP64 labels;
+    factor=torch.float64 with FP32 blocks for the FP32-storage form)."""
+    plan = B.BatchPlan(blocks, b, tol, kmax=kmax, seed=seed, relative=relative, factor=factor)
     plan.launch()
     out = plan.result()
     return out.k.astype(np.int32), out.status.astype(np.int32)
+
+
+def training_set(make_chunk, n_chunks: int, forms, b: int, seed: int):
+    """Features and labels over n_chunks generated chunks of blocks, keeping
+    only those (the blocks of a chunk are dropped before the next one).
+    make_chunk(i) -> list of FP64 device blocks; forms: (tol, storage dtype,
+    factor) triples, each labelled by the batched path itself with the stream
+    of seed + block index within the chunk.  Returns (F: N x 19 device FP32,
+    k: numpy int32)."""
+    torch = _torch()
+    Fs, ks = [], []
+    for i in range(n_chunks):
+        blocks64 = make_chunk(i)
+        for tol, storage, factor in forms:
+            blocks = blocks64 if storage == torch.float64 else [a.to(storage) for a in blocks64]
+            k, _ = labels(blocks, b, tol, seed, factor=factor)
+            Fs.append(B.rank_features(blocks, tol, seed))
+            ks.append(k)
+            del blocks
+        del blocks64
+    return torch.cat(Fs), np.concatenate(ks)
 
 
 def fit(F, k, epochs: int = 60, batch: int = 1024, lr: float = 2e-3, q: float = 0.9,
@@ -137,40 +160,89 @@ def fit(F, k, epochs: int = 60, batch: int = 1024, lr: float = 2e-3, q: float = 
     return model, hist
 
 
+def learned_launch(plan, model: RankModel, caps, margin: float):
+    """The learned batched call on one stream, without host synchronisation
+    (capturable in a HIP graph): probe features of the plan's blocks, the
+    MLP, the hints written into the plan's k_hint array, then the batched
+    launch.  The plan must have been made with a k_hint array."""
+    F = plan.features()
+    h = B.rank_hint(model.predict_log2(F), caps, margin)
+    plan.k_hint.copy_(h)
+    plan.launch()
+
+
 def evaluate(blocks, model: RankModel | None, b: int, tol: float, seed: int, margin=0.25,
-             relative: bool = True):
-    """One batched run with and without the model's hints on the same
-    blocks: time, passes over each block, ranks, statuses, fallback count."""
+             relative: bool = True, factor=None, order=None, graph: bool = False,
+             reps: int = 1):
+    """Batched runs with and without the model's hints on the same blocks:
+    time (the learned time covers the probe features, the MLP and the
+    hints as well), passes over each block, ranks, statuses, fallback count.
+    graph: time replays of the whole call captured in a HIP graph."""
     torch = _torch()
     res = {}
     dev = blocks[0].device
     caps = torch.tensor([min(int(a.shape[0]), int(a.shape[1])) for a in blocks],
                         dtype=torch.int32, device=dev)
-    hint = None
-    if model is not None:
-        F = B.rank_features(blocks, tol, seed, relative)
-        hint = model.hints(F, caps, margin)
-    for name, h in (("adaptive", None), ("learned", hint)):
-        if name == "learned" and h is None:
+    for name in ("adaptive", "learned"):
+        if name == "learned" and model is None:
             continue
-        plan = B.BatchPlan(blocks, b, tol, seed=seed, relative=relative,
-                           k_hint=h.cpu().numpy() if h is not None else None)
-        plan.launch()
+        hint0 = np.zeros(len(blocks), dtype=np.int32) if name == "learned" else None
+        plan = B.BatchPlan(blocks, b, tol, seed=seed, relative=relative, k_hint=hint0,
+                           order=order, factor=factor)
+        if name == "learned":
+            def call(st=None):
+                learned_launch(plan, model, caps, margin)
+        else:
+            def call(st=None):
+                plan.launch()
+        call()
         torch.cuda.synchronize()
+        run = call
+        g = None
+        if graph:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                call()
+            g.replay()
+            torch.cuda.synchronize()
+            run = g.replay
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        plan.launch()
+        for _ in range(reps):
+            run()
         e1.record()
         torch.cuda.synchronize()
         out = plan.result()
-        res[name] = {"ms": float(e0.elapsed_time(e1)), "k": out.k, "status": out.status,
+        res[name] = {"ms": float(e0.elapsed_time(e1)) / reps, "k": out.k, "status": out.status,
                      "passes": out.passes, "err_est": out.err_est}
-    if hint is not None:
-        h = hint.cpu().numpy()
+        if name == "learned":
+            res[name]["hint"] = plan.k_hint.cpu().numpy()
+            # the prediction alone (features, MLP, hints), for the split
+            e0.record()
+            for _ in range(reps):
+                F = plan.features()
+                plan.k_hint.copy_(B.rank_hint(model.predict_log2(F), caps, margin))
+            e1.record()
+            torch.cuda.synchronize()
+            res[name]["predict_ms"] = float(e0.elapsed_time(e1)) / reps
+        del g, plan
+    if "learned" in res:
+        h = res["learned"]["hint"]
         mn = caps.cpu().numpy()
         # the hinted first passes cover w0 + b vectors (w0 alone at full rank),
         # 64 per pass; any further pass is the adaptive fallback
         first = np.where(h < mn, (h + b + 63) // 64, (h + 63) // 64)
         res["learned"]["fallback"] = int(np.sum(res["learned"]["passes"] > first))
-        res["learned"]["hint"] = h
     return res
+
+
+def choose_margin(blocks, model: RankModel, b: int, tol: float, seed: int,
+                  margins=(0.0, 0.1, 0.25, 0.5), **kw):
+    """The hint margin with the shortest measured time on a validation set
+    (blocks not used for training or for the final comparison)."""
+    best, best_ms = margins[0], None
+    for mg in margins:
+        r = evaluate(blocks, model, b, tol, seed, margin=mg, **kw)["learned"]
+        if best_ms is None or r["ms"] < best_ms:
+            best, best_ms = mg, r["ms"]
+    return best
