@@ -101,7 +101,25 @@ typedef struct {
   int embedding;        /* rid_embedding of the sketch: RID_EMB_GAUSSIAN (the
                            default) or RID_EMB_SPARSE_SIGN (a_type == dtype
                            only; not on the batched path)                      */
+  int side;             /* rid_side: RID_COLUMNS (0, the default) or RID_ROWS */
 } rid_config;
+
+/*
+ * Which ID (Sec. 2.2): RID_COLUMNS selects columns J of A with
+ * A(:, J^c) ~= A(:, J) T (the column ID, the form used throughout this
+ * header).  RID_ROWS selects rows I of A with A(I^c, :) ~= T^T A(I, :) (the
+ * row ID, A ~= W A(I, :) with W(I, :) = I and W(I^c, :) = T^T), i.e. the
+ * column ID of A^T: the sketch is Y = A Omega with Omega n x l Gaussian,
+ * formed from A in place (its rows are contracted, no transposed copy), and
+ * LU with partial pivoting on Y picks the rows.  Then J receives row indices
+ * (in [0, m)), T is k x (m - k) with leading dimension ldt >= m (column q for
+ * the q-th non-skeleton row in ascending order), and relative tolerances
+ * refer to ||A||_F as before.  RID_ROWS is supported by rid_lupp_fixed_rank,
+ * rid_lupp_fixed_rank_noalloc, rid_lupp_adaptive, rid_workspace_bytes and
+ * rid_debug_sketch with a_type == dtype (RID_F64 or RID_F32 storage); the
+ * other entry points return RID_ERR_ARG (or 0 bytes) for it.
+ */
+typedef enum { RID_COLUMNS = 0, RID_ROWS = 1 } rid_side;
 
 /*
  * Random embeddings of the sketch (Sec. 5, random matrix distributions).

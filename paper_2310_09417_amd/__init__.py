@@ -17,5 +17,5 @@ from .binding import (  # noqa: F401
     rank_features, mlp_param_count, mlp_forward, mlp_backward, mlp_adamw, rank_hint, N_FEATURES,
     RID_EST_SCHUR, RID_EST_SAMPLE, RID_EST_UR_FRO, RID_EST_UR_MAX, certificate, rid_certificate,
     rid_certificate_workspace_bytes, row_skeletons, rid_lupp_rows, rid_rows_workspace_bytes,
-    RowsOutput, RID_EMB_GAUSSIAN, RID_EMB_SPARSE_SIGN)
+    RowsOutput, RID_EMB_GAUSSIAN, RID_EMB_SPARSE_SIGN, RID_COLUMNS, RID_ROWS)
 from .flops import flops_id  # noqa: F401

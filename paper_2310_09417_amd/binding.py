@@ -30,7 +30,8 @@ class RidConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("a_type", ctypes.c_int),
                 ("a_col_scale", ctypes.c_void_p), ("refine", ctypes.c_int),
                 ("estimator", ctypes.c_int), ("resid_p", ctypes.c_int),
-                ("est_out", ctypes.c_void_p), ("embedding", ctypes.c_int)]
+                ("est_out", ctypes.c_void_p), ("embedding", ctypes.c_int),
+                ("side", ctypes.c_int)]
 
 
 _lib = None
@@ -112,13 +113,17 @@ RID_EST_SCHUR, RID_EST_SAMPLE, RID_EST_UR_FRO, RID_EST_UR_MAX = 0, 1, 2, 3
 RID_EMB_GAUSSIAN, RID_EMB_SPARSE_SIGN = 0, 1
 
 
+# Which ID (rid_side): columns J of A (the default), or rows I of A.
+RID_COLUMNS, RID_ROWS = 0, 1
+
+
 def _cfg(dtype: int, seed: int, tol_relative: bool = True, a_type: int | None = None,
          col_scale: int = 0, refine: bool = False, estimator: int = 0, resid_p: int = 0,
-         est_out: int = 0, embedding: int = 0) -> RidConfig:
+         est_out: int = 0, embedding: int = 0, side: int = 0) -> RidConfig:
     return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed,
                      a_type=dtype if a_type is None else a_type, a_col_scale=col_scale or None,
                      refine=1 if refine else 0, estimator=estimator, resid_p=resid_p,
-                     est_out=est_out or None, embedding=embedding)
+                     est_out=est_out or None, embedding=embedding, side=side)
 
 
 # ---- raw C-ABI mirrors (pointers as ints) ----------------------------------
@@ -231,14 +236,15 @@ def _dtype_code(t) -> int:
 
 
 def _config_for(A, seed: int, relative: bool = True, col_scale=None, refine: bool = False,
-                estimator: int = 0, resid_p: int = 0, est_out: int = 0, embedding: int = 0):
+                estimator: int = 0, resid_p: int = 0, est_out: int = 0, embedding: int = 0,
+                side: int = 0):
     """Config for A's storage: float64 / float32 run the whole path in that
     type; bfloat16 A, or float8_e4m3fn (or uint8 codes) A with col_scale
     (float32 device tensor, ceil(n/128) powers of two), run the sketch in that
     format and the factorisation in FP32.  Returns (cfg, dtype of T)."""
     torch = _torch()
     ex = dict(refine=refine, estimator=estimator, resid_p=resid_p, est_out=est_out,
-              embedding=embedding)
+              embedding=embedding, side=side)
     if A.dtype in (torch.float64, torch.float32):
         if col_scale is not None:
             raise RidError("col_scale applies to FP8 storage only")
@@ -311,55 +317,60 @@ def _work(nbytes, device):
 
 
 def fixed_rank(A, k: int, p: int, seed: int, work=None, col_scale=None,
-               refine: bool = False, estimator: int = 0, embedding: int = 0) -> IDOutput:
+               refine: bool = False, estimator: int = 0, embedding: int = 0,
+               side: int = RID_COLUMNS) -> IDOutput:
     """randLUPP at rank k with p estimation vectors (A: m x n device tensor;
     BF16 / FP8 storage as described in _config_for).  estimator > 0: the p
-    vectors give the Remark-1 estimates (returned in est3)."""
+    vectors give the Remark-1 estimates (returned in est3).  side=RID_ROWS:
+    the row ID (J holds rows of A, T has m - k columns)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
-    cfg, tdt = _config_for(A, seed, True, col_scale, refine, embedding=embedding)
-    out = _Outputs(k, n, tdt, A.device)
+    nc = m if side == RID_ROWS else n
+    cfg, tdt = _config_for(A, seed, True, col_scale, refine, embedding=embedding, side=side)
+    out = _Outputs(k, nc, tdt, A.device)
     if estimator:
         cfg, tdt = _config_for(A, seed, True, col_scale, refine, estimator, 0, out.est.data_ptr(),
-                               embedding)
+                               embedding, side)
     wb = rid_workspace_bytes(m, n, k + p, p, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
     if work is None:
         work = _work(wb, A.device)
     rc = rid_lupp_fixed_rank(A.data_ptr(), m, n, lda, k, p, cfg, out.J.data_ptr(),
-                             out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
+                             out.T.data_ptr(), nc, out.k.data_ptr(), out.E.data_ptr(),
                              out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
     _check(rc, "rid_lupp_fixed_rank")
-    return out.result(n, with_est=bool(estimator))
+    return out.result(nc, with_est=bool(estimator))
 
 
 def adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
              work=None, col_scale=None, refine: bool = False, estimator: int = 0,
-             resid_p: int = 8, embedding: int = 0) -> IDOutput:
+             resid_p: int = 8, embedding: int = 0, side: int = RID_COLUMNS) -> IDOutput:
     """randLUPPadap with block size b, tolerance tol, rank cap kmax (BF16 /
     FP8 storage as described in _config_for).  estimator > 0 stops on a
-    Remark-1 estimate from resid_p set-aside vectors (estimates in est3)."""
+    Remark-1 estimate from resid_p set-aside vectors (estimates in est3).
+    side=RID_ROWS: the row ID (J holds rows of A, T has m - k columns)."""
     m, n = A.shape
     lda = A.stride(0)
     assert A.stride(1) == 1
     cap = min(kmax, m, n)
-    cfg, tdt = _config_for(A, seed, relative, col_scale, refine, embedding=embedding)
-    out = _Outputs(cap, n, tdt, A.device)
+    nc = m if side == RID_ROWS else n
+    cfg, tdt = _config_for(A, seed, relative, col_scale, refine, embedding=embedding, side=side)
+    out = _Outputs(cap, nc, tdt, A.device)
     if estimator:
         cfg, tdt = _config_for(A, seed, relative, col_scale, refine, estimator, resid_p,
-                               out.est.data_ptr(), embedding)
+                               out.est.data_ptr(), embedding, side)
     wb = rid_workspace_bytes(m, n, kmax, b, cfg)
     if wb == 0:
         raise RidError("invalid sizes")
     if work is None:
         work = _work(wb, A.device)
     rc = rid_lupp_adaptive(A.data_ptr(), m, n, lda, b, tol, kmax, cfg, out.J.data_ptr(),
-                           out.T.data_ptr(), n, out.k.data_ptr(), out.E.data_ptr(),
+                           out.T.data_ptr(), nc, out.k.data_ptr(), out.E.data_ptr(),
                            out.st.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr())
     _check(rc, "rid_lupp_adaptive")
-    return out.result(n, with_est=bool(estimator))
+    return out.result(nc, with_est=bool(estimator))
 
 
 @dataclass
@@ -448,16 +459,18 @@ def debug_mfma_probe(kind: int, A, B):
     return D
 
 
-def debug_sketch(A, seed: int, c0: int, w: int, col_scale=None, embedding: int = 0):
+def debug_sketch(A, seed: int, c0: int, w: int, col_scale=None, embedding: int = 0,
+                 side: int = RID_COLUMNS):
     """(Omega(c0:c0+w) A)^T as an n x w tensor, computed by the sketch kernels
     (BF16 / FP8 storage as described in _config_for; result in FP32 then).
-    With the sparse sign embedding the w vectors form one draw."""
+    With the sparse sign embedding the w vectors form one draw.  side=RID_ROWS:
+    A Omega(c0:c0+w)^T (m x w), Omega over A's columns."""
     torch = _torch()
     m, n = A.shape
-    cfg, ydt = _config_for(A, seed, True, col_scale, embedding=embedding)
+    cfg, ydt = _config_for(A, seed, True, col_scale, embedding=embedding, side=side)
     wb = rid_workspace_bytes(m, n, w, w, cfg)
     work = _work(wb, A.device)
-    Yt = torch.empty((n, w), dtype=ydt, device=A.device)
+    Yt = torch.empty((m if side == RID_ROWS else n, w), dtype=ydt, device=A.device)
     _check(rid_debug_sketch(A.data_ptr(), m, n, A.stride(0), c0, w, cfg, Yt.data_ptr(), w,
                             work.data_ptr(), work.numel(), _stream_ptr()), "rid_debug_sketch")
     torch.cuda.current_stream().synchronize()

@@ -200,6 +200,26 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   return g;
 }
 
+// Row-form sketch geometry (k_sketch_rows): 64 rows of A per workgroup and
+// enough splits of the contraction (A's columns, in multiples of 32) for
+// about four workgroups per CU, each split at least 256 columns long.
+struct SketchGeomR {
+  int mt, wp;
+  int64_t ntile, nsplit, cols_per_split;
+};
+
+SketchGeomR sketch_geom_rows(int64_t mrows, int64_t ncols, int w, int cu) {
+  SketchGeomR g;
+  g.mt = w <= 16 ? 1 : w <= 32 ? 2 : 4;
+  g.wp = g.mt * 16;
+  g.ntile = ceil_div(mrows, 64);
+  const int64_t maxsplit = std::max<int64_t>(1, ncols / 256);
+  const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(4 * cu, g.ntile)));
+  g.cols_per_split = ceil_div(ceil_div(ncols, ns), 32) * 32;
+  g.nsplit = ceil_div(ncols, g.cols_per_split);
+  return g;
+}
+
 // Low-precision sketch geometry: 1024 columns per workgroup, one workgroup
 // per CU.  The split count minimises (rounds x bytes of A per workgroup) plus
 // the FP32 partials written and read back, per CU.
@@ -242,6 +262,7 @@ struct Plan {
   int est = 0;                   // rid_estimator of the stopping test
   int emb = 0;                   // rid_embedding of the sketch
   int resid_p = 0;               // set-aside sample width (adaptive, est > 0)
+  int side = RID_COLUMNS;        // RID_ROWS: the column form of A^T, A read in place
   int64_t zr = 0;                // first Z column of the sample (adaptive, est > 0)
   int64_t zs = 0;                // first Z column of its copy that the private LU factors
   int64_t ldz = 0, ldu = 0, ldl = 0, ldg = 0;
@@ -260,9 +281,10 @@ struct Plan {
 // est > 0: a Remark-1 stopping estimate; sample_cols > 0 (adaptive calls)
 // reserves that many Z columns after the decomposition's own for the sample.
 bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, rid_dtype at,
-               bool refine, int est, int sample_cols, Plan& P) {
+               bool refine, int est, int sample_cols, Plan& P, int side = RID_COLUMNS) {
   DeviceInfo di = device_info();
   if (!di.ok) return false;
+  P.side = side;
   P.m = m;
   P.n = n;
   P.kcap = kcap;
@@ -299,6 +321,11 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
     LpGeom g = sketch_geom_lp(m, n, at == RID_BF16 ? 2 : 1, di.cu);
     pb = (size_t)g.nsplit * (size_t)n * 64 * 4;
     fc = (size_t)(g.nsplit * g.ncolg);
+  } else if (side == RID_ROWS) {
+    // candidates are A's rows (n here), the contraction runs over its columns (m)
+    SketchGeomR g = sketch_geom_rows(n, m, (int)std::min<int64_t>(wmax, 64), di.cu);
+    pb = (size_t)g.nsplit * (size_t)n * g.wp * 8;
+    fc = (size_t)(g.nsplit * g.ntile);
   } else {
     SketchGeom g = sketch_geom(m, n, (int)std::min<int64_t>(wmax, 64), dt, di.cu);
     pb = (size_t)g.nsplit * (size_t)n * g.wp * 8;
@@ -347,18 +374,24 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
 }
 
 // Plan of a call with rank cap kmax and block width b (fixed rank: kmax = k + p,
-// b = p): kcap = min(kmax, m, n), widest block min(128, max(b, min(kcap, 128))).
+// b = p): kcap = min(kmax, m, n), widest block min(128, max(b, min(kcap, 64))): the
+// adaptive blocks have b columns, the fixed-rank panels at most 64 and its
+// estimate block p.
 // sample: the call sets a Remark-1 sample aside (adaptive calls with an
 // estimator).
 bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* cfg, Plan& P,
               bool sample = false) {
+  // the row form is the column form of A^T: n "rows" (A's columns) and m
+  // candidates (A's rows)
+  const int side = cfg->side;
+  if (side == RID_ROWS) std::swap(m, n);
   const int64_t kcap = std::min<int64_t>(kmax, std::min(m, n));
   int64_t wmax =
-      std::min<int64_t>(kMaxW, std::max<int64_t>({b, std::min<int64_t>(kcap, kMaxW), 1}));
+      std::min<int64_t>(kMaxW, std::max<int64_t>({b, std::min<int64_t>(kcap, kPanel), 1}));
   const int est = cfg->estimator;
   if (sample && est > 0) wmax = std::max<int64_t>(wmax, cfg->resid_p);
   if (!make_plan(m, n, kcap, wmax, cfg->dtype, cfg->a_type, cfg->refine != 0, est,
-                 sample && est > 0 ? cfg->resid_p : 0, P))
+                 sample && est > 0 ? cfg->resid_p : 0, P, side))
     return false;
   P.emb = cfg->embedding;
   P.scale = cfg->a_col_scale;
@@ -373,7 +406,7 @@ size_t cert_part_bytes(int64_t n, int64_t p) {
 // Plan of the row-skeleton step: the m rows of A are the candidates, C has k
 // columns; there is no sketch (one sketch row keeps its buffers minimal).
 bool plan_rows(int64_t m, int64_t k, const rid_config* cfg, Plan& P) {
-  const int64_t wmax = std::min<int64_t>(kMaxW, std::max<int64_t>(std::min<int64_t>(k, kMaxW), 1));
+  const int64_t wmax = std::max<int64_t>(std::min<int64_t>(k, kPanel), 1);  // panels of <= 64
   return make_plan(1, m, k, wmax, cfg->dtype, cfg->dtype, false, 0, 0, P);
 }
 
@@ -509,6 +542,59 @@ int launch_sketch(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64
                                                st);
 }
 
+// Row form: Omega over A's columns (P.m of them), then the row-form sketch.
+template <typename TC, int MT, bool VEC>
+int launch_sketch_rows_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                         int64_t c0, int w, const SketchGeomR& g, bool norm, bool use_ctrl,
+                         const Draw& dr, hipStream_t st) {
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  TC* om = static_cast<TC*>(W.omega);
+  const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
+  long pm = prof_begin(KC_OMEGA, st);
+  if (P.emb == RID_EMB_SPARSE_SIGN)
+    hipLaunchKernelGGL(k_omega_ss<TC>, dim3((unsigned)ceil_div(mpad, 256)), dim3(256), 0, st, k0,
+                       k1, (uint32_t)dr.c0, dr.w, (int)(c0 - dr.c0), w, g.wp, P.m, mpad, om, ctrl);
+  else
+    hipLaunchKernelGGL(k_omega<TC>, dim3((unsigned)ceil_div(mpad / 4 * g.wp, 256)), dim3(256), 0,
+                       st, k0, k1, (uint32_t)c0, w, g.wp, P.m, mpad, om, ctrl);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  dim3 grid((unsigned)g.ntile, (unsigned)g.nsplit);
+  pm = prof_begin(KC_SKETCH, st);
+  if (norm)
+    hipLaunchKernelGGL((k_sketch_rows<TC, MT, true, VEC>), grid, dim3(256), 0, st,
+                       static_cast<const TC*>(A), P.n, P.m, lda, om, w, g.cols_per_split, W.part,
+                       W.fro, W.nonfinite, ctrl);
+  else
+    hipLaunchKernelGGL((k_sketch_rows<TC, MT, false, VEC>), grid, dim3(256), 0, st,
+                       static_cast<const TC*>(A), P.n, P.m, lda, om, w, g.cols_per_split, W.part,
+                       W.fro, W.nonfinite, ctrl);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+template <typename TC>
+int launch_sketch_rows(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                       int64_t c0, int w, const SketchGeomR& g, bool norm, bool use_ctrl,
+                       const Draw& dr, hipStream_t st) {
+  // 4 consecutive entries per vector load: 16-byte aligned rows
+  const bool vec = (lda % (16 / (int64_t)sizeof(TC)) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+#define RID_ROWS_MT(MTV)                                                                        \
+  return vec ? launch_sketch_rows_t<TC, MTV, true>(P, W, A, lda, seed, c0, w, g, norm, use_ctrl, \
+                                                    dr, st)                                      \
+             : launch_sketch_rows_t<TC, MTV, false>(P, W, A, lda, seed, c0, w, g, norm,         \
+                                                     use_ctrl, dr, st)
+  switch (g.mt) {
+    case 1: RID_ROWS_MT(1);
+    case 2: RID_ROWS_MT(2);
+    default: RID_ROWS_MT(4);
+  }
+#undef RID_ROWS_MT
+}
+
 template <int FMT, bool NORM>
 int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                      int64_t c0, int w, const LpGeom& g, bool use_ctrl, hipStream_t st) {
@@ -566,6 +652,27 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
                          P.at == RID_FP8_E4M3 ? P.scale : nullptr, static_cast<float*>(out), ldo,
                          zcol + off, static_cast<float*>(copy), W.fro, (int)(g.nsplit * g.ncolg),
                          W.nonfinite, ctrl, norm ? 1 : 0);
+      prof_end(pm, st);
+      RID_LAUNCH_CHECK();
+      continue;
+    }
+    if (P.side == RID_ROWS) {
+      SketchGeomR g = sketch_geom_rows(P.n, P.m, wc, P.cu);
+      RID_TRY(P.dt == RID_F64 ? launch_sketch_rows<double>(P, W, A, lda, seed, c0 + off, wc, g,
+                                                           norm, use_ctrl, Draw{c0, w}, st)
+                              : launch_sketch_rows<float>(P, W, A, lda, seed, c0 + off, wc, g,
+                                                          norm, use_ctrl, Draw{c0, w}, st));
+      const long pm = prof_begin(KC_REDUCE, st);
+      if (P.dt == RID_F64)
+        hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
+                           (int)g.nsplit, P.n, g.wp, wc, static_cast<double*>(out), ldo,
+                           zcol + off, static_cast<double*>(copy), W.fro,
+                           (int)(g.nsplit * g.ntile), W.nonfinite, ctrl, norm ? 1 : 0);
+      else
+        hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
+                           (int)g.nsplit, P.n, g.wp, wc, static_cast<float*>(out), ldo,
+                           zcol + off, static_cast<float*>(copy), W.fro,
+                           (int)(g.nsplit * g.ntile), W.nonfinite, ctrl, norm ? 1 : 0);
       prof_end(pm, st);
       RID_LAUNCH_CHECK();
       continue;
@@ -921,6 +1028,9 @@ int init_est_out(double* est_out, hipStream_t st) {
 
 bool valid_cfg(const rid_config* cfg) {
   if (!cfg || (cfg->dtype != RID_F64 && cfg->dtype != RID_F32)) return false;
+  if (cfg->side != RID_COLUMNS && cfg->side != RID_ROWS) return false;
+  // the row form reads A in the factor type
+  if (cfg->side == RID_ROWS && cfg->a_type != cfg->dtype) return false;
   if (cfg->estimator < RID_EST_SCHUR || cfg->estimator > RID_EST_UR_MAX) return false;
   if (cfg->embedding != RID_EMB_GAUSSIAN && cfg->embedding != RID_EMB_SPARSE_SIGN) return false;
   // the low-precision sketch generates Gaussian entries inside its kernel
@@ -935,7 +1045,8 @@ bool valid_cfg(const rid_config* cfg) {
 // The batched path reads A in the factor type, or FP32 blocks under an FP64
 // factorisation.
 bool valid_batched_cfg(const rid_config* cfg) {
-  if (!cfg || cfg->refine != 0 || cfg->embedding != RID_EMB_GAUSSIAN || cfg->estimator != 0)
+  if (!cfg || cfg->refine != 0 || cfg->embedding != RID_EMB_GAUSSIAN || cfg->estimator != 0 ||
+      cfg->side != RID_COLUMNS)
     return false;
   if (cfg->dtype == RID_F64 && cfg->a_type == RID_F32) return true;
   return valid_cfg(cfg) && cfg->a_type == cfg->dtype;
@@ -944,7 +1055,8 @@ bool valid_batched_cfg(const rid_config* cfg) {
 // The row-skeleton step reads A in the factor type, with no refinement or
 // estimator.
 bool valid_rows_cfg(const rid_config* cfg) {
-  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0 && cfg->estimator == 0;
+  return valid_cfg(cfg) && cfg->a_type == cfg->dtype && cfg->refine == 0 && cfg->estimator == 0 &&
+         cfg->side == RID_COLUMNS;
 }
 
 int64_t lds_kcap_limit(rid_dtype dt) { return (int64_t)(kMaxLds / esize(dt)); }
@@ -1029,7 +1141,9 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
                         hipStream_t stream) {
   if (!A || !J || !T || !k_out || !err_est || !status || !work || !valid_cfg(cfg))
     return RID_ERR_ARG;
-  if (m < 1 || n < 1 || lda < n || ldt < n || k < 1 || k > std::min(m, n) || p < 0 ||
+  // T has a column per candidate: A's columns, or its rows in the row form
+  const int64_t ncand = cfg->side == RID_ROWS ? m : n;
+  if (m < 1 || n < 1 || lda < n || ldt < ncand || k < 1 || k > std::min(m, n) || p < 0 ||
       p > kMaxW || m > INT32_MAX || n > INT32_MAX)
     return RID_ERR_ARG;
   if (k > lds_kcap_limit(cfg->dtype)) return RID_ERR_ARG;
@@ -1086,8 +1200,9 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
                       size_t work_bytes, hipStream_t stream) {
   if (!A || !J || !T || !k_out || !err_est || !status || !work || !valid_cfg(cfg))
     return RID_ERR_ARG;
-  if (m < 1 || n < 1 || lda < n || ldt < n || b < 1 || b > kMaxW || kmax < 1 || !(tol >= 0.0) ||
-      m > INT32_MAX || n > INT32_MAX)
+  const int64_t ncand = cfg->side == RID_ROWS ? m : n;
+  if (m < 1 || n < 1 || lda < n || ldt < ncand || b < 1 || b > kMaxW || kmax < 1 ||
+      !(tol >= 0.0) || m > INT32_MAX || n > INT32_MAX)
     return RID_ERR_ARG;
   const int64_t mn = std::min(m, n);
   const int64_t kcap = std::min(kmax, mn);
@@ -1224,7 +1339,8 @@ int rid_lupp_rows(const void* A, int64_t m, int64_t n, int64_t lda, const int64_
 
 size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const rid_config* cfg) {
   // the sketch's plan, then the FP64 partials of the split certificate products
-  if (m < 1 || n < 1 || p < 1 || p > kCertPMax || !valid_cfg(cfg)) return 0;
+  if (m < 1 || n < 1 || p < 1 || p > kCertPMax || !valid_cfg(cfg) || cfg->side != RID_COLUMNS)
+    return 0;
   rid_config c = *cfg;
   c.estimator = 0;
   c.embedding = RID_EMB_GAUSSIAN;  // the certificate draws Gaussian vectors
@@ -1236,7 +1352,8 @@ size_t rid_certificate_workspace_bytes(int64_t m, int64_t n, int64_t p, const ri
 int rid_certificate(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* J, int64_t k,
                     const void* T, int64_t ldt, int64_t p, int64_t c0, const rid_config* cfg,
                     double* cert, void* work, size_t work_bytes, hipStream_t stream) {
-  if (!A || (k > 0 && !J) || (k > 0 && k < n && !T) || !cert || !work || !valid_cfg(cfg))
+  if (!A || (k > 0 && !J) || (k > 0 && k < n && !T) || !cert || !work || !valid_cfg(cfg) ||
+      cfg->side != RID_COLUMNS)
     return RID_ERR_ARG;
   if (m < 1 || n < 1 || lda < n || k < 0 || k > n || p < 1 || p > kCertPMax || c0 < 0 ||
       c0 + p > (int64_t(1) << 32) || (k > 0 && ldt < n - k) || m > INT32_MAX || n > INT32_MAX)

@@ -414,6 +414,172 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sketch of the row form (the column form of A^T, read in place): partial
+// sums of Z(r, c) = sum_j omega(c0 + c, j) A(r, j) for rows r of A (the
+// candidates) over one range of columns j ("split") per grid row.  The
+// contraction runs along A's rows, which are contiguous, so no transposed
+// copy of A is made.
+//   * 256 threads; a workgroup owns 64 rows of A, a wave 16 of them.  Lane l
+//     loads 4 consecutive columns 4 (l / 16) + 16 h .. + 3 (h = 0, 1) of row
+//     l % 16 of its wave's rows per 32-column chunk (16- or 32-byte loads,
+//     128 contiguous bytes per row and chunk in FP32).  In MFMA step (h, t)
+//     lane group g supplies column j = 16 h + 4 g + t of the chunk, and the
+//     Omega operand (from LDS) is taken at that same column.
+//   * Omega comes from the row-major (rows x WP) buffer of k_omega (its rows
+//     are A's columns here), staged through LDS, double buffered; the A
+//     operands of the next chunk are loaded while the current one is
+//     multiplied.
+//   * FP32 sums are folded into FP64 every 64 columns.  Partials
+//     part[split][r][c] (FP64) are summed in split order by k_sketch_reduce.
+//   * NORM: also accumulates sum A^2 (FP64) and flags non-finite entries.
+// ---------------------------------------------------------------------------
+template <typename TC, int MT, bool NORM, bool VEC>
+__global__ __launch_bounds__(256) void k_sketch_rows(
+    const TC* __restrict__ A, int64_t mrows, int64_t ncols, int64_t lda,
+    const TC* __restrict__ omg, int w, int64_t cols_per_split, double* __restrict__ part,
+    double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  constexpr int KC = 32;                 // columns of A per chunk
+  constexpr int WP = MT * 16;            // padded number of sketch vectors
+  constexpr int LDO = WP + 4;            // LDS row pitch of Omega
+  constexpr int NE = KC * WP / 256;      // Omega entries per thread and chunk
+  using M = Mfma<TC>;
+  using acc_t = typename M::acc_t;
+  __shared__ TC sO[2][KC * LDO];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4;
+  const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+  const bool rok = row < mrows;
+  const int64_t j_begin = (int64_t)blockIdx.y * cols_per_split;
+  const int64_t j_end = (j_begin + cols_per_split < ncols) ? j_begin + cols_per_split : ncols;
+  const int nch = (int)((j_end - j_begin + KC - 1) / KC);
+  const TC* arow = A + (rok ? row : 0) * lda;
+
+  acc_t acc[MT];
+  double acc64[MT][4];
+#pragma unroll
+  for (int a = 0; a < MT; ++a) {
+    acc[a] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[a][r] = 0.0;
+  }
+  double fro = 0.0;
+  bool bad = false;
+
+  // A operands of the chunk at column j0: 2 x 4 consecutive columns
+  auto loadA = [&](TC (&buf)[2][4], int64_t j0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t j = j0 + 16 * h + 4 * g;
+      if (VEC && rok && j + 3 < j_end) {
+        if (sizeof(TC) == 4) {
+          const float4 v = *reinterpret_cast<const float4*>(arow + j);
+          buf[h][0] = v.x; buf[h][1] = v.y; buf[h][2] = v.z; buf[h][3] = v.w;
+        } else {
+          const double2 v0 = *reinterpret_cast<const double2*>(arow + j);
+          const double2 v1 = *reinterpret_cast<const double2*>(arow + j + 2);
+          buf[h][0] = v0.x; buf[h][1] = v0.y; buf[h][2] = v1.x; buf[h][3] = v1.y;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) buf[h][t] = (rok && j + t < j_end) ? arow[j + t] : TC(0);
+      }
+    }
+  };
+  // Omega rows [j0, j0 + KC) of the chunk (zero beyond the split), entries
+  // e = tid + 256 v, row e / WP
+  auto loadO = [&](TC (&r)[NE], int64_t j0) {
+#pragma unroll
+    for (int v = 0; v < NE; ++v) {
+      const int e = tid + 256 * v;
+      const int64_t j = j0 + e / WP;
+      r[v] = (j < j_end) ? omg[j * WP + e % WP] : TC(0);
+    }
+  };
+  auto storeO = [&](TC* so, const TC (&r)[NE]) {
+#pragma unroll
+    for (int v = 0; v < NE; ++v) {
+      const int e = tid + 256 * v;
+      so[(e / WP) * LDO + e % WP] = r[v];
+    }
+  };
+  auto compute = [&](const TC* so, const TC (&buf)[2][4]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int jc = 16 * h + 4 * g + t;
+        if (NORM) {
+          fro += (double)buf[h][t] * (double)buf[h][t];
+          bad |= !__builtin_isfinite((double)buf[h][t]);
+        }
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+          acc[a] = M::op(so[jc * LDO + a * 16 + (lane & 15)], buf[h][t], acc[a]);
+      }
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][r] += (double)acc[a][r];
+      acc[a] = M::zero();
+    }
+  };
+
+  TC bA[2][4], bB[2][4];
+  TC on[NE];
+  if (nch > 0) {
+    loadO(on, j_begin);
+    storeO(sO[0], on);
+    loadA(bA, j_begin);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; c += 2) {
+    const int64_t j0 = j_begin + (int64_t)c * KC;
+    const bool n1 = c + 1 < nch, n2 = c + 2 < nch;
+    if (n1) {
+      loadA(bB, j0 + KC);
+      loadO(on, j0 + KC);
+    }
+    compute(sO[0], bA);
+    if (n1) storeO(sO[1], on);
+    if (sizeof(TC) == 4 && !n1) fold();
+    __syncthreads();
+    if (!n1) break;
+    if (n2) {
+      loadA(bA, j0 + 2 * KC);
+      loadO(on, j0 + 2 * KC);
+    }
+    compute(sO[1], bB);
+    if (n2) storeO(sO[0], on);
+    if (sizeof(TC) == 4) fold();
+    __syncthreads();
+  }
+  if (sizeof(TC) == 8) {
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][r] = (double)acc[a][r];
+  }
+  if (rok) {
+    double* dst = part + ((size_t)blockIdx.y * (size_t)mrows + (size_t)row) * WP;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = acc64[a][r];
+  }
+  if (NORM) {
+    fro = wave_sum(fro);
+    if (lane == 0) red[wave] = fro;
+    if (bad) atomicOr(nonfinite, 1);
+    __syncthreads();
+    if (tid == 0) fro_part[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
 // Sum of the split partials in split order; writes Y^T into Z columns
 // [zcol, zcol + w) in the factor type.  With `first`, also finishes ||A||_F^2
 // and the non-finite check.

@@ -233,3 +233,41 @@ def test_fp32_path_against_oracle_rank_cap_256(setup, orc):
     # (measured: all 256 skeletons equal, E and residual within 2e-4).
     assert res_g <= 1.01 * res_o
     assert abs(g32.err_est - o.err_est) <= 0.01 * o.err_est
+
+
+def test_row_id_fp64_against_oracle_rank_cap_256(setup, orc):
+    """The row ID (rows of A among 50000 candidates, the sketch contracting
+    A's 20000 columns in place) in FP64 against the oracle's column ID of an
+    explicit transpose, rank cap 256: skeletons identical (every decision
+    above the FP64 floor), estimate within rounding, reconstructions within
+    1e-12 relative."""
+    torch, rid, A32, sig, g = setup
+    A64 = _KEEP["A64"]
+    print("fullsize: row ID fp64, rank cap 256", file=sys.stderr, flush=True)
+    gr = rid.adaptive(A64, B, TOL, KP, seed=SEED, side=rid.RID_ROWS)
+    At = A64.t().contiguous().cpu().numpy()
+    print("fullsize: oracle on A^T, rank cap 256", file=sys.stderr, flush=True)
+    o = orc.rid_adaptive(At, B, TOL, KP, seed=SEED)
+    del At
+    I = gr.J.cpu().numpy()
+    print("fullsize row ID:", gr.k, o.k, gr.status, o.status, "robust", o.robust_k,
+          "E", gr.err_est, o.err_est, file=sys.stderr, flush=True)
+    assert (gr.status, gr.k) == (o.status, o.k)
+    assert o.robust_k == o.k
+    assert np.array_equal(I, o.J)
+    floor = 64 * 2.0 ** -53 * math.sqrt(KP) * o.fro_a
+    assert abs(gr.err_est - o.err_est) <= 1e-8 * o.err_est + floor
+    # W A(I, :) with W(I, :) = I, W(I^c, :) = T^T, for both results
+    def recon(Iv, T):
+        Id = torch.as_tensor(Iv, device="cuda")
+        W = torch.zeros((M, len(Iv)), dtype=torch.float64, device="cuda")
+        mask = torch.ones(M, dtype=torch.bool, device="cuda")
+        mask[Id] = False
+        W[Id] = torch.eye(len(Iv), dtype=torch.float64, device="cuda")
+        W[mask] = torch.as_tensor(T, device="cuda").t()
+        return W @ A64[Id]
+    D = recon(I, gr.T.cpu().numpy()) - recon(o.J, o.T)
+    gap = float(torch.linalg.vector_norm(D)) / float(torch.linalg.vector_norm(A64))
+    del D
+    print("fullsize row ID reconstruction gap", gap, file=sys.stderr, flush=True)
+    assert gap <= 1e-12, gap
