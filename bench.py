@@ -342,11 +342,21 @@ def main():
         msr = (time.perf_counter() - t0) * 1e3 / args.lp_steps
         kr = int(outr[2].item())
         rr = true_resid(A32, outr[0][:kr], outr[1]) / fro
+        kept_unrefined = bool(kr == k32 and torch.equal(outr[1][:kr, : n - kr],
+                                                        out32[1][:k32, : n - k32]))
+        # the refined T itself (refine = 2 keeps it unconditionally), for the record
+        run2, out2, _ = make_run(A32, rid.RID_F32, refine=2)
+        run2()
+        torch.cuda.synchronize()
+        r2 = true_resid(A32, out2[0][:int(out2[2].item())], out2[1]) / fro
+        del run2, out2
         refine = {"ms_per_step": msr, "overhead_ms": msr - ms, "k": kr,
                   "same_skeleton": bool(torch.equal(outr[0][:kr], out32[0][:k32])),
-                  "resid_rel_true": rr, "resid_rel_unrefined": resid32}
+                  "resid_rel_true": rr, "resid_rel_unrefined": resid32,
+                  "resid_rel_refined_step": r2,
+                  "kept": "unrefined" if kept_unrefined else "refined"}
         log(f"[bench] fp32+refine: {msr:.2f} ms/step (+{msr - ms:.2f}), resid {rr:.4e} "
-            f"(unrefined {resid32:.4e})")
+            f"(unrefined {resid32:.4e}, refined step {r2:.4e}; {refine['kept']} T kept)")
         del runr, outr
 
     # the same FP32 decomposition drawn from the sparse sign embedding (zeta =

@@ -82,9 +82,16 @@ typedef struct {
   const float* a_col_scale; /* (device) RID_FP8_E4M3 only: ceil(n/128) powers of
                            two; A(i, j) = code(i, j) * a_col_scale[j / 128].
                            NULL otherwise.                                      */
-  int refine;           /* 0, or 1 (dtype RID_F32 only): one iterative-refinement
+  int refine;           /* 0, or (dtype RID_F32 only) one iterative-refinement
                            step on T whose residual Y(:,J) T - Y(:,J^c) is
-                           formed in FP64 from the FP32 sketch                  */
+                           formed in FP64 from the FP32 sketch.  1: the device
+                           then keeps whichever of the unrefined and refined T
+                           has the smaller FP64 residual on the last drawn
+                           estimate block (the method's independent sample,
+                           an unbiased estimate of each ID's squared error;
+                           the refined T when there is none: p = 0, k =
+                           min(m, n), a rank-deficient stop).  2: keeps the
+                           refined T unconditionally.                        */
   int estimator;        /* stopping estimate, one of rid_estimator.  0 (the
                            default) is the Schur estimate of eq. (errSch) on the
                            next block; 1-3 are the residual-triangle estimates

@@ -122,7 +122,7 @@ def _cfg(dtype: int, seed: int, tol_relative: bool = True, a_type: int | None = 
          est_out: int = 0, embedding: int = 0, side: int = 0) -> RidConfig:
     return RidConfig(dtype=dtype, tol_relative=1 if tol_relative else 0, seed=seed,
                      a_type=dtype if a_type is None else a_type, a_col_scale=col_scale or None,
-                     refine=1 if refine else 0, estimator=estimator, resid_p=resid_p,
+                     refine=int(refine), estimator=estimator, resid_p=resid_p,
                      est_out=est_out or None, embedding=embedding, side=side)
 
 

@@ -259,6 +259,7 @@ struct Plan {
   rid_dtype at = RID_F64;   // storage type of A
   const float* scale = nullptr;  // FP8 column-tile scales (device)
   bool refine = false;           // FP64-residual refinement step on T
+  bool refine_keep = false;      // keep the refined T without the choice (refine = 2)
   int est = 0;                   // rid_estimator of the stopping test
   int emb = 0;                   // rid_embedding of the sketch
   int resid_p = 0;               // set-aside sample width (adaptive, est > 0)
@@ -274,7 +275,7 @@ struct Plan {
   // offsets
   size_t xwords_end = 0;  // end of the panel exchange words (zeroed per call)
   size_t o_ctrl, o_pos, o_order, o_nonpiv, o_z, o_u2t, o_part, o_fro, o_norm, o_slots,
-      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, o_posr, o_orderr,
+      o_slotrows, o_nonfinite, o_linv, o_mtmp, o_omega, o_yorig, o_tt, o_x, o_t1, o_posr, o_orderr,
       o_ctrlr, o_ytop, total;
 };
 
@@ -365,6 +366,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
   P.o_x = take(refine ? (size_t)n * P.ldl * es : 0);
+  P.o_t1 = take(refine ? (size_t)n * P.ldl * es : 0);  // the refined T, transposed
   // Remark-1 estimate: the private pivot state of the sample's factorisation
   P.o_posr = take(est > 0 ? (size_t)n * 4 : 0);
   P.o_orderr = take(est > 0 ? (size_t)(P.ldz + 1) * 4 : 0);
@@ -395,6 +397,7 @@ bool plan_for(int64_t m, int64_t n, int64_t kmax, int64_t b, const rid_config* c
     return false;
   P.emb = cfg->embedding;
   P.scale = cfg->a_col_scale;
+  P.refine_keep = cfg->refine == 2;
   return true;
 }
 
@@ -431,6 +434,7 @@ struct Ws {
   void* yorig;
   void* tt;
   void* xr;
+  void* t1;
   int* pos_r;
   int* order_r;
   Ctrl* ctrl_r;
@@ -458,6 +462,7 @@ Ws carve(const Plan& P, void* work) {
   w.yorig = P.refine ? b + P.o_yorig : nullptr;
   w.tt = P.refine ? b + P.o_tt : nullptr;
   w.xr = P.refine ? b + P.o_x : nullptr;
+  w.t1 = P.refine ? b + P.o_t1 : nullptr;
   w.pos_r = P.est > 0 ? reinterpret_cast<int*>(b + P.o_posr) : nullptr;
   w.order_r = P.est > 0 ? reinterpret_cast<int*>(b + P.o_orderr) : nullptr;
   w.ctrl_r = P.est > 0 ? reinterpret_cast<Ctrl*>(b + P.o_ctrlr) : nullptr;
@@ -954,9 +959,11 @@ int resid_estimate(const Plan& P, const Ws& W, int kb, int k, int p, bool adapti
 }
 
 // ---- interpolation matrix and outputs --------------------------------------
+// we, klim: the estimate block of the refinement choice (we vectors at Z
+// column k, drawn when k < klim; see k_refine_pick).
 template <typename TF>
 int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32_t* k_out,
-             double* err_est, int32_t* status, hipStream_t st) {
+             double* err_est, int32_t* status, hipStream_t st, int we, int64_t klim) {
   hipLaunchKernelGGL(k_nonpiv, dim3(1), dim3(1024), 0, st, W.pos, P.n, W.nonpiv);
   RID_LAUNCH_CHECK();
   {
@@ -987,9 +994,22 @@ int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32
                          dim3(256), 0, st, static_cast<const float*>(W.z), P.ldz, W.order, P.n,
                          static_cast<float*>(W.xr), P.ldl, W.ctrl);
       RID_LAUNCH_CHECK();
-      hipLaunchKernelGGL((k_tgemm<TF, 2>), grid, dim3(256), 0, st, static_cast<const TF*>(xr),
-                         P.ldl, W.nonpiv, P.n, linv, P.ldl, static_cast<TF*>(T), ldt,
+      // the refined T, transposed, beside the unrefined one
+      hipLaunchKernelGGL((k_tgemm<TF, 3>), grid, dim3(256), 0, st, static_cast<const TF*>(xr),
+                         P.ldl, W.nonpiv, P.n, linv, P.ldl, static_cast<TF*>(W.t1), P.ldl,
                          static_cast<const TF*>(tt), P.ldl, W.ctrl);
+      RID_LAUNCH_CHECK();
+      // keep the one with the smaller residual on the last estimate block
+      const int nparts = (int)std::max<int64_t>(1, ceil_div(P.n, 64));
+      const int klim_i = P.refine_keep ? 0 : (int)std::min<int64_t>(klim, INT32_MAX);
+      hipLaunchKernelGGL(k_refine_pick, dim3((unsigned)nparts), dim3(256), 0, st,
+                         static_cast<const float*>(W.yorig), P.ldz, W.order, W.nonpiv, P.n, we,
+                         klim_i, static_cast<const float*>(W.tt), static_cast<const float*>(W.t1),
+                         P.ldl, W.part, W.ctrl);
+      RID_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_refine_emit, grid, dim3(256), 0, st, static_cast<float*>(T), ldt,
+                         static_cast<const float*>(W.tt), static_cast<const float*>(W.t1), P.ldl,
+                         P.n, W.part, nparts, we, klim_i, W.ctrl);
       RID_LAUNCH_CHECK();
     }
     prof_end(pm, st);
@@ -1002,9 +1022,10 @@ int finish_t(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32
 }
 
 int finish(const Plan& P, const Ws& W, void* T, int64_t ldt, int64_t* J, int32_t* k_out,
-           double* err_est, int32_t* status, hipStream_t st) {
-  return P.dt == RID_F64 ? finish_t<double>(P, W, T, ldt, J, k_out, err_est, status, st)
-                         : finish_t<float>(P, W, T, ldt, J, k_out, err_est, status, st);
+           double* err_est, int32_t* status, hipStream_t st, int we = 0, int64_t klim = 0) {
+  return P.dt == RID_F64
+             ? finish_t<double>(P, W, T, ldt, J, k_out, err_est, status, st, we, klim)
+             : finish_t<float>(P, W, T, ldt, J, k_out, err_est, status, st, we, klim);
 }
 
 int init(const Plan& P, const Ws& W, hipStream_t st) {
@@ -1039,7 +1060,7 @@ bool valid_cfg(const rid_config* cfg) {
     if (cfg->dtype != RID_F32 || !low_precision(cfg->a_type)) return false;
     if (cfg->a_type == RID_FP8_E4M3 && !cfg->a_col_scale) return false;
   }
-  return cfg->refine == 0 || (cfg->refine == 1 && cfg->dtype == RID_F32);
+  return cfg->refine == 0 || ((cfg->refine == 1 || cfg->refine == 2) && cfg->dtype == RID_F32);
 }
 
 // The batched path reads A in the factor type, or FP32 blocks under an FP64
@@ -1173,7 +1194,8 @@ int rid_lupp_fixed_rank(const void* A, int64_t m, int64_t n, int64_t lda, int64_
     else
       RID_TRY(estimate(P, W, (int)p, 0.0, 0, (int)k, true, stream));
   }
-  return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+  // the p estimate vectors sit at Z column k (ctrl->k = k)
+  return finish(P, W, T, ldt, J, k_out, err_est, status, stream, (int)p, p > 0 ? k + 1 : 0);
 }
 
 size_t rid_noalloc_max_bytes(void) { return kScratchBytes; }
@@ -1253,7 +1275,8 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
                              cfg->est_out, stream));
     }
     RID_TRY(side_join(side, stream));
-    return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+    // a stop below kcap has the next block sketched at column k
+    return finish(P, W, T, ldt, J, k_out, err_est, status, stream, (int)b, kcap);
   }
   // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch
   SideLease side;
@@ -1271,7 +1294,8 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     k += f;
   }
   RID_TRY(side_join(side, stream));
-  return finish(P, W, T, ldt, J, k_out, err_est, status, stream);
+  // every estimate of Alg. 1 measures the block at column k (none at k = min(m, n))
+  return finish(P, W, T, ldt, J, k_out, err_est, status, stream, (int)b, mn);
 }
 
 size_t rid_rows_workspace_bytes(int64_t m, int64_t k, const rid_config* cfg) {

@@ -870,6 +870,7 @@ __global__ __launch_bounds__(256) void k_linv_b2(const TF* __restrict__ Mtmp, in
 //   MODE 1: the same rows, T^T(q, s) written row-major to T (ldt = its pitch)
 //   MODE 2: rows X(q) = Z[q] (Z = X, nonpiv unused); T(s, q) = acc + TT(q, s)
 //           (the refinement update T += (X L1^{-1})^T)
+//   MODE 3: as MODE 2, the result transposed, T^T(q, s), row-major to T
 template <typename TF, int MODE>
 __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t ldz,
                                                const int* __restrict__ nonpiv, int64_t n,
@@ -886,7 +887,7 @@ __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t
   using M = Mfma<TF>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t q = q0 + wave * 16 + (lane & 15);
-  const TF* arow = (q < nn) ? Z + (MODE == 2 ? q : (int64_t)nonpiv[q]) * ldz : nullptr;
+  const TF* arow = (q < nn) ? Z + (MODE >= 2 ? q : (int64_t)nonpiv[q]) * ldz : nullptr;
   const int bcols = (k - j0 < 64) ? k - j0 : 64;
   auto brow = [&](int p) -> const TF* { return Linv + (int64_t)p * ldl + j0; };
   typename M::acc_t acc[4];
@@ -908,6 +909,8 @@ __global__ __launch_bounds__(256) void k_tgemm(const TF* __restrict__ Z, int64_t
       if (qq < nn && s < k) {
         if (MODE == 1)
           T[qq * ldt + s] = (TF)acc64[t][r];
+        else if (MODE == 3)
+          T[qq * ldt + s] = (TF)((double)TT[qq * ldtt + s] + acc64[t][r]);
         else if (MODE == 2)
           T[(int64_t)s * ldt + qq] = (TF)((double)TT[qq * ldtt + s] + acc64[t][r]);
         else

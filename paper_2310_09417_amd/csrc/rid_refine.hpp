@@ -169,4 +169,126 @@ __global__ __launch_bounds__(256) void k_refine_solve(const float* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Choice between the unrefined and the refined T.  A better solution of the
+// sketched system is not always a better interpolation (the step moves T
+// toward the exact solution of the FP32 sketch, which carries its own
+// rounding), so the device keeps whichever T has the smaller residual on
+// the independent Gaussian block the method drew last, at Z columns
+// [k, k + we) of the kept sketch copy: the estimate block of the adaptive
+// loop, or the p estimate vectors of the fixed-rank call.  For either T the
+// statistic ||Ye(:, J^c) - Ye(:, J) T||_F^2 / we is unbiased for the squared
+// error of that ID (the a-posteriori estimate Remark 1 ends with), and both
+// are formed from the same vectors in FP64.  When the call drew no such block
+// (k >= klim: the exact full-rank stop, or a fixed-rank call with p = 0; or a
+// rank-deficient stop) the refined T is kept.
+// ---------------------------------------------------------------------------
+
+// Partial sums over 64 non-skeleton columns per workgroup of the squared
+// residual of T0 (unrefined) and T1 (refined), both stored transposed
+// (row q, pitch ldtt): part[2 blk] and part[2 blk + 1].
+__global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ Y, int64_t ldy,
+                                                     const int* __restrict__ order,
+                                                     const int* __restrict__ nonpiv, int64_t n,
+                                                     int we, int klim, const float* __restrict__ T0t,
+                                                     const float* __restrict__ T1t, int64_t ldtt,
+                                                     double* __restrict__ part,
+                                                     const Ctrl* ctrl) {
+  __shared__ double red[2][4];
+  const int k = ctrl->k;
+  const int64_t nn = n - k;
+  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double s0 = 0.0, s1 = 0.0;
+  // a rank-deficient stop leaves no complete fresh block at column k
+  const bool drawn = (ctrl->status == ST_OK || ctrl->status == ST_NOT_CONVERGED) && k < klim &&
+                     we > 0;
+  if (drawn && q0 < nn) {
+    const int64_t q = q0 + wave * 16 + (lane & 15);
+    auto brow = [&](int p) -> const float* { return Y + (int64_t)order[p] * ldy + k; };
+    doublex4 a0[4], a1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      a0[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+      a1[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    }
+    wave_tile_f64acc((q < nn) ? T0t + q * ldtt : nullptr, brow, 0, k, we, a0);
+    wave_tile_f64acc((q < nn) ? T1t + q * ldtt : nullptr, brow, 0, k, we, a1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t qq = q0 + wave * 16 + Mfma<double>::row(lane, r);
+        const int c = 4 * (lane & 15) + t;
+        if (qq < nn && c < we) {
+          const double y = (double)Y[(int64_t)nonpiv[qq] * ldy + k + c];
+          const double r0 = y - a0[t][r], r1 = y - a1[t][r];
+          s0 += r0 * r0;
+          s1 += r1 * r1;
+        }
+      }
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) {
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// T(s, q) from the chosen transposed matrix (T1t unless the unrefined T0t
+// has the smaller residual on the estimate block).  Every workgroup sums
+// the nparts partial pairs in the same fixed order, so all take the same
+// choice.  Grid (ceil(n/64), ceil(kcap/64)): a 64 x 64 tile, transposed
+// through LDS.
+__global__ __launch_bounds__(256) void k_refine_emit(float* __restrict__ T, int64_t ldt,
+                                                     const float* __restrict__ T0t,
+                                                     const float* __restrict__ T1t, int64_t ldtt,
+                                                     int64_t n, const double* __restrict__ part,
+                                                     int nparts, int we, int klim,
+                                                     const Ctrl* ctrl) {
+  __shared__ double red[2][256];
+  __shared__ float tile[64][65];
+  if (ctrl->status < 0) return;
+  const int k = ctrl->k;
+  const int64_t nn = n - k;
+  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  const int s0 = blockIdx.y * 64;
+  if (q0 >= nn || s0 >= k) return;
+  const int tid = threadIdx.x;
+  double e0 = 0.0, e1 = 0.0;
+  for (int i = tid; i < nparts; i += 256) {
+    e0 += part[2 * i];
+    e1 += part[2 * i + 1];
+  }
+  red[0][tid] = e0;
+  red[1][tid] = e1;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      red[0][tid] += red[0][tid + h];
+      red[1][tid] += red[1][tid + h];
+    }
+    __syncthreads();
+  }
+  const bool drawn = (ctrl->status == ST_OK || ctrl->status == ST_NOT_CONVERGED) && k < klim &&
+                     we > 0;
+  const float* src = (drawn && red[0][0] < red[1][0]) ? T0t : T1t;
+  // tile rows q (64) x columns s (64), read along s, written along q
+  for (int t = tid; t < 64 * 64; t += 256) {
+    const int qq = t >> 6, ss = t & 63;
+    tile[qq][ss] = (q0 + qq < nn && s0 + ss < k) ? src[(q0 + qq) * ldtt + s0 + ss] : 0.f;
+  }
+  __syncthreads();
+  for (int t = tid; t < 64 * 64; t += 256) {
+    const int ss = t >> 6, qq = t & 63;
+    if (q0 + qq < nn && s0 + ss < k) T[(int64_t)(s0 + ss) * ldt + q0 + qq] = tile[qq][ss];
+  }
+}
+
 }  // namespace rid

@@ -271,3 +271,21 @@ def test_row_id_fp64_against_oracle_rank_cap_256(setup, orc):
     del D
     print("fullsize row ID reconstruction gap", gap, file=sys.stderr, flush=True)
     assert gap <= 1e-12, gap
+
+
+def test_refinement_does_not_grow_the_residual_at_full_size(setup):
+    """At the benchmark's conditioning (the skeleton block's condition number
+    is about 1e8, beyond the FP32 contraction bound 2^24) one refinement step
+    made the ID residual twice as large.  The device's choice on the last
+    estimate block must keep the unrefined T there, so the result's residual
+    does not grow."""
+    torch, rid, A32, sig, g = setup
+    print("fullsize: refinement with the device's choice", file=sys.stderr, flush=True)
+    g1 = rid.adaptive(A32, B, TOL, KMAX, seed=SEED, refine=1)
+    assert (g1.k, g1.status, g1.err_est) == (g.k, g.status, g.err_est)
+    assert torch.equal(g1.J, g.J)
+    r0 = _true_rel(torch, A32, g.J, g.T)
+    r1 = _true_rel(torch, A32, g1.J, g1.T)
+    print(f"fullsize refine: residual {r0:.4e} unrefined, {r1:.4e} kept", file=sys.stderr,
+          flush=True)
+    assert r1 <= r0 * (1 + 1e-6)
