@@ -66,6 +66,79 @@ def traffic_from_profiles(kernel: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+def host_cpu() -> dict:
+    """Host CPU model and core count (for the record of the CPU baseline)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def fixed_rank_matrix(workloads):
+    """The fixed-rank FP64 workload: 2000 x 1000, sigma_j = 10^(-10 (j-1)/999),
+    U and V from the QR of seeded Gaussian matrices."""
+    A, _ = workloads.fast_decay(2000, 1000, decades=10.0, seed=101)
+    return A
+
+
+def bench_fixed_rank(torch, rid, workloads, calls=50):
+    """The fixed-rank FP64 configuration on the GPU: randLUPP of the 2000 x 1000
+    matrix at k = 100 with p = 20 estimate vectors, per call (HIP events over
+    `calls` calls, A resident), through the workspace form and the form
+    without a caller workspace."""
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(fixed_rank_matrix(workloads), dtype=torch.float64).to(dev)
+    m, n, k, p = 2000, 1000, 100, 20
+    cfg = rid.binding._cfg(rid.RID_F64, 1, True)
+    wb = rid.rid_workspace_bytes(m, n, k + p, p, cfg)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    J = torch.zeros(k, dtype=torch.int64, device=dev)
+    T = torch.zeros((k, n), dtype=torch.float64, device=dev)
+    ko = torch.zeros(1, dtype=torch.int32, device=dev)
+    eo = torch.zeros(1, dtype=torch.float64, device=dev)
+    so = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    args = (J.data_ptr(), T.data_ptr(), n, ko.data_ptr(), eo.data_ptr(), so.data_ptr())
+
+    def call_ws():
+        rc = rid.rid_lupp_fixed_rank(A.data_ptr(), m, n, n, k, p, cfg, *args, work.data_ptr(), wb,
+                                     stream)
+        if rc != 0:
+            raise RuntimeError(f"rid_lupp_fixed_rank -> {rc}")
+
+    def call_na():
+        rc = rid.binding.rid_lupp_fixed_rank_noalloc(A.data_ptr(), m, n, n, k, p, cfg, *args,
+                                                     stream)
+        if rc != 0:
+            raise RuntimeError(f"rid_lupp_fixed_rank_noalloc -> {rc}")
+
+    res = {"workload": "fixed-rank randLUPP, FP64, A 2000x1000 (10 decades), k=100, p=20"}
+    F = rid.flops_id(m, n, k, k + p)
+    for name, fn in (("workspace", call_ws), ("noalloc", call_na)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(calls):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / calls
+        res[name] = {"ms_per_call": ms, "gflops": F / (ms * 1e-3) / 1e9}
+        log(f"[bench] fixed rank FP64 2000x1000 k=100 p=20 ({name}): {ms:.3f} ms per call, "
+            f"{F / (ms * 1e-3) / 1e9:.0f} GFLOP/s")
+    res["k"] = int(ko.item())
+    res["status"] = rid.status_string(int(so.item()))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,6 +527,27 @@ def main():
         log(f"[bench] cpu oracle sample: {tc:.1f}s, {cpu['value']:.2f} GFLOP/s on "
             f"{cpu['cores']} threads")
         del Ah
+        cpu["host"] = host_cpu()
+        # the fixed-rank FP64 configuration (2000 x 1000, k = 100, p = 20) on
+        # one host core and on all of them
+        A0 = fixed_rank_matrix(workloads)
+        F0 = rid.flops_id(2000, 1000, 100, 120)
+        for thr in (1, 0):
+            oracle.set_num_threads(thr)
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                oracle.rid_fixed_rank(A0, 100, 20, seed=1)
+                ts.append(time.perf_counter() - t0)
+            key = "fixed_rank_2000x1000_one_core" if thr == 1 else "fixed_rank_2000x1000_all_cores"
+            cpu[key] = {"ms_mean": 1e3 * sum(ts) / len(ts), "ms_median": 1e3 * sorted(ts)[2],
+                        "threads": oracle.num_threads(),
+                        "gflops": F0 / (sorted(ts)[2]) / 1e9}
+            log(f"[bench] cpu oracle fixed rank 2000x1000 k=100 p=20 on {oracle.num_threads()} "
+                f"thread(s): median {1e3 * sorted(ts)[2]:.1f} ms")
+        oracle.set_num_threads(0)
+
+    fixed0 = bench_fixed_rank(torch, rid, workloads)
 
     batched = None
     if args.batched:
@@ -499,11 +593,14 @@ def main():
         "kernel_breakdown": breakdown,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fixed_rank_fp64": fixed0,
         "batched": batched,
         "learned_rank": learned,
         "paper_workload": paper,
         "source_hash": source_hash(),
     }
+    torch.cuda.synchronize()
+    rid.binding.rid_release()
     print(json.dumps(rec), flush=True)
 
 

@@ -431,6 +431,18 @@ int rid_debug_mfma_probe(int kind, const void* A, const void* B, float* D, hipSt
 int rid_profile_start(void);
 int rid_profile_stop(double* ms, int64_t* launches, int nclass);
 
+/*
+ * Releases the library's host-side resources: the pooled HIP streams and
+ * events of the adaptive calls (after waiting for their work) and the
+ * profiling events, on every device that created them; the current device
+ * is restored.  Later calls create them again as needed.  Call it after all
+ * of the library's work has been issued and before the process tears the
+ * HIP runtime down (e.g. under a profiler that reports at exit).  Returns
+ * RID_ERR_ARG (and leaves that set alone) if a call on another host thread
+ * still holds a stream set, RID_ERR_HIP if a HIP call fails.
+ */
+int rid_release(void);
+
 #ifdef __cplusplus
 }
 #endif

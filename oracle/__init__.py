@@ -109,6 +109,8 @@ def _load():
         lib.orc_rid_lupp_emb.restype = cint
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = cint
+        lib.orc_set_num_threads.argtypes = [cint]
+        lib.orc_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -116,6 +118,11 @@ def _load():
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops (n < 1: the runtime default)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

@@ -36,6 +36,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads for the OpenMP loops from here on (n < 1: the runtime's default);
+ * results do not depend on it (only independent outputs are split). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
+
 /* Status codes (same numbering as the library's public header: an interface
  * both sides must agree on, restated here rather than shared). */
 enum {

@@ -102,6 +102,8 @@ def library() -> ctypes.CDLL:
         lib.rid_profile_start.restype = i32
         lib.rid_profile_stop.argtypes = [P, P, i32]
         lib.rid_profile_stop.restype = i32
+        lib.rid_release.argtypes = []
+        lib.rid_release.restype = i32
         _lib = lib
     return _lib
 
@@ -201,6 +203,11 @@ def rid_lupp_batched(nblk, A, lda, m, n, b, tol, kmax, k_hint, cfg, J, T, ldt, k
 
 KERNEL_CLASSES = ("sketch", "sketch_reduce", "u2", "schur", "panel_lupp", "tgemm", "linv_update",
                   "batched", "omega", "resid_est")
+
+
+def rid_release() -> int:
+    """Release the library's pooled streams and events (see include/rid.h)."""
+    return int(library().rid_release())
 
 
 def rid_profile_start() -> int:

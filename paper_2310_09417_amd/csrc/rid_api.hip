@@ -1643,4 +1643,37 @@ int rid_profile_stop(double* ms, int64_t* launches, int nclass) {
   return RID_OK;
 }
 
+int rid_release(void) {
+  int dev0 = 0;
+  if (hipGetDevice(&dev0) != hipSuccess) return RID_ERR_HIP;
+  int rc = RID_OK;
+  {
+    std::lock_guard<std::mutex> lk(side_mu);
+    for (SideSet& e : side_pool) {
+      if (e.dev < 0) continue;
+      if (e.busy) {  // a call still holds this set
+        rc = RID_ERR_ARG;
+        continue;
+      }
+      if (hipSetDevice(e.dev) != hipSuccess) {
+        rc = RID_ERR_HIP;
+        continue;
+      }
+      if (hipStreamSynchronize(e.s) != hipSuccess || hipEventDestroy(e.fork) != hipSuccess ||
+          hipEventDestroy(e.join) != hipSuccess || hipStreamDestroy(e.s) != hipSuccess)
+        rc = RID_ERR_HIP;
+      e = SideSet{};
+    }
+  }
+  Profiler& p = prof();
+  p.on = false;
+  for (hipEvent_t ev : p.pool)
+    if (hipEventDestroy(ev) != hipSuccess) rc = RID_ERR_HIP;
+  p.pool.clear();
+  p.marks.clear();
+  p.used = 0;
+  if (hipSetDevice(dev0) != hipSuccess) rc = RID_ERR_HIP;
+  return rc;
+}
+
 }  // extern "C"

@@ -146,6 +146,8 @@ int main(int argc, char** argv) {
   CHECK(hipFree(ko));
   CHECK(hipFree(so));
   CHECK(hipFree(eo));
+  CHECK(hipStreamSynchronize(st));
+  if (rid_release() != RID_OK) return 5;
   std::printf("[native] done\n");
   return 0;
 }

@@ -310,3 +310,16 @@ def test_concurrent_calls_match_sequential(torch, rid):
         for J, T, k, st in out[i]:
             assert (k, st) == (seq[i][2], seq[i][3])
             assert np.array_equal(J, seq[i][0]) and np.array_equal(T, seq[i][1])
+
+
+def test_release_and_recreate(torch, rid):
+    """rid_release frees the pooled streams and events; later calls create
+    them again and give the same result bit for bit."""
+    A, _ = workloads.fast_decay(800, 500, decades=10, seed=8)
+    Ad = _dev(torch, A, torch.float64)
+    g1 = rid.adaptive(Ad, 32, 1e-7, 500, seed=4)
+    assert rid.binding.rid_release() == rid.RID_OK
+    g2 = rid.adaptive(Ad, 32, 1e-7, 500, seed=4)
+    assert rid.binding.rid_release() == rid.RID_OK
+    assert (g1.k, g1.status, g1.err_est) == (g2.k, g2.status, g2.err_est)
+    assert torch.equal(g1.J, g2.J) and torch.equal(g1.T, g2.T)
