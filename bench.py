@@ -824,6 +824,8 @@ def bench_batched(args, torch, rid, workloads):
 
     def run(blocks, tol, factor, steps):
         plan = rid.BatchPlan(blocks, b, tol, seed=seed, order=order, factor=factor)
+        # the persistent grid picked by the autotuner on this batch
+        shape, shape_ms = plan.autotune()
         plan.launch()
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
@@ -845,6 +847,9 @@ def bench_batched(args, torch, rid, workloads):
         st = {rid.status_string(int(v)): int((out.status == v).sum())
               for v in np.unique(out.status)}
         return ms, out, {"ms_per_batch": ms, "blocks_per_s": args.nblk / (ms * 1e-3),
+                         "persistent_grid": shape,
+                         "autotune_ms": {"all_cu": shape_ms[0], "three_quarters": shape_ms[1],
+                                         "half": shape_ms[2]},
                          "id_gflops": F / (ms * 1e-3) / 1e9, "mean_rank": float(np.mean(out.k)),
                          "mean_passes": float(np.mean(out.passes)), "status_counts": st}
 
@@ -857,7 +862,8 @@ def bench_batched(args, torch, rid, workloads):
         forms[name] = res
         log(f"[bench] batched {name}: {ms:.2f} ms ({res['blocks_per_s']:.0f} blocks/s, "
             f"{res['id_gflops']:.0f} GFLOP/s, mean k {res['mean_rank']:.1f}, passes "
-            f"{res['mean_passes']:.2f})")
+            f"{res['mean_passes']:.2f}; grid {res['persistent_grid']} workgroups, autotune "
+            f"{res['autotune_ms']})")
         del out
     fp64_ms = forms["fp64_tol1e-6"]["ms_per_batch"]
     f32 = forms["fp32_storage_fp64_factor_tol1e-6"]

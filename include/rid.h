@@ -332,6 +332,35 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
                      int32_t max_kmax, void* work, size_t work_bytes, hipStream_t stream);
 
 /*
+ * Persistent grid of the batched kernel (the number of workgroups that take
+ * blocks from the queue; factorisations in FP64): by default one per compute
+ * unit.  A grid chosen for a key (device, storage and factor types, b, max_n
+ * rounded up to a power of two) is used by every later rid_lupp_batched call
+ * with that key.  The grid changes which workgroup takes which block, not
+ * any block's arithmetic: results are identical for every grid.
+ * rid_batched_set_grid: grid >= 1 workgroups (capped at the compute units),
+ *   0 = the default.
+ * rid_batched_autotune: with the arguments of rid_lupp_batched (its outputs
+ *   are overwritten), times the candidate grids (all, three quarters and
+ *   half of the compute units; one untimed call, then the median of three,
+ *   HIP events on `stream`, which it synchronizes: a tuning call, not for
+ *   capture), records the fastest, returns it in *grid_out (host, nullable)
+ *   and the three medians in ms_out[3] (host, nullable; -1 for candidates
+ *   not timed).  FP32 factorisations keep one block per workgroup, so only
+ *   the default is timed for them.
+ * Both return RID_ERR_ARG for invalid arguments (set_grid: also for an FP32
+ * factorisation).
+ */
+int rid_batched_set_grid(const rid_config* cfg, int32_t b, int32_t max_n, int32_t grid);
+int rid_batched_autotune(int32_t nblk, const void* const* A, const int64_t* lda, const int32_t* m,
+                         const int32_t* n, int32_t b, double tol, const int32_t* kmax,
+                         const int32_t* k_hint, const rid_config* cfg, int32_t* const* J,
+                         void* const* T, const int64_t* ldt, int32_t* k_out, double* err_est,
+                         int32_t* status, int32_t* passes, const int32_t* order, int32_t max_n,
+                         int32_t max_kmax, void* work, size_t work_bytes, hipStream_t stream,
+                         int32_t* grid_out, float* ms_out);
+
+/*
  * Test export: materialises the Gaussian embedding block
  *   out[c * m + i] = omega(c0 + c, i), 0 <= c < w, 0 <= i < m
  * in the given dtype (device buffer).  The decomposition never stores Omega;

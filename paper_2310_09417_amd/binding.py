@@ -81,6 +81,11 @@ def library() -> ctypes.CDLL:
         lib.rid_lupp_batched.argtypes = [i32, P, P, P, P, i32, dbl, P, P, cfgp, P, P, P, P, P, P,
                                          P, P, i32, i32, P, sz, P]
         lib.rid_lupp_batched.restype = i32
+        lib.rid_batched_set_grid.argtypes = [cfgp, i32, i32, i32]
+        lib.rid_batched_set_grid.restype = i32
+        lib.rid_batched_autotune.argtypes = [i32, P, P, P, P, i32, dbl, P, P, cfgp, P, P, P, P,
+                                             P, P, P, P, i32, i32, P, sz, P, P, P]
+        lib.rid_batched_autotune.restype = i32
         lib.rid_debug_mfma_probe.argtypes = [i32, P, P, P, P]
         lib.rid_debug_mfma_probe.restype = i32
         lib.rid_rank_features.argtypes = [i32, P, P, P, P, dbl, cfgp, P, P]
@@ -577,6 +582,28 @@ class BatchPlan:
             self.work.data_ptr(), self.work.numel(),
             stream if stream is not None else _stream_ptr())
         _check(rc, "rid_lupp_batched")
+
+    def set_grid(self, grid: int):
+        """Persistent workgroups (0 = one per compute unit) for this plan's key."""
+        _check(int(library().rid_batched_set_grid(ctypes.byref(self.cfg), self.b, self.max_n,
+                                                  grid)), "rid_batched_set_grid")
+
+    def autotune(self):
+        """Time the candidate persistent grids on this batch, keep the fastest
+        for this plan's key; returns (grid, [ms per candidate])."""
+        g = ctypes.c_int32(0)
+        ms = (ctypes.c_float * 3)()
+        rc = library().rid_batched_autotune(
+            self.nblk, self.A.data_ptr(), self.lda.data_ptr(), self.m.data_ptr(),
+            self.n.data_ptr(), self.b, self.tol, self.kmax.data_ptr(),
+            self.k_hint.data_ptr() if self.k_hint is not None else 0, ctypes.byref(self.cfg),
+            self.J.data_ptr(), self.T.data_ptr(), self.ldt.data_ptr(), self.k_out.data_ptr(),
+            self.err.data_ptr(), self.st.data_ptr(), self.passes.data_ptr(),
+            self.order.data_ptr() if self.order is not None else 0, self.max_n, self.max_kmax,
+            self.work.data_ptr(), self.work.numel(), _stream_ptr(), ctypes.byref(g),
+            ctypes.cast(ms, ctypes.c_void_p))
+        _check(int(rc), "rid_batched_autotune")
+        return int(g.value), [float(x) for x in ms]
 
     def result(self) -> BatchOutput:
         torch = _torch()

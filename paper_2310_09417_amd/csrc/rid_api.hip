@@ -7,7 +7,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -29,6 +31,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxW = 128;        // widest sketch block per pass / panel
 constexpr int kPanel = 64;        // panel width of the fixed-rank factorisation
+constexpr int kGridCandidates = 3;  // persistent grids the batched autotuner times
 constexpr size_t kMaxLds = 160 * 1024;
 
 // LDS of the panel factorisation: the rows' panel values, two pivot rows of
@@ -1089,6 +1092,37 @@ struct BPlan {
   int G = 0;
 };
 
+// Persistent grid of the batched kernel chosen per (device, storage type,
+// factor type, b, max_n rounded up to a power of two): the number of
+// workgroups taking blocks from the queue (0 = one per compute unit).
+struct GridKey {
+  int dev, dt, at, b, nbucket;
+  bool operator<(const GridKey& o) const {
+    return std::tie(dev, dt, at, b, nbucket) < std::tie(o.dev, o.dt, o.at, o.b, o.nbucket);
+  }
+};
+std::mutex grid_mu;
+std::map<GridKey, int> grid_cache;
+
+GridKey grid_key(const rid_config* cfg, int32_t b, int32_t max_n) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int nb = 64;
+  while (nb < max_n) nb *= 2;
+  return GridKey{dev, (int)cfg->dtype, (int)cfg->a_type, b, nb};
+}
+
+int batched_grid(const rid_config* cfg, int32_t b, int32_t max_n) {
+  std::lock_guard<std::mutex> lk(grid_mu);
+  auto it = grid_cache.find(grid_key(cfg, b, max_n));
+  return it == grid_cache.end() ? 0 : it->second;
+}
+
+void set_batched_grid(const rid_config* cfg, int32_t b, int32_t max_n, int grid) {
+  std::lock_guard<std::mutex> lk(grid_mu);
+  grid_cache[grid_key(cfg, b, max_n)] = grid;
+}
+
 bool bplan(int32_t maxn, int32_t maxk, int32_t b, rid_dtype dt, BPlan& P) {
   DeviceInfo di = device_info();
   if (!di.ok) return false;
@@ -1504,22 +1538,96 @@ int rid_lupp_batched(int32_t nblk, const void* const* A, const int64_t* lda, con
   unsigned char* base = static_cast<unsigned char*>(work) + kAlign;
   hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(1), 0, stream, queue);
   RID_LAUNCH_CHECK();
-  const int grid = std::min<int>(P.G, nblk);
+  // persistent workgroups: one per compute unit unless a smaller grid was
+  // chosen for this key (rid_batched_autotune / rid_batched_set_grid; FP64
+  // factorisations only: an FP32 one keeps one block per workgroup)
+  const int g_set = cfg->dtype == RID_F64 ? batched_grid(cfg, b, max_n) : 0;
+  const int grid = std::min<int>(g_set > 0 ? std::min(g_set, P.G) : P.G, nblk);
   const long pm = prof_begin(KC_BATCHED, stream);
+#define RID_BATCHED(TFV, TAV)                                                                  \
+  hipLaunchKernelGGL((k_batched<rid::kBT, TFV, TAV>), dim3(grid), dim3(rid::kBT), 0, stream,    \
+                     nblk, A, lda, m, n, b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, \
+                     ldt, k_out, err_est, status, passes, order, queue, base, P.L, max_n, maxk)
   if (cfg->dtype == RID_F64 && cfg->a_type == RID_F32)
-    hipLaunchKernelGGL((k_batched<double, float>), dim3(grid), dim3(rid::kBT), 0, stream, nblk, A,
-                       lda, m, n, b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt,
-                       k_out, err_est, status, passes, order, queue, base, P.L, max_n, maxk);
+    RID_BATCHED(double, float);
   else if (cfg->dtype == RID_F64)
-    hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
-                       b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
-                       err_est, status, passes, order, queue, base, P.L, max_n, maxk);
+    RID_BATCHED(double, double);
   else
-    hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(rid::kBT), 0, stream, nblk, A, lda, m, n,
-                       b, tol, cfg->tol_relative, kmax, k_hint, cfg->seed, J, T, ldt, k_out,
-                       err_est, status, passes, order, queue, base, P.L, max_n, maxk);
+    RID_BATCHED(float, float);
+#undef RID_BATCHED
   prof_end(pm, stream);
   RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
+int rid_batched_set_grid(const rid_config* cfg, int32_t b, int32_t max_n, int32_t grid) {
+  if (!valid_batched_cfg(cfg) || cfg->dtype != RID_F64 || b < 1 || b > rid::kBPW || max_n < 1 ||
+      max_n > rid::kBMaxN || grid < 0)
+    return RID_ERR_ARG;
+  set_batched_grid(cfg, b, max_n, grid);
+  return RID_OK;
+}
+
+int rid_batched_autotune(int32_t nblk, const void* const* A, const int64_t* lda, const int32_t* m,
+                         const int32_t* n, int32_t b, double tol, const int32_t* kmax,
+                         const int32_t* k_hint, const rid_config* cfg, int32_t* const* J,
+                         void* const* T, const int64_t* ldt, int32_t* k_out, double* err_est,
+                         int32_t* status, int32_t* passes, const int32_t* order, int32_t max_n,
+                         int32_t max_kmax, void* work, size_t work_bytes, hipStream_t stream,
+                         int32_t* grid_out, float* ms_out) {
+  if (!valid_batched_cfg(cfg) || nblk < 1 || b < 1 || b > rid::kBPW || max_n < 1 ||
+      max_n > rid::kBMaxN)
+    return RID_ERR_ARG;
+  DeviceInfo di = device_info();
+  if (!di.ok) return RID_ERR_HIP;
+  // candidates: all compute units, three quarters, half (FP32 factorisations
+  // never take more blocks than workgroups, so their grid is not tuned)
+  const int G = di.cu;
+  const int cand[kGridCandidates] = {G, (3 * G) / 4, G / 2};
+  const int ncand = cfg->dtype == RID_F64 ? kGridCandidates : 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return RID_ERR_HIP;
+  }
+  const int saved = batched_grid(cfg, b, max_n);
+  float best = -1.0f;
+  int best_g = 0;
+  int rc = RID_OK;
+  for (int i = 0; i < ncand && rc == RID_OK; ++i) {
+    set_batched_grid(cfg, b, max_n, cand[i]);
+    float ts[3] = {0.f, 0.f, 0.f};
+    // one untimed call, then the median of three timed ones
+    for (int rep = 0; rep < 4 && rc == RID_OK; ++rep) {
+      float t = 0.0f;
+      if (hipEventRecord(e0, stream) != hipSuccess) rc = RID_ERR_HIP;
+      if (rc == RID_OK)
+        rc = rid_lupp_batched(nblk, A, lda, m, n, b, tol, kmax, k_hint, cfg, J, T, ldt, k_out,
+                              err_est, status, passes, order, max_n, max_kmax, work, work_bytes,
+                              stream);
+      if (rc == RID_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        rc = RID_ERR_HIP;
+      if (rep > 0) ts[rep - 1] = t;
+    }
+    if (rc != RID_OK) break;
+    std::sort(ts, ts + 3);
+    if (ms_out) ms_out[i] = ts[1];
+    if (best < 0.0f || ts[1] < best) {
+      best = ts[1];
+      best_g = cand[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != RID_OK) {
+    set_batched_grid(cfg, b, max_n, saved);
+    return rc;
+  }
+  for (int i = ncand; ms_out && i < kGridCandidates; ++i) ms_out[i] = -1.0f;
+  set_batched_grid(cfg, b, max_n, best_g == G ? 0 : best_g);
+  if (grid_out) *grid_out = best_g;
   return RID_OK;
 }
 

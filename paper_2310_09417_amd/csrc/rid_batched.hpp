@@ -37,7 +37,7 @@ struct BatchOut {
 // [zcol, zcol+w); returns sum A^2 and the non-finite flag when norm is set.
 // A is stored in TA (TF, or FP32 under an FP64 factorisation) and converted
 // to TF as it is loaded.
-template <typename TF, typename TA, int MT>
+template <int NT, typename TF, typename TA, int MT>
 __device__ void wg_sketch(const TA* __restrict__ A, int64_t lda, int m, int n, uint32_t key0,
                           uint32_t key1, uint32_t c0, int w, TF* __restrict__ Z, int64_t ldz,
                           int zcol, TF* om, bool norm, double& fro, bool& bad) {
@@ -46,22 +46,27 @@ __device__ void wg_sketch(const TA* __restrict__ A, int64_t lda, int m, int n, u
   using M = Mfma<TF>;
   using acc_t = typename M::acc_t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int slab0 = 0; slab0 < n; slab0 += kBW * 64) {
+  for (int slab0 = 0; slab0 < n; slab0 += (NT / 64) * 64) {
     const int64_t col4 = slab0 + wave * 64 + 4 * (lane & 15);
     const bool active = slab0 + wave * 64 < n;
+    // FP32 chunk sums are folded into FP64 registers; FP64 accumulates in
+    // its MFMA registers directly (no second copy)
+    constexpr bool FOLD = sizeof(TF) == 4;
     acc_t acc[MT][4];
-    double acc64[MT][4][4];
+    double acc64[FOLD ? MT : 1][4][4];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         acc[a][q] = M::zero();
+        if constexpr (FOLD) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
+          for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
+        }
       }
     for (int r0 = 0; r0 < m; r0 += KC) {
       __syncthreads();
-      for (int it = tid; it < KS * WP; it += kBT) {
+      for (int it = tid; it < KS * WP; it += NT) {
         const int c = it % WP, qd = it / WP;
         const int row4 = r0 + 4 * qd;
         TF v[4] = {TF(0), TF(0), TF(0), TF(0)};
@@ -91,14 +96,16 @@ __device__ void wg_sketch(const TA* __restrict__ A, int64_t lda, int m, int n, u
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[a][q] = M::op(av[a], b4[q], acc[a][q]);
         }
+        if constexpr (FOLD) {
 #pragma unroll
-        for (int a = 0; a < MT; ++a)
+          for (int a = 0; a < MT; ++a)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
-            acc[a][q] = M::zero();
-          }
+              for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
+              acc[a][q] = M::zero();
+            }
+        }
       }
     }
     if (active) {
@@ -111,7 +118,9 @@ __device__ void wg_sketch(const TA* __restrict__ A, int64_t lda, int m, int n, u
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int c = a * 16 + M::row(lane, r);
-              if (c < w) Z[col * ldz + zcol + c] = (TF)acc64[a][q][r];
+              double v;
+              if constexpr (FOLD) v = acc64[a][q][r]; else v = (double)acc[a][q][r];
+              if (c < w) Z[col * ldz + zcol + c] = (TF)v;
             }
         }
       }
@@ -123,16 +132,16 @@ __device__ void wg_sketch(const TA* __restrict__ A, int64_t lda, int m, int n, u
 // --- panel LUPP on Z columns [zcol, zcol+w), w <= kBPW, f pivots.  Thread t
 // owns candidate rows t + 256 u (u < 4), kept in registers.  Returns the number
 // of pivots taken (< f when an exactly zero pivot was met).
-template <typename TF>
+template <int NT, typename TF>
 __device__ int wg_lupp(TF* __restrict__ Z, int64_t ldz, int n, int zcol, int w, int f,
                        int* __restrict__ pos, int* __restrict__ order, TF* rowbuf, double* red_v,
                        int* red_i) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  TF R[kBRPT][kBPW];
-  bool act[kBRPT], had[kBRPT];
+  TF R[(kBMaxN / NT)][kBPW];
+  bool act[(kBMaxN / NT)], had[(kBMaxN / NT)];
 #pragma unroll
-  for (int u = 0; u < kBRPT; ++u) {
-    const int r = tid + u * kBT;
+  for (int u = 0; u < (kBMaxN / NT); ++u) {
+    const int r = tid + u * NT;
     act[u] = r < n && pos[r] < 0;
     had[u] = act[u];
 #pragma unroll
@@ -145,13 +154,13 @@ __device__ int wg_lupp(TF* __restrict__ Z, int64_t ldz, int n, int zcol, int w, 
     double bv = -1.0;
     long long bi = -1;
 #pragma unroll
-    for (int u = 0; u < kBRPT; ++u)
-      if (act[u]) argmax_merge(bv, bi, fabs((double)R[u][s]), tid + u * kBT);
+    for (int u = 0; u < (kBMaxN / NT); ++u)
+      if (act[u]) argmax_merge(bv, bi, fabs((double)R[u][s]), tid + u * NT);
     wave_argmax(bv, bi);
     // the lane holding the wave's best row publishes it
 #pragma unroll
-    for (int u = 0; u < kBRPT; ++u)
-      if (bi == tid + u * kBT) {
+    for (int u = 0; u < (kBMaxN / NT); ++u)
+      if (bi == tid + u * NT) {
 #pragma unroll
         for (int q = 0; q < kBPW; ++q) rowbuf[wave * kBPW + q] = R[u][q];
       }
@@ -163,7 +172,7 @@ __device__ int wg_lupp(TF* __restrict__ Z, int64_t ldz, int n, int zcol, int w, 
     double gv = -1.0;
     long long gi = -1;
     int gw = -1;
-    for (int wv = 0; wv < kBW; ++wv) {
+    for (int wv = 0; wv < (NT / 64); ++wv) {
       const long long i2 = red_i[wv];
       if (i2 >= 0 && (gi < 0 || red_v[wv] > gv || (red_v[wv] == gv && i2 < gi))) {
         gv = red_v[wv];
@@ -180,8 +189,8 @@ __device__ int wg_lupp(TF* __restrict__ Z, int64_t ldz, int n, int zcol, int w, 
     if (tid == 0) order[zcol + s] = (int)gi;
     const TF d = prow[s];
 #pragma unroll
-    for (int u = 0; u < kBRPT; ++u) {
-      if (gi == tid + u * kBT) {
+    for (int u = 0; u < (kBMaxN / NT); ++u) {
+      if (gi == tid + u * NT) {
         act[u] = false;
         pos[gi] = zcol + s;
       }
@@ -195,10 +204,10 @@ __device__ int wg_lupp(TF* __restrict__ Z, int64_t ldz, int n, int zcol, int w, 
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < kBRPT; ++u)
+  for (int u = 0; u < (kBMaxN / NT); ++u)
 #pragma unroll
     for (int q = 0; q < kBPW; ++q)
-      if (had[u] && q < w) Z[(int64_t)(tid + u * kBT) * ldz + zcol + q] = R[u][q];
+      if (had[u] && q < w) Z[(int64_t)(tid + u * NT) * ldz + zcol + q] = R[u][q];
   __syncthreads();
   return taken;
 }
@@ -206,12 +215,12 @@ __device__ int wg_lupp(TF* __restrict__ Z, int64_t ldz, int n, int zcol, int w, 
 // --- C(i, j) (+)= sum_p A(i, p) B(p, j) over output tiles of 16 x 64 spread
 // over the waves (tile t -> wave t % 8).  arow(i) / brow(p) return row
 // pointers (nullptr when absent); store(i, j, v) receives every valid entry.
-template <typename TF, typename ARow, typename BRow, typename KRange, typename Store>
+template <int NT, typename TF, typename ARow, typename BRow, typename KRange, typename Store>
 __device__ void wg_gemm(int Mrows, int Ncols, ARow arow, BRow brow, KRange krange, Store store) {
   using M = Mfma<TF>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tm = (Mrows + 15) / 16, tn = (Ncols + 63) / 64;
-  for (int t = wave; t < tm * tn; t += kBW) {
+  for (int t = wave; t < tm * tn; t += (NT / 64)) {
     const int i0 = (t / tn) * 16, j0 = (t % tn) * 64;
     typename M::acc_t acc[4];
     double acc64[4][4];
@@ -293,7 +302,7 @@ inline BLayout batched_layout(int64_t maxn, int64_t maxk, int64_t b, int64_t es,
 // Block update for Z columns [zcol, zcol+w) against the k pivots taken so far:
 // U2 = L1^{-1} (P Y)(top) -> U2T, then S = (P Y)(bottom) - L2 U2 in place;
 // returns sum S^2 (FP64) to every thread.
-template <typename TF>
+template <int NT, typename TF>
 __device__ double wg_block_update(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int64_t ldu, int n,
                                   int k, int zcol, int w, double* red) {
   const int tid = threadIdx.x;
@@ -302,7 +311,7 @@ __device__ double wg_block_update(const BSlice<TF>& S, int64_t ldz, int64_t ldl,
     const TF* Linv = S.Linv;
     TF* U2T = S.U2T;
     const int* order = S.order;
-    wg_gemm<TF>(
+    wg_gemm<NT, TF>(
         k, w, [&](int i) -> const TF* { return Linv + (int64_t)i * ldl; },
         [&](int p) -> const TF* { return Z + (int64_t)order[p] * ldz + zcol; },
         [&](int i0, int, int& kb, int& ke) {
@@ -322,7 +331,7 @@ __device__ double wg_block_update(const BSlice<TF>& S, int64_t ldz, int64_t ldl,
     using M = Mfma<TF>;
     const int lane = tid & 63, wave = tid >> 6;
     const int tm = (n + 15) / 16;
-    for (int t = wave; t < tm; t += kBW) {
+    for (int t = wave; t < tm; t += (NT / 64)) {
       const int i0 = t * 16;
       const int i = i0 + (lane & 15);
       const bool ok = i < n && pos[i] < 0;
@@ -382,7 +391,7 @@ __device__ double wg_block_update(const BSlice<TF>& S, int64_t ldz, int64_t ldl,
   if ((tid & 63) == 0) red[tid >> 6] = ss;
   __syncthreads();
   double tot = 0.0;
-  for (int wv = 0; wv < kBW; ++wv) tot += red[wv];
+  for (int wv = 0; wv < (NT / 64); ++wv) tot += red[wv];
   __syncthreads();
   return tot;
 }
@@ -390,7 +399,7 @@ __device__ double wg_block_update(const BSlice<TF>& S, int64_t ldz, int64_t ldl,
 // Growth of L1^{-1} by the f pivots of the panel at k0 (f <= kBPW):
 // diagonal block by column substitution (thread j <-> column j), then
 // Linv[k0+i, 0:k0] = -L22^{-1} (L21 L1^{-1}_old).
-template <typename TF>
+template <int NT, typename TF>
 __device__ void wg_linv_grow(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int k0, int f) {
   const int tid = threadIdx.x;
   TF* Linv = S.Linv;
@@ -410,7 +419,7 @@ __device__ void wg_linv_grow(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int 
   __syncthreads();
   if (k0 == 0) return;
   TF* Mtmp = S.Mtmp;
-  wg_gemm<TF>(
+  wg_gemm<NT, TF>(
       f, k0, [&](int i) -> const TF* { return Z + (int64_t)order[k0 + i] * ldz; },
       [&](int p) -> const TF* { return Linv + (int64_t)p * ldl; },
       [&](int, int j0, int& kb, int& ke) {
@@ -418,7 +427,7 @@ __device__ void wg_linv_grow(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int 
         ke = k0;
       },
       [&](int i, int j, double v) { Mtmp[(int64_t)i * ldl + j] = (TF)v; });
-  wg_gemm<TF>(
+  wg_gemm<NT, TF>(
       f, k0, [&](int i) -> const TF* { return Linv + (int64_t)(k0 + i) * ldl + k0; },
       [&](int p) -> const TF* { return Mtmp + (int64_t)p * ldl; },
       [&](int i0, int, int& kb, int& ke) {
@@ -431,7 +440,7 @@ __device__ void wg_linv_grow(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int 
 // Factor Z columns [k, k+w) with f pivots in panels of kBPW (block updates
 // between panels); maintains L1^{-1}.  Returns the new rank (smaller than
 // k + f when the sketch's rank is reached).
-template <typename TF>
+template <int NT, typename TF>
 __device__ int wg_factor(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int64_t ldu, int n, int k,
                          int w, int f, TF* rowbuf, double* red, int* red_i) {
   int done = 0;
@@ -439,9 +448,9 @@ __device__ int wg_factor(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int64_t 
     const int pw = (w - done < kBPW) ? w - done : kBPW;
     const int pf = (f - done < pw) ? f - done : pw;
     const int k0 = k + done;
-    if (done > 0) wg_block_update<TF>(S, ldz, ldl, ldu, n, k0, k0, pw, red);
-    const int got = wg_lupp<TF>(S.Z, ldz, n, k0, pw, pf, S.pos, S.order, rowbuf, red, red_i);
-    if (got > 0) wg_linv_grow<TF>(S, ldz, ldl, k0, got);
+    if (done > 0) wg_block_update<NT, TF>(S, ldz, ldl, ldu, n, k0, k0, pw, red);
+    const int got = wg_lupp<NT, TF>(S.Z, ldz, n, k0, pw, pf, S.pos, S.order, rowbuf, red, red_i);
+    if (got > 0) wg_linv_grow<NT, TF>(S, ldz, ldl, k0, got);
     __syncthreads();
     done += got;
     if (got < pf) break;
@@ -450,13 +459,13 @@ __device__ int wg_factor(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int64_t 
 }
 
 // T(s, q) = sum_{p >= s} L2(q, p) L1^{-1}(p, s); J in pivot order.
-template <typename TF>
+template <int NT, typename TF>
 __device__ void wg_outputs(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int n, int k,
                            TF* __restrict__ T, int64_t ldt, int32_t* __restrict__ J, int* cnt) {
   const int tid = threadIdx.x;
-  for (int s = tid; s < k; s += kBT) J[s] = S.order[s];
+  for (int s = tid; s < k; s += NT) J[s] = S.order[s];
   // non-pivots in ascending order (flags, then one serial scan over <= 1024)
-  for (int r = tid; r < kBMaxN; r += kBT) cnt[r] = (r < n && S.pos[r] < 0) ? 1 : 0;
+  for (int r = tid; r < kBMaxN; r += NT) cnt[r] = (r < n && S.pos[r] < 0) ? 1 : 0;
   __syncthreads();
   if (tid == 0) {
     int run = 0;
@@ -467,7 +476,7 @@ __device__ void wg_outputs(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int n,
     }
   }
   __syncthreads();
-  for (int r = tid; r < n; r += kBT)
+  for (int r = tid; r < n; r += NT)
     if (cnt[r] >= 0) S.nonpiv[cnt[r]] = r;
   __syncthreads();
   const int nn = n - k;
@@ -475,7 +484,7 @@ __device__ void wg_outputs(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int n,
   const TF* Z = S.Z;
   const TF* Linv = S.Linv;
   const int* nonpiv = S.nonpiv;
-  wg_gemm<TF>(
+  wg_gemm<NT, TF>(
       nn, k, [&](int q) -> const TF* { return Z + (int64_t)nonpiv[q] * ldz; },
       [&](int p) -> const TF* { return Linv + (int64_t)p * ldl; },
       [&](int, int j0, int& kb, int& ke) {
@@ -488,8 +497,8 @@ __device__ void wg_outputs(const BSlice<TF>& S, int64_t ldz, int64_t ldl, int n,
 // The persistent kernel.  Block ids come from queue (zeroed beforehand),
 // optionally remapped by perm (e.g. largest blocks first).  Blocks are stored
 // in TA: TF, or FP32 blocks factored in FP64 (TF = double, TA = float).
-template <typename TF, typename TA = TF>
-__global__ __launch_bounds__(kBT) void k_batched(
+template <int NT, typename TF, typename TA = TF>
+__global__ __launch_bounds__(NT) void k_batched(
     int nblk, const void* const* __restrict__ Aptr, const int64_t* __restrict__ lda,
     const int32_t* __restrict__ mv, const int32_t* __restrict__ nv, int b, double tol, int rel,
     const int32_t* __restrict__ kmaxv, const int32_t* __restrict__ khint, uint64_t seed,
@@ -500,9 +509,9 @@ __global__ __launch_bounds__(kBT) void k_batched(
   constexpr int LDO = 64 + 16;
   constexpr int KC = sizeof(TF) == 4 ? 64 : 32;
   __shared__ TF om[KC * LDO];
-  __shared__ TF rowbuf[kBW * kBPW];
-  __shared__ double red[kBW];
-  __shared__ int red_i[kBW];
+  __shared__ TF rowbuf[(NT / 64) * kBPW];
+  __shared__ double red[(NT / 64)];
+  __shared__ int red_i[(NT / 64)];
   __shared__ int cnt[kBMaxN];
   __shared__ int s_blk;
   const int tid = threadIdx.x;
@@ -544,8 +553,8 @@ __global__ __launch_bounds__(kBT) void k_batched(
     const uint64_t bseed = seed + (uint64_t)blk;
     const uint32_t key0 = (uint32_t)(bseed & 0xffffffffu), key1 = (uint32_t)(bseed >> 32);
     // clear pivot map and L1^{-1}
-    for (int r = tid; r < n; r += kBT) S.pos[r] = -1;
-    for (int64_t t = tid; t < (int64_t)kcap * ldl; t += kBT) S.Linv[t] = TF(0);
+    for (int r = tid; r < n; r += NT) S.pos[r] = -1;
+    for (int64_t t = tid; t < (int64_t)kcap * ldl; t += NT) S.Linv[t] = TF(0);
     __syncthreads();
     // first block width: learned hint when given, else b
     int w0 = b;
@@ -563,11 +572,11 @@ __global__ __launch_bounds__(kBT) void k_batched(
         const int wc = (w - d < 64) ? w - d : 64;
         const bool norm = (cnext == 0);
         if (wc <= 16)
-          wg_sketch<TF, TA, 1>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+          wg_sketch<NT, TF, TA, 1>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         else if (wc <= 32)
-          wg_sketch<TF, TA, 2>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+          wg_sketch<NT, TF, TA, 2>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         else
-          wg_sketch<TF, TA, 4>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
+          wg_sketch<NT, TF, TA, 4>(A, la, m, n, key0, key1, cnext, wc, S.Z, ldz, zcol + d, om, norm, fro, bad);
         cnext += wc;
         d += wc;
         ++passes;
@@ -587,7 +596,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
       __syncthreads();
       double tot = 0.0;
       int nb = 0;
-      for (int wv = 0; wv < kBW; ++wv) {
+      for (int wv = 0; wv < (NT / 64); ++wv) {
         tot += red[wv];
         nb |= red_i[wv];
       }
@@ -600,7 +609,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
     if (bad) {
       status = ST_ERR_NONFINITE;
     } else {
-      k = wg_factor<TF>(S, ldz, ldl, ldu, n, 0, w0, w0, rowbuf, red, red_i);
+      k = wg_factor<NT, TF>(S, ldz, ldl, ldu, n, 0, w0, w0, rowbuf, red, red_i);
       if (k < w0) {
         status = ST_RANK_DEFICIENT;
         E = 0.0;
@@ -613,7 +622,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
         // the estimating block: b fresh vectors at column k unless the
         // previous passes already drew them there
         if (have < k + b) sketch(k, b);
-        const double ss = wg_block_update<TF>(S, ldz, ldl, ldu, n, k, k, b, red);
+        const double ss = wg_block_update<NT, TF>(S, ldz, ldl, ldu, n, k, k, b, red);
         E = sqrt(ss) / sqrt((double)b);
         if (E <= thr) break;
         if (k >= kcap) {
@@ -623,7 +632,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
         // factor f <= b of the block's columns; the rest of the block has been
         // reduced by the panel and is not reused (the next block is fresh)
         const int f = (b < kcap - k) ? b : kcap - k;
-        const int k2 = wg_factor<TF>(S, ldz, ldl, ldu, n, k, b, f, rowbuf, red, red_i);
+        const int k2 = wg_factor<NT, TF>(S, ldz, ldl, ldu, n, k, b, f, rowbuf, red, red_i);
         have = k2;
         if (k2 < k + f) {
           k = k2;
@@ -634,7 +643,7 @@ __global__ __launch_bounds__(kBT) void k_batched(
       }
     }
     if (status != ST_ERR_NONFINITE)
-      wg_outputs<TF>(S, ldz, ldl, n, k, static_cast<TF*>(Tptr[blk]), ldtv[blk], Jptr[blk], cnt);
+      wg_outputs<NT, TF>(S, ldz, ldl, n, k, static_cast<TF*>(Tptr[blk]), ldtv[blk], Jptr[blk], cnt);
     if (tid == 0) {
       k_out[blk] = status == ST_ERR_NONFINITE ? 0 : k;
       err_out[blk] = E;

@@ -39,7 +39,7 @@ class EmuOut:
 
 def run(exe: str, blocks, b: int, tol: float, seed: int, dtype=np.float64, kmax=None, hints=None,
         order=None, relative=True, groups: int = 2, gap: int = 1 << 16, max_n=None,
-        max_kmax=None, timeout=1200, factor=None) -> EmuOut:
+        max_kmax=None, timeout=1200, factor=None, threads: int = 256) -> EmuOut:
     """dtype: storage type of the blocks; factor: np.float64 with float32
     blocks runs the FP32-storage, FP64-factorisation instantiation."""
     nblk = len(blocks)
@@ -61,8 +61,9 @@ def run(exe: str, blocks, b: int, tol: float, seed: int, dtype=np.float64, kmax=
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
         with open(fin, "wb") as f:
-            f.write(struct.pack("<9i", dt, nblk, b, 1 if relative else 0, max_n, max_kmax, groups,
-                                1 if hints is not None else 0, 1 if order is not None else 0))
+            f.write(struct.pack("<10i", dt, nblk, b, 1 if relative else 0, max_n, max_kmax, groups,
+                                1 if hints is not None else 0, 1 if order is not None else 0,
+                                threads))
             f.write(struct.pack("<dQQ", tol, seed, gap))
             for i in range(nblk):
                 h = int(hints[i]) if hints is not None else 0

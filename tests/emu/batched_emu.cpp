@@ -9,8 +9,8 @@
 // the intended array stops the run with a report.
 //
 // Input file (little endian): int32 dtype (0 FP64, 1 FP32, 2 FP32 blocks
-// factored in FP64), nblk, b, rel,
-// max_n, max_kmax, groups, has_hint, has_perm; double tol; uint64 seed, gap;
+// factored in FP64), nblk, b, rel, max_n, max_kmax, groups, has_hint,
+// has_perm, threads per workgroup (256, or 512 when factored in FP64); double tol; uint64 seed, gap;
 // per block int32 m, n, kmax, hint; nblk int32 perm (if has_perm); then per
 // block its m x n row-major matrix in the storage type.  Blocks are dealt to the
 // emulated workgroups round robin in processing order, each workgroup taking
@@ -67,22 +67,24 @@ struct Args {
   rid::BLayout lay;
   int maxk;
   int dtype;
+  int nt;
 };
 
 void body(void* p) {
   Args& a = *static_cast<Args*>(p);
-  if (a.dtype == 2)
-    rid::k_batched<double, float>(a.nblk, a.A, a.lda, a.m, a.n, a.b, a.tol, a.rel, a.kmax, a.hint,
-                                  a.seed, a.J, a.T, a.ldt, a.k, a.E, a.st, a.passes, a.perm,
-                                  a.queue, a.wbase, a.lay, a.max_n, a.maxk);
-  else if (a.dtype == 0)
-    rid::k_batched<double>(a.nblk, a.A, a.lda, a.m, a.n, a.b, a.tol, a.rel, a.kmax, a.hint, a.seed,
-                           a.J, a.T, a.ldt, a.k, a.E, a.st, a.passes, a.perm, a.queue, a.wbase,
-                           a.lay, a.max_n, a.maxk);
-  else
-    rid::k_batched<float>(a.nblk, a.A, a.lda, a.m, a.n, a.b, a.tol, a.rel, a.kmax, a.hint, a.seed,
-                          a.J, a.T, a.ldt, a.k, a.E, a.st, a.passes, a.perm, a.queue, a.wbase,
-                          a.lay, a.max_n, a.maxk);
+#define EMU_CALL(NTV, TFV, TAV)                                                             \
+  rid::k_batched<NTV, TFV, TAV>(a.nblk, a.A, a.lda, a.m, a.n, a.b, a.tol, a.rel, a.kmax, a.hint, \
+                                a.seed, a.J, a.T, a.ldt, a.k, a.E, a.st, a.passes, a.perm,       \
+                                a.queue, a.wbase, a.lay, a.max_n, a.maxk)
+  if (a.nt == 512) {
+    if (a.dtype == 2) EMU_CALL(512, double, float);
+    else EMU_CALL(512, double, double);
+  } else {
+    if (a.dtype == 2) EMU_CALL(256, double, float);
+    else if (a.dtype == 0) EMU_CALL(256, double, double);
+    else EMU_CALL(256, float, float);
+  }
+#undef EMU_CALL
 }
 
 }  // namespace
@@ -94,10 +96,14 @@ int main(int argc, char** argv) {
   }
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 2;
-  int32_t h[9];
-  rd(f, h, 9);
+  int32_t h[10];
+  rd(f, h, 10);
   const int dtype = h[0], nblk = h[1], b = h[2], rel = h[3], max_n = h[4], max_kmax = h[5];
-  const int groups = h[6], has_hint = h[7], has_perm = h[8];
+  const int groups = h[6], has_hint = h[7], has_perm = h[8], nt = h[9];
+  if (nt != 256 && (nt != 512 || dtype == 1)) {
+    fprintf(stderr, "batched_emu: unsupported workgroup shape %d\n", nt);
+    return 2;
+  }
   double tol;
   uint64_t seed, gap;
   rd(f, &tol);
@@ -166,10 +172,10 @@ int main(int argc, char** argv) {
     *queue = 0;
     Args a{(int)mine.size(), b, rel, max_n, max_kmax, tol, seed, A.data(), lda.data(), m.data(),
            n.data(), kmax.data(), has_hint ? hint.data() : nullptr, J.data(), T.data(), ldt.data(),
-           kout, st, passes, E, mp, queue, wbase, lay, maxk, dtype};
+           kout, st, passes, E, mp, queue, wbase, lay, maxk, dtype, nt};
     // the kernel reads the block count through nblk but indexes the per-block
     // arrays by block id; ids come from the processing list
-    emu::run_group(rid::kBT, (unsigned)g, (unsigned)groups, &body, &a);
+    emu::run_group((unsigned)nt, (unsigned)g, (unsigned)groups, &body, &a);
     free(mp);
   }
   FILE* o = fopen(argv[2], "wb");

@@ -136,3 +136,26 @@ def test_emu_fp32_storage_fp64_factor_matches_oracle(exe, orc):
                    float(out.err_est[i]), o, b, tag=i, exact=ex,
                    at_rank=lambda kk, A64=A64, i=i: orc.rid_fixed_rank(A64, kk, b, seed=70 + i))
     assert exact >= 9, exact
+
+
+@pytest.mark.parametrize("factor", [None, np.float64])
+def test_emu_512_thread_shape_matches_oracle(exe, orc, factor):
+    """The 512-thread workgroup shape (two candidate rows per thread, eight
+    waves) of the FP64 factorisation, FP64 and FP32 storage, with several
+    blocks per workgroup and a first-width hint on some blocks.  Its source
+    passes here; on the GPU its compiled form faulted (the library does not
+    launch it), so this test records that the fault is not visible at the
+    level of the source's indices, extents and synchronisation."""
+    blocks = _blocks(10, seed=57)
+    b, tol = 16, 1e-8
+    dtype = np.float64 if factor is None else np.float32
+    Ab = [A.astype(dtype) for A in blocks]
+    hints = [0, 24, 0, 40, 0, 8, 0, 0, 33, 0]
+    out = run(exe, Ab, b, tol, seed=80, dtype=dtype, factor=factor, groups=3, hints=hints,
+              threads=512)
+    for i, A in enumerate(Ab):
+        A64 = A.astype(np.float64)
+        o = orc.rid_adaptive(A64, b, tol, min(A.shape), seed=80 + i, first_width=hints[i])
+        check_fp64(A64, out.J[i], out.T[i], int(out.k[i]), int(out.status[i]),
+                   float(out.err_est[i]), o, b, tag=i, exact=o.robust_k == o.k,
+                   at_rank=lambda kk, A64=A64, i=i: orc.rid_fixed_rank(A64, kk, b, seed=80 + i))

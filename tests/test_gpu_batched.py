@@ -139,6 +139,67 @@ def test_batched_fp32_storage_many_blocks_per_workgroup(env, orc):
                                                                       seed=900 + int(i)))
 
 
+@pytest.mark.skip(reason="the 512-thread workgroup shape of the batched kernel faulted the GPU "
+                         "(memory fault, FP64, 300 blocks of 64-300) although its host emulation "
+                         "under AddressSanitizer passes; no cause shown, so the shape is not "
+                         "launched by the library")
+@pytest.mark.parametrize("factor", [None, "float64"])
+def test_batched_512_thread_shape_matches_oracle(env, orc, factor):
+    """The 512-thread workgroup shape of the FP64 factorisation (FP64 and
+    FP32 storage), with more blocks than compute units, against the oracle."""
+    torch, rid = env
+    print("batched 512-thread shape", factor, file=sys.stderr, flush=True)
+    shapes = workloads.kernel_batch_shapes(300, 61, 64, 300)
+    blocks = [workloads.kernel_block(m, n, sep, s_) for (m, n, sep, s_) in shapes]
+    if factor:
+        blocks = [A.astype(np.float32) for A in blocks]
+    dev = [torch.tensor(A, device="cuda") for A in blocks]
+    b, tol = 16, 1e-8
+    plan = rid.BatchPlan(dev, b, tol, seed=500, factor=torch.float64 if factor else None)
+    plan.set_shape(512)
+    try:
+        plan.launch()
+        out = plan.result()
+    finally:
+        plan.set_shape(0)
+    assert np.all(out.status == rid.RID_OK)
+    sample = np.random.default_rng(3).choice(len(blocks), size=24, replace=False)
+    for i in sample:
+        A64 = blocks[i].astype(np.float64)
+        o = orc.rid_adaptive(A64, b, tol, min(A64.shape), seed=500 + int(i))
+        check_fp64(A64, out.J[i].cpu().numpy(), out.T[i].cpu().numpy(), int(out.k[i]),
+                   int(out.status[i]), float(out.err_est[i]), o, b, tag=int(i),
+                   exact=o.robust_k == o.k,
+                   at_rank=lambda kk, A64=A64, i=i: orc.rid_fixed_rank(A64, kk, b,
+                                                                      seed=500 + int(i)))
+
+
+def test_batched_autotune_picks_a_grid(env):
+    """The autotuner times the candidate persistent grids on the batch and
+    records the fastest; a grid changes no block's result."""
+    torch, rid = env
+    blocks = [torch.tensor(A, device="cuda") for A in _blocks(300, seed=71)]
+    plan = rid.BatchPlan(blocks, 16, 1e-8, seed=5)
+    try:
+        plan.launch()
+        ref = plan.result()
+        refJ = [j.clone() for j in ref.J]
+        refT = [t.clone() for t in ref.T]
+        g, ms = plan.autotune()
+        print("autotune:", g, ms, file=sys.stderr, flush=True)
+        cu = torch.cuda.get_device_properties(0).multi_processor_count
+        assert g in (cu, 3 * cu // 4, cu // 2) and all(t > 0 for t in ms)
+        assert ms[[cu, 3 * cu // 4, cu // 2].index(g)] == min(ms)
+        plan.set_grid(cu // 2)
+        plan.launch()
+        out = plan.result()
+        assert np.array_equal(out.k, ref.k) and np.array_equal(out.err_est, ref.err_est)
+        for i in range(len(blocks)):
+            assert torch.equal(out.J[i], refJ[i]) and torch.equal(out.T[i], refT[i]), i
+    finally:
+        plan.set_grid(0)
+
+
 def test_batched_hint_and_order(env, orc):
     """A first-block width (predicted rank) follows the oracle's variant with
     the same first width; the processing order does not change any result."""
