@@ -18,20 +18,12 @@
 #include <type_traits>
 
 #include "rid_device.hpp"
+#include "rid_schur.hpp"
 #include "rid_tile.hpp"
 
 namespace rid {
 
-// Device-resident control block of one decomposition.
-struct Ctrl {
-  int32_t k;          // pivots taken so far
-  int32_t done;       // 1 once the result is final (later kernels return at once)
-  int32_t status;     // rid_status value
-  int32_t nonfinite;  // set by the sketch when A holds NaN / Inf
-  double E;           // latest estimate E = ||S||_F / sqrt(w), -1 before the first
-  double frob2;       // ||A||_F^2 accumulated in FP64 during the first sketch pass
-  int32_t pad[8];
-};
+
 
 
 // ---------------------------------------------------------------------------
@@ -49,112 +41,6 @@ __global__ void k_init(Ctrl* ctrl, int* pos, int64_t n, int* nonfinite) {
     ctrl->frob2 = 0.0;
   }
   if (t < n) pos[t] = -1;
-}
-
-// ---------------------------------------------------------------------------
-// Schur block S = (P Y)(non-pivots, block) - L2 U2 (MFMA, K = [kb, k)),
-// written in place for every non-pivot row (kb > 0: the block already holds
-// the Schur complement for the first kb pivots and is reduced by the pivots
-// kb..k-1 only); with `want_norm` each workgroup also leaves
-// its FP64 sum of S^2 in normpart[blockIdx.x].  Each wave owns 16 rows and
-// all NT 16-column tiles of the block.  The K index is walked in chunks of
-// 16: a lane loads 4 consecutive K values of its A row and of its U2 column
-// and feeds them to 4 MFMAs (a consistent relabelling of K inside the chunk).
-// FP32: the MFMA accumulator is folded into FP64 every 64 K values.
-// ---------------------------------------------------------------------------
-
-// FROM: K starts at kb (else at 0; the kb argument is then ignored).
-// CG: the four waves cover 64/CG rows and CG groups of NT column tiles (wave
-// = row group * CG + column group), so narrow matrices still fill the chip;
-// every output keeps the same K order, whatever CG.
-template <typename TF, int NT, bool FROM = false, int CG = 1>
-__global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, int64_t n,
-                                               const int* __restrict__ pos, int kb, int k, int zcol,
-                                               int w, const TF* __restrict__ U2T, int64_t ldu,
-                                               double* __restrict__ normpart, const Ctrl* ctrl,
-                                               int want_norm) {
-  if (ctrl->done) return;
-  using M = Mfma<TF>;
-  using acc_t = typename M::acc_t;
-  __shared__ double red[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t rbase = (int64_t)blockIdx.x * (64 / CG) + (wave / CG) * 16;
-  const int col0 = (wave % CG) * NT * 16;
-  const int64_t arow = rbase + (lane & 15);
-  const bool arow_ok = arow < n;
-  acc_t acc[NT];
-  double acc64[NT][4];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    acc[t] = M::zero();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
-  }
-  // K chunks of 16; the operands of chunk c+1 are loaded while chunk c is
-  // multiplied (two register buffers, unrolled by two)
-  struct Ops {
-    TF a4[4];
-    TF b4[NT][4];
-  };
-  auto load_ops = [&](Ops& o, int s0) {
-    const int kidx = s0 + 4 * (lane >> 4);
-    load4<TF, FROM>(Z, arow * ldz, kidx, kb, k, arow_ok, o.a4);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int col = col0 + t * 16 + (lane & 15);
-      load4<TF, FROM>(U2T, (int64_t)col * ldu, kidx, kb, k, col < w, o.b4[t]);
-    }
-  };
-  auto mma_ops = [&](const Ops& o, int ci) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[t] = M::op(o.a4[j], o.b4[t][j], acc[t]);
-    if (sizeof(TF) == 4 && (ci & 3) == 3) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc64[t][r] += (double)acc[t][r];
-        acc[t] = M::zero();
-      }
-    }
-  };
-  const int kb16 = FROM ? (kb & ~15) : 0;
-  const int nchk = k > kb16 ? (k - kb16 + 15) / 16 : 0;
-  Ops o0, o1;
-  if (nchk > 0) load_ops(o0, kb16);
-  for (int ci = 0; ci < nchk; ci += 2) {
-    if (ci + 1 < nchk) load_ops(o1, kb16 + 16 * (ci + 1));
-    mma_ops(o0, ci);
-    if (ci + 1 >= nchk) break;
-    if (ci + 2 < nchk) load_ops(o0, kb16 + 16 * (ci + 2));
-    mma_ops(o1, ci + 1);
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc64[t][r] += (double)acc[t][r];
-  double ss = 0.0;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = col0 + t * 16 + (lane & 15);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = rbase + M::row(lane, r);
-      if (row < n && col < w && pos[row] < 0) {
-        TF* zp = Z + row * ldz + zcol + col;
-        TF s = (TF)((double)(*zp) - acc64[t][r]);
-        *zp = s;
-        ss += (double)s * (double)s;
-      }
-    }
-  }
-  if (want_norm) {
-    ss = wave_sum(ss);
-    if (lane == 0) red[wave] = ss;
-    __syncthreads();
-    if (tid == 0) normpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
-  }
 }
 
 // Estimate and stopping test (one workgroup of 256): E = sqrt(sum S^2) /

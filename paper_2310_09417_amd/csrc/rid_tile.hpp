@@ -1,6 +1,6 @@
 // Building blocks shared by the decomposition kernels and the batched
-// persistent kernel: status codes, the masked 4-wide operand loads and the
-// wave-level 16 x 64 MFMA tile routine.
+// persistent kernel: the control block, status codes, the masked 4-wide
+// operand loads and the wave-level 16 x 64 MFMA tile routine.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -8,6 +8,17 @@
 #include "rid_device.hpp"
 
 namespace rid {
+
+// Device-resident control block of one decomposition.
+struct Ctrl {
+  int32_t k;          // pivots taken so far
+  int32_t done;       // 1 once the result is final (later kernels return at once)
+  int32_t status;     // rid_status value
+  int32_t nonfinite;  // set by the sketch when A holds NaN / Inf
+  double E;           // latest estimate E = ||S||_F / sqrt(w), -1 before the first
+  double frob2;       // ||A||_F^2 accumulated in FP64 during the first sketch pass
+  int32_t pad[8];
+};
 
 enum : int32_t {
   ST_OK = 0,

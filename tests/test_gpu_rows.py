@@ -81,7 +81,12 @@ def test_rows_fp32(torch, rid, orc):
     A, _ = workloads.fast_decay(2000, 1200, decades=6.0, seed=9)
     A32 = A.astype(np.float32).astype(np.float64)
     Ad = _dev(torch, A32, torch.float32)
-    g = rid.adaptive(Ad, 64, 1e-4, 1200, 2)
+    # tolerance 3e-4: the oracle stops at k = 1088 with E = 1.9e-4 after 4.7e-4
+    # at 1024, far from the threshold on both sides (at 1e-4 its last
+    # estimate, 1.05e-4 at k = 1152, sits on the threshold, and FP32 rounding
+    # decides between stopping there and the exact full-rank ID)
+    g = rid.adaptive(Ad, 64, 3e-4, 1200, 2)
+    assert g.k < 1200
     r = rid.row_skeletons(Ad, g.J)
     assert (r.status, r.k) == (rid.RID_OK, g.k)
     J, T = g.J.cpu().numpy(), g.T.cpu().numpy().astype(np.float64)
