@@ -77,6 +77,8 @@ def _load():
         lib.orc_rank_features.restype = None
         lib.orc_round_format.argtypes = [dbl, cint]
         lib.orc_round_format.restype = dbl
+        lib.orc_round_format_array.argtypes = [P, i64, cint, P]
+        lib.orc_round_format_array.restype = None
         lib.orc_rid_lupp.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
                                      P, P, i64, P, i64, ctypes.POINTER(_Result)]
         lib.orc_rid_lupp.restype = cint
@@ -162,8 +164,11 @@ def round_format(x, fmt: int) -> np.ndarray:
     """Round every entry of x to nearest (ties to even) in BF16 (FMT_BF16) or
     OCP FP8 e4m3 (FMT_E4M3), saturating at the largest finite value."""
     lib = _load()
-    x = np.asarray(x, dtype=np.float64)
-    return np.vectorize(lambda v: lib.orc_round_format(float(v), fmt), otypes=[np.float64])(x)
+    xa = np.asarray(x, dtype=np.float64)
+    xc = np.ascontiguousarray(xa.reshape(-1))
+    out = np.empty_like(xc)
+    lib.orc_round_format_array(_ptr(xc), xc.size, fmt, _ptr(out))
+    return out.reshape(xa.shape)
 
 
 def omega_format(seed: int, c0: int, w: int, m: int, fmt: int) -> np.ndarray:

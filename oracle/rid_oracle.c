@@ -158,6 +158,11 @@ double orc_round_format(double x, int fmt) {
   return r;
 }
 
+/* The same rounding applied to each of n values (out may alias x). */
+void orc_round_format_array(const double* x, int64_t n, int fmt, double* out) {
+  for (int64_t t = 0; t < n; ++t) out[t] = orc_round_format(x[t], fmt);
+}
+
 /* Omega block rounded into format fmt: out[c * m + i] = round(omega(c0+c, i)). */
 void orc_omega_format(uint64_t seed, int64_t c0, int64_t w, int64_t m, int fmt, double* out) {
   orc_omega(seed, c0, w, m, out);

@@ -53,7 +53,8 @@ def _amb_ulp(om64, fmt_code, orc):
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
 @pytest.mark.parametrize("m,n,w,c0,pad", [(700, 2100, 40, 64, 0), (333, 517, 64, 0, 3),
-                                          (64, 1024, 16, 7, 0), (1, 20, 5, 0, 0)])
+                                          (64, 1024, 16, 7, 0), (1, 20, 5, 0, 0),
+                                          (4100, 3080, 64, 3, 8)])
 def test_lowprec_sketch_matches_oracle(orc, fmt, m, n, w, c0, pad):
     import paper_2310_09417_amd as rid
     rng = np.random.default_rng(m + n)
@@ -67,6 +68,43 @@ def test_lowprec_sketch_matches_oracle(orc, fmt, m, n, w, c0, pad):
     omr = orc.round_format(om64, fc)
     bound = _amb_ulp(om64, fc, orc) @ np.abs(vals) + ACC[fmt] * (np.abs(omr) @ np.abs(vals)) + 1e-30
     err = np.abs(Yt.T - Y)
+    assert np.all(err <= bound), (fmt, float((err / bound).max()))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_lowprec_sketch_fullsize_sampled(orc, fmt):
+    """The 50000 x 20000 matrix in the launch configuration the benchmark
+    times (interior workgroups stage A through LDS, the last column group
+    does not): 64 sampled columns of the device sketch against the oracle's
+    sketch of the same represented columns (the sketch of a column depends
+    on that column alone)."""
+    import torch
+
+    import paper_2310_09417_amd as rid
+    m, n, w, seed = 50000, 20000, 64, 21
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn((m, n), generator=g, device="cuda", dtype=torch.float32)
+    A *= torch.exp2(torch.linspace(-8.0, 8.0, n, device="cuda"))[None, :]
+    St, inv = workloads.quantize_device(A, fmt)
+    del A
+    if fmt == "fp8":
+        St = St.view(torch.uint8)
+    Yt = rid.debug_sketch(St, seed, 0, w, col_scale=inv).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(7)
+    cols = np.sort(np.concatenate([rng.choice(n - 1, 62, replace=False), [0, n - 1]]))
+    ct = torch.as_tensor(cols, device="cuda")
+    if fmt == "bf16":
+        vals = St[:, ct].to(torch.float64).cpu().numpy()
+    else:
+        vals = St[:, ct].view(torch.float8_e4m3fn).to(torch.float64).cpu().numpy()
+        vals *= inv.double().cpu().numpy()[cols // 128][None, :]
+    del St
+    fc = FMTS[fmt]
+    Y = orc.sketch(vals, seed, 0, w, fc)
+    om64 = orc.omega(seed, 0, w, m)
+    omr = orc.round_format(om64, fc)
+    bound = _amb_ulp(om64, fc, orc) @ np.abs(vals) + ACC[fmt] * (np.abs(omr) @ np.abs(vals)) + 1e-30
+    err = np.abs(Yt[cols].T - Y)
     assert np.all(err <= bound), (fmt, float((err / bound).max()))
 
 
