@@ -154,6 +154,11 @@ def main():
     ap.add_argument("--lp-steps", type=int, default=3,
                     help="timed runs of each precision form (A stored in BF16 / FP8-e4m3); "
                          "0 skips them")
+    ap.add_argument("--sweep", type=int, default=1,
+                    help="1: precision forms over tolerances 1e-3/1e-6/1e-9 with errors "
+                         "against the original matrix and the FP64 path (0 skips it)")
+    ap.add_argument("--sweep-second", type=str, default="100000x10000",
+                    help="second matrix shape of the sweep (empty: main shape only)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-kmax", type=int, default=64,
                     help="rank cap of the bounded oracle sample")
@@ -560,6 +565,10 @@ def main():
     if args.paper_sizes:
         paper = bench_paper(args, torch, rid, workloads)
 
+    sweep = None
+    if args.sweep:
+        sweep = bench_precision_sweep(args, torch, rid, workloads, A64)
+
     rec = {
         "metric": "ID GFLOP/s + blocks/s at tol 1e-6; speedup vs plain FP64 GPU path",
         "value": gflops,
@@ -597,11 +606,151 @@ def main():
         "batched": batched,
         "learned_rank": learned,
         "paper_workload": paper,
+        "precision_sweep": sweep,
         "source_hash": source_hash(),
     }
     torch.cuda.synchronize()
     rid.binding.rid_release()
     print(json.dumps(rec), flush=True)
+
+
+def id_error_stats(torch, Aref, J, T, n, ref=None, chunk=2048):
+    """Error of the ID A(:,J) [I T] P (FP64, chunked over columns; a
+    measurement outside timed regions) against Aref: relative Frobenius error
+    and max-abs error (absolute and relative to max|Aref|).  ref = (Jr, Tr):
+    also the relative Frobenius and max-abs gap between this ID's
+    reconstruction and that one's."""
+    dev = Aref.device
+
+    def recon(Jx, Tx, cols):
+        # columns `cols` (ascending) of A(:,J) X, X with identity at J and T elsewhere
+        kk = Jx.numel()
+        pos = torch.full((n,), -1, dtype=torch.int64, device=dev)
+        mask = torch.ones(n, dtype=torch.bool, device=dev)
+        mask[Jx] = False
+        rest = torch.nonzero(mask).squeeze(1)
+        pos[rest] = torch.arange(rest.numel(), device=dev)
+        X = torch.zeros((kk, cols.numel()), dtype=torch.float64, device=dev)
+        pr = pos[cols]
+        nz = pr >= 0
+        X[:, nz] = Tx[:kk, pr[nz]].double()
+        sk = torch.full((n,), -1, dtype=torch.int64, device=dev)
+        sk[Jx] = torch.arange(kk, device=dev)
+        ps = sk[cols]
+        X[ps[~nz], torch.nonzero(~nz).squeeze(1)] = 1.0
+        return Aref[:, Jx].double() @ X
+
+    ss = ss_gap = 0.0
+    mx = mx_gap = 0.0
+    fro2 = 0.0
+    amax = 0.0
+    for c0 in range(0, n, chunk):
+        cols = torch.arange(c0, min(n, c0 + chunk), device=dev)
+        Ac = Aref[:, cols].double()
+        fro2 += float((Ac * Ac).sum())
+        amax = max(amax, float(Ac.abs().max()))
+        Rc = recon(J, T, cols)
+        D = Ac - Rc
+        ss += float((D * D).sum())
+        mx = max(mx, float(D.abs().max()))
+        if ref is not None:
+            G = Rc - recon(ref[0], ref[1], cols)
+            ss_gap += float((G * G).sum())
+            mx_gap = max(mx_gap, float(G.abs().max()))
+        del Ac, Rc, D
+    out = {"rel_fro": (ss / fro2) ** 0.5, "max_abs": mx, "max_abs_rel": mx / amax}
+    if ref is not None:
+        out["gap_rel_fro"] = (ss_gap / fro2) ** 0.5
+        out["gap_max_abs"] = mx_gap
+    return out
+
+
+def bench_precision_sweep(args, torch, rid, workloads, A64_main):
+    """The precision forms over tolerances 1e-3, 1e-6, 1e-9 on the main
+    matrix shape and on a 100000 x 10000 matrix of the same spectrum: A
+    stored in BF16 / FP8-e4m3 (per-128-column power-of-two scale), FP32
+    factorisation with one FP64 refinement step on T, and the plain FP64 path
+    at each tolerance.  Each result states its status, rank, estimate, time,
+    and its relative Frobenius and max-abs error against the original FP64
+    matrix and against the FP64 path's ID at the same tolerance (the FP64
+    path is the one whose skeletons the parity tests hold to the oracle)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    b, kmax = args.b, args.kmax
+    out = []
+    shapes = [(args.m, args.n)]
+    if args.sweep_second:
+        shapes.append(tuple(int(x) for x in args.sweep_second.split("x")))
+    for m, n in shapes:
+        if (m, n) == (args.m, args.n):
+            A64 = A64_main
+        else:
+            t0 = time.time()
+            A64 = workloads.svd_matrix_device(m, n, workloads.sigma_power(min(m, n), 2.0),
+                                              seed=args.seed + 7, device=dev)
+            torch.cuda.synchronize()
+            log(f"[bench] sweep: generated A {m}x{n} (sigma_j = j^-2) in {time.time() - t0:.1f}s")
+        kcap = min(kmax, m, n)
+        A32 = A64.to(torch.float32)
+        forms = [("fp64", A64, rid.RID_F64, None, None, 0)]
+        for fmt, code in (("bf16", rid.RID_BF16), ("fp8", rid.RID_FP8_E4M3)):
+            Aq, sc = workloads.quantize_device(A32, fmt)
+            if fmt == "fp8":
+                Aq = Aq.view(torch.uint8)
+            forms.append((fmt, Aq, rid.RID_F32, code, sc, 1))
+        del A32
+        for tol in (1e-3, 1e-6, 1e-9):
+            ref = None
+            for name, Ax, dt, at, sc, refine in forms:
+                cfg = rid.binding._cfg(dt, args.seed, True, a_type=at,
+                                       col_scale=sc.data_ptr() if sc is not None else 0,
+                                       refine=refine)
+                wb = rid.rid_workspace_bytes(m, n, kmax, b, cfg)
+                work = torch.empty(wb, dtype=torch.uint8, device=dev)
+                J = torch.zeros(kcap, dtype=torch.int64, device=dev)
+                T = torch.zeros((kcap, n), dtype=torch.float64 if dt == rid.RID_F64
+                                else torch.float32, device=dev)
+                ko = torch.zeros(1, dtype=torch.int32, device=dev)
+                eo = torch.zeros(1, dtype=torch.float64, device=dev)
+                so = torch.zeros(1, dtype=torch.int32, device=dev)
+
+                def call():
+                    rc = rid.rid_lupp_adaptive(Ax.data_ptr(), m, n, Ax.stride(0), b, tol, kmax, cfg,
+                                               J.data_ptr(), T.data_ptr(), n, ko.data_ptr(),
+                                               eo.data_ptr(), so.data_ptr(), work.data_ptr(), wb,
+                                               stream)
+                    if rc != 0:
+                        raise RuntimeError(f"rid_lupp_adaptive -> {rc}")
+
+                call()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                call()
+                e1.record()
+                torch.cuda.synchronize()
+                kk = int(ko.item())
+                Jk = J[:kk].clone()
+                errs = id_error_stats(torch, A64, Jk, T, n, ref=ref)
+                if name == "fp64":
+                    ref = (Jk, T.clone())
+                res = {"shape": f"{m}x{n}", "form": name, "tol": tol, "k": kk,
+                       "status": rid.status_string(int(so.item())),
+                       "err_est_rel": float(eo.item()), "ms": float(e0.elapsed_time(e1)),
+                       "refine": refine, "vs_original_fp64": errs}
+                if name == "fp64":
+                    res["vs_original_fp64"].pop("gap_rel_fro", None)
+                out.append(res)
+                log(f"[bench] sweep {m}x{n} {name:4s} tol={tol:g}: k={kk} {res['status']}, "
+                    f"{res['ms']:.2f} ms, rel err {errs['rel_fro']:.3e}, max-abs {errs['max_abs']:.3e}"
+                    + (f", gap to fp64 ID {errs['gap_rel_fro']:.3e} (max-abs "
+                       f"{errs['gap_max_abs']:.3e})" if 'gap_rel_fro' in errs else ""))
+                del work, T, J
+        del forms
+        if A64 is not A64_main:
+            del A64
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_paper(args, torch, rid, workloads):

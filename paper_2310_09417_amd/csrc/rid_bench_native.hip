@@ -3,15 +3,22 @@
 // m x n FP32 matrix resident in HBM, plus one plain device copy of a known
 // size (the reference for hardware traffic counters).
 //
-// usage: rid_bench_native [m n b kmax iters fmt]   (defaults 50000 20000 64 2048 3 0)
+// usage: rid_bench_native [m n b kmax iters fmt [libs]]
+//        (defaults 50000 20000 64 2048 3 0)
 // fmt 0: A in FP32; 1: A stored as BF16; 2: A stored as FP8-e4m3 (scale 1 per
-// 128-column tile; the Gaussian entries fit the format unscaled).
+// 128-column tile; the Gaussian entries fit the format unscaled); 3: the three
+// in turn, in one process.  With a seventh argument "libs" the driver lists the
+// executable address ranges of every loaded object before it returns (to place
+// the addresses of stack traces printed at process exit by tools).
 // The matrix holds Gaussian entries produced by rid_debug_gaussian; traffic
 // and timing of the kernels do not depend on the values.
 #include <hip/hip_runtime.h>
 
+#include <link.h>
+
 #include <chrono>
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <vector>
 
@@ -51,17 +58,19 @@ __global__ void fill_ones(float* p, size_t count) {
   if (i < count) p[i] = 1.0f;
 }
 
-int main(int argc, char** argv) {
-  const int64_t m = argc > 1 ? atoll(argv[1]) : 50000;
-  const int64_t n = argc > 2 ? atoll(argv[2]) : 20000;
-  const int64_t b = argc > 3 ? atoll(argv[3]) : 64;
-  const int64_t kmax = argc > 4 ? atoll(argv[4]) : 2048;
-  const int iters = argc > 5 ? atoi(argv[5]) : 3;
-  const int fmt = argc > 6 ? atoi(argv[6]) : 0;
-  if (fmt < 0 || fmt > 2) return 5;
-  hipStream_t st;
-  CHECK(hipStreamCreate(&st));
+static int print_segments(struct dl_phdr_info* info, size_t, void*) {
+  const char* name = (info->dlpi_name && info->dlpi_name[0]) ? info->dlpi_name : "(main program)";
+  for (int i = 0; i < info->dlpi_phnum; ++i) {
+    const ElfW(Phdr)& ph = info->dlpi_phdr[i];
+    if (ph.p_type == PT_LOAD && (ph.p_flags & PF_X))
+      std::printf("[native] text 0x%lx-0x%lx %s\n", (unsigned long)(info->dlpi_addr + ph.p_vaddr),
+                  (unsigned long)(info->dlpi_addr + ph.p_vaddr + ph.p_memsz), name);
+  }
+  return 0;
+}
 
+// Plain device copy of a known size: the reference for the traffic counters.
+static int calibrate(hipStream_t st) {
   // calibration copy: 1 GiB read, 1 GiB written
   const size_t cbytes = (size_t)1 << 30;
   float *csrc = nullptr, *cdst = nullptr;
@@ -74,6 +83,40 @@ int main(int argc, char** argv) {
   CHECK(hipFree(csrc));
   CHECK(hipFree(cdst));
   std::printf("[native] calibration copy: %zu bytes read, %zu written\n", cbytes, cbytes);
+  return 0;
+}
+
+static int run_format(int64_t m, int64_t n, int64_t b, int64_t kmax, int iters, int fmt,
+                      hipStream_t st);
+
+int main(int argc, char** argv) {
+  std::setvbuf(stdout, nullptr, _IOLBF, 0);  // each line reaches the log at once
+  const int64_t m = argc > 1 ? atoll(argv[1]) : 50000;
+  const int64_t n = argc > 2 ? atoll(argv[2]) : 20000;
+  const int64_t b = argc > 3 ? atoll(argv[3]) : 64;
+  const int64_t kmax = argc > 4 ? atoll(argv[4]) : 2048;
+  const int iters = argc > 5 ? atoi(argv[5]) : 3;
+  const int fmt = argc > 6 ? atoi(argv[6]) : 0;
+  const bool libs = argc > 7 && std::strcmp(argv[7], "libs") == 0;
+  if (fmt < 0 || fmt > 3) return 5;
+  hipStream_t st;
+  CHECK(hipStreamCreate(&st));
+  if (calibrate(st) != 0) return 1;
+  for (int f = (fmt == 3 ? 0 : fmt); f <= (fmt == 3 ? 2 : fmt); ++f) {
+    const int rc = run_format(m, n, b, kmax, iters, f, st);
+    if (rc != 0) return rc;
+  }
+  CHECK(hipStreamSynchronize(st));
+  CHECK(hipStreamDestroy(st));
+  if (rid_release() != RID_OK) return 5;
+  if (libs) dl_iterate_phdr(print_segments, nullptr);
+  std::printf("[native] done\n");
+  return 0;
+}
+
+static int run_format(int64_t m, int64_t n, int64_t b, int64_t kmax, int iters, int fmt,
+                      hipStream_t st) {
+  std::printf("[native] format %d (%s)\n", fmt, fmt == 0 ? "fp32" : fmt == 1 ? "bf16" : "fp8-e4m3");
 
   float* A = nullptr;
   CHECK(hipMalloc(&A, (size_t)m * n * sizeof(float)));
@@ -147,7 +190,5 @@ int main(int argc, char** argv) {
   CHECK(hipFree(so));
   CHECK(hipFree(eo));
   CHECK(hipStreamSynchronize(st));
-  if (rid_release() != RID_OK) return 5;
-  std::printf("[native] done\n");
   return 0;
 }
