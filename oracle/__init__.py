@@ -85,6 +85,10 @@ def _load():
         lib.orc_rid_lupp_gaps.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64, u64,
                                           P, P, i64, P, i64, P, ctypes.POINTER(_Result)]
         lib.orc_rid_lupp_gaps.restype = cint
+        lib.orc_rid_lupp_forced.argtypes = [P, i64, i64, i64, cint, i64, i64, dbl, cint, i64,
+                                            u64, P, i64, P, P, i64, P, i64, P, P,
+                                            ctypes.POINTER(_Result)]
+        lib.orc_rid_lupp_forced.restype = cint
         lib.orc_lupp_factors.argtypes = [P, i64, i64, i64, i64, i64, u64, P, P, P]
         lib.orc_lupp_factors.restype = cint
         lib.orc_rid_adaptive_first.argtypes = [P, i64, i64, i64, i64, i64, dbl, cint, i64, u64,
@@ -195,6 +199,9 @@ class IDResult:
     # decision margin of every pivot step (with gaps=True): (|best| - |runner-up|)
     # / (sqrt(s + 1) max|Y|); see robust_prefix
     gaps: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    # with force=...: each forced step's shortfall from the largest candidate,
+    # (|largest| - |forced|) / (sqrt(s + 1) max|Y|), on the scale of gaps
+    shortfall: np.ndarray = field(default_factory=lambda: np.zeros(0))
     # residual-triangle estimates per step (Remark 1): columns = Schur estimate
     # on the set-aside sample, eq. normUest, eq. maxUest
 
@@ -222,7 +229,7 @@ def robust_prefix(gaps, eps: float) -> int:
 
 
 def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, estimator=0,
-         resid_p=0, embedding=0, gaps=False) -> IDResult:
+         resid_p=0, embedding=0, gaps=False, force=None) -> IDResult:
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
@@ -233,7 +240,20 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, est
     est = np.zeros((hist_cap, 3), dtype=np.float64)
     res = _Result()
     gap = np.full(cap, np.inf)
-    if gaps:
+    short = np.zeros(0)
+    if force is not None:
+        if embedding or estimator or first_w > 0:
+            raise ValueError("force: plain Gaussian fixed-rank or adaptive calls only")
+        fJ = np.ascontiguousarray(force, dtype=np.int64)
+        short = np.zeros(max(1, fJ.size))
+        lib.orc_rid_lupp_forced(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax,
+                                seed, _ptr(fJ), fJ.size, _ptr(J), _ptr(T), n, _ptr(hist),
+                                hist_cap, _ptr(gap), _ptr(short), ctypes.byref(res))
+        if res.status == ERR_ARG:
+            raise ValueError("force: an entry is not a remaining candidate at its step")
+        short = short[: fJ.size]
+        gaps = True
+    elif gaps:
         if embedding or estimator or first_w > 0:
             raise ValueError("gaps: plain Gaussian fixed-rank or adaptive calls only")
         lib.orc_rid_lupp_gaps(_ptr(A), m, n, n, mode, k_or_b, p, tol, 1 if rel else 0, kmax, seed,
@@ -260,21 +280,27 @@ def _run(A, mode, k_or_b, p, tol, rel, kmax, seed, hist_cap=4096, first_w=0, est
                     min_gap=float(res.min_gap), min_gap_step=int(res.min_gap_step),
                     fro_a=float(res.fro_a), robust_k=int(res.robust_k),
                     est_hist=est[: res.nsteps].copy() if estimator else np.zeros((0, 3)),
-                    gaps=gap[:k].copy() if gaps else np.zeros(0))
+                    gaps=gap[:k].copy() if gaps else np.zeros(0), shortfall=short)
 
 
-def rid_fixed_rank(A, k: int, p: int, seed: int, gaps: bool = False) -> IDResult:
-    """randLUPP at fixed rank k with p extra sketch vectors for E_Schur."""
-    return _run(A, 0, k, p, 0.0, False, k, seed, gaps=gaps)
+def rid_fixed_rank(A, k: int, p: int, seed: int, gaps: bool = False, force=None) -> IDResult:
+    """randLUPP at fixed rank k with p extra sketch vectors for E_Schur.
+    force: see rid_adaptive."""
+    return _run(A, 0, k, p, 0.0, False, k, seed, gaps=gaps, force=force)
 
 
 def rid_adaptive(A, b: int, tol: float, kmax: int, seed: int, relative: bool = True,
-                 first_width: int = 0, gaps: bool = False) -> IDResult:
+                 first_width: int = 0, gaps: bool = False, force=None) -> IDResult:
     """randLUPPadap (Alg. 1): blocks of b sketch vectors until E <= tol.
     first_width > 0 makes the first factored block that wide (a rank known
     or predicted beforehand); the rest of the method is unchanged.  gaps:
-    also return every pivot step's decision margin."""
-    return _run(A, 1, b, 0, tol, relative, kmax, seed, first_w=first_width, gaps=gaps)
+    also return every pivot step's decision margin.  force: column indices
+    that the first len(force) pivot steps take instead of the largest
+    candidate (a replay of another run's pivot order; implies gaps); the
+    result's shortfall holds each forced step's distance from the largest
+    candidate on the scale of gaps."""
+    return _run(A, 1, b, 0, tol, relative, kmax, seed, first_w=first_width, gaps=gaps,
+                force=force)
 
 
 # Estimators of Remark 1 (Sec. 3.2): 0 = Schur estimate on the next block

@@ -335,14 +335,16 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                          int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
                          int embedding, int64_t* J, double* T, int64_t ldt, double* E_hist,
-                         double* est_hist, int64_t hist_cap, double* gap_hist, orc_result* res);
+                         double* est_hist, int64_t hist_cap, double* gap_hist,
+                         const int64_t* force_J, int64_t force_len, double* force_short,
+                         orc_result* res);
 
 int orc_rid_lupp(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
                  int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                  uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                  int64_t hist_cap, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, 0,
-                       J, T, ldt, E_hist, NULL, hist_cap, NULL, res);
+                       J, T, ldt, E_hist, NULL, hist_cap, NULL, NULL, 0, NULL, res);
 }
 
 /* Same as orc_rid_lupp with the blocks drawn from the sparse sign embedding
@@ -352,7 +354,7 @@ int orc_rid_lupp_emb(const double* A, int64_t m, int64_t n, int64_t lda, int mod
                      uint64_t seed, int embedding, int64_t* J, double* T, int64_t ldt,
                      double* E_hist, int64_t hist_cap, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0,
-                       embedding, J, T, ldt, E_hist, NULL, hist_cap, NULL, res);
+                       embedding, J, T, ldt, E_hist, NULL, hist_cap, NULL, NULL, 0, NULL, res);
 }
 
 /* Same as orc_rid_lupp with the stopping estimate taken from the residual
@@ -370,7 +372,8 @@ int orc_rid_lupp_est(const double* A, int64_t m, int64_t n, int64_t lda, int mod
                      double* T, int64_t ldt, double* E_hist, double* est_hist, int64_t hist_cap,
                      orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, estimator,
-                       resid_p, embedding, J, T, ldt, E_hist, est_hist, hist_cap, NULL, res);
+                       resid_p, embedding, J, T, ldt, E_hist, est_hist, hist_cap, NULL, NULL, 0,
+                       NULL, res);
 }
 
 /* Adaptive variant whose first factored block has first_width vectors
@@ -381,7 +384,7 @@ int orc_rid_adaptive_first(const double* A, int64_t m, int64_t n, int64_t lda, i
                            uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                            int64_t hist_cap, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, 1, b, 0, tol, tol_relative, kmax, first_width, seed, 0, 0, 0,
-                       J, T, ldt, E_hist, NULL, hist_cap, NULL, res);
+                       J, T, ldt, E_hist, NULL, hist_cap, NULL, NULL, 0, NULL, res);
 }
 
 /* Same as orc_rid_lupp, also reporting every pivot step's decision margin:
@@ -394,7 +397,25 @@ int orc_rid_lupp_gaps(const double* A, int64_t m, int64_t n, int64_t lda, int mo
                       uint64_t seed, int64_t* J, double* T, int64_t ldt, double* E_hist,
                       int64_t hist_cap, double* gap_hist, orc_result* res) {
   return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, 0,
-                       J, T, ldt, E_hist, NULL, hist_cap, gap_hist, res);
+                       J, T, ldt, E_hist, NULL, hist_cap, gap_hist, NULL, 0, NULL, res);
+}
+
+/* Same as orc_rid_lupp_gaps with the first force_len pivots given: step s
+ * takes candidate column force_J[s] (which must not be pivoted yet) instead of
+ * the largest one, and force_short[s] = (|largest| - |forced|) / (sqrt(s + 1)
+ * max|Y|) is its shortfall on the scale of gap_hist (0 when the forced pivot
+ * is a largest one).  The rest of the method is unchanged.  Test diagnostics:
+ * it replays another implementation's pivot order, so that each of its
+ * decisions can be measured against the rounding floor and its T and E
+ * compared with the oracle's for the same skeletons. */
+int orc_rid_lupp_forced(const double* A, int64_t m, int64_t n, int64_t lda, int mode,
+                        int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
+                        uint64_t seed, const int64_t* force_J, int64_t force_len, int64_t* J,
+                        double* T, int64_t ldt, double* E_hist, int64_t hist_cap,
+                        double* gap_hist, double* force_short, orc_result* res) {
+  return rid_lupp_impl(A, m, n, lda, mode, k_or_b, p, tol, tol_relative, kmax, 0, seed, 0, 0, 0,
+                       J, T, ldt, E_hist, NULL, hist_cap, gap_hist, force_J, force_len,
+                       force_short, res);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -598,7 +619,9 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
                          int64_t k_or_b, int64_t p, double tol, int tol_relative, int64_t kmax,
                          int64_t first_width, uint64_t seed, int estimator, int64_t resid_p,
                          int embedding, int64_t* J, double* T, int64_t ldt, double* E_hist,
-                         double* est_hist, int64_t hist_cap, double* gap_hist, orc_result* res) {
+                         double* est_hist, int64_t hist_cap, double* gap_hist,
+                         const int64_t* force_J, int64_t force_len, double* force_short,
+                         orc_result* res) {
   memset(res, 0, sizeof(*res));
   res->err_est = -1.0;
   res->min_gap = INFINITY;
@@ -750,6 +773,28 @@ static int rid_lupp_impl(const double* A, int64_t m, int64_t n, int64_t lda, int
         }
         const double floor_s = 64.0 * 0x1p-52 * sqrt((double)(s + 1)) * ymax;
         if (res->robust_k < 0 && best - second <= floor_s) res->robust_k = s;
+      }
+      if (force_J && s < force_len) {
+        /* the step takes the given candidate instead; its shortfall from the
+         * largest magnitude, on the scale of gap_hist */
+        int64_t fr = -1;
+        for (int64_t r = s; r < n; ++r)
+          if (perm[r] == force_J[s]) {
+            fr = r;
+            break;
+          }
+        if (fr < 0) { /* not a remaining candidate */
+          free(Z);
+          free(perm);
+          free(Ynew);
+          free(Yr);
+          res->status = ORC_ERR_ARG;
+          return ORC_ERR_ARG;
+        }
+        const double v = fabs(Z[fr * zc + s]);
+        if (force_short) force_short[s] = ymax > 0.0 ? (best - v) / (sqrt((double)(s + 1)) * ymax) : 0.0;
+        piv = fr;
+        best = v;
       }
       if (best == 0.0) {
         deficient = 1;

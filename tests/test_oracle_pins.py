@@ -338,6 +338,44 @@ def test_decision_margins(orc):
         assert abs(o.gaps[s] - want) <= 1e-6 * want + 1e-13, (s, o.gaps[s], want)
 
 
+def test_forced_pivot_replay(orc):
+    """A replayed pivot order: forcing the oracle's own order reproduces its
+    run exactly with zero shortfall; forcing another order gives, at each
+    forced step, the shortfall of the forced candidate from the largest one,
+    checked against the pivot column recomputed independently (the Schur
+    complement of the forced rows so far in sketch column s by a library
+    linear solve); the skeletons are the forced ones and T solves the
+    sketched system for them."""
+    A, _ = workloads.fast_decay(300, 200, decades=8.0, seed=1)
+    o = orc.rid_adaptive(A, 16, 1e-6, 200, seed=3, gaps=True)
+    same = orc.rid_adaptive(A, 16, 1e-6, 200, seed=3, force=o.J)
+    assert same.k == o.k and np.array_equal(same.J, o.J) and np.array_equal(same.T, o.T)
+    assert same.err_est == o.err_est and np.all(same.shortfall == 0.0)
+    # swap the pivots of steps 5 and 6 and take step 9's at step 8
+    F = list(o.J[:10])
+    F[5], F[6] = F[6], F[5]
+    F[8], F[9] = F[9], F[8]
+    f = orc.rid_fixed_rank(A, 10, 0, seed=3, force=F)
+    assert list(f.J) == F
+    Yt = orc.sketch(A, 3, 0, 10).T
+    ymax = np.abs(Yt).max()
+    for s in range(10):
+        rest = [r for r in range(Yt.shape[0]) if r not in F[:s]]
+        if s == 0:
+            col = Yt[rest, 0]
+        else:
+            X = np.linalg.solve(Yt[F[:s], :s].T, Yt[rest, :s].T).T
+            col = Yt[rest, s] - X @ Yt[F[:s], s]
+        want = (np.abs(col).max() - abs(col[rest.index(F[s])])) / (np.sqrt(s + 1) * ymax)
+        assert abs(f.shortfall[s] - want) <= 1e-9 * max(want, 1e-3), (s, f.shortfall[s], want)
+    assert f.shortfall[5] > 0.0 and f.shortfall[8] > 0.0
+    Xt = np.linalg.solve(Yt[F, :10].T, Yt[:, :10].T)
+    nonsk = np.setdiff1d(np.arange(A.shape[1]), F)
+    assert np.abs(f.T - Xt[:, nonsk]).max() <= 1e-9 * max(1.0, np.abs(Xt).max())
+    with pytest.raises(ValueError):
+        orc.rid_fixed_rank(A, 3, 0, seed=3, force=[F[0], F[0], F[1]])
+
+
 # ---- rounding into BF16 / OCP e4m3 and the rounded-Gaussian sketch --------
 
 def test_round_format_matches_torch_conversions(orc):
