@@ -363,8 +363,11 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.xwords_end = o;
   P.o_linv = take((size_t)kcap * P.ldl * es);
   P.o_mtmp = take((size_t)wmax * P.ldl * es);
-  // Omega of one sketch launch (at most 64 vectors), rows padded to 64
-  P.o_omega = take(low_precision(at) ? 0 : (size_t)align_up((size_t)m, 64) * 64 * es);
+  // Omega of one sketch launch (at most 64 vectors), rows padded to 64; in
+  // FP32 followed by its three-part BF16 operand form (k_omega_split, 384
+  // bytes per row)
+  P.o_omega = take(low_precision(at) ? 0
+                                     : (size_t)align_up((size_t)m, 64) * (64 * es + (es == 4 ? 384 : 0)));
   // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
@@ -500,6 +503,9 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
   TC* om = static_cast<TC*>(W.omega);
   const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
+  // FP32 blocks of 64 vectors: the split operand form of Omega after it
+  constexpr bool split = sizeof(TC) == 4 && MT == 4;
+  uint32_t* oms = split ? reinterpret_cast<uint32_t*>(om + mpad * 64) : nullptr;
   long pm = prof_begin(KC_OMEGA, st);
   if (P.emb == RID_EMB_SPARSE_SIGN)
     hipLaunchKernelGGL(k_omega_ss<TC>, dim3((unsigned)ceil_div(mpad, 256)), dim3(256), 0, st, k0,
@@ -507,17 +513,20 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   else
     hipLaunchKernelGGL(k_omega<TC>, dim3((unsigned)ceil_div(mpad / 4 * g.wp, 256)), dim3(256), 0,
                        st, k0, k1, (uint32_t)c0, w, g.wp, P.m, mpad, om, ctrl);
+  if (split)
+    hipLaunchKernelGGL(k_omega_split, dim3((unsigned)ceil_div(mpad / 32 * 256, 256)), dim3(256), 0,
+                       st, reinterpret_cast<const float*>(om), mpad, oms, ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   pm = prof_begin(KC_SKETCH, st);
   if (norm)
     hipLaunchKernelGGL((k_sketch<TC, MT, KC, true, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
-                       static_cast<const TC*>(A), P.m, P.n, lda, om, w, g.rows_per_split, W.part,
-                       W.fro, W.nonfinite, ctrl);
+                       static_cast<const TC*>(A), P.m, P.n, lda, om, oms, w, g.rows_per_split,
+                       W.part, W.fro, W.nonfinite, ctrl);
   else
     hipLaunchKernelGGL((k_sketch<TC, MT, KC, false, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
-                       static_cast<const TC*>(A), P.m, P.n, lda, om, w, g.rows_per_split, W.part,
-                       W.fro, W.nonfinite, ctrl);
+                       static_cast<const TC*>(A), P.m, P.n, lda, om, oms, w, g.rows_per_split,
+                       W.part, W.fro, W.nonfinite, ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;

@@ -104,6 +104,82 @@ __device__ __forceinline__ void vm_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// Eight 8-byte LDS reads at byte offsets addr + 128 j (eight consecutive rows
+// of a 32-column FP32 tile), complete on return; see lds_read8x8.
+__device__ __forceinline__ void lds_read8x8_rows(uint32_t addr, floatx2 (&r)[8]) {
+  asm volatile(
+      "ds_read_b64 %0, %8 offset:0\n\t"
+      "ds_read_b64 %1, %8 offset:128\n\t"
+      "ds_read_b64 %2, %8 offset:256\n\t"
+      "ds_read_b64 %3, %8 offset:384\n\t"
+      "ds_read_b64 %4, %8 offset:512\n\t"
+      "ds_read_b64 %5, %8 offset:640\n\t"
+      "ds_read_b64 %6, %8 offset:768\n\t"
+      "ds_read_b64 %7, %8 offset:896\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+        "=&v"(r[6]), "=&v"(r[7])
+      : "v"(addr));
+}
+
+// ---------------------------------------------------------------------------
+// FP32 values as sums of three BF16 values.  hi = bf16(x) (nearest even),
+// mid = bf16(x - hi), lo = x - hi - mid: both differences are exact in FP32,
+// and lo has at most 8 significant bits, so x = hi + mid + lo exactly (for
+// x above 2^-100 or so in magnitude, where no part leaves the normal range),
+// with |mid| <= 2^-9 |x| and |lo| <= 2^-18 |x|.  A product of two such
+// values is the sum of nine BF16 products, each exact in FP32; the six with
+// weight above 2^-27 (hi hi, hi mid, mid hi, hi lo, mid mid, lo hi) give
+// the product to within 2^-26 of its magnitude, below FP32's own rounding,
+// at the BF16 matrix-core rate.  Two values at a time: the three packed
+// BF16 pairs (first value in the low half).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const floatx2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_v));
+}
+
+__device__ __forceinline__ void split3_bf16x2(float a, float b, uint32_t& h, uint32_t& m,
+                                              uint32_t& l) {
+  h = pack_bf16x2(a, b);
+  const float ra = a - __uint_as_float(h << 16), rb = b - __uint_as_float(h & 0xffff0000u);
+  m = pack_bf16x2(ra, rb);
+  l = pack_bf16x2(ra - __uint_as_float(m << 16), rb - __uint_as_float(m & 0xffff0000u));
+}
+
+// Omega (row-major, mpad x 64, FP32) as the BF16 operand tiles of the split
+// sketch: for each chunk of 32 rows, vector tile a (16 vectors) and part p
+// (hi, mid, lo), 64 lanes x 16 bytes; lane i + 16 g holds vector 16 a + i,
+// rows 8 g .. 8 g + 7 of the chunk, two per dword (even row in the low half).
+// Record (c, a, p) starts at dword (12 c + 3 a + p) * 256.  One thread per
+// (chunk, tile, lane).
+__global__ __launch_bounds__(256) void k_omega_split(const float* __restrict__ om, int64_t mpad,
+                                                     uint32_t* __restrict__ oms,
+                                                     const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (mpad / 32) * 4 * 64) return;
+  const int lane = (int)(t & 63), a = (int)((t >> 6) & 3);
+  const int64_t c = t >> 8;
+  const int i = lane & 15, g = lane >> 4;
+  const float* src = om + (32 * c + 8 * g) * 64 + 16 * a + i;
+  u32x4 h, md, lo;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    uint32_t x, y, z;
+    split3_bf16x2(src[(2 * d) * 64], src[(2 * d + 1) * 64], x, y, z);
+    h[d] = x;
+    md[d] = y;
+    lo[d] = z;
+  }
+  u32x4* dst = reinterpret_cast<u32x4*>(oms) + (12 * c + 3 * a) * 64 + lane;
+  dst[0] = h;
+  dst[64] = md;
+  dst[128] = lo;
+}
+
 // Omega rows [0, mpad) for sketch vectors c0 .. c0 + WP - 1, row-major with
 // pitch WP: entry (i, c) is the Gaussian of row i, vector c0 + c; zero for
 // c >= w or i >= m.  One thread per (row quad, vector).
@@ -125,7 +201,7 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uin
 template <typename TC, int MT, int KC, bool NORM, bool VEC>
 __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
     const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, const TC* __restrict__ omg,
-    int w, int64_t rows_per_split, double* __restrict__ part,
+    const uint32_t* __restrict__ oms, int w, int64_t rows_per_split, double* __restrict__ part,
     double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
   if (ctrl && ctrl->done) return;
   constexpr int NQ = SketchShape<TC>::NQ;
@@ -147,6 +223,10 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
   // rows][32 columns]), Omega shared ([stage][KC rows][LDO]).  The other
   // workgroups use the first two Omega stages as a double buffer.
   constexpr bool DMA = sizeof(TC) == 4 && NQ == 2 && KC == 32;
+  // FP32 interior workgroups of a 64-vector block multiply on the BF16 matrix
+  // cores through the three-part split (split3_bf16x2), with Omega's parts
+  // from oms staged in sO (two 12 KB stages)
+  constexpr bool SPLIT = DMA && MT == 4;
   __shared__ __attribute__((aligned(16))) TC sA[DMA ? 3 * NW * KC * 32 : 1];
   __shared__ __attribute__((aligned(16))) TC sO[3 * KC * LDO];
   TC* const om[2] = {sO, sO + KC * LDO};
@@ -198,7 +278,110 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
         *reinterpret_cast<OV*>(omb + (e / WP) * LDO + e % WP) = r[v - v0];
       }
     };
-    if constexpr (FAST && DMA) {
+    // (SPLIT is tested on its own first: the body below does not compile for
+    // FP64 accumulators, and a condition on FAST alone is only decided when
+    // this lambda is instantiated)
+    if constexpr (SPLIT) {
+      if constexpr (FAST) {
+        // Per chunk and wave: 4 copies of A (8 rows x 32 columns each, this
+        // wave's columns) into a three-stage ring, and 3 of the 12 Omega
+        // operand records (1 KB each) into a two-stage ring.  Issue order per
+        // chunk c (after the barrier that ends chunk c-1's reads): Omega of
+        // chunk c+1, then A of chunk c+2, so that vmcnt(4) at the top of
+        // chunk c+1 means its Omega and A have landed while A of c+3 may still
+        // be in flight.  Past the end the last chunk is copied again into a
+        // stage no later chunk reads, so the count per chunk stays fixed.
+        constexpr int NA = KC / 8;
+        constexpr int OREC = 12;                    // Omega records per chunk
+        constexpr int ORW = OREC / NW;              // Omega records per wave
+        static_assert(OREC % NW == 0 && 2 * OREC * 1024 <= (int)sizeof(sO), "split stages");
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int64_t cw = (int64_t)blockIdx.x * CPW + wv * 32;
+        const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
+        const TC* pa[NA];
+  #pragma unroll
+        for (int i = 0; i < NA; ++i)
+          pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + cw + 4 * (lane & 7);
+        const uint32_t* po = oms + ((r_begin / KC) * OREC + ORW * wv) * 256 + 4 * lane;
+        auto copy_a = [&](int chunk, int st) {
+          const int64_t da = (int64_t)chunk * KC * lda;
+  #pragma unroll
+          for (int i = 0; i < NA; ++i)
+            copy16_to_lds(pa[i] + da, sa + (uint32_t)(((st * NW + wv) * KC + 8 * i) * 32 * 4));
+        };
+        auto copy_o = [&](int chunk, int st) {
+  #pragma unroll
+          for (int i = 0; i < ORW; ++i)
+            copy16_to_lds(po + ((int64_t)chunk * OREC + i) * 256,
+                          so + (uint32_t)((st * OREC + ORW * wv + i) * 1024));
+        };
+        // lane (j, g) = (lane % 16, lane / 16): rows 8 g .. 8 g + 7, columns 2 j, 2 j + 1
+        const uint32_t lane_off = (uint32_t)((8 * (lane >> 4) * 32 + 2 * (lane & 15)) * 4);
+        copy_a(0, 0);
+        copy_o(0, 0);
+        copy_a(nch > 1 ? 1 : 0, 1);
+        for (int c = 0; c < nch; ++c) {
+          vm_barrier<NA>();  // chunk c's A and Omega landed in every wave; chunk c-1's stages free
+          copy_o(c + 1 < nch ? c + 1 : c, (c + 1) & 1);
+          copy_a(c + 2 < nch ? c + 2 : c, (c + 2) % 3);
+          floatx2 x[8];
+          lds_read8x8_rows(sa + (uint32_t)((((c % 3) * NW + wv) * KC * 32) * 4) + lane_off, x);
+          if (NORM) {
+  #pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              fro += (double)x[e].x * (double)x[e].x + (double)x[e].y * (double)x[e].y;
+              bad |= !__builtin_isfinite((double)x[e].x) || !__builtin_isfinite((double)x[e].y);
+            }
+          }
+          // B operands (A's entries) of column 2 j + q: parts hi, mid, lo
+          u32x4 bp[3][NQ];
+  #pragma unroll
+          for (int q = 0; q < NQ; ++q)
+  #pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              uint32_t h, md, lo;
+              split3_bf16x2(q ? x[2 * d].y : x[2 * d].x, q ? x[2 * d + 1].y : x[2 * d + 1].x, h, md,
+                            lo);
+              bp[0][q][d] = h;
+              bp[1][q][d] = md;
+              bp[2][q][d] = lo;
+            }
+          // A operands (Omega) of tile a: parts hi, mid, lo
+          const u32x4* osrc = reinterpret_cast<const u32x4*>(
+              reinterpret_cast<const unsigned char*>(sO) + (c & 1) * OREC * 1024);
+          u32x4 op[3][MT];
+  #pragma unroll
+          for (int a = 0; a < MT; ++a)
+  #pragma unroll
+            for (int p = 0; p < 3; ++p) op[p][a] = osrc[(3 * a + p) * 64 + lane];
+          // six partial products, smallest first: (Omega part, A part)
+          constexpr int PO[6] = {2, 1, 0, 1, 0, 0};
+          constexpr int PA[6] = {0, 1, 2, 0, 1, 0};
+  #pragma unroll
+          for (int t = 0; t < 6; ++t)
+  #pragma unroll
+            for (int a = 0; a < MT; ++a)
+  #pragma unroll
+              for (int q = 0; q < NQ; ++q)
+                acc[a][q] = mfma_bf16x32(op[PO[t]][a], bp[PA[t]][q], acc[a][q]);
+          // FP32 sums of 64 rows (two chunks) are folded into FP64
+          if ((c & 1) || c + 1 == nch) {
+  #pragma unroll
+            for (int a = 0; a < MT; ++a)
+  #pragma unroll
+              for (int q = 0; q < NQ; ++q) {
+  #pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
+                acc[a][q] = M::zero();
+              }
+          }
+        }
+        // every copy has landed before the workgroup's LDS is released
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        return;
+      }
+    }
+    if constexpr (FAST && DMA && !SPLIT) {
       // Per chunk and wave: KC/8 copies of A (8 rows x 32 columns each, this
       // wave's columns) and KC/NW of Omega (one row each), always the same
       // number NCP (chunks past the end re-read this chunk's rows into a

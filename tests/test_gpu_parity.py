@@ -66,13 +66,19 @@ def test_gaussian_matches_oracle(torch, rid, orc, m, w, c0):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("m,n,w,c0", [(1, 1, 1, 0), (100, 37, 13, 2), (1000, 333, 64, 64),
-                                      (2000, 1000, 120, 0), (777, 1500, 20, 100),
-                                      (5000, 600, 128, 9)])
-def test_sketch_matches_oracle(torch, rid, orc, dtype, m, n, w, c0):
-    _say("sketch", dtype, m, n, w, c0)
+@pytest.mark.parametrize("m,n,w,c0,spread", [(1, 1, 1, 0, 0), (100, 37, 13, 2, 0),
+                                             (1000, 333, 64, 64, 0), (2000, 1000, 120, 0, 0),
+                                             (777, 1500, 20, 100, 0), (5000, 600, 128, 9, 0),
+                                             (3000, 2048, 64, 5, 0), (2500, 1100, 64, 0, 25)])
+def test_sketch_matches_oracle(torch, rid, orc, dtype, m, n, w, c0, spread):
+    """Device sketch against the oracle's entry by entry.  spread > 0: entries
+    of magnitudes 10^U(-spread, spread), so that within a column the FP32
+    three-part BF16 products meet values many binades apart."""
+    _say("sketch", dtype, m, n, w, c0, spread)
     rng = np.random.default_rng(m * 7 + n)
     A = rng.standard_normal((m, n))
+    if spread:
+        A *= 10.0 ** rng.uniform(-spread, spread, (m, n))
     td = torch.float64 if dtype == "f64" else torch.float32
     Ad = _dev(torch, A, td)
     Aused = Ad.cpu().numpy().astype(np.float64)
@@ -84,6 +90,33 @@ def test_sketch_matches_oracle(torch, rid, orc, dtype, m, n, w, c0):
     u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
     bound = 16 * u * math.sqrt(max(m, 64)) * scale + 1e-300
     assert np.all(np.abs(Yt.T - Yo) <= bound)
+
+
+def test_split_sketch_accuracy(torch, rid, orc):
+    """FP32 blocks of 64 vectors are multiplied on the BF16 matrix cores
+    through the exact three-part split of both operands (six of the nine
+    partial products); blocks of 32 vectors use the FP32 matrix-core
+    instruction.  On the same vectors (one 64-vector launch against two
+    32-vector launches) the split's errors against the oracle's FP64 sketch,
+    relative to sum |omega| |a|, are no larger than the FP32 instruction's
+    (RMS within 1.25x, maximum within 2x)."""
+    m, n = 20000, 1024
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    Ad = torch.tensor(A, device="cuda")
+    Aused = A.astype(np.float64)
+    y64 = rid.debug_sketch(Ad, seed=77, c0=0, w=64).cpu().numpy().astype(np.float64)
+    y32 = np.concatenate([rid.debug_sketch(Ad, seed=77, c0=c0, w=32).cpu().numpy()
+                          for c0 in (0, 32)], axis=1).astype(np.float64)
+    yo = orc.sketch(Aused, 77, 0, 64).T
+    scale = (np.abs(orc.omega(77, 0, 64, m)) @ np.abs(Aused)).T
+    e_split = np.abs(y64 - yo) / scale
+    e_f32 = np.abs(y32 - yo) / scale
+    rms_s, rms_f = float(np.sqrt(np.mean(e_split ** 2))), float(np.sqrt(np.mean(e_f32 ** 2)))
+    print(f"split: rms {rms_s:.3e} max {e_split.max():.3e}; fp32 mfma: rms {rms_f:.3e} "
+          f"max {e_f32.max():.3e} (relative to sum |omega||a|)")
+    assert rms_s <= 1.25 * rms_f
+    assert e_split.max() <= 2.0 * e_f32.max()
 
 
 # -- fixed rank ------------------------------------------------------------------
