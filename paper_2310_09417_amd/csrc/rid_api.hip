@@ -182,7 +182,8 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   // one in FP64 (8 waves).  Pick the number of row splits whose workgroup
   // count fills the last round best, between ~2 and ~8 rounds, preferring
   // fewer.
-  const int64_t slots = (int64_t)cu * (dt == RID_F64 ? 1 : 2);
+  const int64_t slots =
+      (int64_t)cu * (1024 / (dt == RID_F64 ? SketchShape<double>::NT : SketchShape<float>::NT));
   const int64_t maxsplit = ceil_div(m, g.kc);
   const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(2 * slots, g.ncolg)));
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(maxsplit, ceil_div(8 * slots, g.ncolg)));

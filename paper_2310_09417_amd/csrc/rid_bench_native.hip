@@ -39,6 +39,28 @@ __global__ void calib_copy(const float4* __restrict__ src, float4* __restrict__ 
     dst[i] = src[i];
 }
 
+// Streaming read of n4 16-byte words (four independent loads in flight per
+// thread); one value per thread is written so the loads are kept.
+__global__ void calib_read(const float4* __restrict__ src, size_t n4, float* __restrict__ out) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float4 a = {0.f, 0.f, 0.f, 0.f}, b = a, c = a, d = a;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    const float4 x = src[i], y = src[i + stride], z = src[i + 2 * stride], w = src[i + 3 * stride];
+    a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
+    b.x += y.x; b.y += y.y; b.z += y.z; b.w += y.w;
+    c.x += z.x; c.y += z.y; c.z += z.z; c.w += z.w;
+    d.x += w.x; d.y += w.y; d.z += w.z; d.w += w.w;
+  }
+  for (; i < n4; i += stride) {
+    const float4 x = src[i];
+    a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
+  }
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] =
+      (a.x + a.y + a.z + a.w) + (b.x + b.y + b.z + b.w) + (c.x + c.y + c.z + c.w) +
+      (d.x + d.y + d.z + d.w);
+}
+
 // FP32 -> BF16 bits (nearest even) or e4m3 codes, one entry per thread.
 __global__ void to_format(const float* __restrict__ src, unsigned char* __restrict__ dst,
                           size_t count, int fmt) {
@@ -77,12 +99,45 @@ static int calibrate(hipStream_t st) {
   CHECK(hipMalloc(&csrc, cbytes));
   CHECK(hipMalloc(&cdst, cbytes));
   CHECK(hipMemsetAsync(csrc, 0, cbytes, st));
+  hipEvent_t e0, e1;
+  CHECK(hipEventCreate(&e0));
+  CHECK(hipEventCreate(&e1));
+  CHECK(hipEventRecord(e0, st));
   hipLaunchKernelGGL(calib_copy, dim3(4096), dim3(256), 0, st, (const float4*)csrc, (float4*)cdst,
                      cbytes / 16);
+  CHECK(hipEventRecord(e1, st));
   CHECK(hipStreamSynchronize(st));
-  CHECK(hipFree(csrc));
+  float ms_copy = 0.f;
+  CHECK(hipEventElapsedTime(&ms_copy, e0, e1));
+  std::printf("[native] calibration copy: %zu bytes read, %zu written, %.3f ms (%.0f GB/s)\n",
+              cbytes, cbytes, ms_copy, 2.0 * cbytes / (ms_copy * 1e-3) / 1e9);
+  // streaming read of 4 GiB (the two buffers twice), best of three
   CHECK(hipFree(cdst));
-  std::printf("[native] calibration copy: %zu bytes read, %zu written\n", cbytes, cbytes);
+  const size_t rbytes = (size_t)4 << 30;
+  float* rbuf = nullptr;
+  float* rout = nullptr;
+  CHECK(hipMalloc(&rbuf, rbytes));
+  CHECK(hipMemsetAsync(rbuf, 0, rbytes, st));
+  const unsigned rgrid = 256 * 16;
+  CHECK(hipMalloc(&rout, (size_t)rgrid * 256 * sizeof(float)));
+  float best = 0.f;
+  for (int r = 0; r < 3; ++r) {
+    CHECK(hipEventRecord(e0, st));
+    hipLaunchKernelGGL(calib_read, dim3(rgrid), dim3(256), 0, st, (const float4*)rbuf, rbytes / 16,
+                       rout);
+    CHECK(hipEventRecord(e1, st));
+    CHECK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (r == 0 || ms < best) best = ms;
+  }
+  std::printf("[native] streaming read: %zu bytes, %.3f ms (%.0f GB/s)\n", rbytes, best,
+              rbytes / (best * 1e-3) / 1e9);
+  CHECK(hipFree(rbuf));
+  CHECK(hipFree(rout));
+  CHECK(hipFree(csrc));
+  CHECK(hipEventDestroy(e0));
+  CHECK(hipEventDestroy(e1));
   return 0;
 }
 

@@ -292,9 +292,9 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
         // be in flight.  Past the end the last chunk is copied again into a
         // stage no later chunk reads, so the count per chunk stays fixed.
         constexpr int NA = KC / 8;
-        constexpr int OREC = 12;                    // Omega records per chunk
-        constexpr int ORW = OREC / NW;              // Omega records per wave
-        static_assert(OREC % NW == 0 && 2 * OREC * 1024 <= (int)sizeof(sO), "split stages");
+        constexpr int OREC = 12;                      // Omega records per chunk
+        constexpr int ORW = (OREC + NW - 1) / NW;     // Omega copies per wave
+        static_assert(2 * OREC * 1024 <= (int)sizeof(sO), "split stages");
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         const int64_t cw = (int64_t)blockIdx.x * CPW + wv * 32;
         const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
@@ -302,7 +302,11 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
   #pragma unroll
         for (int i = 0; i < NA; ++i)
           pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + cw + 4 * (lane & 7);
-        const uint32_t* po = oms + ((r_begin / KC) * OREC + ORW * wv) * 256 + 4 * lane;
+        // wave wv copies records wv, wv + NW, ...; where that passes the last
+        // record it copies record wv again (same bytes to the same place), so
+        // that every wave issues ORW copies
+        const uint32_t* po = oms + (r_begin / KC) * OREC * 256 + 4 * lane;
+        auto orec = [&](int i) { return wv + NW * i < OREC ? wv + NW * i : wv; };
         auto copy_a = [&](int chunk, int st) {
           const int64_t da = (int64_t)chunk * KC * lda;
   #pragma unroll
@@ -312,8 +316,8 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
         auto copy_o = [&](int chunk, int st) {
   #pragma unroll
           for (int i = 0; i < ORW; ++i)
-            copy16_to_lds(po + ((int64_t)chunk * OREC + i) * 256,
-                          so + (uint32_t)((st * OREC + ORW * wv + i) * 1024));
+            copy16_to_lds(po + ((int64_t)chunk * OREC + orec(i)) * 256,
+                          so + (uint32_t)((st * OREC + orec(i)) * 1024));
         };
         // lane (j, g) = (lane % 16, lane / 16): rows 8 g .. 8 g + 7, columns 2 j, 2 j + 1
         const uint32_t lane_off = (uint32_t)((8 * (lane >> 4) * 32 + 2 * (lane & 15)) * 4);
