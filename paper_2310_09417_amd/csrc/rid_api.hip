@@ -181,9 +181,11 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   // Resident workgroups: two per CU in FP32 (4 waves, ~78 KB of LDS each),
   // one in FP64 (8 waves).  Pick the number of row splits whose workgroup
   // count fills the last round best, between ~2 and ~8 rounds, preferring
-  // fewer.
-  const int64_t slots =
-      (int64_t)cu * (1024 / (dt == RID_F64 ? SketchShape<double>::NT : SketchShape<float>::NT));
+  // fewer.  FP32 counts rounds of twice its resident workgroups: more,
+  // shorter row splits measured faster for the split sketch at 50000 x 20000
+  // (1.02 -> 0.94 ms per launch; the partials then take 1.2 -> 2.2 ms per
+  // decomposition to reduce, before they were stored in FP32).
+  const int64_t slots = (int64_t)cu * (dt == RID_F64 ? 1 : 4);
   const int64_t maxsplit = ceil_div(m, g.kc);
   const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(2 * slots, g.ncolg)));
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(maxsplit, ceil_div(8 * slots, g.ncolg)));
@@ -523,11 +525,11 @@ int launch_sketch_t(const Plan& P, const Ws& W, const void* A, int64_t lda, uint
   if (norm)
     hipLaunchKernelGGL((k_sketch<TC, MT, KC, true, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, om, oms, w, g.rows_per_split,
-                       W.part, W.fro, W.nonfinite, ctrl);
+                       reinterpret_cast<TC*>(W.part), W.fro, W.nonfinite, ctrl);
   else
     hipLaunchKernelGGL((k_sketch<TC, MT, KC, false, VEC>), grid, dim3(SketchShape<TC>::NT), 0, st,
                        static_cast<const TC*>(A), P.m, P.n, lda, om, oms, w, g.rows_per_split,
-                       W.part, W.fro, W.nonfinite, ctrl);
+                       reinterpret_cast<TC*>(W.part), W.fro, W.nonfinite, ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;
@@ -682,12 +684,12 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
                                                           norm, use_ctrl, Draw{c0, w}, st));
       const long pm = prof_begin(KC_REDUCE, st);
       if (P.dt == RID_F64)
-        hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
-                           (int)g.nsplit, P.n, g.wp, wc, static_cast<double*>(out), ldo,
+        hipLaunchKernelGGL((k_sketch_reduce<double, double>), dim3(blocks), dim3(256), 0, st,
+                           W.part, (int)g.nsplit, P.n, g.wp, wc, static_cast<double*>(out), ldo,
                            zcol + off, static_cast<double*>(copy), W.fro,
                            (int)(g.nsplit * g.ntile), W.nonfinite, ctrl, norm ? 1 : 0);
       else
-        hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
+        hipLaunchKernelGGL((k_sketch_reduce<float, double>), dim3(blocks), dim3(256), 0, st, W.part,
                            (int)g.nsplit, P.n, g.wp, wc, static_cast<float*>(out), ldo,
                            zcol + off, static_cast<float*>(copy), W.fro,
                            (int)(g.nsplit * g.ntile), W.nonfinite, ctrl, norm ? 1 : 0);
@@ -704,12 +706,13 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
     if (rc != RID_OK) return rc;
     const long pm = prof_begin(KC_REDUCE, st);
     if (P.dt == RID_F64)
-      hipLaunchKernelGGL(k_sketch_reduce<double>, dim3(blocks), dim3(256), 0, st, W.part,
+      hipLaunchKernelGGL((k_sketch_reduce<double, double>), dim3(blocks), dim3(256), 0, st, W.part,
                          (int)g.nsplit, P.n, g.wp, wc, static_cast<double*>(out), ldo, zcol + off,
                          static_cast<double*>(copy), W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite,
                          ctrl, norm ? 1 : 0);
     else
-      hipLaunchKernelGGL(k_sketch_reduce<float>, dim3(blocks), dim3(256), 0, st, W.part,
+      hipLaunchKernelGGL((k_sketch_reduce<float, float>), dim3(blocks), dim3(256), 0, st,
+                         reinterpret_cast<const float*>(W.part),
                          (int)g.nsplit, P.n, g.wp, wc, static_cast<float*>(out), ldo, zcol + off,
                          static_cast<float*>(copy), W.fro, (int)(g.nsplit * g.ncolg), W.nonfinite,
                          ctrl, norm ? 1 : 0);

@@ -26,8 +26,9 @@ namespace rid {
 //     LDS, double buffered.
 //   * FP32: each chunk is accumulated by MFMA in FP32 and folded into FP64
 //     registers, so rounding grows with KC, not with m.
-//   * Partials part[split][j][c] (FP64) are summed in split order by
-//     k_sketch_reduce, so the result does not depend on scheduling.
+//   * Partials part[split][j][c] (in the factor type: a split's FP64 sum is
+//     rounded once, to FP32 in the FP32 path) are summed in split order in
+//     FP64 by k_sketch_reduce, so the result does not depend on scheduling.
 //   * NORM: also accumulates sum A^2 (FP64) and flags non-finite entries.
 //   * Workgroups away from the matrix edges run the same loop without any
 //     bounds test (see `fast` below).
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uin
 template <typename TC, int MT, int KC, bool NORM, bool VEC>
 __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
     const TC* __restrict__ A, int64_t m, int64_t n, int64_t lda, const TC* __restrict__ omg,
-    const uint32_t* __restrict__ oms, int w, int64_t rows_per_split, double* __restrict__ part,
+    const uint32_t* __restrict__ oms, int w, int64_t rows_per_split, TC* __restrict__ part,
     double* __restrict__ fro_part, int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
   if (ctrl && ctrl->done) return;
   constexpr int NQ = SketchShape<TC>::NQ;
@@ -581,11 +582,11 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
   for (int q = 0; q < NQ; ++q) {
     const int64_t col = colq + q;
     if (col < n) {
-      double* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP;
+      TC* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP;
 #pragma unroll
       for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = acc64[a][q][r];
+        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = (TC)acc64[a][q][r];
     }
   }
   if (NORM) {
@@ -767,11 +768,11 @@ __global__ __launch_bounds__(256) void k_sketch_rows(
   }
 }
 
-// Sum of the split partials in split order; writes Y^T into Z columns
-// [zcol, zcol + w) in the factor type.  With `first`, also finishes ||A||_F^2
-// and the non-finite check.
-template <typename TF>
-__global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int64_t n, int WP,
+// Sum of the split partials (type TP) in split order, in FP64; writes Y^T
+// into Z columns [zcol, zcol + w) in the factor type.  With `first`, also
+// finishes ||A||_F^2 and the non-finite check.
+template <typename TF, typename TP>
+__global__ void k_sketch_reduce(const TP* __restrict__ part, int nsplit, int64_t n, int WP,
                                 int w, TF* __restrict__ Z, int64_t ldz, int zcol,
                                 TF* __restrict__ Z2, const double* __restrict__ fro_part,
                                 int nfro, const int* __restrict__ nonfinite, Ctrl* ctrl,
@@ -782,7 +783,8 @@ __global__ void k_sketch_reduce(const double* __restrict__ part, int nsplit, int
     const int64_t j = t / w;
     const int c = (int)(t % w);
     double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[((size_t)sp * (size_t)n + (size_t)j) * WP + c];
+    for (int sp = 0; sp < nsplit; ++sp)
+      s += (double)part[((size_t)sp * (size_t)n + (size_t)j) * WP + c];
     Z[j * ldz + zcol + c] = (TF)s;
     if (Z2) Z2[j * ldz + zcol + c] = (TF)s;  // kept copy of the sketch (refinement)
   }

@@ -272,6 +272,25 @@ def test_deterministic(torch, rid):
     assert torch.equal(g1.J, g2.J) and torch.equal(g1.T, g2.T)
 
 
+def test_deterministic_fp32_64_vector_blocks(torch, rid):
+    """FP32 path with 64-vector blocks (the split sketch, two workgroups per CU
+    drifting out of phase, the L1^-1 growth overlapping the next sketch on a
+    second stream): repeated sketches and decompositions are bit-identical."""
+    rng = np.random.default_rng(8)
+    m, n = 20000, 4096
+    A = (rng.standard_normal((m, 256)) @ rng.standard_normal((256, n))
+         + 1e-3 * rng.standard_normal((m, n))).astype(np.float32)
+    Ad = torch.tensor(A, device="cuda")
+    y0 = rid.debug_sketch(Ad, seed=3, c0=64, w=64)
+    for _ in range(4):
+        assert torch.equal(rid.debug_sketch(Ad, seed=3, c0=64, w=64), y0)
+    g0 = rid.adaptive(Ad, 64, 1e-9, 1024, seed=4)
+    for _ in range(2):
+        g = rid.adaptive(Ad, 64, 1e-9, 1024, seed=4)
+        assert (g.k, g.status, g.err_est) == (g0.k, g0.status, g0.err_est)
+        assert torch.equal(g.J, g0.J) and torch.equal(g.T, g0.T)
+
+
 # -- the paper's timing workload ----------------------------------------------------
 
 @pytest.mark.parametrize("n,tol", [(1200, 1e-8), (1024, 1e-4)])
