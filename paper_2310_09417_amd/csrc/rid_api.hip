@@ -226,35 +226,43 @@ SketchGeomR sketch_geom_rows(int64_t mrows, int64_t ncols, int w, int cu) {
   return g;
 }
 
-// Low-precision sketch geometry: 1024 columns per workgroup, one workgroup
-// per CU.  The split count minimises (rounds x bytes of A per workgroup) plus
-// the FP32 partials written and read back, per CU.
+// Low-precision sketch geometry (k_sketch_lpr): 256 (BF16) or 512 (FP8)
+// columns per 256-thread workgroup, two resident per CU.  The split count
+// minimises the bytes of A each resident workgroup slot streams (rounds x
+// rows per split x its row bytes) plus the FP32 partials written and read
+// back per slot: the partials are a larger share of a pass over A here than
+// in the FP32 sketch (one FP8 pass is 1 GB at 50000 x 20000).
 struct LpGeom {
   int64_t ncolg, nsplit, rows_per_split;
 };
 
-LpGeom sketch_geom_lp(int64_t m, int64_t n, int es, int cu) {
+LpGeom sketch_geom_lp(int64_t m, int64_t n, int fmt, int cu) {
   LpGeom g;
-  g.ncolg = ceil_div(n, kLpCols);
-  const int64_t maxsplit = ceil_div(m, kLpKs);
-  const int64_t hi = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(8 * cu, g.ncolg)));
+  const int64_t cols = kLprCols(fmt), es = fmt == 1 ? 2 : 1, kc = 32;
+  g.ncolg = ceil_div(n, cols);
+  const int64_t slots = (int64_t)cu * 2;
+  const int64_t maxsplit = ceil_div(m, kc);
+  const int64_t hi = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(8 * slots, g.ncolg)));
   double best = -1.0;
   int64_t best_ns = 1;
   for (int64_t ns = 1; ns <= hi; ++ns) {
-    const int64_t rps = ceil_div(ceil_div(m, ns), kLpKs) * kLpKs;
+    const int64_t rps = ceil_div(ceil_div(m, ns), kc) * kc;
     const int64_t real_ns = ceil_div(m, rps);
     const int64_t items = g.ncolg * real_ns;
-    const double cost = (double)ceil_div(items, cu) * (double)rps * kLpCols * es +
-                        (double)items * kLpCols * 64 * 4 * 2 / cu;
+    const double cost = (double)ceil_div(items, slots) * (double)rps * (double)(cols * es) +
+                        (double)items * (double)cols * 64.0 * 4.0 * 2.0 / (double)slots;
     if (best < 0.0 || cost < best * (1.0 - 1e-3)) {
       best = cost;
       best_ns = ns;
     }
   }
-  g.rows_per_split = ceil_div(ceil_div(m, best_ns), kLpKs) * kLpKs;
+  g.rows_per_split = ceil_div(ceil_div(m, best_ns), kc) * kc;
   g.nsplit = ceil_div(m, g.rows_per_split);
   return g;
 }
+
+// Bytes of the low-precision form's Omega records per 32 rows.
+inline size_t lp_record_bytes(rid_dtype at) { return at == RID_BF16 ? 4096 : 2048; }
 
 inline bool low_precision(rid_dtype t) { return t == RID_BF16 || t == RID_FP8_E4M3; }
 
@@ -325,7 +333,7 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   // sketch partials: every launch covers <= 64 vectors with the same split
   size_t pb = 0, fc = 0;
   if (low_precision(at)) {
-    LpGeom g = sketch_geom_lp(m, n, at == RID_BF16 ? 2 : 1, di.cu);
+    LpGeom g = sketch_geom_lp(m, n, at == RID_BF16 ? 1 : 2, di.cu);
     pb = (size_t)g.nsplit * (size_t)n * 64 * 4;
     fc = (size_t)(g.nsplit * g.ncolg);
   } else if (side == RID_ROWS) {
@@ -369,8 +377,12 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   // Omega of one sketch launch (at most 64 vectors), rows padded to 64; in
   // FP32 followed by its three-part BF16 operand form (k_omega_split, 384
   // bytes per row)
-  P.o_omega = take(low_precision(at) ? 0
-                                     : (size_t)align_up((size_t)m, 64) * (64 * es + (es == 4 ? 384 : 0)));
+  // (the low-precision forms: the FP32 Gaussian entries, then their records
+  // in the format, lp_record_bytes per 32 rows)
+  P.o_omega = take(low_precision(at)
+                       ? (size_t)align_up((size_t)m, 64) * 64 * 4 +
+                             (size_t)align_up((size_t)m, 64) / 32 * lp_record_bytes(at)
+                       : (size_t)align_up((size_t)m, 64) * (64 * es + (es == 4 ? 384 : 0)));
   // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
@@ -619,24 +631,27 @@ template <int FMT, bool NORM>
 int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                      int64_t c0, int w, const LpGeom& g, bool use_ctrl, hipStream_t st) {
   constexpr int ES = FMT == 1 ? 2 : 1;
-  // vector loads of 8 entries (16 bytes BF16, 8 bytes FP8): base and row
-  // pitch aligned to that size
-  const bool vec = ((lda * ES) % (8 * ES) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(A) & (size_t)(8 * ES - 1)) == 0);
-  dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
+  // the ring's 16-byte copies need 16-byte aligned rows
+  const int aligned = ((lda * ES) % 16 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+  const int vec8 = ((lda * ES) % 8 == 0) && ((reinterpret_cast<uintptr_t>(A) & 7u) == 0);
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
-  const unsigned char* a = static_cast<const unsigned char*>(A);
-  float* part = reinterpret_cast<float*>(W.part);
-  const long pm = prof_begin(KC_SKETCH, st);
-  if (vec)
-    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, true>), grid, dim3(kLpThreads), 0, st, a, P.m, P.n, lda,
-                       P.scale, k0, k1, (uint32_t)c0, w, g.rows_per_split, part, W.fro,
-                       W.nonfinite, ctrl);
-  else
-    hipLaunchKernelGGL((k_sketch_lp<FMT, NORM, false>), grid, dim3(kLpThreads), 0, st, a, P.m, P.n, lda,
-                       P.scale, k0, k1, (uint32_t)c0, w, g.rows_per_split, part, W.fro,
-                       W.nonfinite, ctrl);
+  const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
+  float* om = static_cast<float*>(W.omega);
+  unsigned char* rec = reinterpret_cast<unsigned char*>(om + mpad * 64);
+  long pm = prof_begin(KC_OMEGA, st);
+  hipLaunchKernelGGL(k_omega<float>, dim3((unsigned)ceil_div(mpad / 4 * 64, 256)), dim3(256), 0, st,
+                     k0, k1, (uint32_t)c0, w, 64, P.m, mpad, om, ctrl);
+  hipLaunchKernelGGL(k_omega_lp_records<FMT>, dim3((unsigned)ceil_div(mpad / 32 * 256, 256)),
+                     dim3(256), 0, st, om, mpad, rec, ctrl);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  dim3 grid((unsigned)g.ncolg, (unsigned)g.nsplit);
+  pm = prof_begin(KC_SKETCH, st);
+  hipLaunchKernelGGL((k_sketch_lpr<FMT, NORM>), grid, dim3(kLprThreads), 0, st,
+                     static_cast<const unsigned char*>(A), P.m, P.n, lda, P.scale, rec,
+                     g.rows_per_split, reinterpret_cast<float*>(W.part), W.fro, W.nonfinite, ctrl,
+                     aligned, vec8);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
   return RID_OK;
@@ -657,7 +672,7 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
     const unsigned blocks = (unsigned)ceil_div(P.n * wc, 256);
     if (low_precision(P.at)) {
       // factor type is FP32 (checked by the caller)
-      LpGeom g = sketch_geom_lp(P.m, P.n, P.at == RID_BF16 ? 2 : 1, P.cu);
+      LpGeom g = sketch_geom_lp(P.m, P.n, P.at == RID_BF16 ? 1 : 2, P.cu);
       int rc;
       if (P.at == RID_BF16)
         rc = norm ? launch_sketch_lp<1, true>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st)
