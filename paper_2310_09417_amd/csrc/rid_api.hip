@@ -228,10 +228,13 @@ SketchGeomR sketch_geom_rows(int64_t mrows, int64_t ncols, int w, int cu) {
 
 // Low-precision sketch geometry (k_sketch_lpr): 256 (BF16) or 512 (FP8)
 // columns per 256-thread workgroup, two resident per CU.  The split count
-// minimises the bytes of A each resident workgroup slot streams (rounds x
-// rows per split x its row bytes) plus the FP32 partials written and read
-// back per slot: the partials are a larger share of a pass over A here than
-// in the FP32 sketch (one FP8 pass is 1 GB at 50000 x 20000).
+// minimises the bytes of A each workgroup slot streams (rounds x rows per
+// split x its row bytes) plus the FP32 partials written and read back per
+// slot, counting four slots per CU, which gives about two workgroups per
+// resident slot: the partials are a larger share of a pass over A here than
+// in the FP32 sketch (one FP8 pass is 1 GB at 50000 x 20000).  Measured at
+// that size (sketch + reduction per decomposition): one round of slots 17.8
+// (BF16) / 10.4 ms (FP8), about two 15.9 / 10.1 ms, about eight 17.8 / 11.7 ms.
 struct LpGeom {
   int64_t ncolg, nsplit, rows_per_split;
 };
@@ -240,7 +243,7 @@ LpGeom sketch_geom_lp(int64_t m, int64_t n, int fmt, int cu) {
   LpGeom g;
   const int64_t cols = kLprCols(fmt), es = fmt == 1 ? 2 : 1, kc = 32;
   g.ncolg = ceil_div(n, cols);
-  const int64_t slots = (int64_t)cu * 2;
+  const int64_t slots = (int64_t)cu * 4;
   const int64_t maxsplit = ceil_div(m, kc);
   const int64_t hi = std::max<int64_t>(1, std::min<int64_t>(maxsplit, ceil_div(8 * slots, g.ncolg)));
   double best = -1.0;

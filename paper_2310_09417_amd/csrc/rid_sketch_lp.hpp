@@ -3,25 +3,11 @@
 // Sec. 2.4 and Alg. 1, run on matrix cores with FP32 accumulation).
 //
 // Omega is generated as in the FP32 path (Philox4x32-10 + Box-Muller in FP32,
-// the same counters) and rounded to nearest even into the format of A, so
-// each sketch vector is a fixed, slightly rounded Gaussian vector: rounding
-// the embedding changes which random matrix is used, not the method.
-//
-// Geometry: 512 threads (8 waves, two per SIMD, so that one wave's loads and
-// Gaussian generation overlap the other's) own 1024 columns and a range of
-// rows_per_split rows.  Per k-step of 32 rows every lane loads 8 rows of 8
-// columns of A, transposes them in registers into the 16x16x32 operand form
-// (8 consecutive rows of one column), and multiplies them by the 4 Omega
-// tiles (64 vectors) it reads from LDS.  Omega for the next k-step is
-// generated into the other LDS buffer while the current one is in use, so
-// each Gaussian value is reused across 1024 columns.
-//   lane columns {8cg .. 8cg+7} of its wave's 128 (one 16-byte BF16 or 8-byte
-//   FP8 load per row, contiguous over the 16 lanes of a row); a wave's 128
-//   columns are one FP8 scale tile.
-// The FP32 accumulators of a workgroup hold the raw sum over its rows; the
-// partials part[split][col][64] (FP32) are summed in split order in FP64 by
-// k_sketch_reduce_lp, which also applies the FP8 column scale.  NORM also
-// accumulates sum A^2 (FP64 across k-steps) and flags non-finite entries.
+// the same counters, k_omega) and rounded to nearest even into the format of
+// A, so each sketch vector is a fixed, slightly rounded Gaussian vector:
+// rounding the embedding changes which random matrix is used, not the
+// method.  The partials part[split][col][64] (FP32) are summed in split order
+// in FP64 by k_sketch_reduce_lp, which also applies the FP8 column scale.
 #pragma once
 
 #include <type_traits>
@@ -30,64 +16,6 @@
 #include "rid_sketch.hpp"
 
 namespace rid {
-
-constexpr int kLpCols = 1024;  // columns per workgroup
-constexpr int kLpKs = 32;      // rows per k-step
-
-// 16 bytes of row `row` from column `col` (zeros outside the matrix).  The
-// element-wise path serves segments that cross column n and unaligned A.
-template <int ES, bool VEC>
-__device__ __forceinline__ u32x4 lp_load16(const unsigned char* __restrict__ A, int64_t row,
-                                           int64_t r_end, int64_t col, int64_t n, int64_t lda) {
-  constexpr int NE = 16 / ES;  // entries in 16 bytes
-  if (row >= r_end) return u32x4{0u, 0u, 0u, 0u};
-  const unsigned char* p = A + (row * lda + col) * ES;
-  if (VEC && col + NE <= n) return *reinterpret_cast<const u32x4*>(p);
-  uint64_t lo = 0, hi = 0;
-#pragma unroll 1
-  for (int t = 0; t < NE && col + t < n; ++t) {
-    const uint64_t x = (ES == 2) ? (uint64_t) reinterpret_cast<const unsigned short*>(p)[t]
-                                 : (uint64_t)p[t];
-    const int sh = 8 * ES * t;
-    if (sh < 64)
-      lo |= x << sh;
-    else
-      hi |= x << (sh - 64);
-  }
-  return u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
-}
-
-// 8 bytes of row `row` from column `col` (FP8 codes; zeros outside A).
-template <bool VEC>
-__device__ __forceinline__ u32x2 lp_load8(const unsigned char* __restrict__ A, int64_t row,
-                                          int64_t r_end, int64_t col, int64_t n, int64_t lda) {
-  if (row >= r_end) return u32x2{0u, 0u};
-  const unsigned char* p = A + row * lda + col;
-  if (VEC && col + 8 <= n) return *reinterpret_cast<const u32x2*>(p);
-  uint64_t v = 0;
-#pragma unroll 1
-  for (int t = 0; t < 8 && col + t < n; ++t) v |= (uint64_t)p[t] << (8 * t);
-  return u32x2{(uint32_t)v, (uint32_t)(v >> 32)};
-}
-
-// BF16: the operand of column j (0..7) of the 8 rows x 8 columns held in
-// buf[base .. base+7] (row e; entries 2d, 2d+1 in dword d): entries of rows
-// e = 0..7 packed two per dword.
-template <int NB>
-__device__ __forceinline__ u32x4 lp_col_bf16(const u32x4 (&buf)[NB], int base, int j) {
-  const int d = j >> 1;
-  u32x4 o;
-  if (j & 1) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-      o[p] = (buf[base + 2 * p][d] >> 16) | (buf[base + 2 * p + 1][d] & 0xffff0000u);
-  } else {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-      o[p] = (buf[base + 2 * p][d] & 0xffffu) | (buf[base + 2 * p + 1][d] << 16);
-  }
-  return o;
-}
 
 // FP8: 4x4 byte transpose of rows x0..x3 (one dword each): out[s] holds byte
 // s of x0, x1, x2, x3 in bytes 0..3.
@@ -101,175 +29,6 @@ __device__ __forceinline__ void lp_tr4(uint32_t x0, uint32_t x1, uint32_t x2, ui
   out[1] = (a_hi & 0xffffu) | (b_hi << 16);
   out[2] = (a_lo >> 16) | (b_lo & 0xffff0000u);
   out[3] = (a_hi >> 16) | (b_hi & 0xffff0000u);
-}
-
-constexpr int kLpThreads = 512;
-
-template <int FMT, bool NORM, bool VEC>
-__global__ __launch_bounds__(kLpThreads) void k_sketch_lp(
-    const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda,
-    const float* __restrict__ col_scale, uint32_t key0, uint32_t key1, uint32_t c0, int w,
-    int64_t rows_per_split, float* __restrict__ part, double* __restrict__ fro_part,
-    int* __restrict__ nonfinite, const Ctrl* __restrict__ ctrl) {
-  if (ctrl && ctrl->done) return;
-  constexpr int ES = FMT == 1 ? 2 : 1;     // bytes per entry of A and Omega
-  constexpr int WP = 64;                   // sketch vectors (padded)
-  constexpr int PITCH = kLpKs * ES + 16;   // LDS bytes per vector
-  constexpr int NW = kLpThreads / 64;
-  __shared__ __align__(16) unsigned char om[2][WP * PITCH];
-  __shared__ double red[NW];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cg = lane & 15, rs = lane >> 4;
-  const int64_t colA = (int64_t)blockIdx.x * kLpCols + wave * 128 + 8 * cg;  // 8 columns
-  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
-  const int nks = (int)((r_end - r_begin + kLpKs - 1) / kLpKs);
-
-  floatx4 acc[4][8];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[a][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  double fro = 0.0;
-  bool bad = false;
-
-  // Omega for the k-step at row r0: 64 vectors x 8 row quads, one quad per
-  // thread
-  auto gen = [&](unsigned char* omb, int64_t r0) {
-    const int c = tid >> 3, qd = tid & 7;
-    const int64_t row4 = r0 + 4 * qd;
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (c < w && row4 < r_end) gauss4<float>(key0, key1, (uint32_t)(row4 >> 2), c0 + (uint32_t)c, v);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (row4 + e >= r_end) v[e] = 0.f;
-    unsigned char* dst = omb + c * PITCH + 4 * qd * ES;
-    if (FMT == 1) {
-      uint2 p;
-      p.x = bf16_rne(v[0]) | (bf16_rne(v[1]) << 16);
-      p.y = bf16_rne(v[2]) | (bf16_rne(v[3]) << 16);
-      *reinterpret_cast<uint2*>(dst) = p;
-    } else {
-      *reinterpret_cast<uint32_t*>(dst) = fp8x2_rne(v[0], v[1]) | (fp8x2_rne(v[2], v[3]) << 16);
-    }
-  };
-
-  // one k-step of A: 8 rows of the lane's 8 columns
-  using BufT = typename std::conditional<FMT == 1, u32x4, u32x2>::type;
-  auto load = [&](BufT (&buf)[8], int64_t r0) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t row = r0 + 8 * rs + e;
-      if constexpr (FMT == 1)
-        buf[e] = lp_load16<ES, VEC>(A, row, r_end, colA, n, lda);
-      else
-        buf[e] = lp_load8<VEC>(A, row, r_end, colA, n, lda);
-    }
-  };
-
-  auto norm_acc = [&](const BufT (&buf)[8]) {
-    float f = 0.f;
-    constexpr int ND = FMT == 1 ? 4 : 2;
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        const uint32_t x = buf[t][d];
-        if (FMT == 1) {
-          const float lo = __uint_as_float(x << 16), hi = __uint_as_float(x & 0xffff0000u);
-          f += lo * lo + hi * hi;
-          bad |= ((x & 0x7f80u) == 0x7f80u) || ((x & 0x7f800000u) == 0x7f800000u);
-        } else {
-          const float v0 = fp8_to_f32<0>(x), v1 = fp8_to_f32<1>(x);
-          const float v2 = fp8_to_f32<2>(x), v3 = fp8_to_f32<3>(x);
-          f += (v0 * v0 + v1 * v1) + (v2 * v2 + v3 * v3);
-          bad |= ((x & 0x7fu) == 0x7fu) || ((x & 0x7f00u) == 0x7f00u) ||
-                 ((x & 0x7f0000u) == 0x7f0000u) || ((x & 0x7f000000u) == 0x7f000000u);
-        }
-      }
-    fro += (double)f;
-  };
-
-  auto compute = [&](const unsigned char* omc, const BufT (&buf)[8], unsigned char* omn,
-                     int64_t rnext, bool has_next) {
-    if (NORM) norm_acc(buf);
-    if (has_next) gen(omn, rnext);
-    if constexpr (FMT == 1) {
-      u32x4 oa[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        oa[a] = *reinterpret_cast<const u32x4*>(omc + (16 * a + cg) * PITCH + 16 * rs);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const u32x4 bv = lp_col_bf16<8>(buf, 0, j);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) acc[a][j] = mfma_bf16x32(oa[a], bv, acc[a][j]);
-      }
-    } else {
-      u32x2 oa[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        oa[a] = *reinterpret_cast<const u32x2*>(omc + (16 * a + cg) * PITCH + 8 * rs);
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        uint32_t lo[4], hi[4];
-        lp_tr4(buf[0][d], buf[1][d], buf[2][d], buf[3][d], lo);
-        lp_tr4(buf[4][d], buf[5][d], buf[6][d], buf[7][d], hi);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const u32x2 bv = {lo[s], hi[s]};
-#pragma unroll
-          for (int a = 0; a < 4; ++a) acc[a][4 * d + s] = mfma_fp8x32(oa[a], bv, acc[a][4 * d + s]);
-        }
-      }
-    }
-  };
-
-  // A for the next k-step is loaded into bB while bA is in use, then moved
-  // (one copy of the k-step body keeps the accumulators in place)
-  BufT bA[8], bB[8];
-  if (nks > 0) {
-    gen(om[0], r_begin);
-    load(bA, r_begin);
-  }
-  __syncthreads();
-  for (int ks = 0; ks < nks; ++ks) {
-    const int64_t r0 = r_begin + (int64_t)ks * kLpKs;
-    const bool nx = ks + 1 < nks;
-    if (nx) load(bB, r0 + kLpKs);
-    compute(om[ks & 1], bA, om[(ks + 1) & 1], r0 + kLpKs, nx);
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 8; ++t) bA[t] = bB[t];
-  }
-
-  // partials: accumulator (a, j) holds vectors 16a + 4rs + r of column colA + j
-  const int64_t split = blockIdx.y;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int64_t col = colA + j;
-    if (col < n) {
-      float* dst = part + ((size_t)split * (size_t)n + (size_t)col) * WP + 4 * rs;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) *reinterpret_cast<floatx4*>(dst + 16 * a) = acc[a][j];
-    }
-  }
-  if (NORM) {
-    if (FMT == 2 && colA < n) {
-      const double sc = (double)col_scale[colA >> 7];
-      fro *= sc * sc;
-    }
-    fro = wave_sum(fro);
-    if (lane == 0) red[wave] = fro;
-    if (bad) atomicOr(nonfinite, 1);
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int wv = 0; wv < NW; ++wv) t += red[wv];
-      fro_part[blockIdx.y * gridDim.x + blockIdx.x] = t;
-    }
-  }
 }
 
 // Sum of the FP32 split partials in split order (FP64), times the column
@@ -306,9 +65,6 @@ __global__ void k_sketch_reduce_lp(const float* __restrict__ part, int nsplit, i
   }
 }
 
-}  // namespace rid
-
-namespace rid {
 
 // ---------------------------------------------------------------------------
 // Low-precision sketch through an LDS ring (the form the launches use).
@@ -397,7 +153,7 @@ __global__ __launch_bounds__(kLprThreads, 2) void k_sketch_lpr(
   constexpr int CW = 16 * CPL;            // columns per wave
   constexpr int NW = kLprThreads / 64;
   constexpr int KC = 32;                  // rows per chunk
-  constexpr int NST = 4;                  // ring stages
+  constexpr int NST = FMT == 1 ? 3 : 4;   // ring stages
   constexpr int RB = FMT == 1 ? 16 : 8;   // Omega operand bytes per lane and tile
   constexpr int OCH = 4 * 64 * RB;        // Omega record bytes per chunk
   constexpr int NA = KC * 128 / 1024;     // A copies per wave and chunk (4)
@@ -503,11 +259,11 @@ __global__ __launch_bounds__(kLprThreads, 2) void k_sketch_lpr(
     };
     const uint32_t lane_off = (uint32_t)(8 * g * 128 + 8 * j);
     copy_group(0, 0);
-    copy_group(nfull > 1 ? 1 : 0, 1);
-    copy_group(nfull > 2 ? 2 : 0, 2);
+#pragma unroll
+    for (int k = 1; k < NST - 1; ++k) copy_group(nfull > k ? k : 0, k);
     for (int c = 0; c < nfull; ++c) {
-      vm_barrier<2 * GRP>();  // chunk c landed in every wave; chunk c-1's stages free
-      copy_group(c + 3 < nfull ? c + 3 : c, (c + 3) % NST);
+      vm_barrier<(NST - 2) * GRP>();  // chunk c landed in every wave; chunk c-1's stages free
+      copy_group(c + NST - 1 < nfull ? c + NST - 1 : c, (c + NST - 1) % NST);
       const int s = c % NST;
       floatx2 xf[8];
       lds_read8x8_rows(sa + (uint32_t)((s * NW + wv) * KC * 128) + lane_off, xf);
