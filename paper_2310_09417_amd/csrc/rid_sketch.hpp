@@ -768,6 +768,23 @@ __global__ __launch_bounds__(256) void k_sketch_rows(
   }
 }
 
+// sum over sp < nsplit of p[sp * stride] in FP64, in split order, with eight
+// loads in flight at a time
+template <typename TP>
+__device__ __forceinline__ double sum_splits(const TP* __restrict__ p, int nsplit, size_t stride) {
+  double s = 0.0;
+  int sp = 0;
+  for (; sp + 8 <= nsplit; sp += 8) {
+    TP v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[(size_t)(sp + i) * stride];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += (double)v[i];
+  }
+  for (; sp < nsplit; ++sp) s += (double)p[(size_t)sp * stride];
+  return s;
+}
+
 // Sum of the split partials (type TP) in split order, in FP64; writes Y^T
 // into Z columns [zcol, zcol + w) in the factor type.  With `first`, also
 // finishes ||A||_F^2 and the non-finite check.
@@ -782,9 +799,7 @@ __global__ void k_sketch_reduce(const TP* __restrict__ part, int nsplit, int64_t
   if (t < n * w) {
     const int64_t j = t / w;
     const int c = (int)(t % w);
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp)
-      s += (double)part[((size_t)sp * (size_t)n + (size_t)j) * WP + c];
+    const double s = sum_splits(part + (size_t)j * WP + c, nsplit, (size_t)n * WP);
     Z[j * ldz + zcol + c] = (TF)s;
     if (Z2) Z2[j * ldz + zcol + c] = (TF)s;  // kept copy of the sketch (refinement)
   }

@@ -47,8 +47,7 @@ __global__ void k_sketch_reduce_lp(const float* __restrict__ part, int nsplit, i
   if (t < n * w) {
     const int64_t j = t / w;
     const int c = (int)(t % w);
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += (double)part[((size_t)sp * (size_t)n + (size_t)j) * 64 + c];
+    double s = sum_splits(part + (size_t)j * 64 + c, nsplit, (size_t)n * 64);
     if (col_scale) s *= (double)col_scale[j >> 7];
     Z[j * ldz + zcol + c] = (TF)s;
     if (Z2) Z2[j * ldz + zcol + c] = (TF)s;  // kept copy of the sketch (refinement)
