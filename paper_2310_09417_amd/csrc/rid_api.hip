@@ -744,6 +744,9 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
 // Column groups of a Schur launch for a block of w columns: split the
 // workgroup's waves over columns when 64-row workgroups would leave the chip
 // under-filled (fewer than 512 of them, two waves per SIMD).
+// K values per split of the split-K Schur update (k_schur_sk), at least.
+constexpr int kSchurSplitMinK = 128;
+
 int schur_cg(const Plan& P, int w) {
   const int nt = (w + 15) / 16;
   if (ceil_div(P.n, 64) >= 512 || nt < 2) return 1;
@@ -782,6 +785,39 @@ int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, b
   const int cg = schur_cg(P, w);
   const int nt = ((w + 15) / 16 + cg - 1) / cg;  // column tiles per wave
   dim3 grid((unsigned)schur_parts(P, w));
+  // Long K: split-K form (about four workgroups per CU over the 64-row slabs,
+  // each split at least 128 K values, its FP64 partials in the sketch
+  // partials' buffer, which is free between a sketch's reduction and the
+  // next sketch), then the in-place subtraction with the same norm partials.
+  if (kb == 0 && w <= 64 && k >= 2 * kSchurSplitMinK) {
+    const int64_t slabs = ceil_div(P.n, 64);
+    int64_t S = std::min<int64_t>(ceil_div(4 * (int64_t)P.cu, slabs), k / kSchurSplitMinK);
+    S = std::min<int64_t>(S, (int64_t)(P.part_bytes / ((size_t)P.n * 64 * 8)));
+    if (S >= 2) {
+      const int ksplit = (int)(ceil_div(ceil_div(k, S), 64) * 64);
+      S = ceil_div(k, ksplit);
+      const int ntw = (w + 15) / 16;
+      dim3 gsk((unsigned)slabs, (unsigned)S);
+#define RID_SCHUR_SK(NTV)                                                                     \
+  hipLaunchKernelGGL((k_schur_sk<TF, NTV>), gsk, dim3(256), 0, st,                             \
+                     static_cast<const TF*>(W.z), P.ldz, P.n, k, w,                            \
+                     static_cast<const TF*>(W.u2t), P.ldu, ksplit, W.part, W.ctrl)
+      switch (ntw) {
+        case 1: RID_SCHUR_SK(1); break;
+        case 2: RID_SCHUR_SK(2); break;
+        case 3: RID_SCHUR_SK(3); break;
+        default: RID_SCHUR_SK(4); break;
+      }
+#undef RID_SCHUR_SK
+      RID_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_schur_fin<TF>, grid, dim3(256), 0, st, static_cast<TF*>(W.z), P.ldz,
+                         P.n, W.pos, zcol, w, W.part, (int)S, 64 / cg, W.norm, W.ctrl,
+                         norm ? 1 : 0);
+      prof_end(pm, st);
+      RID_LAUNCH_CHECK();
+      return RID_OK;
+    }
+  }
 #define RID_SCHUR(NTV, CGV)                                                                   \
   hipLaunchKernelGGL((k_schur<TF, NTV, false, CGV>), grid, dim3(256), 0, st,                  \
                      static_cast<TF*>(W.z), P.ldz, P.n, W.pos, 0, k, zcol, w,                 \

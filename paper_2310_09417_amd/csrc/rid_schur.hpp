@@ -22,8 +22,8 @@ namespace rid {
 // LK g + LK - 1 of the chunk for its A row and for its U2 columns (LK / 4
 // 16-byte loads each) and MFMA step j takes K = LK g + j from every group (a
 // consistent relabelling of K inside the chunk), so each round trip to
-// memory carries LK K values per operand.  The next chunk's operands are
-// loaded while the current one is multiplied.  FP32: the MFMA accumulator is
+// memory carries LK K values per operand.  Three chunks' operands are in
+// flight while the current one is multiplied.  FP32: the MFMA accumulator is
 // folded into FP64 every 64 K values.
 // ---------------------------------------------------------------------------
 
@@ -59,8 +59,6 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
   }
-  // the operands of chunk c+1 are loaded while chunk c is multiplied (two
-  // register buffers, unrolled by two)
   struct Ops {
     TF a[LK];
     TF b[NT][LK];
@@ -94,14 +92,22 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
   };
   const int kb0 = FROM ? (kb / KCH) * KCH : 0;
   const int nchk = k > kb0 ? (k - kb0 + KCH - 1) / KCH : 0;
-  Ops o0, o1;
-  if (nchk > 0) load_ops(o0, kb0);
-  for (int ci = 0; ci < nchk; ci += 2) {
-    if (ci + 1 < nchk) load_ops(o1, kb0 + KCH * (ci + 1));
-    mma_ops(o0, ci, ci + 1 >= nchk);
-    if (ci + 1 >= nchk) break;
-    if (ci + 2 < nchk) load_ops(o0, kb0 + KCH * (ci + 2));
-    mma_ops(o1, ci + 1, ci + 2 >= nchk);
+  // NB chunks in flight: the grid holds only a few waves per SIMD at the
+  // main path's sizes, so the latency of the L2 operand loads is hidden by
+  // loading NB - 1 chunks ahead (a ring of register buffers, unrolled by NB)
+  constexpr int NB = 4;
+  Ops o[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (u < nchk) load_ops(o[u], kb0 + KCH * u);
+  for (int ci = 0; ci < nchk; ci += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (ci + u < nchk) {
+        mma_ops(o[u], ci + u, ci + u + 1 >= nchk);
+        if (ci + u + NB < nchk) load_ops(o[u], kb0 + KCH * (ci + u + NB));
+      }
+    }
   }
   if (sizeof(TF) == 8) {
 #pragma unroll
@@ -122,6 +128,150 @@ __global__ __launch_bounds__(256) void k_schur(TF* __restrict__ Z, int64_t ldz, 
         *zp = s;
         ss += (double)s * (double)s;
       }
+    }
+  }
+  if (want_norm) {
+    ss = wave_sum(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) normpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K form of the same update for long K (the main path's later blocks):
+// k_schur_sk multiplies L2 U2 over one K range per grid row and leaves FP64
+// partials P[split][row][col] for all n rows; k_schur_fin sums them in split
+// order, subtracts them from the block in place for the non-pivot rows and
+// leaves the FP64 norm partials, one per workgroup of rows_per_wg rows.
+// A workgroup of k_schur_sk owns 64 rows (16 per wave) and all NT column
+// tiles; the U2 values of each 16-K chunk are read once per workgroup into
+// LDS (two stages) and shared by its waves, and each wave keeps its A
+// operands NB chunks ahead in registers.  K is relabelled inside a chunk as
+// in k_schur (lane group g holds K values 4 g .. 4 g + 3, MFMA step j takes
+// K = 4 g + j); FP32 folds into FP64 every 64 K values, and every split
+// starts on a multiple of 64.
+// ---------------------------------------------------------------------------
+template <typename TF, int NT>
+__global__ __launch_bounds__(256) void k_schur_sk(const TF* __restrict__ Z, int64_t ldz, int64_t n,
+                                                  int k, int w, const TF* __restrict__ U2T,
+                                                  int64_t ldu, int ksplit,
+                                                  double* __restrict__ P, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  using M = Mfma<TF>;
+  using acc_t = typename M::acc_t;
+  constexpr int KCH = 16;        // K values per chunk
+  constexpr int FOLD = 64 / KCH;  // chunks per FP64 fold (FP32)
+  constexpr int PB = 20;         // LDS pitch of a column's 16 K values
+  constexpr int NB = 4;          // A chunks in flight per wave
+  __shared__ __attribute__((aligned(16))) TF sB[2][64 * PB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t rbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t arow = rbase + (lane & 15);
+  const bool arow_ok = arow < n;
+  const int kbeg = (int)blockIdx.y * ksplit;
+  const int kend = kbeg + ksplit < k ? kbeg + ksplit : k;
+  const int nchk = kend > kbeg ? (kend - kbeg + KCH - 1) / KCH : 0;
+  const int g = lane >> 4;
+  // B staging: thread t moves the 4 K values 4 (t % 4) .. + 3 of column t / 4
+  const int bcol = tid >> 2, bq = tid & 3;
+  auto load_b = [&](int c, TF out[4]) {
+    load4<TF, false>(U2T, (int64_t)bcol * ldu, kbeg + KCH * c + 4 * bq, 0, kend, bcol < w, out);
+  };
+  auto store_b = [&](int st, const TF v[4]) {
+    TF* d = sB[st] + bcol * PB + 4 * bq;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) d[e] = v[e];
+  };
+  auto load_a = [&](int c, TF out[4]) {
+    load4<TF, false>(Z, arow * ldz, kbeg + KCH * c + 4 * g, 0, kend, arow_ok, out);
+  };
+  acc_t acc[NT];
+  double acc64[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
+  }
+  TF ar[NB][4];
+  TF bn[4];
+  if (nchk > 0) {
+    load_b(0, bn);
+    store_b(0, bn);
+    if (nchk > 1) load_b(1, bn);
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (u < nchk) load_a(u, ar[u]);
+  __syncthreads();
+  for (int c0 = 0; c0 < nchk; c0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int c = c0 + u;
+      if (c < nchk) {
+        const TF* sb = sB[c & 1];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const TF* bp = sb + (16 * t + (lane & 15)) * PB + 4 * g;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[t] = M::op(ar[u][j], bp[j], acc[t]);
+        }
+        if (sizeof(TF) == 4 && ((c % FOLD) == FOLD - 1 || c + 1 == nchk)) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[t][r] += (double)acc[t][r];
+            acc[t] = M::zero();
+          }
+        }
+        if (c + NB < nchk) load_a(c + NB, ar[u]);
+        // the next chunk's U2 values into the other stage (read in chunk
+        // c - 1, which every wave has finished), then the one after it
+        if (c + 1 < nchk) store_b((c + 1) & 1, bn);
+        if (c + 2 < nchk) load_b(c + 2, bn);
+        __syncthreads();
+      }
+    }
+  }
+  if (sizeof(TF) == 8) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[t][r] = (double)acc[t][r];
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rbase + M::row(lane, r);
+      if (row < n && col < w)
+        P[((size_t)blockIdx.y * (size_t)n + (size_t)row) * 64 + col] = acc64[t][r];
+    }
+  }
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_schur_fin(TF* __restrict__ Z, int64_t ldz, int64_t n,
+                                                   const int* __restrict__ pos, int zcol, int w,
+                                                   const double* __restrict__ P, int nsplit,
+                                                   int rows_per_wg, double* __restrict__ normpart,
+                                                   const Ctrl* ctrl, int want_norm) {
+  if (ctrl->done) return;
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  double ss = 0.0;
+  for (int rr = wave; rr < rows_per_wg; rr += 4) {
+    const int64_t row = r0 + rr;
+    if (row < n && lane < w && pos[row] < 0) {
+      double s = 0.0;
+      for (int sp = 0; sp < nsplit; ++sp) s += P[((size_t)sp * (size_t)n + (size_t)row) * 64 + lane];
+      TF* zp = Z + row * ldz + zcol + lane;
+      const TF v = (TF)((double)(*zp) - s);
+      *zp = v;
+      ss += (double)v * (double)v;
     }
   }
   if (want_norm) {

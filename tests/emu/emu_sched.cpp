@@ -134,6 +134,11 @@ void wave_collective(WaveFn fn, const char* name, int arg) {
 }
 
 void run_group(int nthreads, unsigned bx, unsigned gx, void (*body)(void*), void* arg) {
+  run_group2(nthreads, bx, 0, gx, 1, body, arg);
+}
+
+void run_group2(int nthreads, unsigned bx, unsigned by, unsigned gx, unsigned gy,
+                void (*body)(void*), void* arg) {
   if (nthreads < 1 || nthreads > kMaxThreads || nthreads % kWave) die("bad workgroup size", nullptr);
   static Group* G = nullptr;
   if (!G) {
@@ -148,9 +153,9 @@ void run_group(int nthreads, unsigned bx, unsigned gx, void (*body)(void*), void
   }
   g_group = G;
   G->nthreads = nthreads;
-  G->bidx = Dim3{bx, 0, 0};
+  G->bidx = Dim3{bx, by, 0};
   G->bdim = Dim3{(unsigned)nthreads, 1, 1};
-  G->gdim = Dim3{gx, 1, 1};
+  G->gdim = Dim3{gx, gy, 1};
   G->body = body;
   G->body_arg = arg;
   for (int t = 0; t < nthreads; ++t) {

@@ -69,6 +69,9 @@ extern Lane* g_cur;
 // Run body(arg) as one workgroup of nthreads work-items (block index bx of
 // gx).  Returns 0, or aborts with a message on invalid synchronisation.
 void run_group(int nthreads, unsigned bx, unsigned gx, void (*body)(void*), void* arg);
+// The same for block (bx, by) of a gx x gy grid.
+void run_group2(int nthreads, unsigned bx, unsigned by, unsigned gx, unsigned gy,
+                void (*body)(void*), void* arg);
 
 // Called by work-items.
 void syncthreads();

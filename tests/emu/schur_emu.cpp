@@ -6,7 +6,10 @@
 // Input file (little endian): int32 dtype (0 FP64, 1 FP32), n, ldz, k, kb, zcol,
 // w, ldu, nt, from, cg, want_norm; then Z (n x ldz), U2T (w x ldu) in the
 // dtype and pos (n int32).  Output: Z after the kernel, then the grid's FP64
-// norm partials.
+// norm partials.  With a third argument ksplit the split-K form runs instead
+// (rid::k_schur_sk over ceil(n/64) x ceil(k/ksplit) workgroups with nt
+// column tiles, then rid::k_schur_fin with 64/cg rows per workgroup); kb and
+// from must then be 0.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -83,10 +86,55 @@ void body(void* p) {
     dispatch<float>(a);
 }
 
+struct SkArgs {
+  Args* a;
+  int ksplit, nsplit;
+  double* P;
+};
+
+template <typename TF, int NT>
+void launch_sk(SkArgs& s) {
+  Args& a = *s.a;
+  rid::k_schur_sk<TF, NT>(static_cast<const TF*>(a.Z), a.ldz, a.n, a.k, a.w,
+                          static_cast<const TF*>(a.U2T), a.ldu, s.ksplit, s.P, a.ctrl);
+}
+
+template <typename TF>
+void dispatch_sk(SkArgs& s) {
+  switch (s.a->nt) {
+    case 1: return launch_sk<TF, 1>(s);
+    case 2: return launch_sk<TF, 2>(s);
+    case 3: return launch_sk<TF, 3>(s);
+    case 4: return launch_sk<TF, 4>(s);
+  }
+  fprintf(stderr, "schur_emu: no split-K instantiation for nt=%d\n", s.a->nt);
+  exit(2);
+}
+
+void body_sk(void* p) {
+  SkArgs& s = *static_cast<SkArgs*>(p);
+  if (s.a->dtype == 0)
+    dispatch_sk<double>(s);
+  else
+    dispatch_sk<float>(s);
+}
+
+void body_fin(void* p) {
+  SkArgs& s = *static_cast<SkArgs*>(p);
+  Args& a = *s.a;
+  if (a.dtype == 0)
+    rid::k_schur_fin<double>(static_cast<double*>(a.Z), a.ldz, a.n, a.pos, a.zcol, a.w, s.P,
+                             s.nsplit, 64 / a.cg, a.norm, a.ctrl, a.want);
+  else
+    rid::k_schur_fin<float>(static_cast<float*>(a.Z), a.ldz, a.n, a.pos, a.zcol, a.w, s.P,
+                            s.nsplit, 64 / a.cg, a.norm, a.ctrl, a.want);
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 3) return 2;
+  if (argc != 3 && argc != 4) return 2;
+  const int ksplit = argc == 4 ? atoi(argv[3]) : 0;
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 2;
   int32_t h[12];
@@ -105,7 +153,23 @@ int main(int argc, char** argv) {
   double* norm = static_cast<double*>(malloc((size_t)grid * 8));
   rid::Ctrl* ctrl = static_cast<rid::Ctrl*>(calloc(1, sizeof(rid::Ctrl)));
   Args a{Z, ldz, n, pos, kb, k, zcol, w, U2T, ldu, norm, ctrl, want, dtype, nt, from, cg};
-  for (int g = 0; g < grid; ++g) emu::run_group(256, (unsigned)g, (unsigned)grid, &body, &a);
+  if (ksplit > 0) {
+    if (kb != 0 || from != 0) return 2;
+    const int nsplit = (k + ksplit - 1) / ksplit;
+    const int slabs = (n + 63) / 64;
+    const size_t np = (size_t)nsplit * n * 64;
+    double* P = static_cast<double*>(malloc(np * 8));
+    for (size_t i = 0; i < np; ++i) P[i] = __builtin_nan("");  // unwritten partials show up
+    SkArgs s{&a, ksplit, nsplit, P};
+    for (int y = 0; y < nsplit; ++y)
+      for (int x = 0; x < slabs; ++x)
+        emu::run_group2(256, (unsigned)x, (unsigned)y, (unsigned)slabs, (unsigned)nsplit,
+                        &body_sk, &s);
+    for (int g = 0; g < grid; ++g) emu::run_group(256, (unsigned)g, (unsigned)grid, &body_fin, &s);
+    free(P);
+  } else {
+    for (int g = 0; g < grid; ++g) emu::run_group(256, (unsigned)g, (unsigned)grid, &body, &a);
+  }
   FILE* o = fopen(argv[2], "wb");
   if (!o) return 2;
   fwrite(Z, es, (size_t)n * ldz, o);

@@ -3,7 +3,9 @@ the workgroup emulation under AddressSanitizer, against the same product
 formed by NumPy: S = Z(non-pivots, block) - Z(non-pivots, K) U2(K, block) in
 place, pivot rows untouched, and the FP64 sums of S^2 per workgroup, for
 the K ranges, column groups and tile counts the library launches
-(including a K range that starts at kb, ragged K and ragged row counts)."""
+(including a K range that starts at kb, ragged K and ragged row counts).
+The split-K form (k_schur_sk's FP64 partials per K range, summed in split
+order and subtracted by k_schur_fin) is checked the same way."""
 import os
 import struct
 import subprocess
@@ -28,7 +30,7 @@ def exe(tmp_path_factory):
     return out
 
 
-def _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, frm, dtype):
+def _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, frm, dtype, ksplit=0):
     n, ldz = Z.shape
     ldu = U2T.shape[1]
     with tempfile.TemporaryDirectory() as td:
@@ -40,7 +42,8 @@ def _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, frm, dtype):
             f.write(np.ascontiguousarray(U2T, dtype=dtype).tobytes())
             f.write(np.asarray(pos, dtype="<i4").tobytes())
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
-        r = subprocess.run([exe, fin, fout], env=env, capture_output=True, text=True, timeout=600)
+        cmd = [exe, fin, fout] + ([str(ksplit)] if ksplit else [])
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode == 0, r.stderr[-4000:]
         data = open(fout, "rb").read()
     es = np.dtype(dtype).itemsize
@@ -55,9 +58,25 @@ CASES = [(300, 100, 0, 64, 1, 4), (1200, 257, 0, 64, 1, 4), (700, 130, 0, 64, 2,
          (400, 150, 37, 16, 1, 1), (333, 90, 64, 8, 1, 1)]
 
 
+# split-K: (n, k, w, nt, cg, ksplit), splits on multiples of 64, a ragged last
+# split, and the column tiles and row groups of the library's launches
+SK_CASES = [(300, 256, 64, 4, 4, 128), (1000, 300, 64, 4, 1, 128), (517, 400, 48, 3, 2, 192),
+            (200, 129, 16, 1, 4, 64), (700, 640, 33, 3, 1, 256)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n,k,w,nt,cg,ksplit", SK_CASES)
+def test_split_k_schur_matches_numpy(exe, dtype, n, k, w, nt, cg, ksplit):
+    _check(exe, dtype, n, k, 0, w, nt, cg, ksplit)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n,k,kb,w,nt,cg", CASES)
 def test_schur_kernel_matches_numpy(exe, dtype, n, k, kb, w, nt, cg):
+    _check(exe, dtype, n, k, kb, w, nt, cg, 0)
+
+
+def _check(exe, dtype, n, k, kb, w, nt, cg, ksplit):
     rng = np.random.default_rng(n + k + w)
     zcol = k
     ldz = ((k + w + 3) // 4) * 4
@@ -68,7 +87,7 @@ def test_schur_kernel_matches_numpy(exe, dtype, n, k, kb, w, nt, cg):
     pos = -np.ones(n, dtype=np.int64)
     piv = rng.choice(n, size=k, replace=False)
     pos[piv] = np.arange(k)
-    Zo, norm = _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, kb > 0, dtype)
+    Zo, norm = _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, kb > 0, dtype, ksplit)
     Z64 = Z.astype(np.float64)
     rows = pos < 0
     K = slice(kb, k)
