@@ -363,8 +363,9 @@ int rid_batched_autotune(int32_t nblk, const void* const* A, const int64_t* lda,
 /*
  * Test export: materialises the Gaussian embedding block
  *   out[c * m + i] = omega(c0 + c, i), 0 <= c < w, 0 <= i < m
- * in the given dtype (device buffer).  The decomposition never stores Omega;
- * this exists so the generator can be checked on its own.
+ * in the given dtype (device buffer).  The decomposition keeps Omega only
+ * as the workspace tiles of one sketch launch; this exists so the generator
+ * can be checked on its own.
  */
 int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtype, void* out,
                        hipStream_t stream);
@@ -372,8 +373,9 @@ int rid_debug_gaussian(uint64_t seed, int64_t c0, int64_t w, int64_t m, int dtyp
 /*
  * Test export: the sketch alone, Yt = (Omega(c0:c0+w, :) A)^T stored as an
  * n x w row-major matrix with leading dimension ldy (device, dtype), using
- * the same kernels as the decomposition.  Requires a workspace of
- * rid_workspace_bytes(m, n, w, w, cfg) bytes.  w <= 128.
+ * the same kernels as the decomposition (with c0 == 0 the launch also sums
+ * ||A||_F^2, as the first sketch of a decomposition does).  Requires a
+ * workspace of rid_workspace_bytes(m, n, w, w, cfg) bytes.  w <= 128.
  */
 int rid_debug_sketch(const void* A, int64_t m, int64_t n, int64_t lda, int64_t c0, int64_t w,
                      const rid_config* cfg, void* Yt, int64_t ldy, void* work, size_t work_bytes,

@@ -150,32 +150,34 @@ __device__ __forceinline__ void split3_bf16x2(float a, float b, uint32_t& h, uin
   l = pack_bf16x2(ra - __uint_as_float(m << 16), rb - __uint_as_float(m & 0xffff0000u));
 }
 
-// Omega (row-major, mpad x 64, FP32) as the BF16 operand tiles of the split
-// sketch: for each chunk of 32 rows, vector tile a (16 vectors) and part p
-// (hi, mid, lo), 64 lanes x 16 bytes; lane i + 16 g holds vector 16 a + i,
+// Omega (row-major, mpad x 16 MT, FP32) as the BF16 operand tiles of the
+// split sketch: for each chunk of 32 rows, vector tile a (16 vectors) and part
+// p (hi, mid, lo), 64 lanes x 16 bytes; lane i + 16 g holds vector 16 a + i,
 // rows 8 g .. 8 g + 7 of the chunk, two per dword (even row in the low half).
-// Record (c, a, p) starts at dword (12 c + 3 a + p) * 256.  One thread per
+// Record (c, a, p) starts at dword (3 MT c + 3 a + p) * 256.  One thread per
 // (chunk, tile, lane).
+template <int MT>
 __global__ __launch_bounds__(256) void k_omega_split(const float* __restrict__ om, int64_t mpad,
                                                      uint32_t* __restrict__ oms,
                                                      const Ctrl* __restrict__ ctrl) {
   if (ctrl && ctrl->done) return;
+  constexpr int WP = 16 * MT;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (mpad / 32) * 4 * 64) return;
-  const int lane = (int)(t & 63), a = (int)((t >> 6) & 3);
-  const int64_t c = t >> 8;
+  if (t >= (mpad / 32) * MT * 64) return;
+  const int lane = (int)(t & 63), a = (int)((t >> 6) % MT);
+  const int64_t c = (t >> 6) / MT;
   const int i = lane & 15, g = lane >> 4;
-  const float* src = om + (32 * c + 8 * g) * 64 + 16 * a + i;
+  const float* src = om + (32 * c + 8 * g) * WP + 16 * a + i;
   u32x4 h, md, lo;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     uint32_t x, y, z;
-    split3_bf16x2(src[(2 * d) * 64], src[(2 * d + 1) * 64], x, y, z);
+    split3_bf16x2(src[(2 * d) * WP], src[(2 * d + 1) * WP], x, y, z);
     h[d] = x;
     md[d] = y;
     lo[d] = z;
   }
-  u32x4* dst = reinterpret_cast<u32x4*>(oms) + (12 * c + 3 * a) * 64 + lane;
+  u32x4* dst = reinterpret_cast<u32x4*>(oms) + (3 * MT * c + 3 * a) * 64 + lane;
   dst[0] = h;
   dst[64] = md;
   dst[128] = lo;
@@ -224,12 +226,16 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
   // rows][32 columns]), Omega shared ([stage][KC rows][LDO]).  The other
   // workgroups use the first two Omega stages as a double buffer.
   constexpr bool DMA = sizeof(TC) == 4 && NQ == 2 && KC == 32;
-  // FP32 interior workgroups of a 64-vector block multiply on the BF16 matrix
-  // cores through the three-part split (split3_bf16x2), with Omega's parts
-  // from oms staged in sO (two 12 KB stages)
+  // FP32 workgroups of a 64-vector block multiply on the BF16 matrix cores
+  // through the three-part split (split3_bf16x2), with Omega's parts from
+  // oms staged in sO: A three stages deep, Omega two (12 KB each).
   constexpr bool SPLIT = DMA && MT == 4;
-  __shared__ __attribute__((aligned(16))) TC sA[DMA ? 3 * NW * KC * 32 : 1];
-  __shared__ __attribute__((aligned(16))) TC sO[3 * KC * LDO];
+  constexpr int NSA = 3;          // A stages (DMA paths)
+  constexpr int NSO = 2;          // Omega record stages (split path)
+  constexpr int OREC = 3 * MT;    // Omega records per chunk (split path)
+  constexpr int SO_N = (SPLIT && NSO * OREC * 256 > 3 * KC * LDO) ? NSO * OREC * 256 : 3 * KC * LDO;
+  __shared__ __attribute__((aligned(16))) TC sA[DMA ? NSA * NW * KC * 32 : 1];
+  __shared__ __attribute__((aligned(16))) TC sO[SO_N];
   TC* const om[2] = {sO, sO + KC * LDO};
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -241,9 +247,20 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
   const int nch = (int)((r_end - r_begin + KC - 1) / KC);
   // Interior workgroups (all CPW columns, all WP vectors, whole chunks, and
   // one more chunk of rows after the range so that prefetching it stays
-  // inside A) run a loop without bounds tests.
-  const bool fast = VEC && w == WP && (int64_t)blockIdx.x * CPW + CPW <= n &&
-                    (r_end - r_begin) % KC == 0 && r_end + KC <= m;
+  // inside A) run a loop without bounds tests.  The split path streams only
+  // whole chunks of its range, loads a ragged last chunk through masked
+  // loads, and takes any vector count (Omega's tiles are zero past w); it
+  // also takes the last column strip when n is a multiple of 4 and no norm
+  // is summed (lanes past n copy the strip's last valid columns, whose
+  // products are never stored).
+  // (The direct copies move 16 bytes per lane: rows 16-byte aligned.)
+  const bool strip_full = (int64_t)blockIdx.x * CPW + CPW <= n;
+  const bool rows16 = !DMA || lda % 4 == 0;
+  const bool fast =
+      SPLIT ? (VEC && rows16 && (strip_full || (!NORM && n % 4 == 0 && n >= 4)) &&
+               r_end - r_begin >= KC)
+            : (VEC && rows16 && w == WP && strip_full && (r_end - r_begin) % KC == 0 &&
+               r_end + KC <= m);
 
   acc_t acc[MT][NQ];
   double acc64[MT][NQ][4];
@@ -284,53 +301,83 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
     // this lambda is instantiated)
     if constexpr (SPLIT) {
       if constexpr (FAST) {
-        // Per chunk and wave: 4 copies of A (8 rows x 32 columns each, this
-        // wave's columns) into a three-stage ring, and 3 of the 12 Omega
-        // operand records (1 KB each) into a two-stage ring.  Issue order per
-        // chunk c (after the barrier that ends chunk c-1's reads): Omega of
-        // chunk c+1, then A of chunk c+2, so that vmcnt(4) at the top of
-        // chunk c+1 means its Omega and A have landed while A of c+3 may still
-        // be in flight.  Past the end the last chunk is copied again into a
-        // stage no later chunk reads, so the count per chunk stays fixed.
+        // Per chunk and wave: NA copies of A (8 rows x 32 columns each, this
+        // wave's columns) into an NSA-stage ring, and ORW of the chunk's OREC
+        // Omega operand records (1 KB each) into an NSO-stage ring.  Issue
+        // order per chunk c (after the barrier that ends chunk c-1's reads):
+        // Omega of chunk c + DO, then A of chunk c + DA (DO = NSO - 1,
+        // DA = NSA - 1 > DO), each into the stage chunk c-1 used.  At the top
+        // of chunk c, Omega of chunk c was the last of chunk c's copies to be
+        // issued; WAITN copies were issued after it, so vmcnt(WAITN) means
+        // chunk c has landed in this wave.  Past the last whole chunk A's
+        // copies repeat that chunk, and past the last chunk Omega's repeat
+        // it, into stages no later chunk reads, so the count per chunk stays
+        // fixed.  A ragged last chunk is loaded by masked loads into its
+        // stage (whose last copy landed before Omega of that chunk did).
         constexpr int NA = KC / 8;
-        constexpr int OREC = 12;                      // Omega records per chunk
         constexpr int ORW = (OREC + NW - 1) / NW;     // Omega copies per wave
-        static_assert(2 * OREC * 1024 <= (int)sizeof(sO), "split stages");
+        constexpr int DA = NSA - 1, DO = NSO - 1;
+        constexpr int WAITN = NA + (DO - 1) * (ORW + NA);
+        static_assert(DA > DO && DO >= 1, "ring distances");
+        static_assert(NSO * OREC * 256 <= SO_N, "split stages");
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         const int64_t cw = (int64_t)blockIdx.x * CPW + wv * 32;
         const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
+        // this lane's 4 columns; past n (last strip, n a multiple of 4) the
+        // strip's last 4 columns instead
+        int64_t col4 = cw + 4 * (lane & 7);
+        if (col4 + 4 > n) col4 = n - 4;
+        const int nwhole = (int)((r_end - r_begin) / KC);  // >= 1
         const TC* pa[NA];
   #pragma unroll
-        for (int i = 0; i < NA; ++i)
-          pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + cw + 4 * (lane & 7);
+        for (int i = 0; i < NA; ++i) pa[i] = A + (r_begin + 8 * i + (lane >> 3)) * lda + col4;
         // wave wv copies records wv, wv + NW, ...; where that passes the last
         // record it copies record wv again (same bytes to the same place), so
         // that every wave issues ORW copies
         const uint32_t* po = oms + (r_begin / KC) * OREC * 256 + 4 * lane;
         auto orec = [&](int i) { return wv + NW * i < OREC ? wv + NW * i : wv; };
+        auto a_stage = [&](int st) {
+          return sa + (uint32_t)(((st * NW + wv) * KC) * 32 * 4);
+        };
         auto copy_a = [&](int chunk, int st) {
-          const int64_t da = (int64_t)chunk * KC * lda;
+          const int64_t da = (int64_t)(chunk < nwhole ? chunk : nwhole - 1) * KC * lda;
   #pragma unroll
-          for (int i = 0; i < NA; ++i)
-            copy16_to_lds(pa[i] + da, sa + (uint32_t)(((st * NW + wv) * KC + 8 * i) * 32 * 4));
+          for (int i = 0; i < NA; ++i) copy16_to_lds(pa[i] + da, a_stage(st) + (uint32_t)(8 * i * 32 * 4));
         };
         auto copy_o = [&](int chunk, int st) {
+          const int cc = chunk < nch ? chunk : nch - 1;
   #pragma unroll
           for (int i = 0; i < ORW; ++i)
-            copy16_to_lds(po + ((int64_t)chunk * OREC + orec(i)) * 256,
+            copy16_to_lds(po + ((int64_t)cc * OREC + orec(i)) * 256,
                           so + (uint32_t)((st * OREC + orec(i)) * 1024));
         };
         // lane (j, g) = (lane % 16, lane / 16): rows 8 g .. 8 g + 7, columns 2 j, 2 j + 1
         const uint32_t lane_off = (uint32_t)((8 * (lane >> 4) * 32 + 2 * (lane & 15)) * 4);
-        copy_a(0, 0);
-        copy_o(0, 0);
-        copy_a(nch > 1 ? 1 : 0, 1);
+        // prologue: the copies of chunks j = -DA .. -1 of the steady loop
+  #pragma unroll
+        for (int j = -DA; j < 0; ++j) {
+          if (j + DO >= 0) copy_o(j + DO, j + DO);
+          copy_a(j + DA, j + DA);
+        }
         for (int c = 0; c < nch; ++c) {
-          vm_barrier<NA>();  // chunk c's A and Omega landed in every wave; chunk c-1's stages free
-          copy_o(c + 1 < nch ? c + 1 : c, (c + 1) & 1);
-          copy_a(c + 2 < nch ? c + 2 : c, (c + 2) % 3);
+          vm_barrier<WAITN>();  // chunk c landed in every wave; chunk c-1's stages free
+          copy_o(c + DO, (c + DO) % NSO);
+          copy_a(c + DA, (c + DA) % NSA);
+          if (c == nwhole) {
+            // ragged last chunk: rows past r_end are zero
+            const int64_t r0 = r_begin + (int64_t)c * KC;
+  #pragma unroll
+            for (int i = 0; i < NA; ++i) {
+              const int64_t row = r0 + 8 * i + (lane >> 3);
+              floatx4 v = {0.f, 0.f, 0.f, 0.f};
+              if (row < r_end) v = *reinterpret_cast<const floatx4*>(A + row * lda + col4);
+              *reinterpret_cast<floatx4*>(sA + (((c % NSA) * NW + wv) * KC + 8 * i) * 32 +
+                                          4 * lane) = v;
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          }
           floatx2 x[8];
-          lds_read8x8_rows(sa + (uint32_t)((((c % 3) * NW + wv) * KC * 32) * 4) + lane_off, x);
+          lds_read8x8_rows(a_stage(c % NSA) + lane_off, x);
           if (NORM) {
   #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -351,17 +398,17 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
               bp[1][q][d] = md;
               bp[2][q][d] = lo;
             }
-          // A operands (Omega) of tile a: parts hi, mid, lo
+          // A operands (Omega) of tile a: parts hi, mid, lo; six partial
+          // products per accumulator, smallest first: (Omega part, A part)
           const u32x4* osrc = reinterpret_cast<const u32x4*>(
-              reinterpret_cast<const unsigned char*>(sO) + (c & 1) * OREC * 1024);
+              reinterpret_cast<const unsigned char*>(sO) + (c % NSO) * OREC * 1024);
+          constexpr int PO[6] = {2, 1, 0, 1, 0, 0};
+          constexpr int PA[6] = {0, 1, 2, 0, 1, 0};
           u32x4 op[3][MT];
   #pragma unroll
           for (int a = 0; a < MT; ++a)
   #pragma unroll
             for (int p = 0; p < 3; ++p) op[p][a] = osrc[(3 * a + p) * 64 + lane];
-          // six partial products, smallest first: (Omega part, A part)
-          constexpr int PO[6] = {2, 1, 0, 1, 0, 0};
-          constexpr int PA[6] = {0, 1, 2, 0, 1, 0};
   #pragma unroll
           for (int t = 0; t < 6; ++t)
   #pragma unroll
@@ -598,6 +645,163 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
       double t = 0.0;
       for (int wv = 0; wv < NW; ++wv) t += red[wv];
       fro_part[blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 sketch of two 64-vector blocks in one pass over A (k_sketch_pair):
+// partial sums over row splits as k_sketch's split path computes them, for
+// 128 vectors.  Two 256-thread workgroups per CU, 64 columns of A per
+// workgroup; wave w owns columns 32 (w % 2) .. + 31 of the strip and vectors
+// 64 (w / 2) .. + 63, i.e. exactly the work of a k_sketch wave.  Each chunk
+// of A (32 rows x 64 columns) is copied into LDS once and read by the two
+// waves of its column group; Omega's 24 operand records per chunk (both
+// vector halves) are copied once and each wave reads its half's 12.  A is
+// staged three chunks deep, Omega two (72 KB of LDS per workgroup).  Every
+// row split is at least one chunk long: the last split runs to row m (up to
+// rows_per_split + 31 rows), whose ragged last chunk is loaded through
+// masked loads.  Requires 16-byte aligned rows (lda % 4 == 0), n a multiple
+// of 4 (lanes past n copy the strip's last 4 columns, whose products are
+// never stored) and m >= 32.  Partials part[split][j][c] (FP32, c < 128) as
+// k_sketch's.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256, 2) void k_sketch_pair(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+    const uint32_t* __restrict__ oms, int64_t rows_per_split, float* __restrict__ part,
+    const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  constexpr int CGS = 2;                 // column groups of 32 per workgroup
+  constexpr int KC = 32, NW = 2 * CGS, NQ = 2;
+  constexpr int NAW = 2;                 // A copies (8 rows x 32 columns) per wave and chunk
+  constexpr int OREC = 24, ORW = OREC / NW;
+  constexpr int NSA = 3, NSO = 2, DA = NSA - 1, DO = NSO - 1;
+  constexpr int WAITN = NAW + (DO - 1) * (ORW + NAW);
+  constexpr int ASTAGE = CGS * KC * 32;  // floats per A stage
+  __shared__ __attribute__((aligned(16))) float sA[NSA * ASTAGE];
+  __shared__ __attribute__((aligned(16))) uint32_t sO[NSO * OREC * 256];
+  using M = Mfma<float>;
+  using acc_t = typename M::acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int cg = wv % CGS, vh = wv / CGS;
+  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r_end = blockIdx.y + 1 == gridDim.y ? m : r_begin + rows_per_split;
+  const int nwhole = (int)((r_end - r_begin) / KC);  // >= 1
+  const int nch = (int)((r_end - r_begin + KC - 1) / KC);
+  const int64_t cw = (int64_t)blockIdx.x * (32 * CGS) + cg * 32;
+  int64_t col4 = cw + 4 * (lane & 7);
+  if (col4 + 4 > n) col4 = n - 4;
+  const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
+  auto a_stage = [&](int st) { return sa + (uint32_t)((st * ASTAGE + cg * KC * 32) * 4); };
+  // this wave copies row groups 2 vh and 2 vh + 1 (rows 8 i + lane / 8) of its column group
+  const float* pa[NAW];
+#pragma unroll
+  for (int i = 0; i < NAW; ++i)
+    pa[i] = A + (r_begin + 8 * (NAW * vh + i) + (lane >> 3)) * lda + col4;
+  auto copy_a = [&](int chunk, int st) {
+    const int64_t da = (int64_t)(chunk < nwhole ? chunk : nwhole - 1) * KC * lda;
+#pragma unroll
+    for (int i = 0; i < NAW; ++i)
+      copy16_to_lds(pa[i] + da, a_stage(st) + (uint32_t)(8 * (NAW * vh + i) * 32 * 4));
+  };
+  // records wv, wv + NW, ... of the chunk
+  const uint32_t* po = oms + (r_begin / KC) * OREC * 256 + 4 * lane;
+  auto copy_o = [&](int chunk, int st) {
+    const int cc = chunk < nch ? chunk : nch - 1;
+#pragma unroll
+    for (int i = 0; i < ORW; ++i)
+      copy16_to_lds(po + ((int64_t)cc * OREC + wv + NW * i) * 256,
+                    so + (uint32_t)((st * OREC + wv + NW * i) * 1024));
+  };
+  acc_t acc[4][NQ];
+  double acc64[4][NQ][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      acc[a][q] = M::zero();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
+    }
+  const uint32_t lane_off = (uint32_t)((8 * (lane >> 4) * 32 + 2 * (lane & 15)) * 4);
+#pragma unroll
+  for (int j = -DA; j < 0; ++j) {
+    if (j + DO >= 0) copy_o(j + DO, j + DO);
+    copy_a(j + DA, j + DA);
+  }
+  for (int c = 0; c < nch; ++c) {
+    vm_barrier<WAITN>();  // chunk c landed in every wave; chunk c-1's stages free
+    copy_o(c + DO, (c + DO) % NSO);
+    copy_a(c + DA, (c + DA) % NSA);
+    if (c == nwhole) {
+      // ragged last chunk (rows past m are zero); the two waves of a column
+      // group write its halves, so a barrier follows
+      const int64_t r0 = r_begin + (int64_t)c * KC;
+#pragma unroll
+      for (int i = 0; i < NAW; ++i) {
+        const int rg = NAW * vh + i;
+        const int64_t row = r0 + 8 * rg + (lane >> 3);
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (row < r_end) v = *reinterpret_cast<const floatx4*>(A + row * lda + col4);
+        *reinterpret_cast<floatx4*>(sA + (c % NSA) * ASTAGE + (cg * KC + 8 * rg) * 32 + 4 * lane) =
+            v;
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+    floatx2 x[8];
+    lds_read8x8_rows(a_stage(c % NSA) + lane_off, x);
+    u32x4 bp[3][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        uint32_t h, md, lo;
+        split3_bf16x2(q ? x[2 * d].y : x[2 * d].x, q ? x[2 * d + 1].y : x[2 * d + 1].x, h, md, lo);
+        bp[0][q][d] = h;
+        bp[1][q][d] = md;
+        bp[2][q][d] = lo;
+      }
+    const u32x4* osrc = reinterpret_cast<const u32x4*>(sO + (c % NSO) * OREC * 256) + 12 * vh * 64;
+    u32x4 op[3][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) op[p][a] = osrc[(3 * a + p) * 64 + lane];
+    // six partial products, smallest first: (Omega part, A part)
+    constexpr int PO[6] = {2, 1, 0, 1, 0, 0};
+    constexpr int PA[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[a][q] = mfma_bf16x32(op[PO[t]][a], bp[PA[t]][q], acc[a][q]);
+    // FP32 sums of 64 rows (two chunks) are folded into FP64
+    if ((c & 1) || c + 1 == nch) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
+          acc[a][q] = M::zero();
+        }
+    }
+  }
+  // every copy has landed before the workgroup's LDS is released
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  const int64_t colq = cw + 2 * (lane & 15);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int64_t col = colq + q;
+    if (col < n) {
+      float* dst = part + ((size_t)blockIdx.y * (size_t)n + (size_t)col) * 128 + 64 * vh;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = (float)acc64[a][q][r];
     }
   }
 }

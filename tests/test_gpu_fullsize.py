@@ -80,6 +80,29 @@ def test_sampled_sketch_entries(setup, orc):
     assert np.all(np.abs(Yt[cols].T - Yo) <= 16 * 2.0 ** -24 * math.sqrt(64) * scale)
 
 
+def test_sampled_wide_sketch_entries(setup, orc):
+    """The 128-vector pass that the decomposition runs for each pair of
+    blocks after the first (vectors 64..191, no norm pass): 12 row splits of
+    3872 rows, the last running to row 50000 and ending in a ragged 16-row
+    chunk, and a last column strip of 32 columns whose other lanes copy
+    clamped columns.  Sampled columns include that strip."""
+    torch, rid, A32, sig, g = setup
+    rng = np.random.default_rng(1)
+    cols = np.sort(np.concatenate([rng.choice(N - 32, size=44, replace=False),
+                                   [N - 32, N - 17, N - 2, N - 1]]))
+    Yt = rid.debug_sketch(A32, SEED, B, 2 * B).cpu().numpy().astype(np.float64)  # n x 128
+    Asub = A32[:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
+    Yo = orc.sketch(Asub, SEED, B, 2 * B)  # 128 x 48
+    om = orc.omega(SEED, B, 2 * B, M)
+    scale = np.outer(np.linalg.norm(om, axis=1), np.linalg.norm(Asub, axis=0))
+    assert np.all(np.abs(Yt[cols].T - Yo) <= 16 * 2.0 ** -24 * math.sqrt(64) * scale)
+    # the same vectors as the two 64-vector blocks of the decomposition: the
+    # second block's sketch through its own pass agrees to rounding
+    Y2 = rid.debug_sketch(A32, SEED, 2 * B, B).cpu().numpy().astype(np.float64)
+    sc2 = np.outer(np.linalg.norm(Asub, axis=0), np.linalg.norm(om[B:], axis=1))
+    assert np.all(np.abs(Yt[cols, B:] - Y2[cols]) <= 32 * 2.0 ** -24 * math.sqrt(64) * sc2)
+
+
 def test_first_pivots_match_oracle(setup, orc):
     torch, rid, A32, sig, g = setup
     Ah = A32.double().cpu().numpy()

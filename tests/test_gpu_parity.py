@@ -69,11 +69,21 @@ def test_gaussian_matches_oracle(torch, rid, orc, m, w, c0):
 @pytest.mark.parametrize("m,n,w,c0,spread", [(1, 1, 1, 0, 0), (100, 37, 13, 2, 0),
                                              (1000, 333, 64, 64, 0), (2000, 1000, 120, 0, 0),
                                              (777, 1500, 20, 100, 0), (5000, 600, 128, 9, 0),
-                                             (3000, 2048, 64, 5, 0), (2500, 1100, 64, 0, 25)])
+                                             (3000, 2048, 64, 5, 0), (2500, 1100, 64, 0, 25),
+                                             (3001, 1000, 128, 64, 0), (4100, 3080, 100, 5, 0),
+                                             (2500, 1101, 128, 3, 0), (3333, 1024, 128, 0, 25),
+                                             (6000, 2052, 96, 128, 25), (3001, 8004, 128, 64, 0),
+                                             (4001, 6000, 100, 0, 0), (2023, 12000, 128, 3, 25)])
 def test_sketch_matches_oracle(torch, rid, orc, dtype, m, n, w, c0, spread):
     """Device sketch against the oracle's entry by entry.  spread > 0: entries
     of magnitudes 10^U(-spread, spread), so that within a column the FP32
-    three-part BF16 products meet values many binades apart."""
+    three-part BF16 products meet values many binades apart.  FP32 blocks of
+    65-128 vectors without the norm pass (c0 > 0) run the two-block kernel
+    where n % 4 == 0, the others two 64-vector launches.  The cases cover
+    ragged last row chunks (m % 32 != 0, loaded through masked loads), a last
+    column strip of 4-104 columns (clamped copies), n % 4 != 0, vector counts
+    below 128, and (3001 x 8004, 2023 x 12000 on a 256-CU device) row splits
+    of 128-192 rows."""
     _say("sketch", dtype, m, n, w, c0, spread)
     rng = np.random.default_rng(m * 7 + n)
     A = rng.standard_normal((m, n))
