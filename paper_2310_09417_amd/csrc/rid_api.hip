@@ -130,7 +130,7 @@ class SideLease {
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
 enum KClass {
   KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA,
-  KC_RESID, KC_N
+  KC_RESID, KC_SKETCH2, KC_N
 };
 
 struct Profiler {
@@ -608,7 +608,7 @@ int launch_sketch_pair(const Plan& P, const Ws& W, const void* A, int64_t lda, u
                      dim3(256), 0, st, reinterpret_cast<const float*>(om), mpad, oms, ctrl);
   prof_end(pm, st);
   RID_LAUNCH_CHECK();
-  pm = prof_begin(KC_SKETCH, st);
+  pm = prof_begin(KC_SKETCH2, st);
   hipLaunchKernelGGL(k_sketch_pair, dim3((unsigned)g.ncolg, (unsigned)g.nsplit), dim3(256), 0, st,
                      static_cast<const float*>(A), P.m, P.n, lda, oms, g.rows_per_split,
                      reinterpret_cast<float*>(W.part), ctrl);
