@@ -268,34 +268,27 @@ def main():
     for name, (tms, cnt) in prof.items():
         log(f"[bench]   {name:14s} {tms / args.steps:9.3f} ms/step over {cnt // args.steps} launches")
 
-    # dominant kernel and its roofline: after the first block (64 vectors with
-    # the norm pass, k_sketch) the decomposition sketches blocks in pairs,
-    # 128 vectors per pass over A (k_sketch_pair)
+    # dominant kernel and its roofline
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    pair = prof.get("sketch_pair", (0.0, 0))[1] > 0
-    cls = "sketch_pair" if pair else "sketch"
-    sk_ms, sk_cnt = prof[cls]
+    sk_ms, sk_cnt = prof["sketch"]
     sk_avg_s = sk_ms * 1e-3 / max(sk_cnt, 1)
-    wl = 2 * b if pair else b  # sketch vectors per launch
-    sk_flops = 2.0 * wl * m * n  # per launch: wl sketch vectors over all of A
-    # The FP32 sketch multiplies on the BF16 matrix cores through an exact
-    # three-part split (six BF16 products per FP32 one); its roofline is HBM,
-    # algorithmic bytes = one pass over A per launch.  The FP32-equivalent
+    sk_flops = 2.0 * b * m * n  # per launch: one block of b sketch vectors over all of A
+    # The 64-vector FP32 sketch multiplies on the BF16 matrix cores through an
+    # exact three-part split (six BF16 products per FP32 one); its roofline is
+    # HBM, algorithmic bytes = one pass over A per launch.  The FP32-equivalent
     # rate against the FP32 MFMA peak and the BF16 rate actually issued are
     # reported beside it.
     sk_bytes = 4.0 * m * n
     roof = {
-        "kernel": ("k_sketch_pair (FP32 A, 128 vectors per pass" if pair else
-                   "k_sketch (FP32 A, 64 vectors") +
-                  ": BF16 16x16x32 MFMA on the exact three-part split; "
+        "kernel": "k_sketch (FP32 A, 64 vectors: BF16 16x16x32 MFMA on the exact three-part split; "
                   "A and Omega's operand records staged into LDS by direct copies)",
-        "dominant": dom == cls,
+        "dominant": dom == "sketch",
         "bound": "hbm",
         "achieved": sk_bytes / sk_avg_s / 1e9,
         "peak": PEAK["hbm"] / 1e9,
         "unit": "GB/s",
         "frac": (sk_bytes / sk_avg_s) / PEAK["hbm"],
-        "traffic": traffic_from_profiles("k_sketch_pair" if pair else "k_sketch"),
+        "traffic": traffic_from_profiles("k_sketch"),
         "avg_launch_ms": sk_avg_s * 1e3,
         "algorithmic_bytes_per_launch": sk_bytes,
         "algorithmic_flops_per_launch": sk_flops,

@@ -130,7 +130,7 @@ class SideLease {
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
 enum KClass {
   KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA,
-  KC_RESID, KC_SKETCH2, KC_N
+  KC_RESID, KC_N
 };
 
 struct Profiler {
@@ -203,18 +203,6 @@ SketchGeom sketch_geom(int64_t m, int64_t n, int w, rid_dtype dt, int cu) {
   }
   g.rows_per_split = ceil_div(ceil_div(m, best_ns), g.kc) * g.kc;
   g.nsplit = ceil_div(m, g.rows_per_split);
-  return g;
-}
-
-// Geometry of k_sketch_pair (below).
-SketchGeom sketch_geom_pair(int64_t m, int64_t n, int cu) {
-  // 64-column strips, two resident workgroups per CU: the 64-vector rule
-  // over 2n columns (twice as many strips)
-  SketchGeom g = sketch_geom(m, 2 * n, 64, RID_F32, cu);
-  g.mt = 8;
-  g.wp = 128;
-  g.ncolg = ceil_div(n, 64);
-  g.nsplit = std::max<int64_t>(1, m / g.rows_per_split);
   return g;
 }
 
@@ -360,11 +348,6 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
     SketchGeom g = sketch_geom(m, n, (int)std::min<int64_t>(wmax, 64), dt, di.cu);
     pb = (size_t)g.nsplit * (size_t)n * g.wp * 8;
     fc = (size_t)(g.nsplit * g.ncolg);
-    if (dt == RID_F32 && side == RID_COLUMNS) {
-      // k_sketch_pair: 128 vectors (FP32 partials)
-      SketchGeom gw = sketch_geom_pair(m, n, di.cu);
-      pb = std::max(pb, (size_t)gw.nsplit * (size_t)n * 128 * 4);
-    }
   }
   P.part_bytes = pb;
   P.fro_count = fc;
@@ -394,17 +377,15 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   P.xwords_end = o;
   P.o_linv = take((size_t)kcap * P.ldl * es);
   P.o_mtmp = take((size_t)wmax * P.ldl * es);
-  // Omega of one sketch launch (at most 64 vectors; 128 for k_sketch_pair),
-  // rows padded to 64; in FP32 followed by its three-part BF16 operand form
-  // (k_omega_split, 6 bytes per row and vector)
+  // Omega of one sketch launch (at most 64 vectors), rows padded to 64; in
+  // FP32 followed by its three-part BF16 operand form (k_omega_split, 384
+  // bytes per row)
   // (the low-precision forms: the FP32 Gaussian entries, then their records
   // in the format, lp_record_bytes per 32 rows)
   P.o_omega = take(low_precision(at)
                        ? (size_t)align_up((size_t)m, 64) * 64 * 4 +
                              (size_t)align_up((size_t)m, 64) / 32 * lp_record_bytes(at)
-                       : (es == 4 && side == RID_COLUMNS)
-                             ? (size_t)align_up((size_t)m, 64) * (128 * 4 + 768)
-                             : (size_t)align_up((size_t)m, 64) * 64 * es);
+                       : (size_t)align_up((size_t)m, 64) * (64 * es + (es == 4 ? 384 : 0)));
   // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
   P.o_tt = take(refine ? (size_t)n * P.ldl * es : 0);
@@ -583,40 +564,6 @@ int launch_sketch_mt(const Plan& P, const Ws& W, const void* A, int64_t lda, uin
   }
 }
 
-// Two 64-vector blocks in one pass (k_sketch_pair): FP32 column form of the
-// Gaussian embedding, rows 16-byte aligned, n a multiple of 4, m >= 32.
-bool pair_ok(const Plan& P, const void* A, int64_t lda) {
-  return P.dt == RID_F32 && !low_precision(P.at) && P.side == RID_COLUMNS &&
-         P.emb == RID_EMB_GAUSSIAN && lda % 4 == 0 &&
-         (reinterpret_cast<uintptr_t>(A) & 15u) == 0 && P.n % 4 == 0 && P.m >= 32;
-}
-
-// Geometry of k_sketch_pair: the 128-vector split rule (one resident
-// workgroup per CU), the last split running to row m.
-
-int launch_sketch_pair(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
-                       int64_t c0, int w, const SketchGeom& g, bool use_ctrl, hipStream_t st) {
-  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
-  const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
-  float* om = static_cast<float*>(W.omega);
-  const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
-  uint32_t* oms = reinterpret_cast<uint32_t*>(om + mpad * 128);
-  long pm = prof_begin(KC_OMEGA, st);
-  hipLaunchKernelGGL(k_omega<float>, dim3((unsigned)ceil_div(mpad / 4 * 128, 256)), dim3(256), 0,
-                     st, k0, k1, (uint32_t)c0, w, 128, P.m, mpad, om, ctrl);
-  hipLaunchKernelGGL(k_omega_split<8>, dim3((unsigned)ceil_div(mpad / 32 * 8 * 64, 256)),
-                     dim3(256), 0, st, reinterpret_cast<const float*>(om), mpad, oms, ctrl);
-  prof_end(pm, st);
-  RID_LAUNCH_CHECK();
-  pm = prof_begin(KC_SKETCH2, st);
-  hipLaunchKernelGGL(k_sketch_pair, dim3((unsigned)g.ncolg, (unsigned)g.nsplit), dim3(256), 0, st,
-                     static_cast<const float*>(A), P.m, P.n, lda, oms, g.rows_per_split,
-                     reinterpret_cast<float*>(W.part), ctrl);
-  prof_end(pm, st);
-  RID_LAUNCH_CHECK();
-  return RID_OK;
-}
-
 template <typename TC, int KC>
 int launch_sketch(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                   int64_t c0, int w, const SketchGeom& g, bool norm, bool use_ctrl,
@@ -714,35 +661,16 @@ int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uin
 }
 
 // Sketch vectors [c0, c0 + w) into columns [zcol, zcol + w) of `out`
-// (n x ldo, dtype of the plan), in launches of at most 64 vectors, or 128
-// through k_sketch_pair where pair_ok (not with the norm pass).
+// (n x ldo, dtype of the plan), in launches of at most 64 vectors.
 int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                  int64_t c0, int w, void* out, int64_t ldo, int zcol, bool first, bool use_ctrl,
                  hipStream_t st) {
   // the refinement step reads a copy of the sketch columns the factorisation
   // overwrites
   void* copy = (P.refine && out == W.z) ? W.yorig : nullptr;
-  const bool pairs = pair_ok(P, A, lda);
-  for (int off = 0, wc = 0; off < w; off += wc) {
+  for (int off = 0; off < w; off += 64) {
+    const int wc = std::min(64, w - off);
     const bool norm = first && off == 0;
-    wc = std::min(64, w - off);
-    const SketchGeom gp = sketch_geom_pair(P.m, P.n, P.cu);
-    if (pairs && !norm && w - off > 64 &&
-        (size_t)gp.nsplit * (size_t)P.n * 128 * 4 <= P.part_bytes) {
-      wc = std::min(128, w - off);
-      const SketchGeom& g = gp;
-      Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
-      RID_TRY(launch_sketch_pair(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st));
-      const long pm = prof_begin(KC_REDUCE, st);
-      hipLaunchKernelGGL((k_sketch_reduce<float, float>),
-                         dim3((unsigned)ceil_div(P.n * wc, 256)), dim3(256), 0, st,
-                         reinterpret_cast<const float*>(W.part), (int)g.nsplit, P.n, 128, wc,
-                         static_cast<float*>(out), ldo, zcol + off, static_cast<float*>(copy),
-                         W.fro, 0, W.nonfinite, ctrl, 0);
-      prof_end(pm, st);
-      RID_LAUNCH_CHECK();
-      continue;
-    }
     Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
     const unsigned blocks = (unsigned)ceil_div(P.n * wc, 256);
     if (low_precision(P.at)) {
@@ -813,12 +741,12 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
 }
 
 // ---- block update: U2 (triangular solve) then S (Schur GEMM) --------------
-// Column groups of a Schur launch for a block of w columns: split the
-// workgroup's waves over columns when 64-row workgroups would leave the chip
-// under-filled (fewer than 512 of them, two waves per SIMD).
 // K values per split of the split-K Schur update (k_schur_sk), at least.
 constexpr int kSchurSplitMinK = 128;
 
+// Column groups of a Schur launch for a block of w columns: split the
+// workgroup's waves over columns when 64-row workgroups would leave the chip
+// under-filled (fewer than 512 of them, two waves per SIMD).
 int schur_cg(const Plan& P, int w) {
   const int nt = (w + 15) / 16;
   if (ceil_div(P.n, 64) >= 512 || nt < 2) return 1;
@@ -1451,40 +1379,19 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     // a stop below kcap has the next block sketched at column k
     return finish(P, W, T, ldt, J, k_out, err_est, status, stream, (int)b, kcap);
   }
-  // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch.
-  // FP32 Gaussian sketches of blocks of at most 64 vectors draw two blocks
-  // per pass over A where pair_ok (the second into the Z columns after the
-  // first, where
-  // the next block starts when the first is fully factored); Omega's entries
-  // depend only on (seed, vector, row), so each block's sketch is the one a
-  // pass of its own would give.  `ahead` counts the sketched columns from
-  // column k on.
+  // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch
   SideLease side;
   RID_TRY(panel_fork(P, W, 0, w0, w0, true, stream, side));
-  const bool pairs = pair_ok(P, A, lda) && b <= 64;
-  int64_t ahead = 0;
   while (k < mn) {
-    if (ahead == 0) {
-      // a second block is factored or estimated only if this one takes b pivots
-      const int64_t nb = (pairs && kcap - k >= b && k + b < mn) ? 2 : 1;
-      RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)(nb * b), W.z, P.ldz, (int)k,
-                           false, true, stream));
-      cnext += nb * b;
-      ahead = nb * b;
-    }
+    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false, true,
+                         stream));
+    cnext += b;
     RID_TRY(side_join(side, stream));
     RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, true, stream));
     RID_TRY(estimate(P, W, (int)b, tol, cfg->tol_relative, (int)k, false, stream));
     if (k >= kcap) break;
     const int f = (int)std::min<int64_t>(b, kcap - k);
     RID_TRY(panel_fork(P, W, (int)k, (int)b, f, true, stream, side));
-    ahead -= b;
-    if (f < b && ahead > 0) {
-      // (not reached: a pair is drawn only when f = b) the next block would
-      // start at column k + f; draw its vectors again there
-      cnext -= ahead;
-      ahead = 0;
-    }
     k += f;
   }
   RID_TRY(side_join(side, stream));

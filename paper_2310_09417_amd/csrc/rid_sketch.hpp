@@ -650,163 +650,6 @@ __global__ __launch_bounds__(SketchShape<TC>::NT, 2) void k_sketch(
 }
 
 // ---------------------------------------------------------------------------
-// FP32 sketch of two 64-vector blocks in one pass over A (k_sketch_pair):
-// partial sums over row splits as k_sketch's split path computes them, for
-// 128 vectors.  Two 256-thread workgroups per CU, 64 columns of A per
-// workgroup; wave w owns columns 32 (w % 2) .. + 31 of the strip and vectors
-// 64 (w / 2) .. + 63, i.e. exactly the work of a k_sketch wave.  Each chunk
-// of A (32 rows x 64 columns) is copied into LDS once and read by the two
-// waves of its column group; Omega's 24 operand records per chunk (both
-// vector halves) are copied once and each wave reads its half's 12.  A is
-// staged three chunks deep, Omega two (72 KB of LDS per workgroup).  Every
-// row split is at least one chunk long: the last split runs to row m (up to
-// rows_per_split + 31 rows), whose ragged last chunk is loaded through
-// masked loads.  Requires 16-byte aligned rows (lda % 4 == 0), n a multiple
-// of 4 (lanes past n copy the strip's last 4 columns, whose products are
-// never stored) and m >= 32.  Partials part[split][j][c] (FP32, c < 128) as
-// k_sketch's.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void k_sketch_pair(
-    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
-    const uint32_t* __restrict__ oms, int64_t rows_per_split, float* __restrict__ part,
-    const Ctrl* __restrict__ ctrl) {
-  if (ctrl && ctrl->done) return;
-  constexpr int CGS = 2;                 // column groups of 32 per workgroup
-  constexpr int KC = 32, NW = 2 * CGS, NQ = 2;
-  constexpr int NAW = 2;                 // A copies (8 rows x 32 columns) per wave and chunk
-  constexpr int OREC = 24, ORW = OREC / NW;
-  constexpr int NSA = 3, NSO = 2, DA = NSA - 1, DO = NSO - 1;
-  constexpr int WAITN = NAW + (DO - 1) * (ORW + NAW);
-  constexpr int ASTAGE = CGS * KC * 32;  // floats per A stage
-  __shared__ __attribute__((aligned(16))) float sA[NSA * ASTAGE];
-  __shared__ __attribute__((aligned(16))) uint32_t sO[NSO * OREC * 256];
-  using M = Mfma<float>;
-  using acc_t = typename M::acc_t;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wv = __builtin_amdgcn_readfirstlane(wave);
-  const int cg = wv % CGS, vh = wv / CGS;
-  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r_end = blockIdx.y + 1 == gridDim.y ? m : r_begin + rows_per_split;
-  const int nwhole = (int)((r_end - r_begin) / KC);  // >= 1
-  const int nch = (int)((r_end - r_begin + KC - 1) / KC);
-  const int64_t cw = (int64_t)blockIdx.x * (32 * CGS) + cg * 32;
-  int64_t col4 = cw + 4 * (lane & 7);
-  if (col4 + 4 > n) col4 = n - 4;
-  const uint32_t sa = lds_addr(sA), so = lds_addr(sO);
-  auto a_stage = [&](int st) { return sa + (uint32_t)((st * ASTAGE + cg * KC * 32) * 4); };
-  // this wave copies row groups 2 vh and 2 vh + 1 (rows 8 i + lane / 8) of its column group
-  const float* pa[NAW];
-#pragma unroll
-  for (int i = 0; i < NAW; ++i)
-    pa[i] = A + (r_begin + 8 * (NAW * vh + i) + (lane >> 3)) * lda + col4;
-  auto copy_a = [&](int chunk, int st) {
-    const int64_t da = (int64_t)(chunk < nwhole ? chunk : nwhole - 1) * KC * lda;
-#pragma unroll
-    for (int i = 0; i < NAW; ++i)
-      copy16_to_lds(pa[i] + da, a_stage(st) + (uint32_t)(8 * (NAW * vh + i) * 32 * 4));
-  };
-  // records wv, wv + NW, ... of the chunk
-  const uint32_t* po = oms + (r_begin / KC) * OREC * 256 + 4 * lane;
-  auto copy_o = [&](int chunk, int st) {
-    const int cc = chunk < nch ? chunk : nch - 1;
-#pragma unroll
-    for (int i = 0; i < ORW; ++i)
-      copy16_to_lds(po + ((int64_t)cc * OREC + wv + NW * i) * 256,
-                    so + (uint32_t)((st * OREC + wv + NW * i) * 1024));
-  };
-  acc_t acc[4][NQ];
-  double acc64[4][NQ][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      acc[a][q] = M::zero();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[a][q][r] = 0.0;
-    }
-  const uint32_t lane_off = (uint32_t)((8 * (lane >> 4) * 32 + 2 * (lane & 15)) * 4);
-#pragma unroll
-  for (int j = -DA; j < 0; ++j) {
-    if (j + DO >= 0) copy_o(j + DO, j + DO);
-    copy_a(j + DA, j + DA);
-  }
-  for (int c = 0; c < nch; ++c) {
-    vm_barrier<WAITN>();  // chunk c landed in every wave; chunk c-1's stages free
-    copy_o(c + DO, (c + DO) % NSO);
-    copy_a(c + DA, (c + DA) % NSA);
-    if (c == nwhole) {
-      // ragged last chunk (rows past m are zero); the two waves of a column
-      // group write its halves, so a barrier follows
-      const int64_t r0 = r_begin + (int64_t)c * KC;
-#pragma unroll
-      for (int i = 0; i < NAW; ++i) {
-        const int rg = NAW * vh + i;
-        const int64_t row = r0 + 8 * rg + (lane >> 3);
-        floatx4 v = {0.f, 0.f, 0.f, 0.f};
-        if (row < r_end) v = *reinterpret_cast<const floatx4*>(A + row * lda + col4);
-        *reinterpret_cast<floatx4*>(sA + (c % NSA) * ASTAGE + (cg * KC + 8 * rg) * 32 + 4 * lane) =
-            v;
-      }
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      __syncthreads();
-    }
-    floatx2 x[8];
-    lds_read8x8_rows(a_stage(c % NSA) + lane_off, x);
-    u32x4 bp[3][NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        uint32_t h, md, lo;
-        split3_bf16x2(q ? x[2 * d].y : x[2 * d].x, q ? x[2 * d + 1].y : x[2 * d + 1].x, h, md, lo);
-        bp[0][q][d] = h;
-        bp[1][q][d] = md;
-        bp[2][q][d] = lo;
-      }
-    const u32x4* osrc = reinterpret_cast<const u32x4*>(sO + (c % NSO) * OREC * 256) + 12 * vh * 64;
-    u32x4 op[3][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int p = 0; p < 3; ++p) op[p][a] = osrc[(3 * a + p) * 64 + lane];
-    // six partial products, smallest first: (Omega part, A part)
-    constexpr int PO[6] = {2, 1, 0, 1, 0, 0};
-    constexpr int PA[6] = {0, 1, 2, 0, 1, 0};
-#pragma unroll
-    for (int t = 0; t < 6; ++t)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[a][q] = mfma_bf16x32(op[PO[t]][a], bp[PA[t]][q], acc[a][q]);
-    // FP32 sums of 64 rows (two chunks) are folded into FP64
-    if ((c & 1) || c + 1 == nch) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[a][q][r] += (double)acc[a][q][r];
-          acc[a][q] = M::zero();
-        }
-    }
-  }
-  // every copy has landed before the workgroup's LDS is released
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  const int64_t colq = cw + 2 * (lane & 15);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int64_t col = colq + q;
-    if (col < n) {
-      float* dst = part + ((size_t)blockIdx.y * (size_t)n + (size_t)col) * 128 + 64 * vh;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dst[a * 16 + M::row(lane, r)] = (float)acc64[a][q][r];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Sketch of the row form (the column form of A^T, read in place): partial
 // sums of Z(r, c) = sum_j omega(c0 + c, j) A(r, j) for rows r of A (the
 // candidates) over one range of columns j ("split") per grid row.  The

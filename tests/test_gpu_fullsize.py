@@ -80,12 +80,12 @@ def test_sampled_sketch_entries(setup, orc):
     assert np.all(np.abs(Yt[cols].T - Yo) <= 16 * 2.0 ** -24 * math.sqrt(64) * scale)
 
 
-def test_sampled_wide_sketch_entries(setup, orc):
-    """The 128-vector pass that the decomposition runs for each pair of
-    blocks after the first (vectors 64..191, no norm pass): 12 row splits of
-    3872 rows, the last running to row 50000 and ending in a ragged 16-row
-    chunk, and a last column strip of 32 columns whose other lanes copy
-    clamped columns.  Sampled columns include that strip."""
+def test_sampled_later_sketch_entries(setup, orc):
+    """The sketch launches of the blocks after the first (vectors 64..191,
+    no norm pass): on a 256-CU device 26 row splits of 1952 rows, the last
+    one 1200 rows ending in a ragged 16-row chunk, and a last column strip of
+    32 columns whose other waves copy clamped columns.  Sampled columns
+    include that strip."""
     torch, rid, A32, sig, g = setup
     rng = np.random.default_rng(1)
     cols = np.sort(np.concatenate([rng.choice(N - 32, size=44, replace=False),
@@ -96,8 +96,7 @@ def test_sampled_wide_sketch_entries(setup, orc):
     om = orc.omega(SEED, B, 2 * B, M)
     scale = np.outer(np.linalg.norm(om, axis=1), np.linalg.norm(Asub, axis=0))
     assert np.all(np.abs(Yt[cols].T - Yo) <= 16 * 2.0 ** -24 * math.sqrt(64) * scale)
-    # the same vectors as the two 64-vector blocks of the decomposition: the
-    # second block's sketch through its own pass agrees to rounding
+    # the second block sketched on its own agrees to rounding
     Y2 = rid.debug_sketch(A32, SEED, 2 * B, B).cpu().numpy().astype(np.float64)
     sc2 = np.outer(np.linalg.norm(Asub, axis=0), np.linalg.norm(om[B:], axis=1))
     assert np.all(np.abs(Yt[cols, B:] - Y2[cols]) <= 32 * 2.0 ** -24 * math.sqrt(64) * sc2)

@@ -77,13 +77,12 @@ def test_gaussian_matches_oracle(torch, rid, orc, m, w, c0):
 def test_sketch_matches_oracle(torch, rid, orc, dtype, m, n, w, c0, spread):
     """Device sketch against the oracle's entry by entry.  spread > 0: entries
     of magnitudes 10^U(-spread, spread), so that within a column the FP32
-    three-part BF16 products meet values many binades apart.  FP32 blocks of
-    65-128 vectors without the norm pass (c0 > 0) run the two-block kernel
-    where n % 4 == 0, the others two 64-vector launches.  The cases cover
-    ragged last row chunks (m % 32 != 0, loaded through masked loads), a last
-    column strip of 4-104 columns (clamped copies), n % 4 != 0, vector counts
-    below 128, and (3001 x 8004, 2023 x 12000 on a 256-CU device) row splits
-    of 128-192 rows."""
+    three-part BF16 products meet values many binades apart.  Blocks of more
+    than 64 vectors run as 64-vector launches, the first with the norm pass
+    when c0 == 0.  The cases cover ragged last row chunks (m % 32 != 0, loaded
+    through masked loads in the streaming FP32 kernel), a last column strip of
+    4-104 columns (clamped copies without the norm pass), n % 4 != 0, vector
+    counts below 64 per launch, and row splits longer than one chunk."""
     _say("sketch", dtype, m, n, w, c0, spread)
     rng = np.random.default_rng(m * 7 + n)
     A = rng.standard_normal((m, n))
