@@ -456,7 +456,8 @@ int rid_debug_mfma_probe(int kind, const void* A, const void* B, float* D, hipSt
  * Classes: 0 sketch, 1 sketch reduction, 2 U2 = L1^{-1} (P Y)(top),
  * 3 Schur update, 4 panel LUPP, 5 interpolation matrix, 6 update of L1^{-1},
  * 7 batched persistent kernel, 8 generation of the sketch vectors' Gaussian
- * entries, 9 Remark-1 estimate.  Process-wide state:
+ * entries, 9 Remark-1 estimate, 10 two-block low-precision sketch (128
+ * vectors per pass).  Process-wide state:
  * not for concurrent use from several host threads.
  */
 int rid_profile_start(void);

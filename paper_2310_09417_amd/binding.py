@@ -207,7 +207,7 @@ def rid_lupp_batched(nblk, A, lda, m, n, b, tol, kmax, k_hint, cfg, J, T, ldt, k
 
 
 KERNEL_CLASSES = ("sketch", "sketch_reduce", "u2", "schur", "panel_lupp", "tgemm", "linv_update",
-                  "batched", "omega", "resid_est")
+                  "batched", "omega", "resid_est", "sketch_pair")
 
 
 def rid_release() -> int:

@@ -130,7 +130,7 @@ class SideLease {
 // ---- optional per-kernel-class timing (HIP events on the call's stream) ----
 enum KClass {
   KC_SKETCH = 0, KC_REDUCE, KC_TRSM, KC_SCHUR, KC_LUPP, KC_TSOLVE, KC_LINV, KC_BATCHED, KC_OMEGA,
-  KC_RESID, KC_N
+  KC_RESID, KC_SKETCH2, KC_N
 };
 
 struct Profiler {
@@ -239,9 +239,10 @@ struct LpGeom {
   int64_t ncolg, nsplit, rows_per_split;
 };
 
-LpGeom sketch_geom_lp(int64_t m, int64_t n, int fmt, int cu) {
+// vg = 2: k_sketch_lpw (half the columns per workgroup, 128 vectors).
+LpGeom sketch_geom_lp(int64_t m, int64_t n, int fmt, int cu, int vg = 1) {
   LpGeom g;
-  const int64_t cols = kLprCols(fmt), es = fmt == 1 ? 2 : 1, kc = 32;
+  const int64_t cols = kLprCols(fmt) / vg, es = fmt == 1 ? 2 : 1, kc = 32;
   g.ncolg = ceil_div(n, cols);
   const int64_t slots = (int64_t)cu * 4;
   const int64_t maxsplit = ceil_div(m, kc);
@@ -253,7 +254,7 @@ LpGeom sketch_geom_lp(int64_t m, int64_t n, int fmt, int cu) {
     const int64_t real_ns = ceil_div(m, rps);
     const int64_t items = g.ncolg * real_ns;
     const double cost = (double)ceil_div(items, slots) * (double)rps * (double)(cols * es) +
-                        (double)items * (double)cols * 64.0 * 4.0 * 2.0 / (double)slots;
+                        (double)items * (double)cols * 64.0 * vg * 4.0 * 2.0 / (double)slots;
     if (best < 0.0 || cost < best * (1.0 - 1e-3)) {
       best = cost;
       best_ns = ns;
@@ -337,7 +338,8 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   size_t pb = 0, fc = 0;
   if (low_precision(at)) {
     LpGeom g = sketch_geom_lp(m, n, at == RID_BF16 ? 1 : 2, di.cu);
-    pb = (size_t)g.nsplit * (size_t)n * 64 * 4;
+    LpGeom g2 = sketch_geom_lp(m, n, at == RID_BF16 ? 1 : 2, di.cu, 2);
+    pb = std::max((size_t)g.nsplit * (size_t)n * 64 * 4, (size_t)g2.nsplit * (size_t)n * 128 * 4);
     fc = (size_t)(g.nsplit * g.ncolg);
   } else if (side == RID_ROWS) {
     // candidates are A's rows (n here), the contraction runs over its columns (m)
@@ -380,11 +382,12 @@ bool make_plan(int64_t m, int64_t n, int64_t kcap, int64_t wmax, rid_dtype dt, r
   // Omega of one sketch launch (at most 64 vectors), rows padded to 64; in
   // FP32 followed by its three-part BF16 operand form (k_omega_split, 384
   // bytes per row)
-  // (the low-precision forms: the FP32 Gaussian entries, then their records
-  // in the format, lp_record_bytes per 32 rows)
+  // (the low-precision forms: the FP32 Gaussian entries of up to 128
+  // vectors, then their records in the format, lp_record_bytes per 32 rows
+  // and 64 vectors)
   P.o_omega = take(low_precision(at)
-                       ? (size_t)align_up((size_t)m, 64) * 64 * 4 +
-                             (size_t)align_up((size_t)m, 64) / 32 * lp_record_bytes(at)
+                       ? (size_t)align_up((size_t)m, 64) * 128 * 4 +
+                             (size_t)align_up((size_t)m, 64) / 32 * 2 * lp_record_bytes(at)
                        : (size_t)align_up((size_t)m, 64) * (64 * es + (es == 4 ? 384 : 0)));
   // refinement: the kept sketch (n x ldz), T^T and the residual rows (n x ldl)
   P.o_yorig = take(refine ? (size_t)n * P.ldz * es : 0);
@@ -660,18 +663,63 @@ int launch_sketch_lp(const Plan& P, const Ws& W, const void* A, int64_t lda, uin
   return RID_OK;
 }
 
+// Two blocks of the low-precision forms in one pass (k_sketch_lpw): vectors
+// [c0, c0 + w), 64 < w <= 128, Gaussian embedding, no norm pass.
+template <int FMT>
+int launch_sketch_lpw(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
+                      int64_t c0, int w, const LpGeom& g, bool use_ctrl, hipStream_t st) {
+  constexpr int ES = FMT == 1 ? 2 : 1;
+  const int aligned = ((lda * ES) % 16 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15u) == 0);
+  const int vec8 = ((lda * ES) % 8 == 0) && ((reinterpret_cast<uintptr_t>(A) & 7u) == 0);
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  const Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+  const int64_t mpad = (int64_t)align_up((size_t)P.m, 64);
+  float* om = static_cast<float*>(W.omega);
+  unsigned char* rec = reinterpret_cast<unsigned char*>(om + mpad * 128);
+  long pm = prof_begin(KC_OMEGA, st);
+  hipLaunchKernelGGL(k_omega<float>, dim3((unsigned)ceil_div(mpad / 4 * 128, 256)), dim3(256), 0,
+                     st, k0, k1, (uint32_t)c0, w, 128, P.m, mpad, om, ctrl);
+  hipLaunchKernelGGL((k_omega_lp_records<FMT, 8>), dim3((unsigned)ceil_div(mpad / 32 * 512, 256)),
+                     dim3(256), 0, st, om, mpad, rec, ctrl);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  pm = prof_begin(KC_SKETCH2, st);
+  hipLaunchKernelGGL((k_sketch_lpw<FMT>), dim3((unsigned)g.ncolg, (unsigned)g.nsplit),
+                     dim3(kLprThreads), 0, st, static_cast<const unsigned char*>(A), P.m, P.n, lda,
+                     rec, g.rows_per_split, reinterpret_cast<float*>(W.part), ctrl, aligned, vec8);
+  prof_end(pm, st);
+  RID_LAUNCH_CHECK();
+  return RID_OK;
+}
+
 // Sketch vectors [c0, c0 + w) into columns [zcol, zcol + w) of `out`
-// (n x ldo, dtype of the plan), in launches of at most 64 vectors.
+// (n x ldo, dtype of the plan), in launches of at most 64 vectors (the
+// low-precision forms: 128 after the first launch of a call's norm pass).
 int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_t seed,
                  int64_t c0, int w, void* out, int64_t ldo, int zcol, bool first, bool use_ctrl,
                  hipStream_t st) {
   // the refinement step reads a copy of the sketch columns the factorisation
   // overwrites
   void* copy = (P.refine && out == W.z) ? W.yorig : nullptr;
-  for (int off = 0; off < w; off += 64) {
-    const int wc = std::min(64, w - off);
+  for (int off = 0, wc = 0; off < w; off += wc) {
     const bool norm = first && off == 0;
+    wc = std::min(64, w - off);
     Ctrl* ctrl = use_ctrl ? W.ctrl : nullptr;
+    if (low_precision(P.at) && !norm && w - off > 64 && P.emb == RID_EMB_GAUSSIAN) {
+      wc = std::min(128, w - off);
+      const int fmt = P.at == RID_BF16 ? 1 : 2;
+      LpGeom g = sketch_geom_lp(P.m, P.n, fmt, P.cu, 2);
+      RID_TRY(fmt == 1 ? launch_sketch_lpw<1>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st)
+                       : launch_sketch_lpw<2>(P, W, A, lda, seed, c0 + off, wc, g, use_ctrl, st));
+      const long pm = prof_begin(KC_REDUCE, st);
+      hipLaunchKernelGGL(k_sketch_reduce_lp<float>, dim3((unsigned)ceil_div(P.n * wc, 256)),
+                         dim3(256), 0, st, reinterpret_cast<const float*>(W.part), (int)g.nsplit,
+                         P.n, 128, wc, fmt == 2 ? P.scale : nullptr, static_cast<float*>(out), ldo,
+                         zcol + off, static_cast<float*>(copy), W.fro, 0, W.nonfinite, ctrl, 0);
+      prof_end(pm, st);
+      RID_LAUNCH_CHECK();
+      continue;
+    }
     const unsigned blocks = (unsigned)ceil_div(P.n * wc, 256);
     if (low_precision(P.at)) {
       // factor type is FP32 (checked by the caller)
@@ -686,7 +734,7 @@ int sketch_block(const Plan& P, const Ws& W, const void* A, int64_t lda, uint64_
       if (rc != RID_OK) return rc;
       const long pm = prof_begin(KC_REDUCE, st);
       hipLaunchKernelGGL(k_sketch_reduce_lp<float>, dim3(blocks), dim3(256), 0, st,
-                         reinterpret_cast<const float*>(W.part), (int)g.nsplit, P.n, wc,
+                         reinterpret_cast<const float*>(W.part), (int)g.nsplit, P.n, 64, wc,
                          P.at == RID_FP8_E4M3 ? P.scale : nullptr, static_cast<float*>(out), ldo,
                          zcol + off, static_cast<float*>(copy), W.fro, (int)(g.nsplit * g.ncolg),
                          W.nonfinite, ctrl, norm ? 1 : 0);
@@ -1379,19 +1427,39 @@ int rid_lupp_adaptive(const void* A, int64_t m, int64_t n, int64_t lda, int64_t 
     // a stop below kcap has the next block sketched at column k
     return finish(P, W, T, ldt, J, k_out, err_est, status, stream, (int)b, kcap);
   }
-  // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch
+  // Alg. 1 with the growth of L1^{-1} overlapping the next block's sketch.
+  // The low-precision forms (Gaussian embedding, b <= 64) draw two blocks
+  // per pass over A after the first (k_sketch_lpw), the second into the Z
+  // columns after the first, where the next block starts once the first is
+  // fully factored; Omega's entries depend only on (seed, vector, row), so
+  // each block's sketch is the one a pass of its own would give.  `ahead`
+  // counts the sketched columns from column k on.
   SideLease side;
   RID_TRY(panel_fork(P, W, 0, w0, w0, true, stream, side));
+  const bool pairs = low_precision(P.at) && P.emb == RID_EMB_GAUSSIAN && b <= 64;
+  int64_t ahead = 0;
   while (k < mn) {
-    RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)b, W.z, P.ldz, (int)k, false, true,
-                         stream));
-    cnext += b;
+    if (ahead == 0) {
+      // a second block is factored or estimated only if this one takes b pivots
+      const int64_t nb = (pairs && kcap - k >= b && k + b < mn) ? 2 : 1;
+      RID_TRY(sketch_block(P, W, A, lda, cfg->seed, cnext, (int)(nb * b), W.z, P.ldz, (int)k,
+                           false, true, stream));
+      cnext += nb * b;
+      ahead = nb * b;
+    }
     RID_TRY(side_join(side, stream));
     RID_TRY(block_update(P, W, (int)k, (int)k, (int)b, true, stream));
     RID_TRY(estimate(P, W, (int)b, tol, cfg->tol_relative, (int)k, false, stream));
     if (k >= kcap) break;
     const int f = (int)std::min<int64_t>(b, kcap - k);
     RID_TRY(panel_fork(P, W, (int)k, (int)b, f, true, stream, side));
+    ahead -= b;
+    if (f < b && ahead > 0) {
+      // (not reached: a pair is drawn only when f = b) the next block would
+      // start at column k + f; draw its vectors again there
+      cnext -= ahead;
+      ahead = 0;
+    }
     k += f;
   }
   RID_TRY(side_join(side, stream));

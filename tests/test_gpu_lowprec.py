@@ -55,8 +55,15 @@ def _amb_ulp(om64, fmt_code, orc):
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
 @pytest.mark.parametrize("m,n,w,c0,pad", [(700, 2100, 40, 64, 0), (333, 517, 64, 0, 3),
                                           (64, 1024, 16, 7, 0), (1, 20, 5, 0, 0),
-                                          (4100, 3080, 64, 3, 8)])
+                                          (4100, 3080, 64, 3, 8), (3001, 2100, 128, 64, 0),
+                                          (4100, 3080, 100, 3, 8), (2500, 4096, 128, 128, 0),
+                                          (777, 333, 96, 5, 1)])
 def test_lowprec_sketch_matches_oracle(orc, fmt, m, n, w, c0, pad):
+    """Device sketch of the stored matrix against the oracle's sketch of the
+    values it represents, entry by entry.  Blocks of more than 64 vectors
+    without the norm pass (c0 > 0) run the two-block kernel for up to 128
+    vectors: the cases cover ragged last row chunks, edge column strips,
+    padded rows (lda > n) and vector counts below 128."""
     import paper_2310_09417_amd as rid
     rng = np.random.default_rng(m + n)
     A = rng.standard_normal((m, n)) * 10.0 ** rng.uniform(-3, 3, n)[None, :]
@@ -73,16 +80,18 @@ def test_lowprec_sketch_matches_oracle(orc, fmt, m, n, w, c0, pad):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
-def test_lowprec_sketch_fullsize_sampled(orc, fmt):
-    """The 50000 x 20000 matrix in the launch configuration the benchmark
+@pytest.mark.parametrize("c0,w", [(0, 64), (64, 128)])
+def test_lowprec_sketch_fullsize_sampled(orc, fmt, c0, w):
+    """The 50000 x 20000 matrix in the launch configurations the benchmark
     times (interior workgroups stage A through LDS, the last column group
     does not): 64 sampled columns of the device sketch against the oracle's
     sketch of the same represented columns (the sketch of a column depends
-    on that column alone)."""
+    on that column alone).  c0 = 0: the first block with the norm pass;
+    c0 = 64, w = 128: the two-block pass of the blocks after it."""
     import torch
 
     import paper_2310_09417_amd as rid
-    m, n, w, seed = 50000, 20000, 64, 21
+    m, n, seed = 50000, 20000, 21
     g = torch.Generator(device="cuda").manual_seed(5)
     A = torch.randn((m, n), generator=g, device="cuda", dtype=torch.float32)
     A *= torch.exp2(torch.linspace(-8.0, 8.0, n, device="cuda"))[None, :]
@@ -90,7 +99,7 @@ def test_lowprec_sketch_fullsize_sampled(orc, fmt):
     del A
     if fmt == "fp8":
         St = St.view(torch.uint8)
-    Yt = rid.debug_sketch(St, seed, 0, w, col_scale=inv).cpu().numpy().astype(np.float64)
+    Yt = rid.debug_sketch(St, seed, c0, w, col_scale=inv).cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(7)
     cols = np.sort(np.concatenate([rng.choice(n - 1, 62, replace=False), [0, n - 1]]))
     ct = torch.as_tensor(cols, device="cuda")
@@ -101,8 +110,8 @@ def test_lowprec_sketch_fullsize_sampled(orc, fmt):
         vals *= inv.double().cpu().numpy()[cols // 128][None, :]
     del St
     fc = FMTS[fmt]
-    Y = orc.sketch(vals, seed, 0, w, fc)
-    om64 = orc.omega(seed, 0, w, m)
+    Y = orc.sketch(vals, seed, c0, w, fc)
+    om64 = orc.omega(seed, c0, w, m)
     omr = orc.round_format(om64, fc)
     bound = _amb_ulp(om64, fc, orc) @ np.abs(vals) + ACC[fmt] * (np.abs(omr) @ np.abs(vals)) + 1e-30
     err = np.abs(Yt[cols].T - Y)
