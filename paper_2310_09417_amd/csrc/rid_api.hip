@@ -846,10 +846,16 @@ int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, b
       S = ceil_div(k, ksplit);
       const int ntw = (w + 15) / 16;
       dim3 gsk((unsigned)slabs, (unsigned)S);
+      // FP32: on the BF16 matrix cores through the three-part split
 #define RID_SCHUR_SK(NTV)                                                                     \
-  hipLaunchKernelGGL((k_schur_sk<TF, NTV>), gsk, dim3(256), 0, st,                             \
-                     static_cast<const TF*>(W.z), P.ldz, P.n, k, w,                            \
-                     static_cast<const TF*>(W.u2t), P.ldu, ksplit, W.part, W.ctrl)
+  if constexpr (sizeof(TF) == 4)                                                             \
+    hipLaunchKernelGGL((k_schur_skb<NTV>), gsk, dim3(256), 0, st,                              \
+                       static_cast<const float*>(W.z), P.ldz, P.n, k, w,                      \
+                       static_cast<const float*>(W.u2t), P.ldu, ksplit, W.part, W.ctrl);      \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_schur_sk<TF, NTV>), gsk, dim3(256), 0, st,                           \
+                       static_cast<const TF*>(W.z), P.ldz, P.n, k, w,                         \
+                       static_cast<const TF*>(W.u2t), P.ldu, ksplit, W.part, W.ctrl)
       switch (ntw) {
         case 1: RID_SCHUR_SK(1); break;
         case 2: RID_SCHUR_SK(2); break;

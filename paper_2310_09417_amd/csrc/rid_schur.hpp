@@ -282,4 +282,142 @@ __global__ __launch_bounds__(256) void k_schur_fin(TF* __restrict__ Z, int64_t l
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// FP32 form of k_schur_sk on the BF16 matrix cores: both operands split
+// exactly into three BF16 parts (split3_bf16x2) and six of the nine partial
+// products summed by the 16x16x32 BF16 instruction, smallest first, which
+// gives each product to within 2^-26 of its magnitude (the FP32 sketch's
+// scheme).  K runs in chunks of 32, in order: lane group g holds K values
+// 8 g .. 8 g + 7 of the chunk for its A row (two 16-byte loads of Z) and for
+// its U2 columns.  Each chunk of U2 (64 columns x 32 K) is loaded and split
+// once per workgroup into LDS as MFMA operand records (per part and column
+// tile, 64 lanes x 16 bytes; two stages) shared by the four waves; each wave
+// keeps its A values NB chunks ahead in registers.  FP32 sums are folded
+// into FP64 every 64 K values; splits start on multiples of 64.  Same
+// partials as k_schur_sk (k_schur_fin finishes).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(256) void k_schur_skb(const float* __restrict__ Z, int64_t ldz,
+                                                   int64_t n, int k, int w,
+                                                   const float* __restrict__ U2T, int64_t ldu,
+                                                   int ksplit, double* __restrict__ P,
+                                                   const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  constexpr int KCH = 32;       // K values per chunk
+  constexpr int NB = 3;         // A chunks in flight per wave
+  constexpr int REC = 64 * 4;   // dwords of one operand record (64 lanes x 16 bytes)
+  __shared__ __attribute__((aligned(16))) uint32_t sB[2][3 * 4 * REC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t rbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t arow = rbase + (lane & 15);
+  const bool arow_ok = arow < n;
+  const int kbeg = (int)blockIdx.y * ksplit;
+  const int kend = kbeg + ksplit < k ? kbeg + ksplit : k;
+  const int nchk = kend > kbeg ? (kend - kbeg + KCH - 1) / KCH : 0;
+  const int g = lane >> 4;
+  // 8 consecutive K values from kidx (zero past kend or where !ok): two
+  // 16-byte loads when all are inside (rows are 16-byte aligned: ld % 4 == 0)
+  auto load8 = [&](const float* p, int64_t base, int kidx, bool ok, float out[8]) {
+    load4<float, false>(p, base, kidx, 0, kend, ok, out);
+    load4<float, false>(p, base, kidx + 4, 0, kend, ok, out + 4);
+  };
+  // B staging: thread t splits K values 8 (t % 4) .. + 7 of column t / 4
+  // into record (part, tile (t / 4) / 16) at lane (t / 4) % 16 + 16 (t % 4)
+  const int bcol = tid >> 2, bq = tid & 3;
+  const int brec = ((bcol >> 4) * 64 + (bcol & 15) + 16 * bq) * 4;
+  auto load_b = [&](int c, float out[8]) {
+    load8(U2T, (int64_t)bcol * ldu, kbeg + KCH * c + 8 * bq, bcol < w, out);
+  };
+  auto store_b = [&](int st, const float v[8]) {
+    u32x4 h, md, lo;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      uint32_t x, y, z;
+      split3_bf16x2(v[2 * d], v[2 * d + 1], x, y, z);
+      h[d] = x;
+      md[d] = y;
+      lo[d] = z;
+    }
+    *reinterpret_cast<u32x4*>(sB[st] + 0 * 4 * REC + brec) = h;
+    *reinterpret_cast<u32x4*>(sB[st] + 1 * 4 * REC + brec) = md;
+    *reinterpret_cast<u32x4*>(sB[st] + 2 * 4 * REC + brec) = lo;
+  };
+  auto load_a = [&](int c, float out[8]) {
+    load8(Z, arow * ldz, kbeg + KCH * c + 8 * g, arow_ok, out);
+  };
+  floatx4 acc[NT];
+  double acc64[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[t][r] = 0.0;
+  }
+  float ar[NB][8];
+  float bn[8];
+  if (nchk > 0) {
+    load_b(0, bn);
+    store_b(0, bn);
+    if (nchk > 1) load_b(1, bn);
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (u < nchk) load_a(u, ar[u]);
+  __syncthreads();
+  // six partial products per accumulator, smallest first: (A part, B part)
+  constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
+  constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
+  for (int c0 = 0; c0 < nchk; c0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int c = c0 + u;
+      if (c < nchk) {
+        u32x4 ap[3];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          uint32_t x, y, z;
+          split3_bf16x2(ar[u][2 * d], ar[u][2 * d + 1], x, y, z);
+          ap[0][d] = x;
+          ap[1][d] = y;
+          ap[2][d] = z;
+        }
+        if (c + NB < nchk) load_a(c + NB, ar[u]);
+        const u32x4* sb = reinterpret_cast<const u32x4*>(sB[c & 1]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          u32x4 bp[3];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) bp[p] = sb[(p * 4 + t) * 64 + lane];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) acc[t] = mfma_bf16x32(ap[PA[q]], bp[PB[q]], acc[t]);
+        }
+        if ((c & 1) || c + 1 == nchk) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[t][r] += (double)acc[t][r];
+            acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+        // the next chunk's U2 records into the other stage (read in chunk
+        // c - 1, which every wave has finished), then the one after it
+        if (c + 1 < nchk) store_b((c + 1) & 1, bn);
+        if (c + 2 < nchk) load_b(c + 2, bn);
+        __syncthreads();
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rbase + 4 * g + r;
+      if (row < n && col < w)
+        P[((size_t)blockIdx.y * (size_t)n + (size_t)row) * 64 + col] = acc64[t][r];
+    }
+  }
+}
+
 }  // namespace rid

@@ -123,33 +123,6 @@ __device__ __forceinline__ void lds_read8x8_rows(uint32_t addr, floatx2 (&r)[8])
       : "v"(addr));
 }
 
-// ---------------------------------------------------------------------------
-// FP32 values as sums of three BF16 values.  hi = bf16(x) (nearest even),
-// mid = bf16(x - hi), lo = x - hi - mid: both differences are exact in FP32,
-// and lo has at most 8 significant bits, so x = hi + mid + lo exactly (for
-// x above 2^-100 or so in magnitude, where no part leaves the normal range),
-// with |mid| <= 2^-9 |x| and |lo| <= 2^-18 |x|.  A product of two such
-// values is the sum of nine BF16 products, each exact in FP32; the six with
-// weight above 2^-27 (hi hi, hi mid, mid hi, hi lo, mid mid, lo hi) give
-// the product to within 2^-26 of its magnitude, below FP32's own rounding,
-// at the BF16 matrix-core rate.  Two values at a time: the three packed
-// BF16 pairs (first value in the low half).
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-  const floatx2 v = {a, b};
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_v));
-}
-
-__device__ __forceinline__ void split3_bf16x2(float a, float b, uint32_t& h, uint32_t& m,
-                                              uint32_t& l) {
-  h = pack_bf16x2(a, b);
-  const float ra = a - __uint_as_float(h << 16), rb = b - __uint_as_float(h & 0xffff0000u);
-  m = pack_bf16x2(ra, rb);
-  l = pack_bf16x2(ra - __uint_as_float(m << 16), rb - __uint_as_float(m & 0xffff0000u));
-}
-
 // Omega (row-major, mpad x 16 MT, FP32) as the BF16 operand tiles of the
 // split sketch: for each chunk of 32 rows, vector tile a (16 vectors) and part
 // p (hi, mid, lo), 64 lanes x 16 bytes; lane i + 16 g holds vector 16 a + i,

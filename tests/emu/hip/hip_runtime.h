@@ -75,6 +75,30 @@ inline void op_mfma(WaveOp& w) {
       w.out[l][r] = to_bits<T>((T)acc);
     }
 }
+// D = A B + C for the 16x16x32 BF16 tile: lane l supplies A[l%16][8 (l/16) + e]
+// and B[8 (l/16) + e][l%16] as element e of its 8-element operands (two 64-bit
+// words each); accumulator element r of lane l is D[4 (l/16) + r][l%16].
+inline double bf16_value(uint64_t words, int e) {
+  const uint32_t h = (uint32_t)(words >> (16 * e)) & 0xffffu;
+  return (double)from_bits<float>((uint64_t)(h << 16));
+}
+inline void op_mfma_bf16(WaveOp& w) {
+  double A[16][32], B[32][16], C[16][16];
+  for (int l = 0; l < kWave; ++l) {
+    for (int e = 0; e < 8; ++e) {
+      A[l % 16][8 * (l / 16) + e] = bf16_value(w.in[l][e / 4], e % 4);
+      B[8 * (l / 16) + e][l % 16] = bf16_value(w.in[l][2 + e / 4], e % 4);
+    }
+    for (int r = 0; r < 4; ++r) C[4 * (l / 16) + r][l % 16] = (double)from_bits<float>(w.in[l][4 + r]);
+  }
+  for (int l = 0; l < kWave; ++l)
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * (l / 16) + r, col = l % 16;
+      double acc = C[row][col];
+      for (int k = 0; k < 32; ++k) acc += A[row][k] * B[k][col];
+      w.out[l][r] = to_bits<float>((float)acc);
+    }
+}
 }  // namespace emu
 
 template <typename T>
@@ -102,6 +126,7 @@ inline unsigned atomicAdd(unsigned* p, unsigned v) {
 }
 
 inline unsigned __float_as_uint(float f) { return ::emu::to_bits(f) & 0xffffffffu; }
+inline float __uint_as_float(unsigned u) { return ::emu::from_bits<float>(u); }
 
 namespace emu {
 template <typename V, typename T, bool F64>
@@ -114,6 +139,19 @@ inline V mfma16x16x4(T a, T b, V c) {
   wave_collective(&op_mfma<T, F64>, F64 ? "mfma_f64_16x16x4" : "mfma_f32_16x16x4", 0);
   V d;
   for (int r = 0; r < 4; ++r) d[r] = from_bits<T>(w.out[l][r]);
+  return d;
+}
+template <typename V8, typename V>
+inline V mfma16x16x32bf16(V8 a, V8 b, V c) {
+  static_assert(sizeof(V8) == 16, "8 BF16 values");
+  WaveOp& w = my_wave_op();
+  const int l = lane_id();
+  memcpy(&w.in[l][0], &a, 16);
+  memcpy(&w.in[l][2], &b, 16);
+  for (int r = 0; r < 4; ++r) w.in[l][4 + r] = to_bits((float)c[r]);
+  wave_collective(&op_mfma_bf16, "mfma_f32_16x16x32_bf16", 0);
+  V d;
+  for (int r = 0; r < 4; ++r) d[r] = from_bits<float>(w.out[l][r]);
   return d;
 }
 [[noreturn]] inline void unsupported(const char* what) {
@@ -134,7 +172,7 @@ inline V mfma16x16x4(T a, T b, V c) {
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
 // instructions of the low-precision paths, which the emulation does not run
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) \
-  (::emu::unsupported("mfma bf16"), (c))
+  (::emu::mfma16x16x32bf16((a), (b), (c)))
 #define __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, x, y, z) \
   (::emu::unsupported("mfma fp8"), (c))
 #define __builtin_amdgcn_cvt_pk_fp8_f32(a, b, old, hi) (::emu::unsupported("cvt fp8"), 0)

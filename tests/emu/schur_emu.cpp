@@ -9,7 +9,8 @@
 // norm partials.  With a third argument ksplit the split-K form runs instead
 // (rid::k_schur_sk over ceil(n/64) x ceil(k/ksplit) workgroups with nt
 // column tiles, then rid::k_schur_fin with 64/cg rows per workgroup); kb and
-// from must then be 0.
+// from must then be 0; a fourth argument "bf" runs the FP32 form on the BF16
+// matrix cores (rid::k_schur_skb) instead of rid::k_schur_sk.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -90,11 +91,19 @@ struct SkArgs {
   Args* a;
   int ksplit, nsplit;
   double* P;
+  int bf;  // FP32 on the BF16 matrix cores (k_schur_skb)
 };
 
 template <typename TF, int NT>
 void launch_sk(SkArgs& s) {
   Args& a = *s.a;
+  if constexpr (sizeof(TF) == 4) {
+    if (s.bf) {
+      rid::k_schur_skb<NT>(static_cast<const float*>(a.Z), a.ldz, a.n, a.k, a.w,
+                           static_cast<const float*>(a.U2T), a.ldu, s.ksplit, s.P, a.ctrl);
+      return;
+    }
+  }
   rid::k_schur_sk<TF, NT>(static_cast<const TF*>(a.Z), a.ldz, a.n, a.k, a.w,
                           static_cast<const TF*>(a.U2T), a.ldu, s.ksplit, s.P, a.ctrl);
 }
@@ -133,8 +142,9 @@ void body_fin(void* p) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 3 && argc != 4) return 2;
-  const int ksplit = argc == 4 ? atoi(argv[3]) : 0;
+  if (argc < 3 || argc > 5) return 2;
+  const int ksplit = argc >= 4 ? atoi(argv[3]) : 0;
+  const int bf = argc == 5 && strcmp(argv[4], "bf") == 0;
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 2;
   int32_t h[12];
@@ -160,7 +170,7 @@ int main(int argc, char** argv) {
     const size_t np = (size_t)nsplit * n * 64;
     double* P = static_cast<double*>(malloc(np * 8));
     for (size_t i = 0; i < np; ++i) P[i] = __builtin_nan("");  // unwritten partials show up
-    SkArgs s{&a, ksplit, nsplit, P};
+    SkArgs s{&a, ksplit, nsplit, P, bf};
     for (int y = 0; y < nsplit; ++y)
       for (int x = 0; x < slabs; ++x)
         emu::run_group2(256, (unsigned)x, (unsigned)y, (unsigned)slabs, (unsigned)nsplit,

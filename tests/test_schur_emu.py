@@ -5,7 +5,8 @@ place, pivot rows untouched, and the FP64 sums of S^2 per workgroup, for
 the K ranges, column groups and tile counts the library launches
 (including a K range that starts at kb, ragged K and ragged row counts).
 The split-K form (k_schur_sk's FP64 partials per K range, summed in split
-order and subtracted by k_schur_fin) is checked the same way."""
+order and subtracted by k_schur_fin) is checked the same way, and so is its
+FP32 form on the BF16 matrix cores (k_schur_skb)."""
 import os
 import struct
 import subprocess
@@ -30,7 +31,7 @@ def exe(tmp_path_factory):
     return out
 
 
-def _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, frm, dtype, ksplit=0):
+def _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, frm, dtype, ksplit=0, bf=False):
     n, ldz = Z.shape
     ldu = U2T.shape[1]
     with tempfile.TemporaryDirectory() as td:
@@ -42,7 +43,7 @@ def _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, frm, dtype, ksplit=0):
             f.write(np.ascontiguousarray(U2T, dtype=dtype).tobytes())
             f.write(np.asarray(pos, dtype="<i4").tobytes())
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
-        cmd = [exe, fin, fout] + ([str(ksplit)] if ksplit else [])
+        cmd = [exe, fin, fout] + ([str(ksplit)] if ksplit else []) + (["bf"] if bf else [])
         r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode == 0, r.stderr[-4000:]
         data = open(fout, "rb").read()
@@ -70,13 +71,20 @@ def test_split_k_schur_matches_numpy(exe, dtype, n, k, w, nt, cg, ksplit):
     _check(exe, dtype, n, k, 0, w, nt, cg, ksplit)
 
 
+@pytest.mark.parametrize("n,k,w,nt,cg,ksplit", SK_CASES)
+def test_split_k_schur_bf16_split_matches_numpy(exe, n, k, w, nt, cg, ksplit):
+    """The FP32 split-K product on the BF16 matrix cores (three-part split of
+    both operands, six partial products): within the same FP32 bound."""
+    _check(exe, np.float32, n, k, 0, w, nt, cg, ksplit, bf=True)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n,k,kb,w,nt,cg", CASES)
 def test_schur_kernel_matches_numpy(exe, dtype, n, k, kb, w, nt, cg):
     _check(exe, dtype, n, k, kb, w, nt, cg, 0)
 
 
-def _check(exe, dtype, n, k, kb, w, nt, cg, ksplit):
+def _check(exe, dtype, n, k, kb, w, nt, cg, ksplit, bf=False):
     rng = np.random.default_rng(n + k + w)
     zcol = k
     ldz = ((k + w + 3) // 4) * 4
@@ -87,7 +95,7 @@ def _check(exe, dtype, n, k, kb, w, nt, cg, ksplit):
     pos = -np.ones(n, dtype=np.int64)
     piv = rng.choice(n, size=k, replace=False)
     pos[piv] = np.arange(k)
-    Zo, norm = _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, kb > 0, dtype, ksplit)
+    Zo, norm = _run(exe, Z, U2T, pos, k, kb, zcol, w, nt, cg, kb > 0, dtype, ksplit, bf)
     Z64 = Z.astype(np.float64)
     rows = pos < 0
     K = slice(kb, k)
