@@ -833,13 +833,14 @@ int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, b
   const int cg = schur_cg(P, w);
   const int nt = ((w + 15) / 16 + cg - 1) / cg;  // column tiles per wave
   dim3 grid((unsigned)schur_parts(P, w));
-  // Long K: split-K form (about four workgroups per CU over the 64-row slabs,
-  // each split at least 128 K values, its FP64 partials in the sketch
-  // partials' buffer, which is free between a sketch's reduction and the
-  // next sketch), then the in-place subtraction with the same norm partials.
+  // Long K: split-K form (about two workgroups per CU over the 64-row slabs,
+  // measured faster than four or eight; each split at least 128 K values,
+  // its FP64 partials in the sketch partials' buffer, which is free between
+  // a sketch's reduction and the next sketch), then the in-place subtraction
+  // with the same norm partials.
   if (kb == 0 && w <= 64 && k >= 2 * kSchurSplitMinK) {
     const int64_t slabs = ceil_div(P.n, 64);
-    int64_t S = std::min<int64_t>(ceil_div(4 * (int64_t)P.cu, slabs), k / kSchurSplitMinK);
+    int64_t S = std::min<int64_t>(ceil_div(2 * (int64_t)P.cu, slabs), k / kSchurSplitMinK);
     S = std::min<int64_t>(S, (int64_t)(P.part_bytes / ((size_t)P.n * 64 * 8)));
     if (S >= 2) {
       const int ksplit = (int)(ceil_div(ceil_div(k, S), 64) * 64);
