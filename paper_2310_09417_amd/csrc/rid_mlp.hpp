@@ -95,7 +95,35 @@ __global__ __launch_bounds__(256) void k_rank_features(
     }
     __syncthreads();
     const int rend = (m - r0 < 64) ? m - r0 : 64;
-    for (int rr = 0; rr < rend; ++rr) {
+    // FP32 storage: eight rows' loads in flight at a time (same summation
+    // order as one row after another; 27 -> 13 ms for 16384 blocks of
+    // 64-1024; the FP64 form measured slower this way and keeps the loop)
+    int rr = 0;
+    for (; sizeof(TA) == 4 && rr + 8 <= rend; rr += 8) {
+      float a8[8][4];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const TA* arow = A + (int64_t)(r0 + rr + e) * la;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = tid + 256 * u;
+          a8[e][u] = (j < n) ? (float)arow[j] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = tid + 256 * u;
+          if (j < n) {
+            const float a = a8[e][u];
+            fro += (double)a * (double)a;
+#pragma unroll
+            for (int c = 0; c < kProbe; ++c) acc[u][c] += om[c][rr + e] * a;
+          }
+        }
+    }
+    for (; rr < rend; ++rr) {
       const TA* arow = A + (int64_t)(r0 + rr) * la;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
