@@ -97,7 +97,8 @@ __global__ __launch_bounds__(256) void k_rank_features(
     const int rend = (m - r0 < 64) ? m - r0 : 64;
     // FP32 storage: eight rows' loads in flight at a time (same summation
     // order as one row after another; 27 -> 13 ms for 16384 blocks of
-    // 64-1024; the FP64 form measured slower this way and keeps the loop)
+    // 64-1024; the FP64 form measured slower with eight or four rows ahead,
+    // 29.5 -> 33.3 / 33.6 ms, and keeps the loop)
     int rr = 0;
     for (; sizeof(TA) == 4 && rr + 8 <= rend; rr += 8) {
       float a8[8][4];
