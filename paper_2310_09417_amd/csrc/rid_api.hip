@@ -165,8 +165,9 @@ inline void prof_end(long at, hipStream_t st) {
   if (at >= 0) (void)hipEventRecord(prof().pool[(size_t)at + 1], st);
 }
 
-// Sketch launch geometry for a block of w <= 64 vectors: 256 columns per
-// workgroup, enough row splits for 2-8 rounds of workgroups.
+// Sketch launch geometry for a block of w <= 64 vectors: 128 (FP32) or 256
+// (FP64) columns per workgroup, enough row splits for 2-8 rounds of
+// workgroups.
 struct SketchGeom {
   int mt, wp, kc;
   int64_t ncolg, nsplit, rows_per_split;
