@@ -817,7 +817,7 @@ int block_update_t(const Plan& P, const Ws& W, int kb, int k, int zcol, int w, b
                        w, static_cast<TF*>(W.ytop), P.ldg, W.ctrl);
     RID_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_u2<TF>, dim3((unsigned)ceil_div(k - kb, 16), (unsigned)ceil_div(w, 64)),
-                       dim3(256), 0, st, static_cast<const TF*>(W.ytop), P.ldg, kb, k, w,
+                       dim3(512), 0, st, static_cast<const TF*>(W.ytop), P.ldg, kb, k, w,
                        static_cast<const TF*>(W.linv), P.ldl, static_cast<TF*>(W.u2t), P.ldu,
                        W.ctrl);
     RID_LAUNCH_CHECK();

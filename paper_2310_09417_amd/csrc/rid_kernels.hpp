@@ -572,10 +572,10 @@ __global__ __launch_bounds__(1024) void k_nonpiv(const int* __restrict__ pos, in
 }
 
 
-// The four waves of a workgroup split [kb, ke) and their 16 x 64 partial
-// tiles are summed (fixed order) into red (LDS, 16 x 64 doubles) by wave 0's
-// lanes; returns with red complete after a barrier.
-template <typename TF, typename BRow>
+// The NWV waves of a workgroup (4, or 8 for the U2 product) split [kb, ke)
+// and their 16 x 64 partial tiles are summed (fixed order, wave 0 first) into
+// red (LDS, 16 x 64 doubles); returns with red complete after a barrier.
+template <typename TF, typename BRow, int NWV = 4>
 __device__ __forceinline__ void wg_tile_ksplit(const TF* arow, BRow brow, int kb, int ke, int bcols,
                                                double* red) {
   using M = Mfma<TF>;
@@ -591,15 +591,15 @@ __device__ __forceinline__ void wg_tile_ksplit(const TF* arow, BRow brow, int kb
   // split on 16-aligned boundaries
   const int kb16 = kb & ~15;
   const int nchunks = (ke - kb16 + 15) / 16;
-  const int per = (nchunks + 3) / 4;
+  const int per = (nchunks + NWV - 1) / NWV;
   const int c0 = wave * per, c1 = (c0 + per < nchunks) ? c0 + per : nchunks;
   if (c0 < c1) {
     const int lo = (kb16 + 16 * c0 > kb) ? kb16 + 16 * c0 : kb;
     const int hi = (kb16 + 16 * c1 < ke) ? kb16 + 16 * c1 : ke;
     wave_tile<TF>(arow, brow, lo, hi, bcols, acc, acc64);
   }
-  // deterministic reduction: wave order 0,1,2,3
-  for (int wv = 0; wv < 4; ++wv) {
+  // deterministic reduction: wave order 0, 1, ..., NWV - 1
+  for (int wv = 0; wv < NWV; ++wv) {
     if (wave == wv) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -634,8 +634,10 @@ __global__ __launch_bounds__(256) void k_gather_top(const TF* __restrict__ Z, in
 // block of L1^{-1} on those rows (the block's pivot rows kb.. already hold its
 // Schur complement for the first kb pivots).  Grid (ceil((k-kb)/16),
 // ceil(w/64)); output U2T (w x ldu, column-major U2).
+// 512 threads: the 8 waves split the K range (at most k), so the last row
+// tiles do not hold up the launch.
 template <typename TF>
-__global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ G, int64_t ldg, int kb, int k,
+__global__ __launch_bounds__(512) void k_u2(const TF* __restrict__ G, int64_t ldg, int kb, int k,
                                             int w, const TF* __restrict__ Linv, int64_t ldl,
                                             TF* __restrict__ U2T, int64_t ldu, const Ctrl* ctrl) {
   if (ctrl->done) return;
@@ -647,8 +649,8 @@ __global__ __launch_bounds__(256) void k_u2(const TF* __restrict__ G, int64_t ld
   const int bcols = (w - j0 < 64) ? w - j0 : 64;
   auto brow = [&](int p) -> const TF* { return G + (int64_t)p * ldg + j0; };
   const int ke = (i0 + 16 < k) ? i0 + 16 : k;  // lower triangular: p <= i
-  wg_tile_ksplit<TF>(arow, brow, kb, ke, bcols, red);
-  for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+  wg_tile_ksplit<TF, decltype(brow), 8>(arow, brow, kb, ke, bcols, red);
+  for (int t = threadIdx.x; t < 16 * 64; t += 512) {
     const int ii = t % 16, jj = t / 16;
     if (i0 + ii < k && j0 + jj < w) U2T[(int64_t)(j0 + jj) * ldu + i0 + ii] = (TF)red[ii * 64 + jj];
   }
