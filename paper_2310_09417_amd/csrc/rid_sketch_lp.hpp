@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kLprThreads, 2) void k_sketch_lpr(
 // part[split][col][128] (FP32).
 // ---------------------------------------------------------------------------
 template <int FMT>
-__global__ __launch_bounds__(kLprThreads, 2) void k_sketch_lpw(
+__global__ __launch_bounds__(kLprThreads, (FMT == 1 ? 3 : 2)) void k_sketch_lpw(
     const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda,
     const unsigned char* __restrict__ rec, int64_t rows_per_split, float* __restrict__ part,
     const Ctrl* __restrict__ ctrl, int aligned, int vec8) {
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kLprThreads, 2) void k_sketch_lpw(
   constexpr int NW = kLprThreads / 64;
   constexpr int NCG = 2;                  // column groups per workgroup
   constexpr int KC = 32;                  // rows per chunk
-  constexpr int NST = 4;                  // ring stages
+  constexpr int NST = FMT == 1 ? 3 : 4;   // ring stages (BF16: three workgroups per CU)
   constexpr int RB = FMT == 1 ? 16 : 8;   // Omega operand bytes per lane and tile
   constexpr int OCH = 4 * 64 * RB;        // one vector half's records per chunk
   constexpr int OCW = 2 * OCH;            // both halves
